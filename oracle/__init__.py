@@ -1,0 +1,168 @@
+"""CPU FP64 oracle for the SELL-C-sigma augmented SpMMV (GHOST paper, Sec. 5.1-5.3).
+
+TEST INFRASTRUCTURE ONLY. This package is the independent checker: plain C routines
+(``oracle.c``) on CSR input in IEEE double, wrapped here with ctypes and numpy. Only the
+test suite, the smoke check and the benchmark's CPU-baseline leg may import it; the
+library (``paper_1507_08101_amd``) never does, and the two share no code.
+
+Functions take a CSR-like object with ``nrows, ncols, rowptr (int64), col (int32),
+val (float64)`` and row-major float64 numpy block vectors.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from . import build as _build
+
+SHIFT, VSHIFT, SCALE, AXPBY, DOT_YY, DOT_XY, DOT_XX, CHAIN = (1, 2, 4, 8, 16, 32, 64, 128)
+
+_lib = None
+_P = ct.c_void_p
+_I64 = ct.c_int64
+_D = ct.c_double
+
+
+def lib():
+    """Load (building on first use if absent) the oracle shared library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ct.CDLL(_build.LIB)
+        L.orc_spmmv.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _P, _I64]
+        L.orc_spmmv_aug.argtypes = [_I64, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P, _I64,
+                                    ct.c_uint, _D, _D, _D, _P, _D, _D, _P]
+        L.orc_dot.argtypes = [_I64, _P, _I64, _P, _I64]
+        L.orc_dot.restype = _D
+        L.orc_spmmv_T.argtypes = [_I64, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64]
+        L.orc_sell_layout.argtypes = [_I64, _P, _I64, _I64, _P, _P, _P]
+        L.orc_sell_fill.argtypes = [_I64, _P, _P, _P, _I64, _P, _P, _P, _P, _P]
+        L.orc_round_bf16.argtypes = [_I64, _P, _P]
+        L.orc_round_f32.argtypes = [_I64, _P, _P]
+        L.orc_cg.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, _P]
+        L.orc_chebyshev.argtypes = [_I64, _P, _P, _P, _P, _I64, _D, _D, _P, _P]
+        L.orc_num_threads.restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} rejected its arguments (rc={rc})")
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def spmmv(A, X):
+    """Y = A X for a row-major block vector X (ncols x b) or a vector (ncols,)."""
+    X = _f64(X)
+    vec = X.ndim == 1
+    X2 = X.reshape(-1, 1) if vec else X
+    b = X2.shape[1]
+    Y = np.empty((A.nrows, b))
+    _check(lib().orc_spmmv(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), b, _p(Y), b), "spmmv")
+    return Y[:, 0] if vec else Y
+
+
+def spmmv_aug(A, X, Y=None, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0.0, gamma_v=None,
+              delta=0.0, eta=1.0):
+    """Augmented product; returns (Y_new, Z_new or None, dot[3b] or None). Inputs are not modified."""
+    X = _f64(X)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1)
+    b = X.shape[1]
+    Yn = np.zeros((A.nrows, b)) if Y is None else _f64(Y).reshape(A.nrows, b).copy()
+    Zn = None
+    if flags & CHAIN:
+        Zn = np.zeros((A.nrows, b)) if Z is None else _f64(Z).reshape(A.nrows, b).copy()
+    gv = None if gamma_v is None else _f64(gamma_v)
+    dot = np.full(3 * b, np.nan) if flags & (DOT_YY | DOT_XY | DOT_XX) else None
+    rc = lib().orc_spmmv_aug(A.nrows, A.ncols, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X), b,
+                             _p(Yn), b, _p(Zn), b, flags, alpha, beta, gamma, _p(gv), delta, eta, _p(dot))
+    _check(rc, "spmmv_aug")
+    return Yn, Zn, dot
+
+
+def dot(a, b):
+    a = _f64(a)
+    b = _f64(b)
+    assert a.shape == b.shape and a.ndim == 1
+    return lib().orc_dot(a.size, _p(a), 1, _p(b), 1)
+
+
+def spmmv_T(A, X):
+    X = _f64(X)
+    vec = X.ndim == 1
+    X2 = X.reshape(-1, 1) if vec else X
+    b = X2.shape[1]
+    Y = np.empty((A.ncols, b))
+    _check(lib().orc_spmmv_T(A.nrows, A.ncols, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), b,
+                             _p(Y), b), "spmmv_T")
+    return Y[:, 0] if vec else Y
+
+
+def sell_layout(A, C, sigma):
+    """(perm int32[nch*C], cl int32[nch], cs int64[nch+1]) by brute force."""
+    nch = (A.nrows + C - 1) // C
+    perm = np.empty(nch * C, dtype=np.int32)
+    cl = np.empty(nch, dtype=np.int32)
+    cs = np.empty(nch + 1, dtype=np.int64)
+    _check(lib().orc_sell_layout(A.nrows, _p(A.rowptr), C, sigma, _p(perm), _p(cl), _p(cs)), "sell_layout")
+    return perm, cl, cs
+
+
+def sell_fill(A, C, perm, cl, cs):
+    """(scol int32[stored], sval float64[stored]) in SELL order; padding is (-1, 0.0)."""
+    stored = int(cs[-1])
+    scol = np.empty(stored, dtype=np.int32)
+    sval = np.empty(stored, dtype=np.float64)
+    _check(lib().orc_sell_fill(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), C, _p(perm), _p(cl),
+                               _p(cs), _p(scol), _p(sval)), "sell_fill")
+    return scol, sval
+
+
+def round_bf16(a):
+    a = _f64(a)
+    out = np.empty_like(a)
+    lib().orc_round_bf16(a.size, _p(a), _p(out))
+    return out
+
+
+def round_f32(a):
+    a = _f64(a)
+    out = np.empty_like(a)
+    lib().orc_round_f32(a.size, _p(a), _p(out))
+    return out
+
+
+def cg(A, bvec, x0=None, tol=1e-10, maxit=100000):
+    """FP64 CG; returns (x, iterations)."""
+    bvec = _f64(bvec)
+    x = np.zeros(A.nrows) if x0 is None else _f64(x0).copy()
+    it = ct.c_int64(0)
+    _check(lib().orc_cg(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(bvec), _p(x), tol, maxit,
+                        ct.byref(it)), "cg")
+    return x, it.value
+
+
+def chebyshev(A, x, M, s, c=0.0):
+    """Direct KPM moments mu[0..M] = <x, T_m(A~) x> with A~ = (A - cI)/s, and v_M."""
+    x = _f64(x)
+    mu = np.empty(M + 1)
+    v = np.empty(A.nrows)
+    _check(lib().orc_chebyshev(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(x), M, s, c, _p(mu),
+                               _p(v)), "chebyshev")
+    return mu, v

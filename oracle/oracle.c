@@ -1,0 +1,316 @@
+/*
+ * oracle.c -- plain CPU FP64 reference for the GHOST paper's augmented sparse matrix
+ * (multiple) vector product (Sec. 5.3), its block-vector form (Sec. 5.2) and the
+ * SELL-C-sigma layout (Sec. 5.1).
+ *
+ * TEST INFRASTRUCTURE ONLY: the checker, not the product. It is built with
+ * -ffp-contract=off so every multiply and add rounds separately, exactly as written.
+ * SELL-C-sigma is a lossless re-layout of the matrix, so the product it must reach is
+ * the plain CSR product; that plain definition is what is written here.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------------------
+ * Sparse matrix times block vector (Sec. 5.1, 5.2): Y = A X, one row at a time, the
+ * row's entries summed in stored order starting from +0.
+ */
+int orc_spmmv(int64_t nrows, const int64_t *rowptr, const int32_t *col, const double *val,
+              int64_t b, const double *X, int64_t ldx, double *Y, int64_t ldy) {
+    if (nrows < 0 || b < 1 || ldx < b || ldy < b) return -1;
+    if (nrows == 0) return 0;
+    if (!rowptr || !Y) return -1;
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < nrows; ++i) {
+        for (int64_t j = 0; j < b; ++j) {
+            double s = 0.0;
+            for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+                s = s + val[p] * X[(int64_t)col[p] * ldx + j];
+            Y[i * ldy + j] = s;
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Compensated dot product (Neumaier's improvement of Kahan summation; the paper adds a
+ * Kahan-summed reduction for long inner products in Sec. 5.2).
+ */
+double orc_dot(int64_t n, const double *a, int64_t inca, const double *b, int64_t incb) {
+    double s = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double term = a[i * inca] * b[i * incb];
+        double t = s + term;
+        if (fabs(s) >= fabs(term))
+            comp += (s - t) + term;
+        else
+            comp += (term - t) + s;
+        s = t;
+    }
+    return s + comp;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Augmented product (Sec. 5.3):  y = alpha (A - gamma I) x + beta y, then dots of the
+ * final y and the chained z = delta z + eta y.
+ */
+int orc_spmmv_aug(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
+                  const double *val, int64_t b, const double *X, int64_t ldx, double *Y,
+                  int64_t ldy, double *Z, int64_t ldz, unsigned flags, double alpha, double beta,
+                  double gamma, const double *gamma_v, double delta, double eta, double *dot) {
+    const unsigned need_square = ORC_SHIFT | ORC_VSHIFT | ORC_DOT_XY | ORC_DOT_XX;
+    if (nrows < 0 || ncols < 0 || b < 1 || ldx < b || ldy < b) return -1;
+    if ((flags & need_square) && nrows != ncols) return -1;
+    if ((flags & ORC_VSHIFT) && !gamma_v) return -1;
+    if ((flags & ORC_CHAIN) && (!Z || ldz < b)) return -1;
+    if ((flags & (ORC_DOT_YY | ORC_DOT_XY | ORC_DOT_XX)) && !dot) return -1;
+
+    double *s = (double *)malloc(sizeof(double) * (size_t)(nrows > 0 ? nrows : 1) * (size_t)b);
+    if (!s) return -1;
+    /* step 1: s = A x */
+    int rc = orc_spmmv(nrows, rowptr, col, val, b, X, ldx, s, b);
+    if (rc) {
+        free(s);
+        return rc;
+    }
+    const double a = (flags & ORC_SCALE) ? alpha : 1.0;
+    const double bt = (flags & ORC_AXPBY) ? beta : 0.0;
+    /* step 2: y = a * (s - g_j x) + bt * y_old   (y_old only read when bt != 0) */
+    for (int64_t i = 0; i < nrows; ++i) {
+        for (int64_t j = 0; j < b; ++j) {
+            double g = 0.0;
+            if (flags & ORC_VSHIFT)
+                g = gamma_v[j];
+            else if (flags & ORC_SHIFT)
+                g = gamma;
+            double t = s[i * b + j];
+            if (flags & (ORC_SHIFT | ORC_VSHIFT)) t = t - g * X[i * ldx + j];
+            double y = a * t;
+            if (bt != 0.0) y = y + bt * Y[i * ldy + j];
+            Y[i * ldy + j] = y;
+        }
+    }
+    free(s);
+    /* step 3: dots of the final y */
+    for (int64_t j = 0; j < b; ++j) {
+        if (flags & ORC_DOT_YY) dot[j] = orc_dot(nrows, Y + j, ldy, Y + j, ldy);
+        if (flags & ORC_DOT_XY) dot[b + j] = orc_dot(nrows, X + j, ldx, Y + j, ldy);
+        if (flags & ORC_DOT_XX) dot[2 * b + j] = orc_dot(nrows, X + j, ldx, X + j, ldx);
+    }
+    /* step 4: z = delta z + eta y   (z only read when delta != 0) */
+    if (flags & ORC_CHAIN) {
+        for (int64_t i = 0; i < nrows; ++i)
+            for (int64_t j = 0; j < b; ++j) {
+                double z = eta * Y[i * ldy + j];
+                if (delta != 0.0) z = delta * Z[i * ldz + j] + z;
+                Z[i * ldz + j] = z;
+            }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Transposed product Y = A^T X by scattering each row's contribution.
+ */
+int orc_spmmv_T(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
+                const double *val, int64_t b, const double *X, int64_t ldx, double *Y,
+                int64_t ldy) {
+    if (nrows < 0 || ncols < 0 || b < 1 || ldx < b || ldy < b) return -1;
+    for (int64_t c = 0; c < ncols; ++c)
+        for (int64_t j = 0; j < b; ++j) Y[c * ldy + j] = 0.0;
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p)
+            for (int64_t j = 0; j < b; ++j)
+                Y[(int64_t)col[p] * ldy + j] = Y[(int64_t)col[p] * ldy + j] + val[p] * X[i * ldx + j];
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * SELL-C-sigma layout (Sec. 5.1) by brute force.
+ */
+static const int64_t *g_len_for_sort; /* row lengths for the comparator below */
+
+static int by_length_desc_then_index(const void *pa, const void *pb) {
+    int32_t ra = *(const int32_t *)pa, rb = *(const int32_t *)pb;
+    int64_t la = g_len_for_sort[ra], lb = g_len_for_sort[rb];
+    if (la != lb) return la > lb ? -1 : 1; /* longer rows first */
+    return ra < rb ? -1 : (ra > rb ? 1 : 0); /* equal lengths keep their original order */
+}
+
+int orc_sell_layout(int64_t nrows, const int64_t *rowptr, int64_t C, int64_t sigma,
+                    int32_t *perm, int32_t *cl, int64_t *cs) {
+    if (nrows < 0 || C < 1 || sigma < 1) return -1;
+    int64_t nch = (nrows + C - 1) / C;
+    int64_t *len = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nrows > 0 ? nrows : 1));
+    if (!len) return -1;
+    for (int64_t i = 0; i < nrows; ++i) len[i] = rowptr[i + 1] - rowptr[i];
+    for (int64_t s = 0; s < nch * C; ++s) perm[s] = s < nrows ? (int32_t)s : -1;
+    g_len_for_sort = len;
+    for (int64_t w = 0; w < nrows; w += sigma) {
+        int64_t we = w + sigma < nrows ? w + sigma : nrows;
+        qsort(perm + w, (size_t)(we - w), sizeof(int32_t), by_length_desc_then_index);
+    }
+    g_len_for_sort = NULL;
+    cs[0] = 0;
+    for (int64_t c = 0; c < nch; ++c) {
+        int64_t m = 0;
+        for (int64_t r = 0; r < C; ++r) {
+            int32_t row = perm[c * C + r];
+            if (row >= 0 && len[row] > m) m = len[row];
+        }
+        cl[c] = (int32_t)m;
+        cs[c + 1] = cs[c] + C * m;
+    }
+    free(len);
+    return 0;
+}
+
+int orc_sell_fill(int64_t nrows, const int64_t *rowptr, const int32_t *col, const double *val,
+                  int64_t C, const int32_t *perm, const int32_t *cl, const int64_t *cs,
+                  int32_t *scol, double *sval) {
+    if (nrows < 0 || C < 1) return -1;
+    int64_t nch = (nrows + C - 1) / C;
+    for (int64_t c = 0; c < nch; ++c)
+        for (int64_t r = 0; r < C; ++r) {
+            int32_t row = perm[c * C + r];
+            int64_t len = row >= 0 ? rowptr[row + 1] - rowptr[row] : 0;
+            for (int64_t k = 0; k < cl[c]; ++k) {
+                int64_t at = cs[c] + k * C + r;
+                if (k < len) {
+                    scol[at] = col[rowptr[row] + k];
+                    sval[at] = val[rowptr[row] + k];
+                } else {
+                    scol[at] = -1;
+                    sval[at] = 0.0;
+                }
+            }
+        }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Rounding to bfloat16 / binary32, nearest with ties to even, taken straight from the
+ * definition: the representable neighbours of v are the multiples of the quantum
+ * q = 2^(e - p) for v = f * 2^e with 0.5 <= |f| < 1 and p significant bits (clamped at
+ * the subnormal quantum), so v rounds to q * nearbyint(v / q) in the default rounding
+ * mode (which breaks ties to the even multiple). Dividing by a power of two is exact.
+ */
+static double round_to_format(double v, int p, int emin_sub, double maxfinite) {
+    if (!isfinite(v) || v == 0.0) return v;
+    int e;
+    frexp(v, &e);
+    int qe = e - p;
+    if (qe < emin_sub) qe = emin_sub;
+    double q = ldexp(1.0, qe);
+    double r = nearbyint(v / q) * q;
+    if (fabs(r) > maxfinite) return v > 0 ? INFINITY : -INFINITY;
+    return r;
+}
+
+int orc_round_bf16(int64_t n, const double *in, double *out) {
+    /* bfloat16: 8 significant bits, smallest subnormal 2^-133, largest finite
+     * (2 - 2^-7) * 2^127 */
+    const double maxf = ldexp(2.0 - ldexp(1.0, -7), 127);
+    for (int64_t i = 0; i < n; ++i) out[i] = round_to_format(in[i], 8, -133, maxf);
+    return 0;
+}
+
+int orc_round_f32(int64_t n, const double *in, double *out) {
+    /* binary32: 24 significant bits, smallest subnormal 2^-149 */
+    const double maxf = ldexp(2.0 - ldexp(1.0, -23), 127);
+    for (int64_t i = 0; i < n; ++i) out[i] = round_to_format(in[i], 24, -149, maxf);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Conjugate gradients, textbook Hestenes-Stiefel form, FP64.
+ */
+int orc_cg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+           const double *bvec, double *x, double tol, int64_t maxit, int64_t *iters) {
+    if (n < 0 || maxit < 0) return -1;
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(sz), *p = (double *)malloc(sz), *q = (double *)malloc(sz);
+    if (!r || !p || !q) {
+        free(r);
+        free(p);
+        free(q);
+        return -1;
+    }
+    orc_spmmv(n, rowptr, col, val, 1, x, 1, q, 1);
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = bvec[i] - q[i];
+        p[i] = r[i];
+    }
+    double bnorm = sqrt(orc_dot(n, bvec, 1, bvec, 1));
+    double rr = orc_dot(n, r, 1, r, 1);
+    int64_t it = 0;
+    while (it < maxit && sqrt(rr) > tol * bnorm) {
+        orc_spmmv(n, rowptr, col, val, 1, p, 1, q, 1);
+        double alpha = rr / orc_dot(n, p, 1, q, 1);
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * q[i];
+        }
+        double rr_new = orc_dot(n, r, 1, r, 1);
+        double beta = rr_new / rr;
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        ++it;
+    }
+    if (iters) *iters = it;
+    free(r);
+    free(p);
+    free(q);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------------
+ * Chebyshev recurrence of the kernel polynomial method, direct moments.
+ */
+int orc_chebyshev(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                  const double *x, int64_t M, double s, double c, double *mu, double *vlast) {
+    if (n < 0 || M < 0 || s == 0.0) return -1;
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *vprev = (double *)malloc(sz), *vcur = (double *)malloc(sz), *t = (double *)malloc(sz);
+    if (!vprev || !vcur || !t) {
+        free(vprev);
+        free(vcur);
+        free(t);
+        return -1;
+    }
+    memcpy(vcur, x, sizeof(double) * (size_t)n);
+    mu[0] = orc_dot(n, x, 1, vcur, 1);
+    for (int64_t m = 1; m <= M; ++m) {
+        orc_spmmv(n, rowptr, col, val, 1, vcur, 1, t, 1);
+        for (int64_t i = 0; i < n; ++i) {
+            double at = (t[i] - c * vcur[i]) / s; /* A~ v_{m-1} */
+            double next = (m == 1) ? at : 2.0 * at - vprev[i];
+            vprev[i] = vcur[i];
+            t[i] = next;
+        }
+        double *sw = vcur;
+        vcur = t;
+        t = sw;
+        mu[m] = orc_dot(n, x, 1, vcur, 1);
+    }
+    if (vlast) memcpy(vlast, vcur, sizeof(double) * (size_t)n);
+    free(vprev);
+    free(vcur);
+    free(t);
+    return 0;
+}
