@@ -1,0 +1,283 @@
+"""Benchmark: SELL-C-sigma augmented SpMMV in the kernel polynomial method recurrence.
+
+Workload (one "step"): the Chebyshev/KPM recurrence of M = 200 augmented SpMMVs
+    v_{m+1} = (2/s) (A - c I) v_m - v_{m-1},  with fused <v,v> and <v_m, v_{m+1}>,
+on the 3D periodic Anderson Hamiltonian of a 128^3 lattice (n = 2,097,152, 7 nonzeros per
+row, disorder U[-8.25, 8.25]), FP64, SELL-32-1, row-major block vector of width b = 8
+(b = 1 is reported beside it). Inputs are synthetic and seeded and resident in HBM before
+the timed region.
+
+Prints ONE JSON line: GFLOP/s (2 flops per true nonzero per vector) of the whole recurrence,
+with HBM GB/s against the MI355X's 8 TB/s in "roofline" (algorithmic bytes per launch /
+average launch duration from HIP events recorded on the launch stream), measured
+achievable bandwidth from streaming probes, the FP64-vs-mixed-precision CG comparison and
+the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W_DISORDER = 16.5
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("spmmv_impl.h", "spmmv_f64.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_1507_08101_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name: str, src_hash: str):
+    """HBM traffic per launch measured with rocprofv3 counters (profiles/), or None when the
+    kernel source changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != src_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def probe_bandwidth(sc, torch, nbytes=4 << 30, reps=10):
+    """Achievable HBM bandwidth with the library's streaming probes (best of reps)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    out = {}
+    for kind, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "write", nbytes)):
+        best = float("inf")
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sc.sell_probe_bandwidth(kind, b, a, nbytes)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[name] = moved / (best * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def kpm_run(sc, torch, M_h, V0d, b, M, s, timed_steps, warmup):
+    n = V0d.shape[0]
+    V = torch.empty((n, b), dtype=torch.float64, device="cuda")
+    W = torch.empty_like(V)
+    mu = torch.empty((2 * M + 1) * b, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        V.copy_(V0d)
+        sc.sell_kpm(M_h, V, W, M, s, 0.0, mu)
+    torch.cuda.synchronize()
+    step_ms = []
+    launch_ms = []
+    for _ in range(timed_steps):
+        V.copy_(V0d)  # outside the step timing: restore v0
+        torch.cuda.synchronize()
+        lm = np.zeros(M, dtype=np.float32)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sc.sell_kpm(M_h, V, W, M, s, 0.0, mu, step_ms=lm)
+        e1.record()
+        e1.synchronize()
+        step_ms.append(e0.elapsed_time(e1))
+        launch_ms.append(lm)
+    return np.array(step_ms), np.concatenate(launch_ms), mu
+
+
+def cg_compare(sc, torch, synth, edge, nrhs=8, tol=1e-10):
+    """Time to ||b - Ax|| <= tol ||b||: FP64 CG vs BF16-value CG with FP64 refinement."""
+    A = synth.laplacian3d(edge)
+    B = synth.block_vector(A.nrows, nrhs, synth.SEED_Y)
+    Bd = torch.from_numpy(B).cuda()
+    out = {"matrix": f"3D 7-point Dirichlet Laplacian {edge}^3", "n": A.nrows, "nnz": A.nnz, "nrhs": nrhs}
+    A64 = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype="f64")
+    for lo in ("bf16", "f32"):
+        Alo = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=lo)
+        for rep in range(2):
+            Xd = torch.zeros_like(Bd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sc.sell_cg_mixed(A64, Alo, Bd, Xd, tol=tol)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+        out[f"mixed_{lo}"] = dict(seconds=t, **st)
+        Alo.close()
+    for rep in range(2):
+        Xd = torch.zeros_like(Bd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sc.sell_cg(A64, Bd, Xd, tol=tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+    out["fp64"] = dict(seconds=t, **st)
+    A64.close()
+    out["speedup_bf16_vs_fp64"] = out["fp64"]["seconds"] / out["mixed_bf16"]["seconds"]
+    return out
+
+
+def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
+    """The oracle's augmented product (one KPM step) on the host cores, bounded sample."""
+    X = synth.block_vector(A.nrows, b, synth.SEED_X)
+    Y = synth.block_vector(A.nrows, b, synth.SEED_Y)
+    flags = oracle.SCALE | oracle.SHIFT | oracle.AXPBY | oracle.DOT_YY | oracle.DOT_XY
+    calls = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.spmmv_aug(A, X, Y=Y, flags=flags, alpha=2.0 / s, beta=-1.0, gamma=0.0)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or calls >= 200:
+            break
+    gf = calls * 2 * A.nnz * b / el / 1e9
+    return {"value": gf, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{calls} augmented products (one KPM step each, b={b}) on the full "
+                      f"{A.name} matrix, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--L", type=int, default=128)
+    ap.add_argument("--M", type=int, default=200)
+    ap.add_argument("--b", type=int, default=8)
+    ap.add_argument("--C", type=int, default=32)
+    ap.add_argument("--sigma", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-b1", action="store_true")
+    ap.add_argument("--cg-edge", type=int, default=100)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not offered (the sharded design is "
+              f"described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1507_08101_amd as sc
+    import synth
+    from paper_1507_08101_amd import model
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    log(f"[bench] device {torch.cuda.get_device_name(0)}")
+
+    t0 = time.perf_counter()
+    A = synth.anderson3d(args.L, W=W_DISORDER)
+    log(f"[bench] generated {A} in {time.perf_counter() - t0:.1f} s")
+    s = (6.0 + W_DISORDER / 2) / 0.99  # Gershgorin bound with 1 % margin
+    t0 = time.perf_counter()
+    Mh = sc.SellMatrix.from_csr(A, C=args.C, sigma=args.sigma, dtype="f64")
+    build_s = time.perf_counter() - t0
+    info = Mh.info
+    log(f"[bench] SELL-{args.C}-{args.sigma} build+upload {build_s:.2f} s, stored {info['stored']}")
+
+    results = {}
+    widths = [args.b] + ([] if args.no_b1 or args.b == 1 else [1])
+    for b in widths:
+        V0 = synth.block_vector(A.nrows, b, synth.SEED_X)
+        V0d = torch.from_numpy(V0).cuda()
+        steps = args.steps if b == args.b else max(2, args.steps // 2)
+        step_ms, launch_ms, mu = kpm_run(sc, torch, Mh, V0d, b, args.M, s, steps, args.warmup)
+        flops_step = args.M * model.flops(A.nnz, b)
+        # algorithmic bytes: first product writes y only, the others read and write y
+        b0 = model.bytes_min(A.nnz, A.nrows, A.ncols, b, 8, 8, read_y=False, nchunks=info["nchunks"])
+        b1 = model.bytes_min(A.nnz, A.nrows, A.ncols, b, 8, 8, read_y=True, nchunks=info["nchunks"])
+        bytes_launch = (b0 + (args.M - 1) * b1) / args.M
+        launch_avg_ms = float(np.mean(launch_ms))
+        results[b] = dict(
+            ms_per_step=float(np.mean(step_ms)),
+            gflops=flops_step / (float(np.mean(step_ms)) * 1e-3) / 1e9,
+            gflops_pmax=flops_step / (float(np.min(step_ms)) * 1e-3) / 1e9,
+            launch_avg_us=launch_avg_ms * 1e3,
+            launch_min_us=float(np.min(launch_ms)) * 1e3,
+            bytes_per_launch=bytes_launch,
+            hbm_gbs=bytes_launch / (launch_avg_ms * 1e-3) / 1e9,
+            mu0=float(mu[0].item()), steps=steps)
+        log(f"[bench] b={b}: {results[b]['ms_per_step']:.3f} ms/step, {results[b]['gflops']:.1f} GFLOP/s, "
+            f"launch {results[b]['launch_avg_us']:.1f} us, {results[b]['hbm_gbs']:.0f} GB/s")
+        del V0d
+
+    head = results[args.b]
+    probes = None if args.no_probe else probe_bandwidth(sc, torch)
+    if probes:
+        log(f"[bench] probes GB/s: {probes}")
+    cg = None
+    if not args.no_cg:
+        try:
+            cg = cg_compare(sc, torch, synth, args.cg_edge)
+            log(f"[bench] CG: {json.dumps(cg)}")
+        except sc.SellError as e:
+            cg = {"error": str(e)}
+            log(f"[bench] CG skipped: {e}")
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        cpu = cpu_baseline(oracle, synth, A, args.b, s)
+        log(f"[bench] cpu baseline: {cpu}")
+
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(f"traffic_anderson{args.L}_b{args.b}.json", src_hash)
+    frac = head["hbm_gbs"] / HBM_PEAK_GBS
+    line = {
+        "metric": "SpMMV GFLOP/s and HBM GB/s (% of peak) FP64 vs BF16-value+refine, 1 MI355X",
+        "value": round(head["gflops"], 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded 3D Anderson Hamiltonian, block vector U[-1,1])",
+        "config": {"workload": f"KPM recurrence, {args.M} augmented SpMMVs with fused dots, 3D periodic "
+                               f"Anderson {args.L}^3 (n={A.nrows}, nnz={A.nnz}), SELL-{args.C}-{args.sigma}",
+                   "n": A.nrows, "nnz": A.nnz, "b": args.b, "C": args.C, "sigma": args.sigma,
+                   "kpm_steps": args.M},
+        "roofline": {"bound": "hbm", "achieved": round(head["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(frac, 4), "traffic": traffic,
+                     "kernel": "prod_kernel<VK_F64F64, 8, 4, AUG=true>",
+                     "bytes_per_launch": int(head["bytes_per_launch"]),
+                     "launch_avg_us": round(head["launch_avg_us"], 2)},
+        "cpu_baseline": cpu,
+        "hbm_gbs": round(head["hbm_gbs"], 1),
+        "pmax_gflops": round(head["gflops_pmax"], 2),
+        "b1": None if 1 not in results or args.b == 1 else {k: (round(v, 3) if isinstance(v, float) else v)
+                                                            for k, v in results[1].items()},
+        "achievable_gbs": probes,
+        "frac_of_achievable": None if not probes else round(head["hbm_gbs"] / max(probes.values()), 4),
+        "cg_time_to_1e-10": cg,
+        "build_s": round(build_s, 3),
+        "kernel_source_hash": src_hash,
+    }
+    print(json.dumps(line), flush=True)
+    Mh.close()
+
+
+if __name__ == "__main__":
+    main()

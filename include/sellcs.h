@@ -1,0 +1,277 @@
+/*
+ * sellcs.h -- C ABI of libsellcs: SELL-C-sigma sparse matrix times (block) vector,
+ * plain and augmented, for one AMD Instinct MI355X (gfx950).
+ *
+ * What is computed follows the GHOST paper (Kreutzer et al., "GHOST: Building blocks for
+ * high performance sparse linear algebra on heterogeneous systems"):
+ *   - the SELL-C-sigma storage format (Sec. 5.1): rows cut into chunks of C, each chunk
+ *     padded with trailing zeros to its longest row and stored column by column, rows
+ *     sorted by length inside windows of sigma rows;
+ *   - block vectors (Sec. 3.2, 5.2): tall, skinny dense matrices, preferably row-major
+ *     ("interleaved"), usable as views of memory the caller owns;
+ *   - the augmented product (Sec. 5.3):  y = alpha (A - gamma I) x + beta y, fused with
+ *     the dot products <y,y>, <x,y>, <x,x> and the chained z = delta z + eta y, each
+ *     augmentation switched on separately.
+ *
+ * General rules for every entry point:
+ *   - Return value: SELL_OK (0) or a negative SELL_ERR_* code; sell_strerror() names it.
+ *     No C++ exception crosses this interface. Arguments are checked before any GPU work
+ *     is issued; a call that fails a check has no effect.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream). Compute calls
+ *     are asynchronous on that stream: they enqueue kernels and return. Results (including
+ *     dot products, which land in device memory) are valid once the stream has reached
+ *     that point.
+ *   - All device memory passed in must belong to the current HIP device.
+ *   - Indices: local row and column indices are 32-bit (nrows, ncols < 2^31); offsets into
+ *     the stored arrays are 64-bit, so a matrix may store more than 2^31 entries
+ *     (Sec. 5.1 discusses 32-bit local indices).
+ */
+#ifndef SELLCS_H
+#define SELLCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sell_mat sell_mat; /* opaque SELL-C-sigma matrix            */
+typedef struct sell_bv sell_bv;   /* opaque block vector (owner or view)   */
+
+/* Element types. Matrix values may be F64, F32 or BF16; block vectors F64, F32 or BF16
+ * (BF16 block vectors are storage only: sell_bv_copy converts them, the products do not
+ * take them). */
+typedef enum { SELL_F64 = 0, SELL_F32 = 1, SELL_BF16 = 2 } sell_dtype;
+
+/* Block-vector storage (Sec. 3.2): row-major = interleaved, element (i, j) at
+ * ptr[i * ld + j]; column-major: element (i, j) at ptr[j * ld + i]. */
+typedef enum { SELL_ROW_MAJOR = 0, SELL_COL_MAJOR = 1 } sell_layout;
+
+enum {
+    SELL_OK = 0,
+    SELL_ERR_ARG = -1,         /* null pointer, bad size or bad parameter          */
+    SELL_ERR_SHAPE = -2,       /* operand dimensions do not fit together           */
+    SELL_ERR_DTYPE = -3,       /* element-type combination not offered             */
+    SELL_ERR_UNSUPPORTED = -4, /* valid request that this library does not do      */
+    SELL_ERR_OOM = -5,         /* device or host allocation failed                  */
+    SELL_ERR_HIP = -6,         /* a HIP runtime call failed                         */
+    SELL_ERR_STATE = -7        /* object not in a usable state (e.g. host-only)     */
+};
+
+/* ------------------------------------------------------------------------------------ */
+/* Library                                                                              */
+
+/* Static text for an error code (never NULL). */
+const char *sell_strerror(int code);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int sell_version(void);
+
+/* ------------------------------------------------------------------------------------ */
+/* Sparse matrix (Sec. 3.1, 5.1)                                                        */
+
+/* Build a SELL-C-sigma matrix on the current device from host CSR arrays (Sec. 5.1
+ * describes construction from raw CRS data).
+ *   rowptr: int64[nrows + 1], rowptr[0] = 0, non-decreasing; col: int32[nnz] with
+ *   0 <= col < ncols; val: double[nnz]. Entries of a row keep their order; duplicated
+ *   (row, col) pairs stay separate entries. The host arrays are only read, and are not
+ *   referenced after the call returns.
+ *   C >= 1 (chunk height), 1 <= sigma (sorting window; sigma > nrows acts as nrows).
+ *   Rows are sorted by descending length inside each window of sigma rows, ties keeping
+ *   their original order; sigma = 1 keeps the original order.
+ *   vdt: storage type of the values; F64 values are converted to F32 or BF16 by
+ *   rounding to nearest, ties to even, directly from the double.
+ * On success *A owns device memory; release it with sell_destroy. The call returns after
+ * the upload has finished (it synchronises "stream").
+ * Errors: SELL_ERR_ARG (null pointers, C < 1, sigma < 1, rowptr not monotone or
+ * rowptr[0] != 0, a column outside [0, ncols), nrows or ncols >= 2^31),
+ * SELL_ERR_DTYPE, SELL_ERR_OOM, SELL_ERR_HIP. */
+int sell_build(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr,
+               const int32_t *col, const double *val, int32_t C, int64_t sigma,
+               sell_dtype vdt, void *stream);
+
+/* Same as sell_build but keeps the SELL arrays in host memory only and touches no GPU.
+ * The result serves sell_info, sell_export_csr, sell_export_sell and sell_destroy; the
+ * compute calls reject it with SELL_ERR_STATE. */
+int sell_build_host(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                    const int32_t *col, const double *val, int32_t C, int64_t sigma,
+                    sell_dtype vdt);
+
+/* Replace the values of a matrix with the same sparsity pattern (Sec. 5.1: later
+ * constructions with an unchanged pattern only update values).
+ *   val: double[nnz] in the CSR order given at build time, in host memory
+ *   (sell_update_values) or device memory (sell_update_values_device). Converted to the
+ *   matrix's storage type. Asynchronous on "stream" for the device variant; the host
+ *   variant returns after the copy. */
+int sell_update_values(sell_mat *A, const double *val, void *stream);
+int sell_update_values_device(sell_mat *A, const double *val, void *stream);
+
+/* Copy the matrix back out as CSR into caller-owned host arrays (rowptr int64[nrows+1],
+ * col int32[nnz], val double[nnz]). For an F64 matrix this reproduces the build input
+ * bit for bit; F32/BF16 values come back as the doubles they represent. */
+int sell_export_csr(const sell_mat *A, int64_t *rowptr, int32_t *col, double *val);
+
+/* Copy the raw SELL-C-sigma arrays into caller-owned host arrays (any may be NULL):
+ *   perm int32[nchunks*C] (slot -> original row, -1 for slots past the last row),
+ *   cl int32[nchunks] (chunk lengths), cs int64[nchunks+1] (chunk starts),
+ *   col int32[stored] and val double[stored] (entry k of slot r of chunk c at
+ *   cs[c] + k*C + r; padding has col = -1 and val = 0). */
+int sell_export_sell(const sell_mat *A, int32_t *perm, int32_t *cl, int64_t *cs,
+                     int32_t *col, double *val);
+
+typedef struct {
+    int64_t nrows, ncols;
+    int64_t nnz;           /* true nonzeros                                      */
+    int64_t stored;        /* stored entries including padding                  */
+    int64_t nchunks;       /* ceil(nrows / C)                                    */
+    int64_t sigma;
+    int32_t C;
+    int32_t vdtype;        /* sell_dtype of the values                           */
+    int32_t on_device;     /* 1 for sell_build results, 0 for sell_build_host    */
+    int32_t device;        /* HIP device id (-1 if host-only)                    */
+    int32_t ntiles;        /* work partitions of one product launch              */
+    int32_t has_perm;      /* 0 when the row order is unchanged (sigma = 1)      */
+    int64_t matrix_bytes;  /* bytes of all device arrays of the matrix           */
+} sell_info_t;
+
+int sell_info(const sell_mat *A, sell_info_t *out);
+
+/* Free a matrix (device and host memory). NULL is a no-op. Must not race with work
+ * still queued on a stream that uses A. */
+int sell_destroy(sell_mat *A);
+
+/* ------------------------------------------------------------------------------------ */
+/* Block vectors (Sec. 3.2, 5.2)                                                        */
+
+/* Create an nrows x ncols block vector of type dt and layout lay on the current device.
+ *   data == NULL: the library allocates (ld is then ignored and set to ncols for
+ *   row-major, nrows for column-major) and owns the memory; the contents are zeroed.
+ *   data != NULL: a view of caller-owned device memory (Sec. 3.2 "views of raw data",
+ *   e.g. a torch tensor), never freed by the library; ld >= ncols (row-major) or
+ *   ld >= nrows (column-major).
+ * nrows >= 0, 1 <= ncols. */
+int sell_bv_create(sell_bv **X, int64_t nrows, int32_t ncols, sell_dtype dt, sell_layout lay,
+                   void *data, int64_t ld);
+
+/* Free an owned block vector, or forget a view. NULL is a no-op. */
+int sell_bv_destroy(sell_bv *X);
+
+/* Pointer, leading dimension and shape of a block vector (any out-pointer may be NULL). */
+int sell_bv_data(const sell_bv *X, void **data, int64_t *ld, int64_t *nrows, int32_t *ncols,
+                 int32_t *dtype, int32_t *layout);
+
+/* dst = src elementwise, converting layout (row-/column-major, Sec. 3.2) and element type
+ * (F64 <-> F32 <-> BF16, narrowing by round to nearest, ties to even). Shapes must agree;
+ * dst and src must not overlap unless they are the same object with the same type and
+ * layout (then nothing is done). Asynchronous on stream. */
+int sell_bv_copy(sell_bv *dst, const sell_bv *src, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Products (Sec. 5.2, 5.3)                                                             */
+
+/* Y = A X (Sec. 5.1, 5.2). X: ncols x b, Y: nrows x b, both row- or column-major.
+ * Types: F64 matrix with F64 vectors (FP64 arithmetic); F32 or BF16 matrix with F32
+ * vectors (FP32 accumulation). Y must not overlap X. Deterministic: repeated calls give
+ * identical bits. */
+int sell_spmmv(const sell_mat *A, const sell_bv *X, sell_bv *Y, void *stream);
+
+/* Augmentation switches (Sec. 5.3); combine with |. Each one is independent. */
+#define SELL_SPMV_SHIFT 0x01u  /* subtract gamma * x, one gamma for all columns      */
+#define SELL_SPMV_VSHIFT 0x02u /* subtract gamma_v[j] * x_j, one per column           */
+#define SELL_SPMV_SCALE 0x04u  /* multiply by alpha                                   */
+#define SELL_SPMV_AXPBY 0x08u  /* add beta * y (y is not read when beta == 0)        */
+#define SELL_SPMV_DOT_YY 0x10u /* <y, y> per column of the final y                    */
+#define SELL_SPMV_DOT_XY 0x20u /* <x, y> per column                                   */
+#define SELL_SPMV_DOT_XX 0x40u /* <x, x> per column                                   */
+#define SELL_SPMV_CHAIN 0x80u  /* z = delta z + eta y (z not read when delta == 0)    */
+#define SELL_SPMV_DOTS (SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY | SELL_SPMV_DOT_XX)
+
+typedef struct {
+    uint32_t flags;
+    double alpha;          /* used with SELL_SPMV_SCALE, else 1                       */
+    double beta;           /* used with SELL_SPMV_AXPBY, else 0                       */
+    double gamma;          /* used with SELL_SPMV_SHIFT                               */
+    const double *gamma_v; /* HOST array of b shifts, with SELL_SPMV_VSHIFT; read
+                              before the call returns                                 */
+    double delta, eta;     /* used with SELL_SPMV_CHAIN                               */
+    double *dot;           /* DEVICE array of 3*b doubles receiving
+                              [<y,y>_0..b-1 | <x,y>_0..b-1 | <x,x>_0..b-1];
+                              entries of dots not requested are left untouched        */
+} sell_spmv_opts;
+
+/* Defaults: alpha = 1, beta = 0, gamma = 0, delta = 0, eta = 1, no flags. */
+#define SELL_SPMV_OPTS_INIT {0u, 1.0, 0.0, 0.0, (const double *)0, 0.0, 1.0, (double *)0}
+
+/* Augmented product (Sec. 5.3):
+ *   y <- alpha (A x - gamma_j x) + beta y ;  dots of the final y ;  z <- delta z + eta y.
+ * All arithmetic of the epilogue is FP64; the dots are accumulated in FP64 for every
+ * type and are computed from the stored y. Shifts and x-dots need a square A. Z (same
+ * shape and type as Y) is required with SELL_SPMV_CHAIN, else ignored (may be NULL).
+ * opts == NULL means the defaults. Deterministic, dots included (fixed reduction order,
+ * no floating-point atomics). Concurrent calls with dots on different streams are safe;
+ * calls with dots on one stream are ordered by the stream. */
+int sell_spmmv_aug(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z,
+                   const sell_spmv_opts *opts, void *stream);
+
+/* Y = A^T X. X: nrows x b, Y: ncols x b, row-major. deterministic = 0 scatters with
+ * floating-point atomics (results may differ in the last bits from run to run);
+ * deterministic = 1 runs the forward kernel on a SELL-C-sigma copy of A^T, which the
+ * first such call builds and keeps with A (a synchronous, allocating call). */
+int sell_spmmv_T(const sell_mat *A, const sell_bv *X, sell_bv *Y, int deterministic,
+                 void *stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Solver drivers built from the products (Sec. 5.2 block BLAS-1 operations, Sec. 6)    */
+
+/* Kernel polynomial method recurrence for A~ = (A - c I) / s on a block of starting
+ * vectors: v_0 = V (nrows x b, F64 row-major, overwritten), v_1 = A~ v_0,
+ * v_{m+1} = 2 A~ v_m - v_{m-1}, using M augmented products with fused dots.
+ * mu (DEVICE, (2M + 1) * b doubles, column j's moments at mu[m * b + j]) receives the
+ * Chebyshev moments mu_m = <v_0, T_m(A~) v_0> for m = 0..2M, from the doubling
+ * identities mu_2m = 2 <v_m, v_m> - mu_0 and mu_2m+1 = 2 <v_m+1, v_m> - mu_1.
+ * W is a work block vector of the same shape. On return V and W hold v_M and v_{M-1}
+ * (which one holds which is reported in *last_in_w, may be NULL). M >= 1.
+ * step_ms: NULL for an asynchronous call; else a HOST array of M floats that receives the
+ * duration of each augmented product, timed with HIP events recorded on "stream" around
+ * each launch (the call then synchronises the stream before returning). */
+int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double s, double c,
+             double *mu, int *last_in_w, float *step_ms, void *stream);
+
+typedef struct {
+    int64_t iterations;       /* total inner (low-precision) or plain CG iterations  */
+    int64_t refinements;      /* outer FP64 residual corrections (0 for plain CG)     */
+    double relres;            /* max over columns of ||b - A x|| / ||b|| (FP64)       */
+    int32_t converged;        /* 1 if relres <= tol                                   */
+} sell_cg_stats;
+
+/* Conjugate gradients for each column of B (A symmetric positive definite, F64 matrix,
+ * F64 row-major vectors). X holds the initial guess and receives the solution. Stops
+ * when every column has ||b - A x|| <= tol ||b|| (true FP64 residual, checked every few
+ * iterations) or after maxit iterations. Synchronous (returns when done). */
+int sell_cg(const sell_mat *A, const sell_bv *B, sell_bv *X, double tol, int64_t maxit,
+            sell_cg_stats *stats, void *stream);
+
+/* Mixed-precision CG with FP64 iterative refinement: the residual r = b - A x is formed
+ * in FP64 with A64 (F64 matrix); the correction d solves Alo d = r approximately by FP32
+ * CG with the F32 or BF16 matrix Alo (same pattern), to a relative residual reduction
+ * inner_tol or inner_maxit iterations; x += d in FP64. Stops at the same criterion as
+ * sell_cg (true FP64 residual <= tol) or after maxit inner iterations in total.
+ * Synchronous. */
+int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *B, sell_bv *X,
+                  double tol, int64_t maxit, double inner_tol, int64_t inner_maxit,
+                  sell_cg_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Measurement helpers                                                                  */
+
+/* Streaming probes of achievable device bandwidth on caller-owned device buffers:
+ *   kind 0: copy  dst[i] = src[i]                      (2 * bytes moved)
+ *   kind 1: read  reduce src into dst[0..255]          (bytes moved)
+ *   kind 2: write dst[i] = constant                    (bytes moved)
+ * bytes must be a positive multiple of 16; both buffers 16-byte aligned. Asynchronous. */
+int sell_probe_bandwidth(int kind, void *dst, const void *src, int64_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SELLCS_H */

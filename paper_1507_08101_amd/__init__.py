@@ -1,0 +1,407 @@
+"""Python binding of libsellcs: SELL-C-sigma sparse matrix times (block) vector on MI355X.
+
+Argument marshalling only. Every computation runs in the HIP kernels of ``libsellcs.so``
+(built in-tree by ``__graft_entry__.build()``); there is no fallback: if the library is
+missing, importing its functions raises. PyTorch serves as the source of device memory
+and of the current HIP stream (``torch.cuda.current_stream().cuda_stream``).
+
+The raw entry points carry the C names (``sell_build``, ``sell_spmmv``, ``sell_spmmv_aug``,
+``sell_spmmv_T``, ``sell_bv_create``, ``sell_bv_copy`` ...). The small classes below wrap
+the opaque handles: ``SellMatrix`` (a device SELL-C-sigma matrix) and block-vector views of
+torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsellcs.so")
+
+# ---- constants of include/sellcs.h
+SELL_F64, SELL_F32, SELL_BF16 = 0, 1, 2
+SELL_ROW_MAJOR, SELL_COL_MAJOR = 0, 1
+SELL_OK, SELL_ERR_ARG, SELL_ERR_SHAPE, SELL_ERR_DTYPE = 0, -1, -2, -3
+SELL_ERR_UNSUPPORTED, SELL_ERR_OOM, SELL_ERR_HIP, SELL_ERR_STATE = -4, -5, -6, -7
+SHIFT, VSHIFT, SCALE, AXPBY = 0x01, 0x02, 0x04, 0x08
+DOT_YY, DOT_XY, DOT_XX, CHAIN = 0x10, 0x20, 0x40, 0x80
+DOTS = DOT_YY | DOT_XY | DOT_XX
+
+DTYPE_NAMES = {"f64": SELL_F64, "f32": SELL_F32, "bf16": SELL_BF16}
+
+
+class SellError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+
+
+class sell_spmv_opts(ct.Structure):
+    _fields_ = [("flags", ct.c_uint32), ("alpha", ct.c_double), ("beta", ct.c_double),
+                ("gamma", ct.c_double), ("gamma_v", ct.c_void_p), ("delta", ct.c_double),
+                ("eta", ct.c_double), ("dot", ct.c_void_p)]
+
+
+class sell_info_t(ct.Structure):
+    _fields_ = [("nrows", ct.c_int64), ("ncols", ct.c_int64), ("nnz", ct.c_int64),
+                ("stored", ct.c_int64), ("nchunks", ct.c_int64), ("sigma", ct.c_int64),
+                ("C", ct.c_int32), ("vdtype", ct.c_int32), ("on_device", ct.c_int32),
+                ("device", ct.c_int32), ("ntiles", ct.c_int32), ("has_perm", ct.c_int32),
+                ("matrix_bytes", ct.c_int64)]
+
+
+class sell_cg_stats(ct.Structure):
+    _fields_ = [("iterations", ct.c_int64), ("refinements", ct.c_int64), ("relres", ct.c_double),
+                ("converged", ct.c_int32)]
+
+
+_P = ct.c_void_p
+_I = ct.c_int
+_I32 = ct.c_int32
+_I64 = ct.c_int64
+_D = ct.c_double
+_PP = ct.POINTER(ct.c_void_p)
+
+_SIGNATURES = {
+    "sell_strerror": ([_I], ct.c_char_p),
+    "sell_version": ([], _I),
+    "sell_build": ([_PP, _I64, _I64, _P, _P, _P, _I32, _I64, _I, _P], _I),
+    "sell_build_host": ([_PP, _I64, _I64, _P, _P, _P, _I32, _I64, _I], _I),
+    "sell_update_values": ([_P, _P, _P], _I),
+    "sell_update_values_device": ([_P, _P, _P], _I),
+    "sell_export_csr": ([_P, _P, _P, _P], _I),
+    "sell_export_sell": ([_P, _P, _P, _P, _P, _P], _I),
+    "sell_info": ([_P, ct.POINTER(sell_info_t)], _I),
+    "sell_destroy": ([_P], _I),
+    "sell_bv_create": ([_PP, _I64, _I32, _I, _I, _P, _I64], _I),
+    "sell_bv_destroy": ([_P], _I),
+    "sell_bv_data": ([_P, _PP, ct.POINTER(_I64), ct.POINTER(_I64), ct.POINTER(_I32), ct.POINTER(_I32),
+                      ct.POINTER(_I32)], _I),
+    "sell_bv_copy": ([_P, _P, _P], _I),
+    "sell_spmmv": ([_P, _P, _P, _P], _I),
+    "sell_spmmv_aug": ([_P, _P, _P, _P, ct.POINTER(sell_spmv_opts), _P], _I),
+    "sell_spmmv_T": ([_P, _P, _P, _I, _P], _I),
+    "sell_kpm": ([_P, _P, _P, _I64, _D, _D, _P, ct.POINTER(_I), _P, _P], _I),
+    "sell_cg": ([_P, _P, _P, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
+    "sell_cg_mixed": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
+    "sell_probe_bandwidth": ([_I, _P, _P, _I64, _P], _I),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libsellcs; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libsellcs.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ct.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().sell_strerror(code).decode()
+    except Exception:  # pragma: no cover - only when the library itself is absent
+        return "error"
+
+
+def _ok(rc: int, what: str) -> None:
+    if rc != SELL_OK:
+        raise SellError(rc, what)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _stream(stream=None):
+    """HIP stream handle as void*: an explicit int/handle, or torch's current stream."""
+    if stream is not None:
+        return ct.c_void_p(int(stream))
+    import torch
+
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(dt) -> int:
+    if isinstance(dt, int):
+        return dt
+    if isinstance(dt, str):
+        return DTYPE_NAMES[dt]
+    import torch
+
+    return {torch.float64: SELL_F64, torch.float32: SELL_F32, torch.bfloat16: SELL_BF16}[dt]
+
+
+# ==================================================================== sparse matrices
+
+
+def _csr_arrays(rowptr, col, val):
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    return rowptr, col, val
+
+
+def sell_build(nrows, ncols, rowptr, col, val, C, sigma, vdt=SELL_F64, stream=None, host_only=False):
+    """Build a SELL-C-sigma matrix from host CSR arrays; returns the opaque handle."""
+    rowptr, col, val = _csr_arrays(rowptr, col, val)
+    if rowptr.size != nrows + 1:
+        raise SellError(SELL_ERR_ARG, "sell_build: rowptr must have nrows + 1 entries")
+    nnz = int(rowptr[-1]) if rowptr.size else 0
+    if col.size < nnz or val.size < nnz:
+        raise SellError(SELL_ERR_ARG, "sell_build: col/val shorter than rowptr[-1]")
+    h = ct.c_void_p()
+    if host_only:
+        rc = lib().sell_build_host(ct.byref(h), nrows, ncols, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val),
+                                   int(C), int(sigma), _dtype_code(vdt))
+    else:
+        rc = lib().sell_build(ct.byref(h), nrows, ncols, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val), int(C),
+                              int(sigma), _dtype_code(vdt), _stream(stream))
+    _ok(rc, "sell_build")
+    return h
+
+
+def sell_info(h) -> dict:
+    info = sell_info_t()
+    _ok(lib().sell_info(h, ct.byref(info)), "sell_info")
+    return {k: getattr(info, k) for k, _ in sell_info_t._fields_}
+
+
+def sell_export_csr(h):
+    i = sell_info(h)
+    rowptr = np.empty(i["nrows"] + 1, np.int64)
+    col = np.empty(i["nnz"], np.int32)
+    val = np.empty(i["nnz"], np.float64)
+    _ok(lib().sell_export_csr(h, _np_ptr(rowptr), _np_ptr(col), _np_ptr(val)), "sell_export_csr")
+    return rowptr, col, val
+
+
+def sell_export_sell(h):
+    i = sell_info(h)
+    perm = np.empty(i["nchunks"] * i["C"], np.int32)
+    cl = np.empty(i["nchunks"], np.int32)
+    cs = np.empty(i["nchunks"] + 1, np.int64)
+    col = np.empty(i["stored"], np.int32)
+    val = np.empty(i["stored"], np.float64)
+    _ok(lib().sell_export_sell(h, _np_ptr(perm), _np_ptr(cl), _np_ptr(cs), _np_ptr(col), _np_ptr(val)),
+        "sell_export_sell")
+    return perm, cl, cs, col, val
+
+
+def sell_update_values(h, val, stream=None):
+    """New values (CSR order). ``val`` is a host numpy array or a float64 device tensor."""
+    if isinstance(val, np.ndarray):
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        _ok(lib().sell_update_values(h, _np_ptr(v), _stream(stream)), "sell_update_values")
+    else:
+        import torch
+
+        assert val.dtype == torch.float64 and val.is_cuda and val.is_contiguous()
+        _ok(lib().sell_update_values_device(h, ct.c_void_p(val.data_ptr()), _stream(stream)),
+            "sell_update_values_device")
+
+
+def sell_destroy(h) -> None:
+    if h:
+        lib().sell_destroy(h)
+
+
+class SellMatrix:
+    """Owner of a SELL-C-sigma matrix handle."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.info = sell_info(handle)
+
+    @classmethod
+    def from_csr(cls, A, C=32, sigma=1, dtype="f64", stream=None, host_only=False):
+        """``A`` has nrows, ncols, rowptr, col, val (e.g. a scipy CSR wrapper or synth.CSR)."""
+        h = sell_build(A.nrows, A.ncols, A.rowptr, A.col, A.val, C, sigma, _dtype_code(dtype), stream,
+                       host_only=host_only)
+        return cls(h)
+
+    @property
+    def nrows(self):
+        return self.info["nrows"]
+
+    @property
+    def ncols(self):
+        return self.info["ncols"]
+
+    @property
+    def vector_dtype(self):
+        import torch
+
+        return torch.float64 if self.info["vdtype"] == SELL_F64 else torch.float32
+
+    def export_csr(self):
+        return sell_export_csr(self.handle)
+
+    def export_sell(self):
+        return sell_export_sell(self.handle)
+
+    def update_values(self, val, stream=None):
+        if not self.info["on_device"]:
+            stream = 0  # host-only matrix: no stream involved
+        sell_update_values(self.handle, val, stream)
+
+    def close(self):
+        if self.handle:
+            sell_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover - best effort at interpreter exit
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ==================================================================== block vectors
+
+
+class BlockVector:
+    """A libsellcs block vector: a view of a 2-D torch tensor (row- or column-major) or an
+    owned allocation. Keeps the tensor alive while the view exists."""
+
+    def __init__(self, handle, tensor=None):
+        self.handle = handle
+        self.tensor = tensor
+
+    @classmethod
+    def view(cls, t):
+        if t.dim() == 1:
+            t = t.view(-1, 1)
+        if t.dim() != 2:
+            raise SellError(SELL_ERR_ARG, "block vectors are 2-D")
+        n, b = t.shape
+        if b == 1 or (t.stride(1) == 1 and t.stride(0) >= b):
+            lay, ld = SELL_ROW_MAJOR, max(t.stride(0), b) if n > 1 else b
+        elif t.stride(0) == 1 and t.stride(1) >= n:
+            lay, ld = SELL_COL_MAJOR, t.stride(1)
+        else:
+            raise SellError(SELL_ERR_ARG, "tensor is neither row- nor column-major")
+        h = ct.c_void_p()
+        ptr = ct.c_void_p(t.data_ptr()) if t.numel() else None  # empty: a zero-size owned object
+        _ok(lib().sell_bv_create(ct.byref(h), n, b, _dtype_code(t.dtype), lay, ptr, ld), "sell_bv_create")
+        return cls(h, t)
+
+    def close(self):
+        if self.handle:
+            lib().sell_bv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bv(x):
+    return x if isinstance(x, BlockVector) else BlockVector.view(x)
+
+
+def sell_bv_create(nrows, ncols, dtype, layout=SELL_ROW_MAJOR, data=None, ld=0):
+    h = ct.c_void_p()
+    _ok(lib().sell_bv_create(ct.byref(h), nrows, ncols, _dtype_code(dtype), layout,
+                             None if data is None else ct.c_void_p(int(data)), ld), "sell_bv_create")
+    return h
+
+
+def sell_bv_destroy(h):
+    lib().sell_bv_destroy(h)
+
+
+def sell_bv_copy(dst, src, stream=None):
+    """dst[:] = src with layout/type conversion (tensors or BlockVector)."""
+    d, s = _bv(dst), _bv(src)
+    _ok(lib().sell_bv_copy(d.handle, s.handle, _stream(stream)), "sell_bv_copy")
+
+
+# ==================================================================== products
+
+
+def _mat(A):
+    return A.handle if isinstance(A, SellMatrix) else A
+
+
+def sell_spmmv(A, X, Y, stream=None):
+    """Y = A X (tensors of the matrix's vector type)."""
+    x, y = _bv(X), _bv(Y)
+    _ok(lib().sell_spmmv(_mat(A), x.handle, y.handle, _stream(stream)), "sell_spmmv")
+
+
+def make_opts(flags=0, alpha=1.0, beta=0.0, gamma=0.0, gamma_v=None, delta=0.0, eta=1.0, dot=None):
+    o = sell_spmv_opts()
+    o.flags = int(flags)
+    o.alpha, o.beta, o.gamma, o.delta, o.eta = float(alpha), float(beta), float(gamma), float(delta), float(eta)
+    keep = None
+    if gamma_v is not None:
+        keep = np.ascontiguousarray(gamma_v, dtype=np.float64)
+        o.gamma_v = keep.ctypes.data
+    if dot is not None:
+        o.dot = dot.data_ptr()
+    return o, keep
+
+
+def sell_spmmv_aug(A, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0.0, gamma_v=None, delta=0.0,
+                   eta=1.0, dot=None, stream=None):
+    """y = alpha (A - gamma I) x + beta y with optional dots (into the float64 device tensor
+    ``dot`` of 3b entries) and chained z = delta z + eta y."""
+    x, y = _bv(X), _bv(Y)
+    z = _bv(Z) if Z is not None else None
+    o, keep = make_opts(flags, alpha, beta, gamma, gamma_v, delta, eta, dot)
+    _ok(lib().sell_spmmv_aug(_mat(A), x.handle, y.handle, z.handle if z else None, ct.byref(o), _stream(stream)),
+        "sell_spmmv_aug")
+    del keep
+
+
+def sell_spmmv_T(A, X, Y, deterministic=False, stream=None):
+    """Y = A^T X."""
+    x, y = _bv(X), _bv(Y)
+    _ok(lib().sell_spmmv_T(_mat(A), x.handle, y.handle, 1 if deterministic else 0, _stream(stream)),
+        "sell_spmmv_T")
+
+
+def sell_kpm(A, V, W, M, s, c, mu, step_ms=None, stream=None):
+    """Kernel polynomial method recurrence; returns True if v_M ended in W. ``step_ms``: a
+    float32 numpy array of M entries to receive per-product HIP-event durations (the call is
+    then synchronous)."""
+    v, w = _bv(V), _bv(W)
+    last = ct.c_int(0)
+    if step_ms is not None:
+        assert step_ms.dtype == np.float32 and step_ms.size >= M and step_ms.flags.c_contiguous
+    _ok(lib().sell_kpm(_mat(A), v.handle, w.handle, int(M), float(s), float(c), ct.c_void_p(mu.data_ptr()),
+                       ct.byref(last), _np_ptr(step_ms), _stream(stream)), "sell_kpm")
+    return bool(last.value)
+
+
+def sell_cg(A, B, X, tol=1e-10, maxit=100000, stream=None):
+    st = sell_cg_stats()
+    _ok(lib().sell_cg(_mat(A), _bv(B).handle, _bv(X).handle, float(tol), int(maxit), ct.byref(st),
+                      _stream(stream)), "sell_cg")
+    return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
+
+
+def sell_cg_mixed(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=1e-4, inner_maxit=1000, stream=None):
+    st = sell_cg_stats()
+    _ok(lib().sell_cg_mixed(_mat(A64), _mat(Alo), _bv(B).handle, _bv(X).handle, float(tol), int(maxit),
+                            float(inner_tol), int(inner_maxit), ct.byref(st), _stream(stream)), "sell_cg_mixed")
+    return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
+
+
+def sell_probe_bandwidth(kind, dst, src, nbytes, stream=None):
+    _ok(lib().sell_probe_bandwidth(int(kind), ct.c_void_p(dst.data_ptr()),
+                                   ct.c_void_p(src.data_ptr()) if src is not None else None, int(nbytes),
+                                   _stream(stream)), "sell_probe_bandwidth")

@@ -1,0 +1,193 @@
+// build.cpp -- host construction of SELL-C-sigma from CSR (GHOST paper, Sec. 5.1).
+//
+// The format: rows are cut into chunks of C consecutive rows; inside each window of sigma
+// rows the rows are first sorted by their number of nonzeros; a chunk is padded with
+// trailing zeros to the length of its longest row, and its entries are stored column by
+// column ("diagonal-wise"), so that entry k of the row in slot r of chunk c sits at
+// cs[c] + k*C + r. Sorting direction and tie-break are not fixed by the paper; this
+// library sorts by descending length and keeps equal lengths in their original order
+// (a stable sort), which also puts the longest chunks of a window first.
+//
+// Padding entries carry column -1 and value 0, so the kernels can skip them exactly
+// (no gather, no arithmetic) and the original CSR can be recovered bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+#include <thread>
+
+#include "convert.h"
+#include "internal.h"
+
+namespace sellcs {
+
+namespace {
+
+template <class F>
+void parallel_for(int64_t n, F &&f) {
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 16));
+    if (n < 65536 || nt == 1) {
+        f(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t step = (n + nt - 1) / nt;
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t lo = t * step, hi = std::min(n, lo + step);
+        if (lo >= hi) break;
+        th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+uint16_t f64_to_bf16_bits(double v) { return bf16_from_f64(v); }
+
+float bf16_bits_to_f32(uint16_t b) { return f32_from_bf16(b); }
+
+void convert_values(const double *src, int64_t n, int vdt, void *dst) {
+    if (vdt == SELL_F64) {
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            std::memcpy(static_cast<double *>(dst) + lo, src + lo, sizeof(double) * (hi - lo));
+        });
+    } else if (vdt == SELL_F32) {
+        float *d = static_cast<float *>(dst);
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) d[i] = float(src[i]);
+        });
+    } else {
+        uint16_t *d = static_cast<uint16_t *>(dst);
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i) d[i] = f64_to_bf16_bits(src[i]);
+        });
+    }
+}
+
+int32_t default_tile_count(int64_t nch) {
+    int64_t t = 1024;
+    if (const char *e = std::getenv("SELLCS_TILES")) {
+        long v = std::strtol(e, nullptr, 10);
+        if (v >= 1 && v <= kMaxTiles) t = v;
+    }
+    return int32_t(std::max<int64_t>(std::min<int64_t>(nch, t), nch > 0 ? 1 : 0));
+}
+
+// Contiguous chunk ranges of about equal cost. A chunk's cost is its stored entries plus
+// two units per row slot for the epilogue (reads and writes of y).
+void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
+                std::vector<int32_t> &tiles) {
+    const int64_t nch = int64_t(cl.size());
+    tiles.assign(size_t(ntiles) + 1, 0);
+    if (ntiles == 0) return;
+    std::vector<int64_t> pre(size_t(nch) + 1, 0);
+    for (int64_t c = 0; c < nch; ++c) pre[c + 1] = pre[c] + int64_t(C) * (int64_t(cl[c]) + 2);
+    const int64_t total = pre[nch];
+    for (int32_t t = 1; t < ntiles; ++t) {
+        // first chunk whose prefix cost reaches t/ntiles of the total
+        const long double goal = (long double)total * t / ntiles;
+        int64_t c = std::lower_bound(pre.begin(), pre.end(), (int64_t)std::ceil(goal)) - pre.begin();
+        c = std::min<int64_t>(std::max<int64_t>(c, tiles[t - 1]), nch);
+        tiles[t] = int32_t(c);
+    }
+    tiles[ntiles] = int32_t(nch);
+}
+
+int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                    const int32_t *col, const double *val, int32_t C, int64_t sigma, int vdt) {
+    if (nrows < 0 || ncols < 0 || nrows >= (int64_t(1) << 31) || ncols >= (int64_t(1) << 31))
+        return SELL_ERR_ARG;
+    if (C < 1 || C > (1 << 20) || sigma < 1) return SELL_ERR_ARG;
+    if (vdt != SELL_F64 && vdt != SELL_F32 && vdt != SELL_BF16) return SELL_ERR_DTYPE;
+    if (!rowptr) return SELL_ERR_ARG;
+    if (rowptr[0] != 0) return SELL_ERR_ARG;
+    for (int64_t i = 0; i < nrows; ++i)
+        if (rowptr[i + 1] < rowptr[i]) return SELL_ERR_ARG;
+    const int64_t nnz = rowptr[nrows];
+    if (nnz > 0 && (!col || !val)) return SELL_ERR_ARG;
+    {
+        bool bad = false;
+        for (int64_t p = 0; p < nnz; ++p)
+            if (col[p] < 0 || int64_t(col[p]) >= ncols) {
+                bad = true;
+                break;
+            }
+        if (bad) return SELL_ERR_ARG;
+    }
+
+    h = HostSell();
+    h.nrows = nrows;
+    h.ncols = ncols;
+    h.nnz = nnz;
+    h.C = C;
+    h.sigma = sigma;
+    h.vdt = vdt;
+    const int64_t nch = (nrows + C - 1) / C;
+    h.nch = nch;
+    const int64_t nslots = nch * C;
+
+    // row lengths
+    std::vector<int64_t> len(static_cast<size_t>(nrows));
+    for (int64_t i = 0; i < nrows; ++i) len[i] = rowptr[i + 1] - rowptr[i];
+
+    // sigma-window sort (descending length, stable)
+    std::vector<int32_t> slot_row(static_cast<size_t>(nslots));
+    for (int64_t s = 0; s < nslots; ++s) slot_row[s] = s < nrows ? int32_t(s) : -1;
+    const int64_t win = std::min<int64_t>(sigma, std::max<int64_t>(nrows, 1));
+    if (win > 1) {
+        const int64_t nwin = (nrows + win - 1) / win;
+        parallel_for(nwin, [&](int64_t lo, int64_t hi) {
+            for (int64_t w = lo; w < hi; ++w) {
+                auto b = slot_row.begin() + w * win;
+                auto e = slot_row.begin() + std::min(nrows, (w + 1) * win);
+                std::stable_sort(b, e, [&](int32_t a, int32_t c) { return len[a] > len[c]; });
+            }
+        });
+        bool ident = true;
+        for (int64_t s = 0; s < nrows && ident; ++s) ident = slot_row[s] == s;
+        h.has_perm = !ident;
+    }
+
+    // chunk lengths and starts
+    h.cl.assign(size_t(nch), 0);
+    h.cs.assign(size_t(nch) + 1, 0);
+    for (int64_t c = 0; c < nch; ++c) {
+        int64_t m = 0;
+        for (int32_t r = 0; r < C; ++r) {
+            int32_t row = slot_row[c * C + r];
+            if (row >= 0) m = std::max(m, len[row]);
+        }
+        if (m >= (int64_t(1) << 31)) return SELL_ERR_ARG;
+        h.cl[c] = int32_t(m);
+        h.cs[c + 1] = h.cs[c] + int64_t(C) * m;
+    }
+    h.stored = h.cs[nch];
+
+    // column-major fill with padding (col -1, val 0)
+    h.col.assign(size_t(h.stored), -1);
+    std::vector<double> sval(size_t(h.stored), 0.0);
+    parallel_for(nch, [&](int64_t lo, int64_t hi) {
+        for (int64_t c = lo; c < hi; ++c)
+            for (int32_t r = 0; r < C; ++r) {
+                const int32_t row = slot_row[c * C + r];
+                if (row < 0) continue;
+                const int64_t p0 = rowptr[row];
+                for (int64_t k = 0; k < len[row]; ++k) {
+                    const int64_t at = h.cs[c] + k * C + r;
+                    h.col[at] = col[p0 + k];
+                    sval[at] = val[p0 + k];
+                }
+            }
+    });
+    h.val.resize(size_t(h.stored) * dtype_bytes(vdt));
+    convert_values(sval.data(), h.stored, vdt, h.val.data());
+
+    if (h.has_perm) h.perm = std::move(slot_row);
+    h.rowptr.assign(rowptr, rowptr + nrows + 1);
+    const int32_t nt = default_tile_count(nch);
+    make_tiles(h.cl, C, nt, h.tiles);
+    return SELL_OK;
+}
+
+}  // namespace sellcs

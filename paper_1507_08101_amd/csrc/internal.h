@@ -1,0 +1,146 @@
+// internal.h -- shared definitions of libsellcs (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "sellcs.h"
+
+namespace sellcs {
+
+constexpr int kMaxSliceCols = 64;   // widest column slice one product launch handles
+constexpr int kMaxTiles = 4096;     // upper bound on work partitions per launch
+constexpr int kBlock = 512;         // threads per block of the product kernels
+
+inline int dtype_bytes(int dt) { return dt == SELL_F64 ? 8 : dt == SELL_F32 ? 4 : 2; }
+
+// Host-side SELL-C-sigma arrays (the build result before upload).
+struct HostSell {
+    int64_t nrows = 0, ncols = 0, nnz = 0, stored = 0, nch = 0, sigma = 1;
+    int32_t C = 1;
+    int vdt = SELL_F64;
+    bool has_perm = false;
+    std::vector<int32_t> perm;    // slot -> row (-1 past the end); empty when identity
+    std::vector<int32_t> cl;      // chunk lengths
+    std::vector<int64_t> cs;      // chunk starts (nch + 1)
+    std::vector<int32_t> col;     // stored column indices (-1 = padding)
+    std::vector<uint8_t> val;     // stored values in storage type
+    std::vector<int32_t> tiles;   // ntiles + 1 chunk boundaries
+    std::vector<int64_t> rowptr;  // CSR row pointers of the input (for export and updates)
+};
+
+// Work partitions: contiguous chunk ranges of roughly equal cost.
+int32_t default_tile_count(int64_t nch);
+void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
+                std::vector<int32_t> &tiles);
+
+// Validates CSR input and builds the host SELL arrays. Returns SELL_OK or an error.
+int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                    const int32_t *col, const double *val, int32_t C, int64_t sigma, int vdt);
+
+// Value conversion (round to nearest, ties to even, from the double).
+uint16_t f64_to_bf16_bits(double v);
+float bf16_bits_to_f32(uint16_t b);
+void convert_values(const double *src, int64_t n, int vdt, void *dst);
+
+}  // namespace sellcs
+
+struct sell_mat {
+    sellcs::HostSell h;           // metadata always; col/val only for host-only builds
+    bool on_device = false;
+    int device = -1;
+    int32_t ntiles = 0;
+    int32_t *d_col = nullptr;
+    void *d_val = nullptr;
+    int32_t *d_cl = nullptr;
+    int64_t *d_cs = nullptr;
+    int32_t *d_perm = nullptr;    // null when rows keep their order
+    int32_t *d_tiles = nullptr;
+    int32_t *d_rowslot = nullptr; // row -> slot, built on first device value update
+    int64_t *d_rowptr = nullptr;  // CSR row pointers, built on first device value update
+    sell_mat *transpose = nullptr;  // SELL copy of A^T for the deterministic transpose
+    int64_t matrix_bytes = 0;
+};
+
+struct sell_bv {
+    int64_t nrows = 0;
+    int32_t ncols = 0;
+    int dt = SELL_F64;
+    int lay = SELL_ROW_MAJOR;
+    void *ptr = nullptr;
+    int64_t ld = 0;
+    bool owned = false;
+    int device = -1;
+};
+
+namespace sellcs {
+
+// ---------------------------------------------------------------- kernel launchers
+// Parameters of one product launch over a slice of columns [j0, j0 + nb).
+struct ProdArgs {
+    const int32_t *col;
+    const void *val;
+    const int32_t *cl;
+    const int64_t *cs;
+    const int32_t *perm;   // may be null (identity)
+    const int32_t *tiles;
+    int32_t ntiles, C;
+    int32_t cshift;        // log2(C) when C is a power of two, else -1
+    int64_t nrows;
+    int32_t nb;            // columns in this slice
+    const void *X; int64_t xrs, xcs;   // element (i, j) at X[i * xrs + j * xcs]
+    void *Y; int64_t yrs, ycs;
+    void *Z; int64_t zrs, zcs;
+    uint32_t flags;
+    double alpha, beta, delta, eta;
+    int32_t has_gamma_v;   // per-column shifts below (else the scalar gamma_s)
+    double gamma_s;        // scalar shift
+    double gamma_v[kMaxSliceCols];
+    double *dot;           // device: dot + j0 (yy), with stride dot_b between groups
+    int32_t dot_b;         // b of the full call (yy | xy | xx groups are dot_b apart)
+    double *partials;      // workspace: 3 * nb * ntiles doubles
+    unsigned *counter;     // workspace: one zeroed counter
+};
+
+enum VecKind { VK_F64F64 = 0, VK_F32F32 = 1, VK_BF16F32 = 2 };
+
+int launch_product(const ProdArgs &a, int vk, bool aug, hipStream_t s);
+int launch_transpose_atomic(const ProdArgs &a, int vk, hipStream_t s);
+int launch_fill(void *p, int dt, int64_t nrows, int32_t ncols, int64_t rs, int64_t cs,
+                double value, hipStream_t s);
+int launch_copy(const sell_bv *dst, const sell_bv *src, hipStream_t s);
+int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s);
+int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s);
+int launch_kpm_moments(const double *dots, int64_t M, int32_t b, double *mu, hipStream_t s);
+
+// CG building blocks (FP64 scalars on the device; see solvers.cpp).
+struct CgScalars {
+    double *rho;      // <r, r> current, b
+    double *rho_new;  // b
+    double *pq;       // <p, A p>, 3b (dot layout of the product: xy group used)
+    double *thresh2;  // per column squared stopping threshold
+    int32_t *active;  // per column flag
+};
+int launch_cg_update_xr(void *Xv, void *R, const void *P, const void *Q, int vec_dt,
+                        int64_t n, int32_t b, int64_t ld, const CgScalars &sc,
+                        double *partials, unsigned *counter, int32_t ntiles, hipStream_t s);
+int launch_cg_update_p(void *P, const void *R, int vec_dt, int64_t n, int32_t b, int64_t ld,
+                       const CgScalars &sc, hipStream_t s);
+int launch_axpy_mixed(double *X, const void *D, int d_dt, int64_t n, int32_t b, int64_t ld,
+                      const double *scale, hipStream_t s);
+int launch_scale_to_f32(float *dst, const double *src, int64_t n, int32_t b, int64_t ld,
+                        const double *rr, double *scale, hipStream_t s);
+
+// Per-(device, stream) workspace for reductions.
+struct Workspace {
+    double *partials = nullptr;   // kMaxTiles * 3 * kMaxSliceCols doubles
+    unsigned *counter = nullptr;  // 4 counters, zero between launches
+    double *scalars = nullptr;    // small scratch for solver scalars
+};
+int get_workspace(hipStream_t s, Workspace **ws);
+
+}  // namespace sellcs

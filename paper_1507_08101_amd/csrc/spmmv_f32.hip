@@ -1,0 +1,12 @@
+// spmmv_f32.hip -- instantiations of the product kernels for one value/vector type pair.
+#include "spmmv_impl.h"
+
+namespace sellcs {
+
+int prod_f32(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
+    return aug ? dispatch_prod<VK_F32F32, true>(a, s, fixed_ok) : dispatch_prod<VK_F32F32, false>(a, s, fixed_ok);
+}
+
+int transpose_f32(const ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_F32F32>(a, s); }
+
+}  // namespace sellcs

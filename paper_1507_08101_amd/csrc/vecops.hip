@@ -1,0 +1,259 @@
+// vecops.hip -- block-vector kernels (fill, layout/type copy), value updates, KPM moment
+// assembly, bandwidth probes, and the launch front-ends of the product kernels.
+#include <cstdlib>
+
+#include "convert.h"
+#include "internal.h"
+
+namespace sellcs {
+
+int prod_f64(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
+int prod_f32(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
+int prod_bf16(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
+int transpose_f64(const ProdArgs &a, hipStream_t s);
+int transpose_f32(const ProdArgs &a, hipStream_t s);
+int transpose_bf16(const ProdArgs &a, hipStream_t s);
+
+int choose_vpt(int vk, int b) {
+    int v = b >= 4 ? 4 : b;
+    (void)vk;
+    if (const char *e = std::getenv("SELLCS_VPT")) {
+        int x = std::atoi(e);
+        if ((x == 1 || x == 2 || x == 4) && x <= b) v = x;
+    }
+    return v;
+}
+
+int launch_product(const ProdArgs &a, int vk, bool aug, hipStream_t s) {
+    if (a.ntiles == 0) return SELL_OK;
+    switch (vk) {
+        case VK_F64F64: return prod_f64(a, aug, true, s);
+        case VK_F32F32: return prod_f32(a, aug, true, s);
+        case VK_BF16F32: return prod_bf16(a, aug, true, s);
+        default: return SELL_ERR_DTYPE;
+    }
+}
+
+int launch_transpose_atomic(const ProdArgs &a, int vk, hipStream_t s) {
+    if (a.ntiles == 0) return SELL_OK;
+    switch (vk) {
+        case VK_F64F64: return transpose_f64(a, s);
+        case VK_F32F32: return transpose_f32(a, s);
+        case VK_BF16F32: return transpose_bf16(a, s);
+        default: return SELL_ERR_DTYPE;
+    }
+}
+
+static inline unsigned grid_for(int64_t n, int threads, unsigned cap = 8192) {
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return unsigned(g);
+}
+
+// ---------------------------------------------------------------- fill
+
+template <class T>
+__global__ void __launch_bounds__(256) fill_kernel(T *p, int64_t nrows, int32_t ncols, int64_t rs,
+                                                   int64_t cs, T v) {
+    const int64_t n = nrows * ncols;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = e / ncols, j = e - i * ncols;
+        p[i * rs + j * cs] = v;
+    }
+}
+
+int launch_fill(void *p, int dt, int64_t nrows, int32_t ncols, int64_t rs, int64_t cs,
+                double value, hipStream_t s) {
+    const int64_t n = nrows * ncols;
+    if (n == 0) return SELL_OK;
+    const unsigned g = grid_for(n, 256);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(fill_kernel<double>, dim3(g), dim3(256), 0, s, static_cast<double *>(p),
+                           nrows, ncols, rs, cs, value);
+    else if (dt == SELL_F32)
+        hipLaunchKernelGGL(fill_kernel<float>, dim3(g), dim3(256), 0, s, static_cast<float *>(p), nrows,
+                           ncols, rs, cs, float(value));
+    else
+        hipLaunchKernelGGL(fill_kernel<uint16_t>, dim3(g), dim3(256), 0, s,
+                           static_cast<uint16_t *>(p), nrows, ncols, rs, cs, bf16_from_f64(value));
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- block-vector copy
+
+template <class D, class S>
+__global__ void __launch_bounds__(256) copy_kernel(D *dst, int64_t drs, int64_t dcs, const S *src,
+                                                   int64_t srs, int64_t scs, int64_t nrows,
+                                                   int32_t ncols) {
+    const int64_t n = nrows * ncols;
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        // walk in destination order so the stores are contiguous
+        int64_t i, j;
+        if (dcs == 1) {
+            i = e / ncols;
+            j = e - i * ncols;
+        } else {
+            j = e / nrows;
+            i = e - j * nrows;
+        }
+        dst[i * drs + j * dcs] = Conv<D, S>::go(src[i * srs + j * scs]);
+    }
+}
+
+static void strides(const sell_bv *v, int64_t &rs, int64_t &cs) {
+    if (v->lay == SELL_ROW_MAJOR) {
+        rs = v->ld;
+        cs = 1;
+    } else {
+        rs = 1;
+        cs = v->ld;
+    }
+}
+
+template <class D>
+static int copy_from(const sell_bv *dst, const sell_bv *src, hipStream_t s) {
+    int64_t drs, dcs, srs, scs;
+    strides(dst, drs, dcs);
+    strides(src, srs, scs);
+    const unsigned g = grid_for(dst->nrows * dst->ncols, 256);
+    D *d = static_cast<D *>(dst->ptr);
+    if (src->dt == SELL_F64)
+        hipLaunchKernelGGL((copy_kernel<D, double>), dim3(g), dim3(256), 0, s, d, drs, dcs,
+                           static_cast<const double *>(src->ptr), srs, scs, dst->nrows, dst->ncols);
+    else if (src->dt == SELL_F32)
+        hipLaunchKernelGGL((copy_kernel<D, float>), dim3(g), dim3(256), 0, s, d, drs, dcs,
+                           static_cast<const float *>(src->ptr), srs, scs, dst->nrows, dst->ncols);
+    else
+        hipLaunchKernelGGL((copy_kernel<D, uint16_t>), dim3(g), dim3(256), 0, s, d, drs, dcs,
+                           static_cast<const uint16_t *>(src->ptr), srs, scs, dst->nrows, dst->ncols);
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
+int launch_copy(const sell_bv *dst, const sell_bv *src, hipStream_t s) {
+    if (dst->nrows * dst->ncols == 0) return SELL_OK;
+    if (dst->dt == SELL_F64) return copy_from<double>(dst, src, s);
+    if (dst->dt == SELL_F32) return copy_from<float>(dst, src, s);
+    return copy_from<uint16_t>(dst, src, s);
+}
+
+// ---------------------------------------------------------------- value update
+
+template <class V>
+__global__ void __launch_bounds__(256) update_values_kernel(V *sval, const double *csr_val,
+                                                            const int64_t *rowptr,
+                                                            const int32_t *rowslot,
+                                                            const int64_t *cs, int32_t C,
+                                                            int64_t nrows) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nrows;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t slot = rowslot[i];
+        const int64_t c = slot / C, r = slot - c * C;
+        const int64_t base = cs[c] + r;
+        const int64_t p0 = rowptr[i], len = rowptr[i + 1] - p0;
+        for (int64_t k = 0; k < len; ++k) sval[base + k * C] = Conv<V, double>::go(csr_val[p0 + k]);
+    }
+}
+
+int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s) {
+    const int64_t n = A->h.nrows;
+    if (n == 0) return SELL_OK;
+    const unsigned g = grid_for(n, 256);
+    if (A->h.vdt == SELL_F64)
+        hipLaunchKernelGGL(update_values_kernel<double>, dim3(g), dim3(256), 0, s,
+                           static_cast<double *>(A->d_val), val_dev, A->d_rowptr, A->d_rowslot, A->d_cs,
+                           A->h.C, n);
+    else if (A->h.vdt == SELL_F32)
+        hipLaunchKernelGGL(update_values_kernel<float>, dim3(g), dim3(256), 0, s,
+                           static_cast<float *>(A->d_val), val_dev, A->d_rowptr, A->d_rowslot, A->d_cs,
+                           A->h.C, n);
+    else
+        hipLaunchKernelGGL(update_values_kernel<uint16_t>, dim3(g), dim3(256), 0, s,
+                           static_cast<uint16_t *>(A->d_val), val_dev, A->d_rowptr, A->d_rowslot,
+                           A->d_cs, A->h.C, n);
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- KPM moments
+// dots: M groups of 3b doubles [<y,y> | <x,y> | <x,x>] written by the M augmented products
+// of the recurrence; step 0 has x = v0, y = v1; step m >= 1 has x = v_m, y = v_{m+1}.
+// Chebyshev doubling: T_2m = 2 T_m^2 - T_0 and T_2m+1 = 2 T_m T_m+1 - T_1, so for a
+// symmetric matrix mu_2m = 2 <v_m, v_m> - mu_0 and mu_2m+1 = 2 <v_m+1, v_m> - mu_1.
+__global__ void kpm_moments_kernel(const double *dots, int64_t M, int32_t b, double *mu) {
+    const int64_t g = 3 * int64_t(b);
+    for (int j = threadIdx.x; j < b; j += blockDim.x) {
+        const double mu0 = dots[2 * b + j];  // <v0, v0>
+        const double mu1 = dots[b + j];      // <v0, v1>
+        mu[0 * b + j] = mu0;
+        mu[1 * b + j] = mu1;
+        mu[2 * b + j] = 2.0 * dots[j] - mu0;  // 2 <v1, v1> - mu0
+        for (int64_t m = 1; m < M; ++m) {
+            mu[(2 * m + 1) * b + j] = 2.0 * dots[m * g + b + j] - mu1;  // 2 <v_m, v_m+1> - mu1
+            mu[(2 * m + 2) * b + j] = 2.0 * dots[m * g + j] - mu0;      // 2 <v_m+1, v_m+1> - mu0
+        }
+    }
+}
+
+int launch_kpm_moments(const double *dots, int64_t M, int32_t b, double *mu, hipStream_t s) {
+    hipLaunchKernelGGL(kpm_moments_kernel, dim3(1), dim3(256), 0, s, dots, M, b, mu);
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
+// ---------------------------------------------------------------- bandwidth probes
+// Plain streaming kernels over 16-byte elements, 4 loads in flight per thread, nontemporal
+// hints so the probe measures HBM and not the caches.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) probe_copy(f4 *__restrict__ d, const f4 *__restrict__ s, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        f4 a = __builtin_nontemporal_load(s + i), b = __builtin_nontemporal_load(s + i + stride);
+        f4 c = __builtin_nontemporal_load(s + i + 2 * stride), e = __builtin_nontemporal_load(s + i + 3 * stride);
+        __builtin_nontemporal_store(a, d + i);
+        __builtin_nontemporal_store(b, d + i + stride);
+        __builtin_nontemporal_store(c, d + i + 2 * stride);
+        __builtin_nontemporal_store(e, d + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(s + i), d + i);
+}
+
+__global__ void __launch_bounds__(256) probe_read(float *__restrict__ d, const f4 *__restrict__ s, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        f4 a = __builtin_nontemporal_load(s + i), b = __builtin_nontemporal_load(s + i + stride);
+        f4 c = __builtin_nontemporal_load(s + i + 2 * stride), e = __builtin_nontemporal_load(s + i + 3 * stride);
+        acc += (a + b) + (c + e);
+    }
+    for (; i < n; i += stride) acc += __builtin_nontemporal_load(s + i);
+    const float t = acc.x + acc.y + acc.z + acc.w;
+    if (t == 1.2345e-30f) d[threadIdx.x] = t;  // keeps the loads alive; practically never taken
+}
+
+__global__ void __launch_bounds__(256) probe_write(f4 *__restrict__ d, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const f4 v = {1.f, 2.f, 3.f, 4.f};
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+        __builtin_nontemporal_store(v, d + i);
+}
+
+int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s) {
+    const int64_t n = bytes / 16;
+    const unsigned g = 256 * 16;
+    if (kind == 0)
+        hipLaunchKernelGGL(probe_copy, dim3(g), dim3(256), 0, s, static_cast<f4 *>(dst),
+                           static_cast<const f4 *>(src), n);
+    else if (kind == 1)
+        hipLaunchKernelGGL(probe_read, dim3(g), dim3(256), 0, s, static_cast<float *>(dst),
+                           static_cast<const f4 *>(src), n);
+    else
+        hipLaunchKernelGGL(probe_write, dim3(g), dim3(256), 0, s, static_cast<f4 *>(dst), n);
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
+}  // namespace sellcs

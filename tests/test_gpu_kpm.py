@@ -1,0 +1,133 @@
+"""GPU parity of the kernel polynomial method recurrence (sell_kpm) and of one augmented
+product at the full size of the 128^3 Anderson workload."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import abs_product, colwise_relerr, dev, host
+
+pytestmark = pytest.mark.gpu
+
+W = 16.5
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+
+    import paper_1507_08101_amd as sc
+
+    assert torch.cuda.is_available()
+    sc.lib()
+    return sc
+
+
+def _scale(W=W):
+    # Gershgorin: |lambda| <= 6 + W/2, with a 1 % margin
+    return (6 + W / 2) / 0.99
+
+
+@pytest.mark.parametrize("b", [1, 3, 8])
+def test_kpm_moments_match_direct_chebyshev(sc, b):
+    import torch
+
+    A = synth.anderson3d(10)
+    M = 40
+    s = _scale()
+    V0 = synth.block_vector(A.nrows, b, synth.SEED_X)
+    Vd = dev(V0)
+    Wd = torch.zeros_like(Vd)
+    mu = torch.zeros((2 * M + 1) * b, dtype=torch.float64, device="cuda:0")
+    Mx = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    last_in_w = sc.sell_kpm(Mx, Vd, Wd, M, s, 0.0, mu)
+    mu_h = host(mu).reshape(2 * M + 1, b)
+    vlast = host(Wd if last_in_w else Vd)
+    for j in range(b):
+        ref_mu, ref_v = oracle.chebyshev(A, V0[:, j], 2 * M, s, 0.0)
+        nx = float(V0[:, j] @ V0[:, j])
+        assert np.all(np.abs(mu_h[:, j] - ref_mu) <= 1e-11 * nx), j
+        _, vM = oracle.chebyshev(A, V0[:, j], M, s, 0.0)
+        assert np.linalg.norm(vlast[:, j] - vM) <= 1e-11 * np.linalg.norm(V0[:, j])
+    Mx.close()
+
+
+def test_kpm_step_local_parity(sc):
+    # each step compared with the oracle applied to the same device input
+    import torch
+
+    A = synth.anderson3d(16)
+    s = _scale()
+    b = 2
+    Mx = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    x = dev(synth.block_vector(A.nrows, b, 3))
+    y = dev(synth.block_vector(A.nrows, b, 4))
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    for step in range(20):
+        xin, yin = host(x), host(y)
+        sc.sell_spmmv_aug(Mx, x, y, flags=sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_YY | sc.DOT_XY,
+                          alpha=2.0 / s, gamma=0.3, beta=-1.0, dot=dot)
+        ref, _, rd = oracle.spmmv_aug(A, xin, Y=yin, flags=oracle.SCALE | oracle.SHIFT | oracle.AXPBY
+                                      | oracle.DOT_YY | oracle.DOT_XY, alpha=2.0 / s, gamma=0.3, beta=-1.0)
+        scale = (2.0 / s) * (abs_product(A, xin) + 0.3 * np.abs(xin)) + np.abs(yin)
+        assert colwise_relerr(host(y), ref, scale) <= 1e-12, step
+        d = host(dot)
+        assert np.all(np.abs(d[:2 * b] - rd[:2 * b]) <= 1e-12 * np.abs(rd[:2 * b]) + 1e-300), step
+        x, y = y, x
+
+
+def test_chebyshev_diagonal_closed_form_on_gpu(sc):
+    import torch
+
+    n = 4000
+    d = synth.uniform(5, n, -0.95, 0.95)
+    A = synth.CSR(n, n, np.arange(n + 1), np.arange(n, dtype=np.int32), d, "diag")
+    Mx = sc.SellMatrix.from_csr(A, C=64, sigma=1)
+    x = synth.block_vector(n, 1, 6)
+    M = 30
+    mu = torch.zeros(2 * M + 1, dtype=torch.float64, device="cuda:0")
+    V = dev(x)
+    Wd = torch.zeros_like(V)
+    sc.sell_kpm(Mx, V, Wd, M, 1.0, 0.0, mu)
+    m = np.arange(2 * M + 1)
+    ref = np.cos(m[:, None] * np.arccos(d)[None, :]) @ (x[:, 0] ** 2)
+    assert np.all(np.abs(host(mu) - ref) <= 1e-11 * float(x[:, 0] @ x[:, 0]))
+    Mx.close()
+
+
+@pytest.mark.parametrize("b", [1, 8])
+def test_full_size_anderson_128_sampled_rows(sc, b):
+    """The workload the benchmark times (128^3 periodic Anderson, SELL-32-1), one KPM step,
+    checked on 4096 sampled rows computed one by one, and the dots as a property of the
+    whole output."""
+    import torch
+
+    A = synth.anderson3d(128)
+    s = _scale()
+    Mx = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    X = synth.block_vector(A.nrows, b, synth.SEED_X)
+    Y0 = synth.block_vector(A.nrows, b, synth.SEED_Y)
+    Xd, Yd = dev(X), dev(Y0)
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    alpha, gamma = 2.0 / s, 0.0
+    sc.sell_spmmv_aug(Mx, Xd, Yd, flags=sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOTS, alpha=alpha, gamma=gamma,
+                      beta=-1.0, dot=dot)
+    y = host(Yd)
+    rows = np.sort(synth.randint(77, 4096, 0, A.nrows - 1))
+    rows = np.unique(np.concatenate([rows, [0, A.nrows - 1]]))
+    for i in rows:
+        p0, p1 = A.rowptr[i], A.rowptr[i + 1]
+        acc = np.zeros(b)
+        for p in range(p0, p1):
+            acc = acc + A.val[p] * X[A.col[p]]
+        ref = alpha * (acc - gamma * X[i]) - Y0[i]
+        sc_ = alpha * (np.abs(A.val[p0:p1]) @ np.abs(X[A.col[p0:p1]])) + np.abs(Y0[i])
+        assert np.all(np.abs(y[i] - ref) <= 1e-12 * sc_ * 8), i
+    d = host(dot)
+    for j in range(b):
+        for g, (u, v) in enumerate([(y, y), (X, y), (X, X)]):
+            ref = math.fsum((u[:, j] * v[:, j]).tolist())
+            assert abs(d[g * b + j] - ref) <= 1e-12 * float(np.sum(np.abs(u[:, j] * v[:, j]))), (j, g)
+    Mx.close()

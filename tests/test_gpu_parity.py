@@ -1,0 +1,443 @@
+"""GPU parity of the HIP path (called through the C ABI) against the CPU oracle.
+
+FP64 bar: per-column normwise relative error <= 1e-12; integer-valued inputs (exact in
+every order of summation) must agree bit for bit; dots within 1e-12 * sum |x_i y_i|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import abs_product, colwise_relerr, dev, host, to_oracle_flags
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+
+    import paper_1507_08101_amd as sc
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sc.lib()
+    return sc
+
+
+def _mats():
+    return {
+        "lap2d_64": synth.laplacian2d(64),
+        "anderson_12": synth.anderson3d(12),
+        "irregular_5000": synth.irregular(5000, band=300, max_len=2000, seed=21),
+        "random_ragged": synth.random_sparse(333, 333, 0.03, 22, empty_rows=17, long_row=333),
+        "rect_270x190": synth.random_sparse(270, 190, 0.05, 23, empty_rows=5),
+    }
+
+
+MATS = _mats()
+
+
+def _plain_case(sc, A, C, sigma, b, dt="f64"):
+    import torch
+
+    X = synth.block_vector(A.ncols, b, synth.SEED_X)
+    M = sc.SellMatrix.from_csr(A, C=C, sigma=sigma, dtype=dt)
+    Xd = dev(X)
+    Yd = torch.full((A.nrows, b), float("nan"), dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv(M, Xd, Yd)
+    got = host(Yd)
+    M.close()
+    return X, got
+
+
+@pytest.mark.parametrize("name", list(MATS))
+@pytest.mark.parametrize("C,sigma", [(1, 1), (8, 1), (32, 1), (32, 32), (32, 1024), (64, 1), (64, 10 ** 9),
+                                     (12, 7)])
+def test_spmmv_f64_matrix_shapes(sc, name, C, sigma):
+    A = MATS[name]
+    for b in (1, 3, 8):
+        X, got = _plain_case(sc, A, C, sigma, b)
+        ref = oracle.spmmv(A, X)
+        assert colwise_relerr(got, ref, abs_product(A, X)) <= TOL, (name, C, sigma, b)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 5, 8, 16, 17, 32, 40, 64, 70, 100])
+def test_spmmv_f64_block_widths(sc, b):
+    A = MATS["irregular_5000"]
+    X, got = _plain_case(sc, A, 32, 256, b)
+    ref = oracle.spmmv(A, X)
+    assert colwise_relerr(got, ref, abs_product(A, X)) <= TOL, b
+
+
+@pytest.mark.parametrize("b", [1, 4, 8, 32])
+def test_spmmv_integer_inputs_bit_exact(sc, b):
+    import torch
+
+    A0 = MATS["random_ragged"]
+    A = synth.CSR(A0.nrows, A0.ncols, A0.rowptr, A0.col, np.rint(8 * A0.val), "int")
+    X = synth.int_block_vector(A.ncols, b, 5)
+    for C, sigma in [(32, 1), (64, 333), (5, 10)]:
+        M = sc.SellMatrix.from_csr(A, C=C, sigma=sigma)
+        Yd = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
+        sc.sell_spmmv(M, dev(X), Yd)
+        assert np.array_equal(host(Yd), oracle.spmmv(A, X)), (C, sigma)
+        M.close()
+
+
+def test_spmmv_deterministic(sc):
+    import torch
+
+    A = MATS["irregular_5000"]
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1024)
+    X = dev(synth.block_vector(A.ncols, 8, 3))
+    Y1 = torch.empty((A.nrows, 8), dtype=torch.float64, device="cuda:0")
+    Y2 = torch.empty_like(Y1)
+    d1 = torch.zeros(24, dtype=torch.float64, device="cuda:0")
+    d2 = torch.zeros_like(d1)
+    sc.sell_spmmv_aug(M, X, Y1, flags=sc.DOTS | sc.SHIFT, gamma=0.7, dot=d1)
+    sc.sell_spmmv_aug(M, X, Y2, flags=sc.DOTS | sc.SHIFT, gamma=0.7, dot=d2)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2) and torch.equal(d1, d2)
+    M.close()
+
+
+# ------------------------------------------------------------------ augmented product
+
+
+def _aug_case(sc, A, b, flags, C=32, sigma=64, integer=False, **kw):
+    import torch
+
+    if integer:
+        X = synth.int_block_vector(A.ncols, b, 31)
+        Y0 = synth.int_block_vector(A.nrows, b, 32)
+        Z0 = synth.int_block_vector(A.nrows, b, 33)
+    else:
+        X = synth.block_vector(A.ncols, b, synth.SEED_X)
+        Y0 = synth.block_vector(A.nrows, b, synth.SEED_Y)
+        Z0 = synth.block_vector(A.nrows, b, synth.SEED_Y + 7)
+    M = sc.SellMatrix.from_csr(A, C=C, sigma=sigma)
+    Xd, Yd, Zd = dev(X), dev(Y0), dev(Z0)
+    dot = torch.full((3 * b,), -7.0, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, Xd, Yd, Z=Zd, flags=flags, dot=dot, **kw)
+    got_y, got_z, got_d = host(Yd), host(Zd), host(dot)
+    M.close()
+    ref_y, ref_z, ref_d = oracle.spmmv_aug(A, X, Y=Y0, Z=Z0, flags=to_oracle_flags(flags), **kw)
+    return X, Y0, Z0, (got_y, got_z, got_d), (ref_y, ref_z, ref_d)
+
+
+SCALARS = dict(alpha=0.5, beta=-2.0, gamma=0.25, gamma_v=None, delta=4.0, eta=-0.5)
+
+
+@pytest.mark.parametrize("flags", list(range(256)))
+def test_aug_every_flag_combination_bit_exact_on_integers(sc, flags):
+    A0 = MATS["random_ragged"]
+    A = synth.CSR(A0.nrows, A0.ncols, A0.rowptr, A0.col, np.rint(8 * A0.val), "int")
+    b = 4
+    kw = dict(SCALARS)
+    kw["gamma_v"] = np.array([1.0, -2.0, 0.5, 0.0])
+    X, Y0, Z0, got, ref = _aug_case(sc, A, b, flags, integer=True, **kw)
+    assert np.array_equal(got[0], ref[0]), flags
+    if flags & 0x80:
+        assert np.array_equal(got[1], ref[1]), flags
+    else:
+        assert np.array_equal(got[1], Z0)  # untouched
+    for g, bit in enumerate((0x10, 0x20, 0x40)):
+        seg = slice(g * b, (g + 1) * b)
+        if flags & bit:
+            assert np.array_equal(got[2][seg], ref[2][seg]), (flags, g)
+        else:
+            assert np.all(got[2][seg] == -7.0), (flags, g)
+
+
+@pytest.mark.parametrize("b", [1, 2, 3, 8, 32, 33])
+@pytest.mark.parametrize("flags", [0x01 | 0x04 | 0x08 | 0x70, 0x02 | 0x08 | 0x80 | 0x10, 0xFF & ~0x01, 0x70])
+def test_aug_random_inputs(sc, b, flags):
+    A = MATS["anderson_12"]
+    kw = dict(SCALARS)
+    kw["gamma_v"] = synth.uniform(40, b, -1, 1)
+    X, Y0, Z0, got, ref = _aug_case(sc, A, b, flags, C=32, sigma=1, **kw)
+    # cancellation-safe scale: |alpha| (|A||x| + |gamma||x|) + |beta||y|
+    scale = abs(kw["alpha"]) * (abs_product(A, X) + 1.0 * np.abs(X)) + abs(kw["beta"]) * np.abs(Y0)
+    assert colwise_relerr(got[0], ref[0], scale) <= TOL
+    if flags & 0x80:
+        zscale = abs(kw["delta"]) * np.abs(Z0) + abs(kw["eta"]) * scale
+        assert colwise_relerr(got[1], ref[1], zscale) <= TOL
+    yref = ref[0]
+    bounds = [np.sum(yref * yref, axis=0), np.sum(np.abs(X * yref), axis=0), np.sum(X * X, axis=0)]
+    for g, bit in enumerate((0x10, 0x20, 0x40)):
+        if flags & bit:
+            seg = slice(g * b, (g + 1) * b)
+            assert np.all(np.abs(got[2][seg] - ref[2][seg]) <= TOL * bounds[g] + 1e-300), (g, b)
+
+
+def test_aug_beta_zero_ignores_nan_y_and_delta_zero_ignores_nan_z(sc):
+    import torch
+
+    A = MATS["lap2d_64"]
+    b = 2
+    X = synth.block_vector(A.ncols, b, 1)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    Yd = torch.full((A.nrows, b), float("nan"), dtype=torch.float64, device="cuda:0")
+    Zd = torch.full((A.nrows, b), float("inf"), dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, dev(X), Yd, Z=Zd, flags=sc.AXPBY | sc.CHAIN, beta=0.0, delta=0.0, eta=3.0)
+    y, z = host(Yd), host(Zd)
+    ref = oracle.spmmv(A, X)
+    assert np.all(np.isfinite(y)) and colwise_relerr(y, ref) <= TOL
+    assert np.array_equal(z, 3.0 * y)
+    M.close()
+
+
+def test_aug_paper_listing_sequence(sc):
+    # Sec. 5.3 usage example: y = (A - gamma_j I) x, then y = (A - gamma_j I) x - 2 y with <x, y>
+    import torch
+
+    A = MATS["irregular_5000"]
+    b = 4
+    shift = np.array([1.0, 2.0, -1.0, 0.5])
+    X = synth.block_vector(A.ncols, b, 2)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=32)
+    Yd = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, dev(X), Yd, flags=sc.VSHIFT, gamma_v=shift)
+    sc.sell_spmmv_aug(M, dev(X), Yd, flags=sc.VSHIFT | sc.AXPBY | sc.DOT_XY, beta=-2.0, gamma_v=shift, dot=dot)
+    y1, _, _ = oracle.spmmv_aug(A, X, flags=oracle.VSHIFT, gamma_v=shift)
+    y2, _, d = oracle.spmmv_aug(A, X, Y=y1, flags=oracle.VSHIFT | oracle.AXPBY | oracle.DOT_XY, beta=-2.0,
+                                gamma_v=shift)
+    scale = 3 * (abs_product(A, X) + 2 * np.abs(X))
+    assert colwise_relerr(host(Yd), y2, scale) <= TOL
+    got = host(dot)[b:2 * b]
+    assert np.all(np.abs(got - d[b:2 * b]) <= TOL * np.sum(np.abs(X * y2), axis=0))
+    M.close()
+
+
+def test_column_major_vectors(sc):
+    import torch
+
+    A = MATS["irregular_5000"]
+    b = 5
+    X = synth.block_vector(A.ncols, b, 9)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=128)
+    Xcm = dev(X.T.copy()).t()  # column-major view (stride (1, n))
+    assert Xcm.stride(0) == 1
+    Ycm = torch.zeros((b, A.nrows), dtype=torch.float64, device="cuda:0").t()
+    sc.sell_spmmv(M, Xcm, Ycm)
+    ref = oracle.spmmv(A, X)
+    assert colwise_relerr(host(Ycm), ref, abs_product(A, X)) <= TOL
+    M.close()
+
+
+def test_empty_and_zero_matrices(sc):
+    import torch
+
+    E = synth.CSR(0, 0, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0), "empty")
+    M = sc.SellMatrix.from_csr(E, C=32, sigma=1)
+    X = torch.zeros((0, 3), dtype=torch.float64, device="cuda:0")
+    Y = torch.zeros((0, 3), dtype=torch.float64, device="cuda:0")
+    dot = torch.full((9,), 5.0, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, X, Y, flags=sc.DOTS, dot=dot)
+    assert np.all(host(dot) == 0.0)
+    M.close()
+    Z = synth.CSR(70, 70, np.zeros(71, np.int64), np.zeros(0, np.int32), np.zeros(0), "zero")
+    M = sc.SellMatrix.from_csr(Z, C=32, sigma=1)
+    X = dev(synth.block_vector(70, 2, 1))
+    Y = torch.full((70, 2), 9.0, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv(M, X, Y)
+    assert np.all(host(Y) == 0.0)
+    M.close()
+
+
+def test_bad_arguments_are_rejected_before_launch(sc):
+    import torch
+
+    A = MATS["rect_270x190"]
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    X = torch.zeros((190, 2), dtype=torch.float64, device="cuda:0")
+    Y = torch.zeros((270, 2), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(sc.SellError) as e:
+        sc.sell_spmmv(M, Y, X)  # swapped shapes
+    assert e.value.code == sc.SELL_ERR_SHAPE
+    with pytest.raises(sc.SellError) as e:
+        sc.sell_spmmv(M, X.float(), Y.float())
+    assert e.value.code == sc.SELL_ERR_DTYPE
+    with pytest.raises(sc.SellError) as e:
+        sc.sell_spmmv_aug(M, X, Y, flags=sc.SHIFT, gamma=1.0)  # shift needs a square matrix
+    assert e.value.code == sc.SELL_ERR_SHAPE
+    with pytest.raises(sc.SellError) as e:
+        sc.sell_spmmv_aug(M, X, Y, flags=sc.DOT_YY)  # no dot buffer
+    assert e.value.code == sc.SELL_ERR_ARG
+    with pytest.raises(sc.SellError) as e:
+        sc.sell_spmmv_aug(M, X, Y, flags=sc.CHAIN)  # no z
+    assert e.value.code == sc.SELL_ERR_ARG
+    with pytest.raises(sc.SellError) as e:
+        sc.sell_spmmv_aug(M, X, Y, flags=0x100)
+    assert e.value.code == sc.SELL_ERR_ARG
+    M.close()
+
+
+# ------------------------------------------------------------------ low precision values
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_low_precision_integer_laplacian_bit_exact(sc, dt):
+    import torch
+
+    A = synth.laplacian3d(17)  # 6 / -1 are exact in bf16; integer sums far below 2^24
+    X = synth.int_block_vector(A.ncols, 8, 4)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=dt)
+    Yd = torch.zeros((A.nrows, 8), dtype=torch.float32, device="cuda:0")
+    sc.sell_spmmv(M, dev(X, torch.float32), Yd)
+    assert np.array_equal(host(Yd), oracle.spmmv(A, X))
+    M.close()
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("b", [1, 8])
+def test_low_precision_error_bound(sc, dt, b):
+    import torch
+
+    A = MATS["irregular_5000"]
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1024, dtype=dt)
+    X32 = synth.block_vector(A.ncols, b, 6).astype(np.float32).astype(np.float64)
+    Yd = torch.zeros((A.nrows, b), dtype=torch.float32, device="cuda:0")
+    sc.sell_spmmv(M, dev(X32, torch.float32), Yd)
+    got = host(Yd)
+    Ar = synth.CSR(A.nrows, A.ncols, A.rowptr, A.col,
+                   oracle.round_f32(A.val) if dt == "f32" else oracle.round_bf16(A.val), "rounded")
+    exact = oracle.spmmv(Ar, X32)  # exact product of the rounded inputs, up to FP64 rounding
+    k = A.row_lengths().reshape(-1, 1) + 1
+    u = 2.0 ** -24
+    gam = k * u / (1 - k * u)
+    assert np.all(np.abs(got - exact) <= gam * abs_product(Ar, X32) + 1e-30)
+    # error against the unrounded FP64 product, reported rather than pinned
+    err = colwise_relerr(got, oracle.spmmv(A, X32))
+    print(f"{dt} b={b}: rel err vs unrounded FP64 product {err:.2e}")
+    M.close()
+
+
+def test_low_precision_aug_dots_in_fp64(sc):
+    import torch
+
+    A = MATS["anderson_12"]
+    b = 4
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype="f32")
+    X32 = synth.block_vector(A.ncols, b, 6).astype(np.float32)
+    Xd = dev(X32)
+    Yd = torch.zeros((A.nrows, b), dtype=torch.float32, device="cuda:0")
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, Xd, Yd, flags=sc.SHIFT | sc.DOTS, gamma=0.5, dot=dot)
+    y = host(Yd)
+    x = X32.astype(np.float64)
+    # the dots are FP64 sums of the stored FP32 values
+    for g, (u, v) in enumerate([(y, y), (x, y), (x, x)]):
+        ref = np.array([oracle.dot(u[:, j], v[:, j]) for j in range(b)])
+        assert np.all(np.abs(host(dot)[g * b:(g + 1) * b] - ref) <= TOL * np.sum(np.abs(u * v), axis=0))
+    M.close()
+
+
+# ------------------------------------------------------------------ transpose
+
+
+@pytest.mark.parametrize("det", [False, True])
+@pytest.mark.parametrize("b", [1, 3, 8])
+def test_transpose(sc, det, b):
+    import torch
+
+    for name in ("rect_270x190", "irregular_5000"):
+        A = MATS[name]
+        M = sc.SellMatrix.from_csr(A, C=32, sigma=64)
+        X = synth.block_vector(A.nrows, b, 8)
+        Yd = torch.full((A.ncols, b), 3.0, dtype=torch.float64, device="cuda:0")
+        sc.sell_spmmv_T(M, dev(X), Yd, deterministic=det)
+        got = host(Yd)
+        ref = oracle.spmmv_T(A, X)
+        from synth import CSR
+
+        At = CSR(A.nrows, A.ncols, A.rowptr, A.col, np.abs(A.val))
+        scale = oracle.spmmv_T(At, np.abs(X))
+        assert colwise_relerr(got, ref, scale) <= TOL, (name, det)
+        if det:
+            Y2 = torch.zeros_like(Yd)
+            sc.sell_spmmv_T(M, dev(X), Y2, deterministic=True)
+            torch.cuda.synchronize()
+            assert torch.equal(Yd, Y2)
+        M.close()
+
+
+def test_transpose_adjoint_identity(sc):
+    import torch
+
+    A = MATS["irregular_5000"]
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    u = synth.block_vector(A.nrows, 1, 10)
+    v = synth.block_vector(A.ncols, 1, 11)
+    ATu = torch.zeros((A.ncols, 1), dtype=torch.float64, device="cuda:0")
+    Av = torch.zeros((A.nrows, 1), dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_T(M, dev(u), ATu)
+    sc.sell_spmmv(M, dev(v), Av)
+    lhs = float(np.dot(host(ATu)[:, 0], v[:, 0]))
+    rhs = float(np.dot(u[:, 0], host(Av)[:, 0]))
+    assert abs(lhs - rhs) <= 1e-12 * float(np.abs(u[:, 0]) @ abs_product(A, np.abs(v))[:, 0])
+    M.close()
+
+
+# ------------------------------------------------------------------ block-vector copy
+
+
+@pytest.mark.parametrize("src_dt,dst_dt", [("f64", "f32"), ("f64", "bf16"), ("f32", "bf16"), ("bf16", "f64"),
+                                           ("f32", "f64"), ("f64", "f64")])
+def test_bv_copy_conversions_and_layouts(sc, src_dt, dst_dt):
+    import torch
+
+    tmap = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+    n, b = 1001, 6
+    vals = synth.normal(12, n * b).reshape(n, b) * np.exp(synth.uniform(13, n * b, -30, 30)).reshape(n, b)
+    if src_dt == "bf16":
+        vals = oracle.round_bf16(vals.ravel()).reshape(n, b)
+    if src_dt == "f32":
+        vals = vals.astype(np.float32).astype(np.float64)
+    src = dev(vals, tmap[src_dt]) if src_dt != "bf16" else dev(vals).to(torch.bfloat16)
+    for dst_colmajor in (False, True):
+        dst = torch.zeros((b, n) if dst_colmajor else (n, b), dtype=tmap[dst_dt], device="cuda:0")
+        if dst_colmajor:
+            dst = dst.t()
+        sc.sell_bv_copy(dst, src)
+        got = host(dst)
+        want = {"f64": vals, "f32": oracle.round_f32(vals.ravel()).reshape(n, b),
+                "bf16": oracle.round_bf16(vals.ravel()).reshape(n, b)}[dst_dt]
+        assert np.array_equal(got, want), (src_dt, dst_dt, dst_colmajor)
+
+
+# ------------------------------------------------------------------ value updates
+
+
+@pytest.mark.parametrize("dt", ["f64", "bf16"])
+def test_update_values_device_and_host(sc, dt):
+    import torch
+
+    A = MATS["irregular_5000"]
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=256, dtype=dt)
+    newv = synth.uniform(14, A.nnz, -3, 3)
+    M.update_values(dev(newv))
+    torch.cuda.synchronize()
+    _, col, val = M.export_csr()
+    want = newv if dt == "f64" else oracle.round_bf16(newv)
+    assert np.array_equal(val, want) and np.array_equal(col, A.col)
+    newv2 = synth.uniform(15, A.nnz, -3, 3)
+    M.update_values(newv2)
+    _, _, val2 = M.export_csr()
+    assert np.array_equal(val2, newv2 if dt == "f64" else oracle.round_bf16(newv2))
+    M.close()
+
+
+def test_device_export_round_trip(sc):
+    A = MATS["random_ragged"]
+    M = sc.SellMatrix.from_csr(A, C=16, sigma=40)
+    rp, col, val = M.export_csr()
+    assert np.array_equal(rp, A.rowptr) and np.array_equal(col, A.col) and np.array_equal(val, A.val)
+    perm, cl, cs, scol, sval = M.export_sell()
+    operm, ocl, ocs = oracle.sell_layout(A, 16, 40)
+    ocol, oval = oracle.sell_fill(A, 16, operm, ocl, ocs)
+    assert np.array_equal(perm, operm) and np.array_equal(scol, ocol) and np.array_equal(sval, oval)
+    M.close()
