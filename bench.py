@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-b1", action="store_true")
     ap.add_argument("--cg-edge", type=int, default=100)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run one copy probe of this many MiB (calibrates HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not offered (the sharded design is "
@@ -182,6 +184,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        sc.sell_probe_bandwidth(0, b, a, nbytes)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes}), flush=True)
+        return
     log(f"[bench] device {torch.cuda.get_device_name(0)}")
 
     t0 = time.perf_counter()

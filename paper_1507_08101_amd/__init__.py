@@ -388,16 +388,20 @@ def sell_kpm(A, V, W, M, s, c, mu, step_ms=None, stream=None):
 
 
 def sell_cg(A, B, X, tol=1e-10, maxit=100000, stream=None):
+    """FP64 CG per column of B (A symmetric positive definite); X: initial guess -> solution."""
     st = sell_cg_stats()
-    _ok(lib().sell_cg(_mat(A), _bv(B).handle, _bv(X).handle, float(tol), int(maxit), ct.byref(st),
-                      _stream(stream)), "sell_cg")
+    b, x = _bv(B), _bv(X)  # the views must outlive the call
+    _ok(lib().sell_cg(_mat(A), b.handle, x.handle, float(tol), int(maxit), ct.byref(st), _stream(stream)),
+        "sell_cg")
     return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
 
 
 def sell_cg_mixed(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=1e-4, inner_maxit=1000, stream=None):
+    """CG with FP64 iterative refinement around an FP32-vector inner solve on Alo."""
     st = sell_cg_stats()
-    _ok(lib().sell_cg_mixed(_mat(A64), _mat(Alo), _bv(B).handle, _bv(X).handle, float(tol), int(maxit),
-                            float(inner_tol), int(inner_maxit), ct.byref(st), _stream(stream)), "sell_cg_mixed")
+    b, x = _bv(B), _bv(X)
+    _ok(lib().sell_cg_mixed(_mat(A64), _mat(Alo), b.handle, x.handle, float(tol), int(maxit), float(inner_tol),
+                            int(inner_maxit), ct.byref(st), _stream(stream)), "sell_cg_mixed")
     return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
 
 

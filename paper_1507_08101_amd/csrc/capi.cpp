@@ -100,17 +100,6 @@ int get_workspace(hipStream_t s, Workspace **ws) {
     Workspace w;
     const size_t np = size_t(kMaxTiles) * 3 * kMaxSliceCols;
     HIPCHK(hipMalloc(&w.partials, np * sizeof(double)));
-    if (hipMalloc(&w.counter, 64 * sizeof(unsigned)) != hipSuccess) {
-        hipFree(w.partials);
-        return SELL_ERR_OOM;
-    }
-    if (hipMalloc(&w.scalars, 64 * 1024 * sizeof(double)) != hipSuccess) {
-        hipFree(w.partials);
-        hipFree(w.counter);
-        return SELL_ERR_OOM;
-    }
-    HIPCHK(hipMemset(w.counter, 0, 64 * sizeof(unsigned)));
-    HIPCHK(hipDeviceSynchronize());
     auto res = g_ws.emplace(key, w);
     *ws = &res.first->second;
     return SELL_OK;
@@ -190,19 +179,24 @@ int validate_bv(const sell_bv *v) {
     return SELL_OK;
 }
 
+}  // namespace
+
+namespace sellcs {
+
 // y = alpha (A x - gamma x) + beta y, dots, chain; no argument checks (callers check).
 int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o,
-             bool aug, hipStream_t s) {
+             bool aug, hipStream_t s, double *partials_out) {
     const int b = X->ncols;
     const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
     Workspace *ws = nullptr;
-    if (dots) {
+    if (dots && !partials_out) {
         int rc = get_workspace(s, &ws);
         if (rc) return rc;
     }
     if (A->h.nrows == 0 || A->h.tiles.size() < 2) {
         // empty matrix: y is empty; dots of empty columns are zero
         if (dots) {
+            if (partials_out) return SELL_OK;  // no tiles: nothing to sum
             const uint32_t g[3] = {SELL_SPMV_DOT_YY, SELL_SPMV_DOT_XY, SELL_SPMV_DOT_XX};
             for (int q = 0; q < 3; ++q)
                 if (o.flags & g[q]) {
@@ -212,7 +206,9 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
         }
         return SELL_OK;
     }
-    for (auto sl : slices(b)) {
+    auto sl_list = slices(b);
+    if (partials_out && sl_list.size() != 1) return SELL_ERR_UNSUPPORTED;
+    for (auto sl : sl_list) {
         ProdArgs a;
         base_args(a, A);
         a.nb = sl.second;
@@ -235,18 +231,21 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
                 a.has_gamma_v = 1;
                 for (int j = 0; j < sl.second; ++j) a.gamma_v[j] = o.gamma_v[sl.first + j];
             }
-            if (dots) {
-                a.dot = o.dot + sl.first;
-                a.dot_b = b;
-                a.partials = ws->partials;
-                a.counter = ws->counter;
-            }
+            if (dots) a.partials = partials_out ? partials_out : ws->partials;
         }
         int rc = launch_product(a, vec_kind(A->h.vdt), aug, s);
         if (rc) return rc;
+        if (dots && !partials_out) {
+            rc = launch_dot_finish(ws->partials, a.ntiles, a.nb, o.flags, o.dot + sl.first, b, 1, 0, s);
+            if (rc) return rc;
+        }
     }
     return SELL_OK;
 }
+
+}  // namespace sellcs
+
+namespace {
 
 int check_product_operands(const sell_mat *A, const sell_bv *X, const sell_bv *Y) {
     int rc = check_device(A);
@@ -663,6 +662,7 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
     if (M < 1 || !mu || !(scale != 0.0) || !std::isfinite(scale) || !std::isfinite(c)) return SELL_ERR_ARG;
     if (V->ptr == W->ptr && A->h.nrows > 0) return SELL_ERR_ARG;
     const int b = V->ncols;
+    if (b > kMaxSliceCols) return SELL_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<hipEvent_t> ev;
     if (step_ms) {
@@ -674,29 +674,39 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
                 return SELL_ERR_HIP;
             }
     }
-    double *dots = nullptr;
+    // per-step tile partials of the dots, summed once after the recurrence
+    const int32_t nt = A->ntiles;
+    const size_t per_step = size_t(3) * b * size_t(nt > 0 ? nt : 1);
+    double *dots = nullptr, *parts = nullptr;
     hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&dots), size_t(M) * 3 * b * sizeof(double), s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&parts), size_t(M) * per_step * sizeof(double), s);
     if (e != hipSuccess) rc = hip_err(e);
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
     // v1 = (A v0 - c v0) / s, with <v1,v1>, <v0,v1>, <v0,v0>
     o.flags = SELL_SPMV_SCALE | SELL_SPMV_SHIFT | SELL_SPMV_DOTS;
     o.alpha = 1.0 / scale;
     o.gamma = c;
-    o.dot = dots;
     if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[0], s);
-    if (rc == SELL_OK) rc = aug_impl(A, V, W, nullptr, o, true, s);
+    if (rc == SELL_OK) rc = aug_impl(A, V, W, nullptr, o, true, s, parts);
     if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[1], s);
     sell_bv *x = W, *y = V;  // x = v_m, y = v_{m-1} -> v_{m+1}
     o.flags = SELL_SPMV_SCALE | SELL_SPMV_SHIFT | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
     o.alpha = 2.0 / scale;
     o.beta = -1.0;
     for (int64_t m = 1; m < M && rc == SELL_OK; ++m) {
-        o.dot = dots + m * 3 * b;
-        rc = aug_impl(A, x, y, nullptr, o, true, s);
+        rc = aug_impl(A, x, y, nullptr, o, true, s, parts + size_t(m) * per_step);
         if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[size_t(m) + 1], s);
         std::swap(x, y);
     }
+    if (rc == SELL_OK && A->h.nrows > 0 && nt > 0)
+        rc = launch_dot_finish(parts, nt, b, SELL_SPMV_DOTS, dots, b, M, 3 * b, s);
+    else if (rc == SELL_OK)
+        rc = launch_fill(dots, SELL_F64, M, 3 * b, 3 * b, 1, 0.0, s);
     if (rc == SELL_OK) rc = launch_kpm_moments(dots, M, b, mu, s);
+    if (parts) {
+        e = hipFreeAsync(parts, s);
+        if (rc == SELL_OK && e != hipSuccess) rc = hip_err(e);
+    }
     if (dots) {
         e = hipFreeAsync(dots, s);
         if (rc == SELL_OK && e != hipSuccess) rc = hip_err(e);

@@ -1,0 +1,235 @@
+// cg.hip -- vector kernels of the conjugate-gradient drivers (block vectors, one CG per
+// column, all scalars kept in FP64 on the device so an iteration needs no host sync).
+//
+// Column sums are deterministic: butterfly shuffles inside a wave, LDS across waves, one
+// partial per workgroup (plain stores), then a one-workgroup-per-column kernel adds the
+// partials in workgroup order and performs the per-column scalar updates.
+#include "devutil.h"
+#include "internal.h"
+
+namespace sellcs {
+
+constexpr int kVT = 256;  // threads per workgroup of the vector kernels
+
+// Per-workgroup column sums of one FP64 value per thread (column j = tid & (bpad - 1);
+// lanes with j >= b give 0), written with plain stores to partials[j * gridDim.x + block].
+// Butterfly inside the wave, waves in order: a fixed order.
+__device__ void colsum_store(double v, int bpad, int b, double *partials) {
+    __shared__ double red[kVT / 64][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int m = 32; m >= bpad; m >>= 1) v += __shfl_xor(v, m, 64);
+    if (lane < bpad) red[w][lane] = v;
+    __syncthreads();
+    if (tid < b) {
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kVT / 64; ++ww) s += red[ww][tid];
+        partials[size_t(tid) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// Sum of n consecutive partials by one 256-thread workgroup (fixed order); thread 0 only.
+__device__ double sum_partials(const double *p, int n) {
+    double s = 0.0;
+    for (int t = threadIdx.x; t < n; t += kVT) s += p[t];
+    return block_sum_256(s);
+}
+
+// alpha_j = rho_j / <p, A p>_j for active columns, from the product's tile partials
+// (quantity b + j). One workgroup per column.
+__global__ void __launch_bounds__(kVT) cg_alpha_kernel(const double *prod_partials, int ntiles, int b, CgDev sc) {
+    const int j = blockIdx.x;
+    const double pq = sum_partials(prod_partials + size_t(b + j) * ntiles, ntiles);
+    if (threadIdx.x == 0) {
+        sc.pq[j] = pq;
+        sc.alpha[j] = (sc.active[j] && pq != 0.0) ? sc.rho[j] / pq : 0.0;
+    }
+}
+
+// x += alpha p ; r -= alpha q ; per-workgroup partials of <r, r>.
+template <class T>
+__global__ void __launch_bounds__(kVT) cg_xr_kernel(T *X, T *R, const T *P, const T *Q, int64_t n, int b,
+                                                    int bpad, int64_t ld, const double *alpha_v,
+                                                    double *partials) {
+    const int tid = threadIdx.x;
+    const int j = tid & (bpad - 1);
+    const int rows_per = kVT / bpad;
+    double acc = 0.0;
+    if (j < b) {
+        const double alpha = alpha_v[j];
+        for (int64_t i = int64_t(blockIdx.x) * rows_per + tid / bpad; i < n; i += int64_t(gridDim.x) * rows_per) {
+            const int64_t e = i * ld + j;
+            const T x = T(double(X[e]) + alpha * double(P[e]));
+            const T r = T(double(R[e]) - alpha * double(Q[e]));
+            X[e] = x;
+            R[e] = r;
+            acc += double(r) * double(r);
+        }
+    }
+    colsum_store(acc, bpad, b, partials);
+}
+
+// rho_new = <r, r>; beta = rho_new / rho; rho = rho_new; active &= rho_new > thresh2.
+__global__ void __launch_bounds__(kVT) cg_beta_kernel(const double *partials, int G, CgDev sc) {
+    const int j = blockIdx.x;
+    const double rn = sum_partials(partials + size_t(j) * G, G);
+    if (threadIdx.x == 0) {
+        const double rho = sc.rho[j];
+        const bool act = sc.active[j] != 0;
+        sc.beta[j] = (act && rho != 0.0) ? rn / rho : 0.0;
+        sc.rho[j] = rn;
+        sc.active[j] = (act && rn > sc.thresh2[j]) ? 1 : 0;
+    }
+}
+
+// p = r + beta p
+template <class T>
+__global__ void __launch_bounds__(kVT) cg_p_kernel(T *P, const T *R, int64_t n, int b, int64_t ld,
+                                                   const double *beta) {
+    const int64_t N = n * b;
+    for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
+        const int64_t i = e / b;
+        const int j = int(e - i * b);
+        const int64_t k = i * ld + j;
+        P[k] = T(double(R[k]) + beta[j] * double(P[k]));
+    }
+}
+
+// per-workgroup partials of <U_j, V_j>
+template <class T>
+__global__ void __launch_bounds__(kVT) coldot_kernel(const T *U, const T *V, int64_t n, int b, int bpad,
+                                                     int64_t ld, double *partials) {
+    const int tid = threadIdx.x;
+    const int j = tid & (bpad - 1);
+    const int rows_per = kVT / bpad;
+    double acc = 0.0;
+    if (j < b)
+        for (int64_t i = int64_t(blockIdx.x) * rows_per + tid / bpad; i < n; i += int64_t(gridDim.x) * rows_per)
+            acc += double(U[i * ld + j]) * double(V[i * ld + j]);
+    colsum_store(acc, bpad, b, partials);
+}
+
+// result_j = sum of the partials; optionally thresh2_j = f2 * (ref_j or result_j) and
+// active_j = result_j > thresh2_j.
+__global__ void __launch_bounds__(kVT) coldot_finish_kernel(const double *partials, int G, double *result,
+                                                            double *thresh2, int32_t *active, const double *ref,
+                                                            double f2) {
+    const int j = blockIdx.x;
+    const double v = sum_partials(partials + size_t(j) * G, G);
+    if (threadIdx.x == 0) {
+        result[j] = v;
+        if (thresh2) {
+            thresh2[j] = f2 * (ref ? ref[j] : v);
+            active[j] = v > thresh2[j] ? 1 : 0;
+        }
+    }
+}
+
+// dst32 = src64 * s_j with s_j = 1 / sqrt(rr_j) for active columns, else 0; scale[j] = sqrt(rr_j)
+// (or 0). A column is active when rr_j > thresh2_j.
+__global__ void __launch_bounds__(kVT) scale_to_f32_kernel(float *dst, const double *src, int64_t n, int b,
+                                                           int64_t ld, const double *rr, const double *thresh2,
+                                                           double *scale) {
+    const int64_t N = n * b;
+    for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
+        const int64_t i = e / b;
+        const int j = int(e - i * b);
+        const bool act = rr[j] > thresh2[j];
+        const double s = act ? 1.0 / sqrt(rr[j]) : 0.0;
+        dst[i * ld + j] = float(src[i * ld + j] * s);
+        if (e < b) scale[j] = act ? sqrt(rr[j]) : 0.0;
+    }
+}
+
+// x += scale_j * d
+__global__ void __launch_bounds__(kVT) axpy_mixed_kernel(double *X, const float *D, int64_t n, int b, int64_t ld,
+                                                         const double *scale) {
+    const int64_t N = n * b;
+    for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
+        const int64_t i = e / b;
+        const int j = int(e - i * b);
+        X[i * ld + j] += scale[j] * double(D[i * ld + j]);
+    }
+}
+
+static unsigned vgrid(int64_t work, unsigned cap) {
+    int64_t g = (work + kVT - 1) / kVT;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return unsigned(g);
+}
+
+static int pow2_at_least(int b) {
+    int p = 1;
+    while (p < b) p <<= 1;
+    return p;
+}
+
+static int ok() { return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP; }
+
+unsigned cg_reduce_grid(int64_t n, int b) { return vgrid(n * pow2_at_least(b), kCgMaxGrid); }
+
+int cg_launch_alpha(const double *prod_partials, int ntiles, int b, const CgDev &sc, hipStream_t s) {
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(b), dim3(kVT), 0, s, prod_partials, ntiles, b, sc);
+    return ok();
+}
+
+int cg_launch_xr(int dt, void *X, void *R, const void *P, const void *Q, int64_t n, int b, int64_t ld,
+                 const CgDev &sc, double *partials, hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    const unsigned g = cg_reduce_grid(n, b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(cg_xr_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(X),
+                           static_cast<double *>(R), static_cast<const double *>(P),
+                           static_cast<const double *>(Q), n, b, bpad, ld, sc.alpha, partials);
+    else
+        hipLaunchKernelGGL(cg_xr_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(X),
+                           static_cast<float *>(R), static_cast<const float *>(P), static_cast<const float *>(Q),
+                           n, b, bpad, ld, sc.alpha, partials);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(b), dim3(kVT), 0, s, partials, int(g), sc);
+    return ok();
+}
+
+int cg_launch_p(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const double *beta, hipStream_t s) {
+    const unsigned g = vgrid(n * b, 4096);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(cg_p_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(P),
+                           static_cast<const double *>(R), n, b, ld, beta);
+    else
+        hipLaunchKernelGGL(cg_p_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(P),
+                           static_cast<const float *>(R), n, b, ld, beta);
+    return ok();
+}
+
+int cg_launch_coldot(int dt, const void *U, const void *V, int64_t n, int b, int64_t ld, double *result,
+                     double *partials, double *thresh2, int32_t *active, const double *ref, double f2,
+                     hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    const unsigned g = cg_reduce_grid(n, b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(coldot_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<const double *>(U),
+                           static_cast<const double *>(V), n, b, bpad, ld, partials);
+    else
+        hipLaunchKernelGGL(coldot_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<const float *>(U),
+                           static_cast<const float *>(V), n, b, bpad, ld, partials);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(coldot_finish_kernel, dim3(b), dim3(kVT), 0, s, partials, int(g), result, thresh2, active,
+                       ref, f2);
+    return ok();
+}
+
+int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int64_t ld, const double *rr,
+                           const double *thresh2, double *scale, hipStream_t s) {
+    hipLaunchKernelGGL(scale_to_f32_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, dst, src, n, b, ld, rr,
+                       thresh2, scale);
+    return ok();
+}
+
+int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(axpy_mixed_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, X, D, n, b, ld, scale);
+    return ok();
+}
+
+}  // namespace sellcs

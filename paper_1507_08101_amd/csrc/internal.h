@@ -100,10 +100,8 @@ struct ProdArgs {
     int32_t has_gamma_v;   // per-column shifts below (else the scalar gamma_s)
     double gamma_s;        // scalar shift
     double gamma_v[kMaxSliceCols];
-    double *dot;           // device: dot + j0 (yy), with stride dot_b between groups
-    int32_t dot_b;         // b of the full call (yy | xy | xx groups are dot_b apart)
-    double *partials;      // workspace: 3 * nb * ntiles doubles
-    unsigned *counter;     // workspace: one zeroed counter
+    double *partials;      // dots: 3 * nb * ntiles doubles, partials[q * ntiles + tile],
+                           // q = g * nb + j for g = yy, xy, xx
 };
 
 enum VecKind { VK_F64F64 = 0, VK_F32F32 = 1, VK_BF16F32 = 2 };
@@ -116,30 +114,46 @@ int launch_copy(const sell_bv *dst, const sell_bv *src, hipStream_t s);
 int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s);
 int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s);
 int launch_kpm_moments(const double *dots, int64_t M, int32_t b, double *mu, hipStream_t s);
+// dot[g * dot_b + j] = sum_t partials[(g * nb + j) * ntiles + t] for the groups g requested
+// in flags (yy, xy, xx), fixed summation order; batch > 1 handles consecutive partial
+// blocks (stride 3 * nb * ntiles) writing dot + k * dot_stride.
+int launch_dot_finish(const double *partials, int32_t ntiles, int32_t nb, uint32_t flags, double *dot,
+                      int32_t dot_b, int64_t batch, int64_t dot_stride, hipStream_t s);
 
-// CG building blocks (FP64 scalars on the device; see solvers.cpp).
-struct CgScalars {
-    double *rho;      // <r, r> current, b
-    double *rho_new;  // b
-    double *pq;       // <p, A p>, 3b (dot layout of the product: xy group used)
-    double *thresh2;  // per column squared stopping threshold
-    int32_t *active;  // per column flag
+// CG building blocks (cg.hip): FP64 scalars live on the device.
+constexpr int kCgMaxGrid = 1024;  // workgroups of the reducing vector kernels
+struct CgDev {
+    double *rho;      // <r, r> per column (b)
+    double *pq;       // <p, A p> per column (b)
+    double *alpha;    // b
+    double *beta;     // b
+    double *thresh2;  // squared stopping threshold per column (b)
+    int32_t *active;  // per column: 1 while not converged
 };
-int launch_cg_update_xr(void *Xv, void *R, const void *P, const void *Q, int vec_dt,
-                        int64_t n, int32_t b, int64_t ld, const CgScalars &sc,
-                        double *partials, unsigned *counter, int32_t ntiles, hipStream_t s);
-int launch_cg_update_p(void *P, const void *R, int vec_dt, int64_t n, int32_t b, int64_t ld,
-                       const CgScalars &sc, hipStream_t s);
-int launch_axpy_mixed(double *X, const void *D, int d_dt, int64_t n, int32_t b, int64_t ld,
-                      const double *scale, hipStream_t s);
-int launch_scale_to_f32(float *dst, const double *src, int64_t n, int32_t b, int64_t ld,
-                        const double *rr, double *scale, hipStream_t s);
+unsigned cg_reduce_grid(int64_t n, int b);
+int cg_launch_alpha(const double *prod_partials, int ntiles, int b, const CgDev &sc, hipStream_t s);
+int cg_launch_xr(int dt, void *X, void *R, const void *P, const void *Q, int64_t n, int b, int64_t ld,
+                 const CgDev &sc, double *partials, hipStream_t s);
+int cg_launch_p(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const double *beta, hipStream_t s);
+int cg_launch_coldot(int dt, const void *U, const void *V, int64_t n, int b, int64_t ld, double *result,
+                     double *partials, double *thresh2, int32_t *active, const double *ref, double f2,
+                     hipStream_t s);
+int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int64_t ld, const double *rr,
+                           const double *thresh2, double *scale, hipStream_t s);
+int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
+                         hipStream_t s);
+
+// The fused product of capi.cpp (no argument checks): y = alpha (A x - gamma x) + beta y,
+// dots, chain; aug = false runs the plain product y = A x.
+// partials_out == nullptr: the dots are summed into o.dot right away (workspace partials and
+// a finishing kernel). Else the tile partials of the (single, b <= 64) slice are left in
+// partials_out (3 * b * ntiles doubles) for the caller to reduce, and o.dot is not used.
+int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
+             hipStream_t s, double *partials_out = nullptr);
 
 // Per-(device, stream) workspace for reductions.
 struct Workspace {
     double *partials = nullptr;   // kMaxTiles * 3 * kMaxSliceCols doubles
-    unsigned *counter = nullptr;  // 4 counters, zero between launches
-    double *scalars = nullptr;    // small scratch for solver scalars
 };
 int get_workspace(hipStream_t s, Workspace **ws);
 

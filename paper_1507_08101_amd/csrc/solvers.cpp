@@ -1,15 +1,278 @@
-// solvers.cpp -- conjugate-gradient drivers (placeholder until the CG kernels land).
+// solvers.cpp -- conjugate-gradient drivers on top of the augmented SpMMV.
+//
+// Both drivers run one CG per column of a block of right-hand sides (the paper's block
+// vectors, Sec. 5.2, with per-column scalars as in its vaxpy/vaxpby operations). An
+// iteration is three launches with no host synchronisation:
+//   q = A p            augmented product with the fused dot <p, q>
+//   x += a p, r -= a q fused update with <r, r> and the per-column scalars (device FP64)
+//   p = r + b p
+// The host reads the per-column "active" flags every few iterations.
+//
+// sell_cg:        FP64 throughout; convergence is confirmed on the true residual b - A x.
+// sell_cg_mixed:  iterative refinement. The residual r = b - A x is formed in FP64 with the
+//                 FP64 matrix (one augmented product: y = b preloaded, alpha = -1, beta = 1,
+//                 fused <r, r>); the correction solves A d = r / ||r|| in FP32 vectors with
+//                 the FP32 or BF16 matrix; x += ||r|| d in FP64.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 #include "internal.h"
+
+using namespace sellcs;
+
+namespace {
+
+#define HIPCHK(x)                                                                      \
+    do {                                                                               \
+        hipError_t e_ = (x);                                                           \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? SELL_ERR_OOM : SELL_ERR_HIP; \
+    } while (0)
+
+constexpr int kCheckEvery = 8;
+
+struct Buffers {
+    std::vector<void *> ptrs;
+    ~Buffers() {
+        for (void *p : ptrs) hipFree(p);
+    }
+    int alloc(void **p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 16;
+        HIPCHK(hipMalloc(p, bytes));
+        ptrs.push_back(*p);
+        return SELL_OK;
+    }
+};
+
+sell_bv view(void *p, int64_t n, int b, int dt) {
+    sell_bv v;
+    v.nrows = n;
+    v.ncols = b;
+    v.dt = dt;
+    v.lay = SELL_ROW_MAJOR;
+    v.ptr = p;
+    v.ld = b;
+    v.owned = false;
+    return v;
+}
+
+struct Scalars {
+    double *rho, *pq, *alpha, *beta, *thresh2, *bb, *rr, *scale, *thresh_out;
+    int32_t *active;
+    double *prod_parts;   // tile partials of the product's dots (3 b ntiles)
+    double *vec_parts;    // workgroup partials of the vector kernels (b kCgMaxGrid)
+    int32_t prod_tiles;
+    CgDev dev() const { return CgDev{rho, pq, alpha, beta, thresh2, active}; }
+};
+
+int alloc_scalars(Buffers &B, Scalars &S, int b, int32_t max_tiles) {
+    double *d = nullptr;
+    const size_t nt = size_t(max_tiles > 0 ? max_tiles : 1);
+    const size_t n = 16 * size_t(b) + 3 * size_t(b) * nt + size_t(b) * kCgMaxGrid + 64;
+    int rc = B.alloc(reinterpret_cast<void **>(&d), sizeof(double) * n);
+    if (rc) return rc;
+    S.rho = d;
+    S.pq = d + b;
+    S.alpha = d + 2 * b;
+    S.beta = d + 3 * b;
+    S.thresh2 = d + 4 * b;
+    S.bb = d + 5 * b;
+    S.rr = d + 6 * b;         // 3b
+    S.scale = d + 9 * b;
+    S.thresh_out = d + 10 * b;
+    S.active = reinterpret_cast<int32_t *>(d + 11 * b);
+    S.prod_parts = d + 16 * b;
+    S.vec_parts = S.prod_parts + 3 * size_t(b) * nt;
+    S.prod_tiles = max_tiles;
+    return SELL_OK;
+}
+
+int any_active(const Scalars &S, int b, hipStream_t s, bool *any) {
+    int32_t h[64];
+    HIPCHK(hipMemcpyAsync(h, S.active, sizeof(int32_t) * b, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *any = false;
+    for (int j = 0; j < b; ++j) *any = *any || h[j] != 0;
+    return SELL_OK;
+}
+
+// CG iterations on A for X (correction or solution), R (current residual), P, Q work.
+// Expects S.rho, S.thresh2 and S.active set for R. Runs until no column is active or
+// maxit iterations; returns the iterations done in *its.
+int cg_iterate(const sell_mat *A, int dt, sell_bv &X, sell_bv &R, sell_bv &P, sell_bv &Q, const Scalars &S,
+               int64_t maxit, int64_t *its, hipStream_t s) {
+    const int64_t n = A->h.nrows;
+    const int b = R.ncols;
+    int rc = launch_copy(&P, &R, s);
+    if (rc) return rc;
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    o.flags = SELL_SPMV_DOT_XY;
+    *its = 0;
+    bool any = true;
+    if ((rc = any_active(S, b, s, &any))) return rc;
+    while (any && *its < maxit) {
+        if ((rc = aug_impl(A, &P, &Q, nullptr, o, true, s, S.prod_parts))) return rc;
+        if ((rc = cg_launch_alpha(S.prod_parts, A->ntiles, b, S.dev(), s))) return rc;
+        if ((rc = cg_launch_xr(dt, X.ptr, R.ptr, P.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
+        if ((rc = cg_launch_p(dt, P.ptr, R.ptr, n, b, b, S.beta, s))) return rc;
+        ++*its;
+        if (*its % kCheckEvery == 0 && (rc = any_active(S, b, s, &any))) return rc;
+    }
+    return SELL_OK;
+}
+
+// r = b - A x in FP64 (b preloaded into R), <r, r> into S.rr[0..b)
+int true_residual(const sell_mat *A64, const sell_bv *Bv, const sell_bv *X, sell_bv &R, const Scalars &S,
+                  hipStream_t s) {
+    int rc = launch_copy(&R, Bv, s);
+    if (rc) return rc;
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    o.flags = SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY;
+    o.alpha = -1.0;
+    o.beta = 1.0;
+    o.dot = S.rr;
+    return aug_impl(A64, X, &R, nullptr, o, true, s);
+}
+
+int relres_host(const Scalars &S, int b, hipStream_t s, double *worst) {
+    double rr[64], bb[64];
+    HIPCHK(hipMemcpyAsync(rr, S.rr, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(bb, S.bb, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *worst = 0.0;
+    for (int j = 0; j < b; ++j) {
+        const double r = bb[j] > 0 ? std::sqrt(rr[j] / bb[j]) : std::sqrt(rr[j]);
+        if (!(r <= *worst)) *worst = r;  // NaN propagates
+    }
+    return SELL_OK;
+}
+
+int check_cg_operands(const sell_mat *A, const sell_bv *Bv, const sell_bv *X) {
+    if (!A || !Bv || !X) return SELL_ERR_ARG;
+    if (!A->on_device) return SELL_ERR_STATE;
+    if (A->h.nrows != A->h.ncols) return SELL_ERR_SHAPE;
+    if (Bv->dt != SELL_F64 || X->dt != SELL_F64) return SELL_ERR_DTYPE;
+    if (Bv->nrows != A->h.nrows || X->nrows != A->h.nrows || Bv->ncols != X->ncols) return SELL_ERR_SHAPE;
+    if (Bv->ncols < 1 || Bv->ncols > 64) return SELL_ERR_UNSUPPORTED;
+    if (Bv->lay != SELL_ROW_MAJOR || X->lay != SELL_ROW_MAJOR || Bv->ld != Bv->ncols || X->ld != X->ncols)
+        return SELL_ERR_UNSUPPORTED;
+    if ((!Bv->ptr || !X->ptr) && A->h.nrows > 0) return SELL_ERR_ARG;
+    return SELL_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
-int sell_cg(const sell_mat *, const sell_bv *, sell_bv *, double, int64_t, sell_cg_stats *, void *) {
-    return SELL_ERR_UNSUPPORTED;
+int sell_cg(const sell_mat *A, const sell_bv *Bv, sell_bv *X, double tol, int64_t maxit, sell_cg_stats *stats,
+            void *stream) {
+    int rc = check_cg_operands(A, Bv, X);
+    if (rc) return rc;
+    if (A->h.vdt != SELL_F64) return SELL_ERR_DTYPE;
+    if (!(tol > 0) || maxit < 0) return SELL_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->h.nrows;
+    const int b = Bv->ncols;
+    sell_cg_stats st{0, 0, 0.0, 0};
+    if (n == 0) {
+        st.converged = 1;
+        if (stats) *stats = st;
+        return SELL_OK;
+    }
+    Buffers B;
+    void *pr, *pp, *pq;
+    const size_t bytes = size_t(n) * b * sizeof(double);
+    if ((rc = B.alloc(&pr, bytes)) || (rc = B.alloc(&pp, bytes)) || (rc = B.alloc(&pq, bytes))) return rc;
+    Scalars S;
+    if ((rc = alloc_scalars(B, S, b, A->ntiles))) return rc;
+    sell_bv R = view(pr, n, b, SELL_F64), P = view(pp, n, b, SELL_F64), Q = view(pq, n, b, SELL_F64);
+    // ||b||^2 and the stopping threshold tol^2 ||b||^2
+    if ((rc = cg_launch_coldot(SELL_F64, Bv->ptr, Bv->ptr, n, b, b, S.bb, S.vec_parts, S.thresh_out,
+                               S.active, nullptr, tol * tol, s)))
+        return rc;
+    double worst = 0.0;
+    while (true) {
+        if ((rc = true_residual(A, Bv, X, R, S, s))) return rc;
+        if ((rc = relres_host(S, b, s, &worst))) return rc;
+        if (worst <= tol || st.iterations >= maxit) break;
+        // rho = <r, r>, active = rho > tol^2 ||b||^2
+        if ((rc = cg_launch_coldot(SELL_F64, R.ptr, R.ptr, n, b, b, S.rho, S.vec_parts, S.thresh2,
+                                   S.active, S.thresh_out, 1.0, s)))
+            return rc;
+        int64_t its = 0;
+        if ((rc = cg_iterate(A, SELL_F64, *X, R, P, Q, S, maxit - st.iterations, &its, s))) return rc;
+        st.iterations += its;
+        if (its == 0) break;
+        ++st.refinements;  // restarts from the true residual
+    }
+    st.refinements = st.refinements > 0 ? st.refinements - 1 : 0;
+    st.relres = worst;
+    st.converged = worst <= tol ? 1 : 0;
+    if (stats) *stats = st;
+    return SELL_OK;
 }
 
-int sell_cg_mixed(const sell_mat *, const sell_mat *, const sell_bv *, sell_bv *, double, int64_t, double,
-                  int64_t, sell_cg_stats *, void *) {
-    return SELL_ERR_UNSUPPORTED;
+int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, sell_bv *X, double tol,
+                  int64_t maxit, double inner_tol, int64_t inner_maxit, sell_cg_stats *stats, void *stream) {
+    int rc = check_cg_operands(A64, Bv, X);
+    if (rc) return rc;
+    if (!Alo) return SELL_ERR_ARG;
+    if (!Alo->on_device) return SELL_ERR_STATE;
+    if (A64->h.vdt != SELL_F64 || Alo->h.vdt == SELL_F64) return SELL_ERR_DTYPE;
+    if (Alo->h.nrows != A64->h.nrows || Alo->h.ncols != A64->h.ncols || Alo->h.nnz != A64->h.nnz)
+        return SELL_ERR_SHAPE;
+    if (!(tol > 0) || !(inner_tol > 0) || maxit < 0 || inner_maxit < 1) return SELL_ERR_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A64->h.nrows;
+    const int b = Bv->ncols;
+    sell_cg_stats st{0, 0, 0.0, 0};
+    if (n == 0) {
+        st.converged = 1;
+        if (stats) *stats = st;
+        return SELL_OK;
+    }
+    Buffers B;
+    void *pr64, *pr, *pd, *pp, *pq;
+    const size_t b64 = size_t(n) * b * sizeof(double), b32 = size_t(n) * b * sizeof(float);
+    if ((rc = B.alloc(&pr64, b64)) || (rc = B.alloc(&pr, b32)) || (rc = B.alloc(&pd, b32)) ||
+        (rc = B.alloc(&pp, b32)) || (rc = B.alloc(&pq, b32)))
+        return rc;
+    Scalars S;
+    if ((rc = alloc_scalars(B, S, b, std::max(A64->ntiles, Alo->ntiles)))) return rc;
+    sell_bv R64 = view(pr64, n, b, SELL_F64);
+    sell_bv R = view(pr, n, b, SELL_F32), D = view(pd, n, b, SELL_F32), P = view(pp, n, b, SELL_F32),
+            Q = view(pq, n, b, SELL_F32);
+    if ((rc = cg_launch_coldot(SELL_F64, Bv->ptr, Bv->ptr, n, b, b, S.bb, S.vec_parts, S.thresh_out,
+                               S.active, nullptr, tol * tol, s)))
+        return rc;
+    double worst = 0.0;
+    while (true) {
+        if ((rc = true_residual(A64, Bv, X, R64, S, s))) return rc;
+        if ((rc = relres_host(S, b, s, &worst))) return rc;
+        if (worst <= tol || st.iterations >= maxit) break;
+        // r^ = r / ||r|| for columns still above tol (others get 0 and stay put)
+        if ((rc = cg_launch_scale_to_f32(static_cast<float *>(R.ptr), static_cast<const double *>(R64.ptr), n, b, b,
+                                         S.rr, S.thresh_out, S.scale, s)))
+            return rc;
+        if ((rc = launch_fill(D.ptr, SELL_F32, n, b, b, 1, 0.0, s))) return rc;
+        if ((rc = cg_launch_coldot(SELL_F32, R.ptr, R.ptr, n, b, b, S.rho, S.vec_parts, S.thresh2,
+                                   S.active, nullptr, inner_tol * inner_tol, s)))
+            return rc;
+        int64_t its = 0;
+        const int64_t cap = std::min<int64_t>(inner_maxit, maxit - st.iterations);
+        if ((rc = cg_iterate(Alo, SELL_F32, D, R, P, Q, S, cap, &its, s))) return rc;
+        st.iterations += its;
+        if ((rc = cg_launch_axpy_mixed(static_cast<double *>(X->ptr), static_cast<const float *>(D.ptr), n, b, b,
+                                       S.scale, s)))
+            return rc;
+        ++st.refinements;
+        if (its == 0) break;
+    }
+    st.relres = worst;
+    st.converged = worst <= tol ? 1 : 0;
+    if (stats) *stats = st;
+    return SELL_OK;
 }
 
 }  // extern "C"

@@ -19,9 +19,11 @@
 //     gathers, to keep enough loads in flight for HBM. Padding entries (column -1) are
 //     skipped: no gather, no arithmetic.
 //   * Dots are reduced without floating-point atomics: butterfly shuffles inside the
-//     wave, LDS across the waves of the workgroup, one partial per tile in a workspace,
-//     and the last workgroup to finish (an integer atomic ticket) sums the partials in
-//     tile order. The order is fixed, so results are bitwise reproducible.
+//     wave, LDS across the waves of the workgroup, one partial per tile written with a
+//     plain store; a separate small kernel (or the caller's next kernel) sums the partials
+//     in tile order. The order is fixed, so results are bitwise reproducible. There is no
+//     "last workgroup" ticket: on a multi-XCD part the device-scope release/acquire it
+//     needs writes back and invalidates the L2 once per workgroup.
 #pragma once
 
 #include "internal.h"
@@ -66,43 +68,70 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
-// Sum of the per-tile partials (laid out quantity-major: partials[q * ntiles + t]) by the
-// last workgroup to finish; writes the requested dots.
-__device__ __forceinline__ void finish_dots(const ProdArgs &a, int nq, int nb, int tile,
-                                            const double *blocksum /* LDS, nq */) {
-    __shared__ int s_last;
-    const int tid = threadIdx.x;
-    for (int q = tid; q < nq; q += kBlock) a.partials[size_t(q) * a.ntiles + tile] = blocksum[q];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(a.counter, 1u) == unsigned(a.ntiles - 1));
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    const int lane = tid & 63, w = tid >> 6;
-    for (int q = w; q < nq; q += kBlock / 64) {
-        double s = 0.0;
-        const double *p = a.partials + size_t(q) * a.ntiles;
-        for (int t = lane; t < a.ntiles; t += 64) s += __builtin_nontemporal_load(p + t);
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// VPT consecutive elements at p (element stride cs). VEC: cs == 1 and p aligned to
+// min(16, VPT * sizeof(X)) bytes, so the row piece moves as 8- or 16-byte vector accesses.
+template <class X, int VPT, bool VEC>
+__device__ __forceinline__ void load_row(const X *p, int64_t cs, X (&o)[VPT]) {
+    constexpr int bytes = VPT * int(sizeof(X));
+    if constexpr (VEC && bytes % 16 == 0) {
 #pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) s += shfl_xor_d(s, m);
-        if (lane == 0) {
-            const int g = q / nb, j = q - g * nb;
-            const uint32_t want = g == 0 ? SELL_SPMV_DOT_YY : g == 1 ? SELL_SPMV_DOT_XY : SELL_SPMV_DOT_XX;
-            if (a.flags & want) a.dot[size_t(g) * a.dot_b + j] = s;
+        for (int q = 0; q < bytes / 16; ++q) {
+            const u32x4 v = reinterpret_cast<const u32x4 *>(p)[q];
+            __builtin_memcpy(reinterpret_cast<char *>(o) + 16 * q, &v, 16);
         }
+    } else if constexpr (VEC && bytes == 8) {
+        const u32x2 v = *reinterpret_cast<const u32x2 *>(p);
+        __builtin_memcpy(o, &v, 8);
+    } else {
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) o[t] = p[t * cs];
     }
-    if (tid == 0) *a.counter = 0u;
 }
 
-// B > 0: compile-time slice width with VPT columns per lane (VL = B / VPT lanes per row).
-// B == 0: run-time width nb <= 64, one column per lane, VL = next power of two >= nb.
+template <class X, int VPT, bool VEC>
+__device__ __forceinline__ void store_row(X *p, int64_t cs, const X (&o)[VPT]) {
+    constexpr int bytes = VPT * int(sizeof(X));
+    if constexpr (VEC && bytes % 16 == 0) {
+#pragma unroll
+        for (int q = 0; q < bytes / 16; ++q) {
+            u32x4 v;
+            __builtin_memcpy(&v, reinterpret_cast<const char *>(o) + 16 * q, 16);
+            reinterpret_cast<u32x4 *>(p)[q] = v;
+        }
+    } else if constexpr (VEC && bytes == 8) {
+        u32x2 v;
+        __builtin_memcpy(&v, o, 8);
+        *reinterpret_cast<u32x2 *>(p) = v;
+    } else {
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) p[t * cs] = o[t];
+    }
+}
+
+// Entries gathered per batch: all index/value loads of a batch are issued before its
+// gathers, and all gathers before the FMAs (bounded so the gathered values fit in about
+// 32 VGPRs).
+template <class X, int VPT>
+constexpr int batch_len() {
+    constexpr int regs = VPT * int(sizeof(X)) / 4;  // VGPRs per gathered row piece
+    return regs <= 4 ? 8 : (regs <= 8 ? 4 : 2);
+}
+
+// B > 0: compile-time slice width with VPT columns per lane (VL = B / VPT lanes per row);
+//        the block vectors are row-major with rows aligned for vector accesses (VEC).
+// B == 0: run-time width nb <= 64, one column per lane, VL = next power of two >= nb,
+//         any strides.
 template <int VK, int B, int VPT, bool AUG>
 __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     using V = typename KTypes<VK>::V;
     using X = typename KTypes<VK>::X;
     using Acc = typename KTypes<VK>::Acc;
     constexpr bool DYN = (B == 0);
+    constexpr bool VEC = !DYN;
+    constexpr int U = batch_len<X, VPT>();
     const int nb = DYN ? a.nb : B;
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
@@ -122,6 +151,9 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const X *__restrict__ Xp = static_cast<const X *>(a.X);
     X *__restrict__ Yp = static_cast<X *>(a.Y);
     X *__restrict__ Zp = static_cast<X *>(a.Z);
+    const int64_t xrs = a.xrs, xcs = VEC ? 1 : a.xcs;
+    const int64_t yrs = a.yrs, ycs = VEC ? 1 : a.ycs;
+    const int64_t zrs = a.zrs, zcs = VEC ? 1 : a.zcs;
 
     const bool want_dots = AUG && (a.flags & SELL_SPMV_DOTS);
     const bool shift = AUG && (a.flags & (SELL_SPMV_SHIFT | SELL_SPMV_VSHIFT));
@@ -135,86 +167,117 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
 #pragma unroll
     for (int t = 0; t < VPT; ++t) dyy[t] = dxy[t] = dxx[t] = 0.0;
 
-    for (int64_t s = s_begin + (tid >> vls); s < s_end; s += rows_per_pass) {
+    if (s_begin >= s_end && !want_dots) return;
+    double gam[VPT];
+#pragma unroll
+    for (int t = 0; t < VPT; ++t) gam[t] = (a.has_gamma_v && col_ok) ? a.gamma_v[jb + t] : a.gamma_s;
+
+    // Chunk metadata of a slot, loaded one pass ahead. The loads are unconditional (the slot
+    // is clamped into the tile, and without a permutation the row load re-reads the chunk
+    // length) and nothing is computed from them until the next pass, so their latency
+    // overlaps the current pass.
+    auto load_meta = [&](int64_t ss, int &clv, int64_t &csv, int &pv) {
+        const int64_t sc = ss < s_end ? ss : s_end - 1;
+        const int64_t c = a.cshift >= 0 ? (sc >> a.cshift) : int64_t(uint32_t(sc) / uint32_t(C));
+        const int32_t *pp = a.perm ? a.perm + sc : a.cl + c;
+        clv = a.cl[c];
+        csv = a.cs[c];
+        pv = *pp;
+    };
+
+    int64_t s = s_begin + (tid >> vls);
+    int cl_n = 0, pv_n = 0;
+    int64_t cs_n = 0;
+    if (s_begin < s_end) load_meta(s, cl_n, cs_n, pv_n);
+    for (; s < s_end; s += rows_per_pass) {
         const int64_t c = a.cshift >= 0 ? (s >> a.cshift) : int64_t(uint32_t(s) / uint32_t(C));
-        const int r = int(s - c * C);
-        const int len = a.cl[c];
-        const int64_t base = a.cs[c] + r;
+        const int len = cl_n;
+        const int64_t base = cs_n + (s - c * C);
+        const int64_t row = s < a.nrows ? (a.perm ? int64_t(pv_n) : s) : -1;
+        load_meta(s + rows_per_pass, cl_n, cs_n, pv_n);  // one pass ahead
+        const bool live = row >= 0 && col_ok;
+
+        // epilogue operands, issued before the gathers so their latency overlaps
+        X xin[VPT], yin[VPT], zin[VPT];
+#pragma unroll
+        for (int t = 0; t < VPT; ++t) xin[t] = yin[t] = zin[t] = X(0);
+        if (AUG && live) {
+            if (need_x) load_row<X, VPT, VEC>(Xp + row * xrs + int64_t(jb) * xcs, xcs, xin);
+            if (read_y) load_row<X, VPT, VEC>(Yp + row * yrs + int64_t(jb) * ycs, ycs, yin);
+            if (read_z) load_row<X, VPT, VEC>(Zp + row * zrs + int64_t(jb) * zcs, zcs, zin);
+        }
+
         Acc acc[VPT];
 #pragma unroll
         for (int t = 0; t < VPT; ++t) acc[t] = Acc(0);
-
         if (col_ok) {
-            int k = 0;
-            for (; k + 4 <= len; k += 4) {
-                int ci[4];
-                V vv[4];
+            for (int k0 = 0; k0 < len; k0 += U) {
+                int ci[U];
+                V vv[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ci[u] = __builtin_nontemporal_load(col + base + int64_t(k + u) * C);
-                    vv[u] = __builtin_nontemporal_load(val + base + int64_t(k + u) * C);
+                for (int u = 0; u < U; ++u) {
+                    // clamp to the row's last entry so every load is in bounds and unconditional
+                    const int k = min(k0 + u, len - 1);
+                    const int64_t at = base + int64_t(k) * C;
+                    const int cc = __builtin_nontemporal_load(col + at);
+                    const V v = __builtin_nontemporal_load(val + at);
+                    ci[u] = (k0 + u < len) ? cc : -1;
+                    vv[u] = v;
+                }
+                X xg[U][VPT];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cu = ci[u] >= 0 ? ci[u] : 0;  // padding / tail: harmless in-bounds gather
+                    load_row<X, VPT, VEC>(Xp + int64_t(cu) * xrs + int64_t(jb) * xcs, xcs, xg[u]);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (ci[u] >= 0) {
-                        const X *xr = Xp + int64_t(ci[u]) * a.xrs + int64_t(jb) * a.xcs;
-                        const Acc v = to_acc(vv[u], Acc(0));
+                for (int u = 0; u < U; ++u) {
+                    const Acc v = to_acc(vv[u], Acc(0));
 #pragma unroll
-                        for (int t = 0; t < VPT; ++t) acc[t] = fmadd(v, Acc(xr[t * a.xcs]), acc[t]);
+                    for (int t = 0; t < VPT; ++t) {
+                        const Acc f = fmadd(v, Acc(xg[u][t]), acc[t]);
+                        acc[t] = ci[u] >= 0 ? f : acc[t];
                     }
-                }
-            }
-            for (; k < len; ++k) {
-                const int ci = __builtin_nontemporal_load(col + base + int64_t(k) * C);
-                const V vv = __builtin_nontemporal_load(val + base + int64_t(k) * C);
-                if (ci >= 0) {
-                    const X *xr = Xp + int64_t(ci) * a.xrs + int64_t(jb) * a.xcs;
-                    const Acc v = to_acc(vv, Acc(0));
-#pragma unroll
-                    for (int t = 0; t < VPT; ++t) acc[t] = fmadd(v, Acc(xr[t * a.xcs]), acc[t]);
                 }
             }
         }
 
-        if (s < a.nrows && col_ok) {
-            const int64_t row = a.perm ? int64_t(a.perm[s]) : s;
+        if (live) {
+            X out[VPT];
+            if (!AUG) {
 #pragma unroll
-            for (int t = 0; t < VPT; ++t) {
-                const int j = jb + t;
-                X *yp = Yp + row * a.yrs + int64_t(j) * a.ycs;
-                if (!AUG) {
-                    *yp = X(acc[t]);
-                } else {
-                    double xv = 0.0;
-                    if (need_x) xv = double(Xp[row * a.xrs + int64_t(j) * a.xcs]);
+                for (int t = 0; t < VPT; ++t) out[t] = X(acc[t]);
+                store_row<X, VPT, VEC>(Yp + row * yrs + int64_t(jb) * ycs, ycs, out);
+            } else {
+                X zout[VPT];
+#pragma unroll
+                for (int t = 0; t < VPT; ++t) {
+                    const double xv = double(xin[t]);
                     double tv = double(acc[t]);
-                    if (shift) tv = tv - (a.has_gamma_v ? a.gamma_v[j] : a.gamma_s) * xv;
+                    if (shift) tv = tv - gam[t] * xv;
                     double y = alpha * tv;
-                    if (read_y) y = y + a.beta * double(*yp);
-                    const X ys = X(y);
-                    *yp = ys;
-                    const double yd = double(ys);
+                    if (read_y) y = y + a.beta * double(yin[t]);
+                    out[t] = X(y);
+                    const double yd = double(out[t]);
                     if (want_dots) {
                         dyy[t] += yd * yd;
                         dxy[t] += xv * yd;
                         dxx[t] += xv * xv;
                     }
-                    if (chain) {
-                        X *zp = Zp + row * a.zrs + int64_t(j) * a.zcs;
-                        double z = a.eta * yd;
-                        if (read_z) z = a.delta * double(*zp) + z;
-                        *zp = X(z);
-                    }
+                    double z = a.eta * yd;
+                    if (read_z) z = a.delta * double(zin[t]) + z;
+                    zout[t] = X(z);
                 }
+                store_row<X, VPT, VEC>(Yp + row * yrs + int64_t(jb) * ycs, ycs, out);
+                if (chain) store_row<X, VPT, VEC>(Zp + row * zrs + int64_t(jb) * zcs, zcs, zout);
             }
         }
     }
 
     if (!want_dots) return;
 
-    // ---- deterministic dot reduction
+    // ---- dot partials of this tile (deterministic: butterfly in the wave, waves in order)
     __shared__ double red[kBlock / 64][3 * kMaxSliceCols];
-    __shared__ double bsum[3 * kMaxSliceCols];
     const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int t = 0; t < VPT; ++t) {
@@ -233,15 +296,15 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         }
     }
     __syncthreads();
+    // one partial per tile and quantity, plain stores: the sums over tiles are taken by a
+    // separate kernel (kernel boundaries order the memory without device-wide fences)
     const int nq = 3 * nb;
     for (int q = tid; q < nq; q += kBlock) {
         double sum = 0.0;
 #pragma unroll
         for (int ww = 0; ww < kBlock / 64; ++ww) sum += red[ww][q];
-        bsum[q] = sum;
+        a.partials[size_t(q) * a.ntiles + tile] = sum;
     }
-    __syncthreads();
-    finish_dots(a, nq, nb, tile, bsum);
 }
 
 // Transposed product by scattering with floating-point atomics: Y[col, j] += v * X[row, j].

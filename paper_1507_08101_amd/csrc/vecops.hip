@@ -3,6 +3,7 @@
 #include <cstdlib>
 
 #include "convert.h"
+#include "devutil.h"
 #include "internal.h"
 
 namespace sellcs {
@@ -14,9 +15,11 @@ int transpose_f64(const ProdArgs &a, hipStream_t s);
 int transpose_f32(const ProdArgs &a, hipStream_t s);
 int transpose_bf16(const ProdArgs &a, hipStream_t s);
 
+// Columns per lane of the fixed-width kernels: 16 bytes of a row per lane for FP32
+// vectors; two doubles for FP64 (keeps a batch of 8 gathered row pieces in 32 VGPRs).
+// SELLCS_VPT overrides the choice (1, 2 or 4) for tuning experiments.
 int choose_vpt(int vk, int b) {
-    int v = b >= 4 ? 4 : b;
-    (void)vk;
+    int v = vk == VK_F64F64 ? (b >= 2 ? 2 : 1) : (b >= 4 ? 4 : b);
     if (const char *e = std::getenv("SELLCS_VPT")) {
         int x = std::atoi(e);
         if ((x == 1 || x == 2 || x == 4) && x <= b) v = x;
@@ -24,12 +27,24 @@ int choose_vpt(int vk, int b) {
     return v;
 }
 
+static bool fixed_width(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32; }
+
+static bool vec_ok(const void *p, int64_t rs, int64_t cs, int esize, int align) {
+    return cs == 1 && (reinterpret_cast<uintptr_t>(p) % align) == 0 && ((rs * esize) % align) == 0;
+}
+
 int launch_product(const ProdArgs &a, int vk, bool aug, hipStream_t s) {
     if (a.ntiles == 0) return SELL_OK;
+    const int esize = vk == VK_F64F64 ? 8 : 4;
+    const int vpt = choose_vpt(vk, a.nb);
+    const int align = vpt * esize < 16 ? vpt * esize : 16;
+    bool fixed_ok = fixed_width(a.nb) && vec_ok(a.X, a.xrs, a.xcs, esize, align) &&
+                    vec_ok(a.Y, a.yrs, a.ycs, esize, align);
+    if (aug && (a.flags & SELL_SPMV_CHAIN)) fixed_ok = fixed_ok && vec_ok(a.Z, a.zrs, a.zcs, esize, align);
     switch (vk) {
-        case VK_F64F64: return prod_f64(a, aug, true, s);
-        case VK_F32F32: return prod_f32(a, aug, true, s);
-        case VK_BF16F32: return prod_bf16(a, aug, true, s);
+        case VK_F64F64: return prod_f64(a, aug, fixed_ok, s);
+        case VK_F32F32: return prod_f32(a, aug, fixed_ok, s);
+        case VK_BF16F32: return prod_bf16(a, aug, fixed_ok, s);
         default: return SELL_ERR_DTYPE;
     }
 }
@@ -176,6 +191,30 @@ int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
+// ---------------------------------------------------------------- dot partial sums
+
+// blockIdx.x = quantity q = g * nb + j, blockIdx.y = batch entry k.
+__global__ void __launch_bounds__(256) dot_finish_kernel(const double *partials, int32_t ntiles, int32_t nb,
+                                                         uint32_t flags, double *dot, int32_t dot_b,
+                                                         int64_t dot_stride) {
+    const int q = blockIdx.x, g = q / nb, j = q - g * nb;
+    const uint32_t want = g == 0 ? SELL_SPMV_DOT_YY : g == 1 ? SELL_SPMV_DOT_XY : SELL_SPMV_DOT_XX;
+    if (!(flags & want)) return;
+    const double *p = partials + (size_t(blockIdx.y) * 3 * nb + q) * size_t(ntiles);
+    double s = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += 256) s += p[t];
+    s = block_sum_256(s);
+    if (threadIdx.x == 0) dot[size_t(blockIdx.y) * dot_stride + size_t(g) * dot_b + j] = s;
+}
+
+int launch_dot_finish(const double *partials, int32_t ntiles, int32_t nb, uint32_t flags, double *dot,
+                      int32_t dot_b, int64_t batch, int64_t dot_stride, hipStream_t s) {
+    if (batch < 1 || ntiles < 1) return SELL_OK;
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(3 * nb, unsigned(batch)), dim3(256), 0, s, partials, ntiles, nb,
+                       flags, dot, dot_b, dot_stride);
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
 // ---------------------------------------------------------------- KPM moments
 // dots: M groups of 3b doubles [<y,y> | <x,y> | <x,x>] written by the M augmented products
 // of the recurrence; step 0 has x = v0, y = v1; step m >= 1 has x = v_m, y = v_{m+1}.
@@ -183,21 +222,29 @@ int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s
 // symmetric matrix mu_2m = 2 <v_m, v_m> - mu_0 and mu_2m+1 = 2 <v_m+1, v_m> - mu_1.
 __global__ void kpm_moments_kernel(const double *dots, int64_t M, int32_t b, double *mu) {
     const int64_t g = 3 * int64_t(b);
-    for (int j = threadIdx.x; j < b; j += blockDim.x) {
+    const int64_t total = (2 * M + 1) * int64_t(b);
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t k = e / b;
+        const int j = int(e - k * b);
         const double mu0 = dots[2 * b + j];  // <v0, v0>
         const double mu1 = dots[b + j];      // <v0, v1>
-        mu[0 * b + j] = mu0;
-        mu[1 * b + j] = mu1;
-        mu[2 * b + j] = 2.0 * dots[j] - mu0;  // 2 <v1, v1> - mu0
-        for (int64_t m = 1; m < M; ++m) {
-            mu[(2 * m + 1) * b + j] = 2.0 * dots[m * g + b + j] - mu1;  // 2 <v_m, v_m+1> - mu1
-            mu[(2 * m + 2) * b + j] = 2.0 * dots[m * g + j] - mu0;      // 2 <v_m+1, v_m+1> - mu0
-        }
+        double r;
+        if (k == 0)
+            r = mu0;
+        else if (k == 1)
+            r = mu1;
+        else if (k % 2 == 0)
+            r = 2.0 * dots[(k / 2 - 1) * g + j] - mu0;  // 2 <v_m, v_m> - mu0, m = k/2
+        else
+            r = 2.0 * dots[((k - 1) / 2) * g + b + j] - mu1;  // 2 <v_m, v_m+1> - mu1, m = (k-1)/2
+        mu[e] = r;
     }
 }
 
 int launch_kpm_moments(const double *dots, int64_t M, int32_t b, double *mu, hipStream_t s) {
-    hipLaunchKernelGGL(kpm_moments_kernel, dim3(1), dim3(256), 0, s, dots, M, b, mu);
+    const unsigned g = grid_for((2 * M + 1) * b, 256, 1024);
+    hipLaunchKernelGGL(kpm_moments_kernel, dim3(g), dim3(256), 0, s, dots, M, b, mu);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
