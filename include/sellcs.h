@@ -251,12 +251,13 @@ typedef struct {
 int sell_cg(const sell_mat *A, const sell_bv *B, sell_bv *X, double tol, int64_t maxit,
             sell_cg_stats *stats, void *stream);
 
-/* Mixed-precision CG with FP64 iterative refinement: the residual r = b - A x is formed
- * in FP64 with A64 (F64 matrix); the correction d solves Alo d = r approximately by FP32
- * CG with the F32 or BF16 matrix Alo (same pattern), to a relative residual reduction
- * inner_tol or inner_maxit iterations; x += d in FP64. Stops at the same criterion as
- * sell_cg (true FP64 residual <= tol) or after maxit inner iterations in total.
- * Synchronous. */
+/* Mixed-precision CG with FP64 iterative refinement by reliable updates: CG runs in FP32
+ * vectors on the F32 or BF16 matrix Alo (same pattern as A64) and accumulates its correction
+ * d in FP32. Whenever the FP32 residual has dropped by the factor inner_tol (0 < inner_tol < 1)
+ * since the last update, or after inner_maxit iterations, d is added to x in FP64 and the
+ * residual is replaced by the true r = b - A64 x computed in FP64 with the F64 matrix A64;
+ * the search direction is kept. Stops at the same criterion as sell_cg (true FP64 residual
+ * <= tol ||b|| per column) or after maxit iterations in total. Synchronous. */
 int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *B, sell_bv *X,
                   double tol, int64_t maxit, double inner_tol, int64_t inner_maxit,
                   sell_cg_stats *stats, void *stream);
@@ -265,10 +266,13 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *B, se
 /* Measurement helpers                                                                  */
 
 /* Streaming probes of achievable device bandwidth on caller-owned device buffers:
- *   kind 0: copy  dst[i] = src[i]                      (2 * bytes moved)
- *   kind 1: read  reduce src into dst[0..255]          (bytes moved)
- *   kind 2: write dst[i] = constant                    (bytes moved)
- * bytes must be a positive multiple of 16; both buffers 16-byte aligned. Asynchronous. */
+ *   kind 0: copy  dst[i] = src[i], nontemporal loads and stores   (2 * bytes moved)
+ *   kind 1: read  sum of src (nontemporal loads); dst must hold 1 KiB (bytes moved)
+ *   kind 2: write dst[i] = constant, nontemporal stores           (bytes moved)
+ *   kind 3: copy with ordinary loads and stores                    (2 * bytes moved)
+ *   kind 4: write with ordinary stores                             (bytes moved)
+ * bytes must be a positive multiple of 16; both buffers 16-byte aligned; src is not read
+ * by kinds 2 and 4 (may be NULL). Asynchronous. */
 int sell_probe_bandwidth(int kind, void *dst, const void *src, int64_t bytes, void *stream);
 
 #ifdef __cplusplus

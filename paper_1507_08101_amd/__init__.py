@@ -396,7 +396,7 @@ def sell_cg(A, B, X, tol=1e-10, maxit=100000, stream=None):
     return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
 
 
-def sell_cg_mixed(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=1e-4, inner_maxit=1000, stream=None):
+def sell_cg_mixed(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=0.1, inner_maxit=1000, stream=None):
     """CG with FP64 iterative refinement around an FP32-vector inner solve on Alo."""
     st = sell_cg_stats()
     b, x = _bv(B), _bv(X)

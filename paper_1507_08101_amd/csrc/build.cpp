@@ -66,7 +66,7 @@ void convert_values(const double *src, int64_t n, int vdt, void *dst) {
 }
 
 int32_t default_tile_count(int64_t nch) {
-    int64_t t = 1024;
+    int64_t t = kMaxTiles;
     if (const char *e = std::getenv("SELLCS_TILES")) {
         long v = std::strtol(e, nullptr, 10);
         if (v >= 1 && v <= kMaxTiles) t = v;

@@ -100,6 +100,10 @@ int get_workspace(hipStream_t s, Workspace **ws) {
     Workspace w;
     const size_t np = size_t(kMaxTiles) * 3 * kMaxSliceCols;
     HIPCHK(hipMalloc(&w.partials, np * sizeof(double)));
+    if (hipMalloc(&w.scratch, kScratchBytes) != hipSuccess) {
+        hipFree(w.partials);
+        return SELL_ERR_OOM;
+    }
     auto res = g_ws.emplace(key, w);
     *ws = &res.first->second;
     return SELL_OK;
@@ -185,11 +189,12 @@ namespace sellcs {
 
 // y = alpha (A x - gamma x) + beta y, dots, chain; no argument checks (callers check).
 int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o,
-             bool aug, hipStream_t s, double *partials_out) {
+             bool aug, hipStream_t s, double *partials_out, int32_t *nblocks_out) {
+    if (nblocks_out) *nblocks_out = 0;
     const int b = X->ncols;
     const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
     Workspace *ws = nullptr;
-    if (dots && !partials_out) {
+    {
         int rc = get_workspace(s, &ws);
         if (rc) return rc;
     }
@@ -216,6 +221,7 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
         bv_strides(Y, a.yrs, a.ycs);
         a.X = elem_ptr(X, 0, sl.first);
         a.Y = elem_ptr(Y, 0, sl.first);
+        a.scratch = ws->scratch;
         if (aug && (o.flags & SELL_SPMV_CHAIN)) {
             bv_strides(Z, a.zrs, a.zcs);
             a.Z = elem_ptr(Z, 0, sl.first);
@@ -235,8 +241,9 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
         }
         int rc = launch_product(a, vec_kind(A->h.vdt), aug, s);
         if (rc) return rc;
+        if (nblocks_out) *nblocks_out = a.nblocks;
         if (dots && !partials_out) {
-            rc = launch_dot_finish(ws->partials, a.ntiles, a.nb, o.flags, o.dot + sl.first, b, 1, 0, s);
+            rc = launch_dot_finish(ws->partials, a.nblocks, a.nb, o.flags, o.dot + sl.first, b, 1, 0, s);
             if (rc) return rc;
         }
     }
@@ -687,7 +694,8 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
     o.alpha = 1.0 / scale;
     o.gamma = c;
     if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[0], s);
-    if (rc == SELL_OK) rc = aug_impl(A, V, W, nullptr, o, true, s, parts);
+    int32_t nblk = 0;
+    if (rc == SELL_OK) rc = aug_impl(A, V, W, nullptr, o, true, s, parts, &nblk);
     if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[1], s);
     sell_bv *x = W, *y = V;  // x = v_m, y = v_{m-1} -> v_{m+1}
     o.flags = SELL_SPMV_SCALE | SELL_SPMV_SHIFT | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
@@ -698,8 +706,10 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
         if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[size_t(m) + 1], s);
         std::swap(x, y);
     }
-    if (rc == SELL_OK && A->h.nrows > 0 && nt > 0)
-        rc = launch_dot_finish(parts, nt, b, SELL_SPMV_DOTS, dots, b, M, 3 * b, s);
+    // every step used the same launch shape: nblk partials per quantity, 3 b quantities,
+    // packed at the start of each step's region of the buffer
+    if (rc == SELL_OK && A->h.nrows > 0 && nblk > 0)
+        rc = launch_dot_finish_strided(parts, nblk, b, SELL_SPMV_DOTS, dots, b, M, 3 * b, per_step, s);
     else if (rc == SELL_OK)
         rc = launch_fill(dots, SELL_F64, M, 3 * b, 3 * b, 1, 0.0, s);
     if (rc == SELL_OK) rc = launch_kpm_moments(dots, M, b, mu, s);
@@ -731,8 +741,8 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
 // ---------------------------------------------------------------- probes
 
 int sell_probe_bandwidth(int kind, void *dst, const void *src, int64_t bytes, void *stream) {
-    if (kind < 0 || kind > 2 || bytes <= 0 || bytes % 16 != 0 || !dst) return SELL_ERR_ARG;
-    if (kind != 2 && !src) return SELL_ERR_ARG;
+    if (kind < 0 || kind > 4 || bytes <= 0 || bytes % 16 != 0 || !dst) return SELL_ERR_ARG;
+    if (kind != 2 && kind != 4 && !src) return SELL_ERR_ARG;
     if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) return SELL_ERR_ARG;
     return launch_probe(kind, dst, src, bytes, static_cast<hipStream_t>(stream));
 }

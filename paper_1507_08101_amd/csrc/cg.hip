@@ -141,14 +141,14 @@ __global__ void __launch_bounds__(kVT) scale_to_f32_kernel(float *dst, const dou
     }
 }
 
-// x += scale_j * d
+// x += scale_j * d  (scale_j = 1 when scale is null)
 __global__ void __launch_bounds__(kVT) axpy_mixed_kernel(double *X, const float *D, int64_t n, int b, int64_t ld,
                                                          const double *scale) {
     const int64_t N = n * b;
     for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
         const int64_t i = e / b;
         const int j = int(e - i * b);
-        X[i * ld + j] += scale[j] * double(D[i * ld + j]);
+        X[i * ld + j] += (scale ? scale[j] : 1.0) * double(D[i * ld + j]);
     }
 }
 

@@ -88,7 +88,9 @@ struct ProdArgs {
     const int64_t *cs;
     const int32_t *perm;   // may be null (identity)
     const int32_t *tiles;
-    int32_t ntiles, C;
+    int32_t ntiles, C;     // fine work partitions of the matrix; chunk height
+    int32_t nblocks;       // workgroups of the launch (set by the launcher); workgroup g
+                           // owns fine tiles [g * ntiles / nblocks, (g + 1) * ntiles / nblocks)
     int32_t cshift;        // log2(C) when C is a power of two, else -1
     int64_t nrows;
     int32_t nb;            // columns in this slice
@@ -100,25 +102,29 @@ struct ProdArgs {
     int32_t has_gamma_v;   // per-column shifts below (else the scalar gamma_s)
     double gamma_s;        // scalar shift
     double gamma_v[kMaxSliceCols];
-    double *partials;      // dots: 3 * nb * ntiles doubles, partials[q * ntiles + tile],
-                           // q = g * nb + j for g = yy, xy, xx
+    void *scratch;         // kBlock * 16 bytes of write-only scratch for lanes without a row
+    double *partials;      // dots: 3 * nb * nblocks doubles, partials[q * nblocks + g],
+                           // q = group * nb + j for group = yy, xy, xx
 };
 
 enum VecKind { VK_F64F64 = 0, VK_F32F32 = 1, VK_BF16F32 = 2 };
 
-int launch_product(const ProdArgs &a, int vk, bool aug, hipStream_t s);
-int launch_transpose_atomic(const ProdArgs &a, int vk, hipStream_t s);
+int launch_product(ProdArgs &a, int vk, bool aug, hipStream_t s);
+int launch_transpose_atomic(ProdArgs &a, int vk, hipStream_t s);
 int launch_fill(void *p, int dt, int64_t nrows, int32_t ncols, int64_t rs, int64_t cs,
                 double value, hipStream_t s);
 int launch_copy(const sell_bv *dst, const sell_bv *src, hipStream_t s);
 int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s);
 int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s);
 int launch_kpm_moments(const double *dots, int64_t M, int32_t b, double *mu, hipStream_t s);
-// dot[g * dot_b + j] = sum_t partials[(g * nb + j) * ntiles + t] for the groups g requested
+// dot[g * dot_b + j] = sum_t partials[(g * nb + j) * nparts + t] for the groups g requested
 // in flags (yy, xy, xx), fixed summation order; batch > 1 handles consecutive partial
-// blocks (stride 3 * nb * ntiles) writing dot + k * dot_stride.
-int launch_dot_finish(const double *partials, int32_t ntiles, int32_t nb, uint32_t flags, double *dot,
+// blocks (stride 3 * nb * nparts, or part_stride) writing dot + k * dot_stride.
+int launch_dot_finish(const double *partials, int32_t nparts, int32_t nb, uint32_t flags, double *dot,
                       int32_t dot_b, int64_t batch, int64_t dot_stride, hipStream_t s);
+int launch_dot_finish_strided(const double *partials, int32_t nparts, int32_t nb, uint32_t flags, double *dot,
+                              int32_t dot_b, int64_t batch, int64_t dot_stride, int64_t part_stride,
+                              hipStream_t s);
 
 // CG building blocks (cg.hip): FP64 scalars live on the device.
 constexpr int kCgMaxGrid = 1024;  // workgroups of the reducing vector kernels
@@ -148,13 +154,19 @@ int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld
 // partials_out == nullptr: the dots are summed into o.dot right away (workspace partials and
 // a finishing kernel). Else the tile partials of the (single, b <= 64) slice are left in
 // partials_out (3 * b * ntiles doubles) for the caller to reduce, and o.dot is not used.
+// *nblocks_out (may be null) receives the number of partials per quantity (workgroups).
 int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
-             hipStream_t s, double *partials_out = nullptr);
+             hipStream_t s, double *partials_out = nullptr, int32_t *nblocks_out = nullptr);
+// Workgroups of one product launch: as many as the device holds at once (occupancy of the
+// kernel times the compute units), at most the number of fine tiles.
+int32_t resident_grid(const void *kernel, int threads, int32_t ntiles);
 
 // Per-(device, stream) workspace for reductions.
 struct Workspace {
     double *partials = nullptr;   // kMaxTiles * 3 * kMaxSliceCols doubles
+    void *scratch = nullptr;      // write-only scratch of the product kernels (kScratchBytes)
 };
+constexpr size_t kScratchBytes = size_t(kBlock) * 64;
 int get_workspace(hipStream_t s, Workspace **ws);
 
 }  // namespace sellcs

@@ -9,10 +9,13 @@
 // The host reads the per-column "active" flags every few iterations.
 //
 // sell_cg:        FP64 throughout; convergence is confirmed on the true residual b - A x.
-// sell_cg_mixed:  iterative refinement. The residual r = b - A x is formed in FP64 with the
-//                 FP64 matrix (one augmented product: y = b preloaded, alpha = -1, beta = 1,
-//                 fused <r, r>); the correction solves A d = r / ||r|| in FP32 vectors with
-//                 the FP32 or BF16 matrix; x += ||r|| d in FP64.
+// sell_cg_mixed:  FP64 iterative refinement by reliable updates. CG runs with FP32 vectors on
+//                 the FP32 or BF16 matrix and accumulates its correction d in FP32; whenever
+//                 the FP32 residual has dropped by inner_tol (or after inner_maxit steps) the
+//                 correction is folded into x in FP64 and the residual is replaced by the
+//                 true r = b - A x, formed in FP64 with the FP64 matrix (one augmented product:
+//                 y = b preloaded, alpha = -1, beta = 1, fused <r, r>). The search direction is
+//                 kept across updates, so the Krylov space is not restarted.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -112,8 +115,9 @@ int cg_iterate(const sell_mat *A, int dt, sell_bv &X, sell_bv &R, sell_bv &P, se
     bool any = true;
     if ((rc = any_active(S, b, s, &any))) return rc;
     while (any && *its < maxit) {
-        if ((rc = aug_impl(A, &P, &Q, nullptr, o, true, s, S.prod_parts))) return rc;
-        if ((rc = cg_launch_alpha(S.prod_parts, A->ntiles, b, S.dev(), s))) return rc;
+        int32_t nblk = 0;
+        if ((rc = aug_impl(A, &P, &Q, nullptr, o, true, s, S.prod_parts, &nblk))) return rc;
+        if ((rc = cg_launch_alpha(S.prod_parts, nblk, b, S.dev(), s))) return rc;
         if ((rc = cg_launch_xr(dt, X.ptr, R.ptr, P.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
         if ((rc = cg_launch_p(dt, P.ptr, R.ptr, n, b, b, S.beta, s))) return rc;
         ++*its;
@@ -222,7 +226,7 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
     if (A64->h.vdt != SELL_F64 || Alo->h.vdt == SELL_F64) return SELL_ERR_DTYPE;
     if (Alo->h.nrows != A64->h.nrows || Alo->h.ncols != A64->h.ncols || Alo->h.nnz != A64->h.nnz)
         return SELL_ERR_SHAPE;
-    if (!(tol > 0) || !(inner_tol > 0) || maxit < 0 || inner_maxit < 1) return SELL_ERR_ARG;
+    if (!(tol > 0) || !(inner_tol > 0) || !(inner_tol < 1) || maxit < 0 || inner_maxit < 1) return SELL_ERR_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = A64->h.nrows;
     const int b = Bv->ncols;
@@ -243,34 +247,80 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
     sell_bv R64 = view(pr64, n, b, SELL_F64);
     sell_bv R = view(pr, n, b, SELL_F32), D = view(pd, n, b, SELL_F32), P = view(pp, n, b, SELL_F32),
             Q = view(pq, n, b, SELL_F32);
-    if ((rc = cg_launch_coldot(SELL_F64, Bv->ptr, Bv->ptr, n, b, b, S.bb, S.vec_parts, S.thresh_out,
-                               S.active, nullptr, tol * tol, s)))
+    // ||b||^2 (into S.bb)
+    if ((rc = cg_launch_coldot(SELL_F64, Bv->ptr, Bv->ptr, n, b, b, S.bb, S.vec_parts, nullptr, nullptr, nullptr,
+                               0.0, s)))
         return rc;
-    double worst = 0.0;
-    while (true) {
-        if ((rc = true_residual(A64, Bv, X, R64, S, s))) return rc;
-        if ((rc = relres_host(S, b, s, &worst))) return rc;
-        if (worst <= tol || st.iterations >= maxit) break;
-        // r^ = r / ||r|| for columns still above tol (others get 0 and stay put)
-        if ((rc = cg_launch_scale_to_f32(static_cast<float *>(R.ptr), static_cast<const double *>(R64.ptr), n, b, b,
-                                         S.rr, S.thresh_out, S.scale, s)))
-            return rc;
-        if ((rc = launch_fill(D.ptr, SELL_F32, n, b, b, 1, 0.0, s))) return rc;
-        if ((rc = cg_launch_coldot(SELL_F32, R.ptr, R.ptr, n, b, b, S.rho, S.vec_parts, S.thresh2,
-                                   S.active, nullptr, inner_tol * inner_tol, s)))
-            return rc;
-        int64_t its = 0;
-        const int64_t cap = std::min<int64_t>(inner_maxit, maxit - st.iterations);
-        if ((rc = cg_iterate(Alo, SELL_F32, D, R, P, Q, S, cap, &its, s))) return rc;
-        st.iterations += its;
-        if ((rc = cg_launch_axpy_mixed(static_cast<double *>(X->ptr), static_cast<const float *>(D.ptr), n, b, b,
-                                       S.scale, s)))
-            return rc;
-        ++st.refinements;
-        if (its == 0) break;
+    double bb[64], rr[64], rho[64], rho_last[64];
+    int32_t act[64];
+    HIPCHK(hipMemcpyAsync(bb, S.bb, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+
+    // Reliable update: fold the FP32 correction into x (FP64), recompute the true residual
+    // r = b - A x in FP64, restart the FP32 recursion from it (the search direction is
+    // kept). Returns through *done whether every column meets the tolerance.
+    auto reliable_update = [&](bool fold, bool *done) -> int {
+        int r;
+        if (fold && (r = cg_launch_axpy_mixed(static_cast<double *>(X->ptr), static_cast<const float *>(D.ptr), n,
+                                              b, b, nullptr, s)))
+            return r;
+        if ((r = true_residual(A64, Bv, X, R64, S, s))) return r;
+        HIPCHK(hipMemcpyAsync(rr, S.rr, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double worst = 0.0;
+        bool all = true;
+        for (int j = 0; j < b; ++j) {
+            const double rel = bb[j] > 0 ? std::sqrt(rr[j] / bb[j]) : std::sqrt(rr[j]);
+            if (!(rel <= worst)) worst = rel;
+            act[j] = rel <= tol ? 0 : 1;
+            all = all && !act[j];
+        }
+        st.relres = worst;
+        *done = all;
+        if (all) return SELL_OK;
+        if ((r = launch_copy(&R, &R64, s))) return r;  // FP64 -> FP32, round to nearest
+        if ((r = launch_fill(D.ptr, SELL_F32, n, b, b, 1, 0.0, s))) return r;
+        // rho = <r32, r32>; thresh2 = 0 so the FP32 recursion never retires a column itself
+        if ((r = cg_launch_coldot(SELL_F32, R.ptr, R.ptr, n, b, b, S.rho, S.vec_parts, S.thresh2, S.active, nullptr,
+                                  0.0, s)))
+            return r;
+        HIPCHK(hipMemcpyAsync(S.active, act, sizeof(int32_t) * b, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(rho_last, S.rho, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return SELL_OK;
+    };
+
+    bool done = false;
+    if ((rc = reliable_update(false, &done))) return rc;
+    if (!done && (rc = launch_copy(&P, &R, s))) return rc;
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    o.flags = SELL_SPMV_DOT_XY;
+    int64_t since = 0;
+    while (!done && st.iterations < maxit) {
+        int32_t nblk = 0;
+        if ((rc = aug_impl(Alo, &P, &Q, nullptr, o, true, s, S.prod_parts, &nblk))) return rc;
+        if ((rc = cg_launch_alpha(S.prod_parts, nblk, b, S.dev(), s))) return rc;
+        if ((rc = cg_launch_xr(SELL_F32, D.ptr, R.ptr, P.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
+        if ((rc = cg_launch_p(SELL_F32, P.ptr, R.ptr, n, b, b, S.beta, s))) return rc;
+        ++st.iterations;
+        ++since;
+        if (st.iterations % kCheckEvery == 0 || st.iterations == maxit) {
+            HIPCHK(hipMemcpyAsync(rho, S.rho, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            bool update = st.iterations == maxit || since >= inner_maxit;
+            for (int j = 0; j < b; ++j)
+                if (act[j] && (!(rho[j] > inner_tol * inner_tol * rho_last[j]))) update = true;  // NaN too
+            if (update) {
+                if ((rc = reliable_update(true, &done))) return rc;
+                ++st.refinements;
+                since = 0;
+            }
+        }
     }
-    st.relres = worst;
-    st.converged = worst <= tol ? 1 : 0;
+    if (!done && st.iterations > 0 && since > 0) {
+        if ((rc = reliable_update(true, &done))) return rc;
+        ++st.refinements;
+    }
+    st.converged = done ? 1 : 0;
     if (stats) *stats = st;
     return SELL_OK;
 }

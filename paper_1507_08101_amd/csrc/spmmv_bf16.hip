@@ -3,10 +3,10 @@
 
 namespace sellcs {
 
-int prod_bf16(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
+int prod_bf16(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
     return aug ? dispatch_prod<VK_BF16F32, true>(a, s, fixed_ok) : dispatch_prod<VK_BF16F32, false>(a, s, fixed_ok);
 }
 
-int transpose_bf16(const ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_BF16F32>(a, s); }
+int transpose_bf16(ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_BF16F32>(a, s); }
 
 }  // namespace sellcs

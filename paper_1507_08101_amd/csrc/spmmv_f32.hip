@@ -3,10 +3,10 @@
 
 namespace sellcs {
 
-int prod_f32(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
+int prod_f32(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
     return aug ? dispatch_prod<VK_F32F32, true>(a, s, fixed_ok) : dispatch_prod<VK_F32F32, false>(a, s, fixed_ok);
 }
 
-int transpose_f32(const ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_F32F32>(a, s); }
+int transpose_f32(ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_F32F32>(a, s); }
 
 }  // namespace sellcs

@@ -3,10 +3,10 @@
 
 namespace sellcs {
 
-int prod_f64(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
+int prod_f64(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
     return aug ? dispatch_prod<VK_F64F64, true>(a, s, fixed_ok) : dispatch_prod<VK_F64F64, false>(a, s, fixed_ok);
 }
 
-int transpose_f64(const ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_F64F64>(a, s); }
+int transpose_f64(ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_F64F64>(a, s); }
 
 }  // namespace sellcs

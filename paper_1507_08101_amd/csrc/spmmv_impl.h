@@ -136,10 +136,11 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // this workgroup's index in the partials
     const int C = a.C;
-    const int64_t s_begin = int64_t(a.tiles[tile]) * C;
-    const int64_t s_end = int64_t(a.tiles[tile + 1]) * C;
+    const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
+    const int64_t s_begin = int64_t(a.tiles[t0]) * C;
+    const int64_t s_end = int64_t(a.tiles[t1]) * C;
     const int tid = threadIdx.x;
     const int vg = tid & (VL - 1);
     const int rows_per_pass = kBlock >> vls;
@@ -189,6 +190,10 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     int cl_n = 0, pv_n = 0;
     int64_t cs_n = 0;
     if (s_begin < s_end) load_meta(s, cl_n, cs_n, pv_n);
+    // Settle the first pass's metadata here, so that at the loop head only the previous
+    // pass's stores are outstanding and the metadata loads of the following pass are not
+    // held up behind them.
+    __builtin_amdgcn_s_waitcnt(0);
     for (; s < s_end; s += rows_per_pass) {
         const int64_t c = a.cshift >= 0 ? (s >> a.cshift) : int64_t(uint32_t(s) / uint32_t(C));
         const int len = cl_n;
@@ -196,15 +201,20 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         const int64_t row = s < a.nrows ? (a.perm ? int64_t(pv_n) : s) : -1;
         load_meta(s + rows_per_pass, cl_n, cs_n, pv_n);  // one pass ahead
         const bool live = row >= 0 && col_ok;
+        // Lanes without an output row (slots past the last row, or unused columns of the
+        // generic kernel) read row 0 / column 0 and store into the scratch area, so no load
+        // or store of a pass sits under a divergent branch.
+        const int64_t rowc = live ? row : 0;
+        const int jl = col_ok ? jb : 0;
 
         // epilogue operands, issued before the gathers so their latency overlaps
         X xin[VPT], yin[VPT], zin[VPT];
 #pragma unroll
         for (int t = 0; t < VPT; ++t) xin[t] = yin[t] = zin[t] = X(0);
-        if (AUG && live) {
-            if (need_x) load_row<X, VPT, VEC>(Xp + row * xrs + int64_t(jb) * xcs, xcs, xin);
-            if (read_y) load_row<X, VPT, VEC>(Yp + row * yrs + int64_t(jb) * ycs, ycs, yin);
-            if (read_z) load_row<X, VPT, VEC>(Zp + row * zrs + int64_t(jb) * zcs, zcs, zin);
+        if (AUG) {
+            if (need_x) load_row<X, VPT, VEC>(Xp + rowc * xrs + int64_t(jl) * xcs, xcs, xin);
+            if (read_y) load_row<X, VPT, VEC>(Yp + rowc * yrs + int64_t(jl) * ycs, ycs, yin);
+            if (read_z) load_row<X, VPT, VEC>(Zp + rowc * zrs + int64_t(jl) * zcs, zcs, zin);
         }
 
         Acc acc[VPT];
@@ -242,34 +252,38 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
             }
         }
 
-        if (live) {
-            X out[VPT];
-            if (!AUG) {
+        X *scratch = static_cast<X *>(a.scratch) + size_t(tid) * VPT;
+        X *ydst = live ? Yp + row * yrs + int64_t(jb) * ycs : scratch;
+        const int64_t ysd = live ? ycs : 1;
+        X out[VPT];
+        if (!AUG) {
 #pragma unroll
-                for (int t = 0; t < VPT; ++t) out[t] = X(acc[t]);
-                store_row<X, VPT, VEC>(Yp + row * yrs + int64_t(jb) * ycs, ycs, out);
-            } else {
-                X zout[VPT];
+            for (int t = 0; t < VPT; ++t) out[t] = X(acc[t]);
+            store_row<X, VPT, VEC>(ydst, ysd, out);
+        } else {
+            X zout[VPT];
 #pragma unroll
-                for (int t = 0; t < VPT; ++t) {
-                    const double xv = double(xin[t]);
-                    double tv = double(acc[t]);
-                    if (shift) tv = tv - gam[t] * xv;
-                    double y = alpha * tv;
-                    if (read_y) y = y + a.beta * double(yin[t]);
-                    out[t] = X(y);
-                    const double yd = double(out[t]);
-                    if (want_dots) {
-                        dyy[t] += yd * yd;
-                        dxy[t] += xv * yd;
-                        dxx[t] += xv * xv;
-                    }
-                    double z = a.eta * yd;
-                    if (read_z) z = a.delta * double(zin[t]) + z;
-                    zout[t] = X(z);
+            for (int t = 0; t < VPT; ++t) {
+                const double xv = double(xin[t]);
+                double tv = double(acc[t]);
+                if (shift) tv = tv - gam[t] * xv;
+                double y = alpha * tv;
+                if (read_y) y = y + a.beta * double(yin[t]);
+                out[t] = X(y);
+                const double yd = double(out[t]);
+                if (want_dots && live) {
+                    dyy[t] += yd * yd;
+                    dxy[t] += xv * yd;
+                    dxx[t] += xv * xv;
                 }
-                store_row<X, VPT, VEC>(Yp + row * yrs + int64_t(jb) * ycs, ycs, out);
-                if (chain) store_row<X, VPT, VEC>(Zp + row * zrs + int64_t(jb) * zcs, zcs, zout);
+                double z = a.eta * yd;
+                if (read_z) z = a.delta * double(zin[t]) + z;
+                zout[t] = X(z);
+            }
+            store_row<X, VPT, VEC>(ydst, ysd, out);
+            if (chain) {
+                X *zdst = live ? Zp + row * zrs + int64_t(jb) * zcs : scratch;
+                store_row<X, VPT, VEC>(zdst, live ? zcs : 1, zout);
             }
         }
     }
@@ -303,7 +317,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         double sum = 0.0;
 #pragma unroll
         for (int ww = 0; ww < kBlock / 64; ++ww) sum += red[ww][q];
-        a.partials[size_t(q) * a.ntiles + tile] = sum;
+        a.partials[size_t(q) * a.nblocks + tile] = sum;
     }
 }
 
@@ -319,8 +333,9 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(ProdArgs a, int vl_lo
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int C = a.C;
-    const int64_t s_begin = int64_t(a.tiles[tile]) * C;
-    const int64_t s_end = int64_t(a.tiles[tile + 1]) * C;
+    const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
+    const int64_t s_begin = int64_t(a.tiles[t0]) * C;
+    const int64_t s_end = int64_t(a.tiles[t1]) * C;
     const int tid = threadIdx.x;
     const int vg = tid & (VL - 1);
     const int jb = vg * VPT;
@@ -350,22 +365,26 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(ProdArgs a, int vl_lo
 }
 
 template <int VK, int B, int VPT, bool AUG>
-inline int go_prod(const ProdArgs &a, hipStream_t s) {
+inline int go_prod(ProdArgs &a, hipStream_t s) {
     int vl_log2 = 0;
     if (B == 0) {
         while ((1 << vl_log2) < a.nb) ++vl_log2;
     }
-    hipLaunchKernelGGL((prod_kernel<VK, B, VPT, AUG>), dim3(a.ntiles), dim3(kBlock), 0, s, a, vl_log2);
+    auto k = prod_kernel<VK, B, VPT, AUG>;
+    a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles);
+    hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
 template <int VK, int B, int VPT>
-inline int go_transpose(const ProdArgs &a, hipStream_t s) {
+inline int go_transpose(ProdArgs &a, hipStream_t s) {
     int vl_log2 = 0;
     if (B == 0) {
         while ((1 << vl_log2) < a.nb) ++vl_log2;
     }
-    hipLaunchKernelGGL((transpose_kernel<VK, B, VPT>), dim3(a.ntiles), dim3(kBlock), 0, s, a, vl_log2);
+    auto k = transpose_kernel<VK, B, VPT>;
+    a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles);
+    hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
@@ -373,7 +392,7 @@ inline int go_transpose(const ProdArgs &a, hipStream_t s) {
 int choose_vpt(int vk, int b);
 
 template <int VK, bool AUG>
-int dispatch_prod(const ProdArgs &a, hipStream_t s, bool fixed_ok) {
+int dispatch_prod(ProdArgs &a, hipStream_t s, bool fixed_ok) {
     const int b = a.nb;
     const int vpt = choose_vpt(VK, b);
     if (fixed_ok) {
@@ -399,7 +418,7 @@ int dispatch_prod(const ProdArgs &a, hipStream_t s, bool fixed_ok) {
 }
 
 template <int VK>
-int dispatch_transpose(const ProdArgs &a, hipStream_t s) {
+int dispatch_transpose(ProdArgs &a, hipStream_t s) {
     switch (a.nb) {
         case 1: return go_transpose<VK, 1, 1>(a, s);
         case 2: return go_transpose<VK, 2, 2>(a, s);

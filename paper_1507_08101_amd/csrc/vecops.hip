@@ -1,6 +1,8 @@
 // vecops.hip -- block-vector kernels (fill, layout/type copy), value updates, KPM moment
 // assembly, bandwidth probes, and the launch front-ends of the product kernels.
 #include <cstdlib>
+#include <map>
+#include <utility>
 
 #include "convert.h"
 #include "devutil.h"
@@ -8,23 +10,49 @@
 
 namespace sellcs {
 
-int prod_f64(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
-int prod_f32(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
-int prod_bf16(const ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
-int transpose_f64(const ProdArgs &a, hipStream_t s);
-int transpose_f32(const ProdArgs &a, hipStream_t s);
-int transpose_bf16(const ProdArgs &a, hipStream_t s);
+int prod_f64(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
+int prod_f32(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
+int prod_bf16(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s);
+int transpose_f64(ProdArgs &a, hipStream_t s);
+int transpose_f32(ProdArgs &a, hipStream_t s);
+int transpose_bf16(ProdArgs &a, hipStream_t s);
 
-// Columns per lane of the fixed-width kernels: 16 bytes of a row per lane for FP32
-// vectors; two doubles for FP64 (keeps a batch of 8 gathered row pieces in 32 VGPRs).
-// SELLCS_VPT overrides the choice (1, 2 or 4) for tuning experiments.
+// Columns per lane of the fixed-width kernels: up to four (16 bytes of a row per lane for
+// FP32 vectors, two 16-byte pieces for FP64; measured fastest for FP64 at b = 8 on the
+// 128^3 Anderson workload). SELLCS_VPT overrides the choice (1, 2 or 4) for tuning.
 int choose_vpt(int vk, int b) {
-    int v = vk == VK_F64F64 ? (b >= 2 ? 2 : 1) : (b >= 4 ? 4 : b);
+    int v = b >= 4 ? 4 : b;
     if (const char *e = std::getenv("SELLCS_VPT")) {
         int x = std::atoi(e);
         if ((x == 1 || x == 2 || x == 4) && x <= b) v = x;
     }
     return v;
+}
+
+int32_t resident_grid(const void *kernel, int threads, int32_t ntiles) {
+    if (ntiles <= 0) return 0;
+    static thread_local std::map<std::pair<int, const void *>, int32_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    auto key = std::make_pair(dev, kernel);
+    auto it = cache.find(key);
+    int32_t full;
+    if (it != cache.end()) {
+        full = it->second;
+    } else {
+        int per_cu = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        if (const char *e = std::getenv("SELLCS_BLOCKS_PER_CU")) {
+            const int v = std::atoi(e);
+            if (v >= 1 && v <= 64) per_cu = v;
+        }
+        full = int32_t(per_cu) * ncu;
+        cache.emplace(key, full);
+    }
+    return full < ntiles ? full : ntiles;
 }
 
 static bool fixed_width(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32; }
@@ -33,7 +61,7 @@ static bool vec_ok(const void *p, int64_t rs, int64_t cs, int esize, int align) 
     return cs == 1 && (reinterpret_cast<uintptr_t>(p) % align) == 0 && ((rs * esize) % align) == 0;
 }
 
-int launch_product(const ProdArgs &a, int vk, bool aug, hipStream_t s) {
+int launch_product(ProdArgs &a, int vk, bool aug, hipStream_t s) {
     if (a.ntiles == 0) return SELL_OK;
     const int esize = vk == VK_F64F64 ? 8 : 4;
     const int vpt = choose_vpt(vk, a.nb);
@@ -49,7 +77,7 @@ int launch_product(const ProdArgs &a, int vk, bool aug, hipStream_t s) {
     }
 }
 
-int launch_transpose_atomic(const ProdArgs &a, int vk, hipStream_t s) {
+int launch_transpose_atomic(ProdArgs &a, int vk, hipStream_t s) {
     if (a.ntiles == 0) return SELL_OK;
     switch (vk) {
         case VK_F64F64: return transpose_f64(a, s);
@@ -193,25 +221,33 @@ int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s
 
 // ---------------------------------------------------------------- dot partial sums
 
-// blockIdx.x = quantity q = g * nb + j, blockIdx.y = batch entry k.
-__global__ void __launch_bounds__(256) dot_finish_kernel(const double *partials, int32_t ntiles, int32_t nb,
+// blockIdx.x = quantity q = g * nb + j, blockIdx.y = batch entry k (its partials start at
+// partials + k * part_stride).
+__global__ void __launch_bounds__(256) dot_finish_kernel(const double *partials, int32_t nparts, int32_t nb,
                                                          uint32_t flags, double *dot, int32_t dot_b,
-                                                         int64_t dot_stride) {
+                                                         int64_t dot_stride, int64_t part_stride) {
     const int q = blockIdx.x, g = q / nb, j = q - g * nb;
     const uint32_t want = g == 0 ? SELL_SPMV_DOT_YY : g == 1 ? SELL_SPMV_DOT_XY : SELL_SPMV_DOT_XX;
     if (!(flags & want)) return;
-    const double *p = partials + (size_t(blockIdx.y) * 3 * nb + q) * size_t(ntiles);
+    const double *p = partials + size_t(blockIdx.y) * size_t(part_stride) + size_t(q) * size_t(nparts);
     double s = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 256) s += p[t];
+    for (int t = threadIdx.x; t < nparts; t += 256) s += p[t];
     s = block_sum_256(s);
     if (threadIdx.x == 0) dot[size_t(blockIdx.y) * dot_stride + size_t(g) * dot_b + j] = s;
 }
 
-int launch_dot_finish(const double *partials, int32_t ntiles, int32_t nb, uint32_t flags, double *dot,
+int launch_dot_finish(const double *partials, int32_t nparts, int32_t nb, uint32_t flags, double *dot,
                       int32_t dot_b, int64_t batch, int64_t dot_stride, hipStream_t s) {
-    if (batch < 1 || ntiles < 1) return SELL_OK;
-    hipLaunchKernelGGL(dot_finish_kernel, dim3(3 * nb, unsigned(batch)), dim3(256), 0, s, partials, ntiles, nb,
-                       flags, dot, dot_b, dot_stride);
+    return launch_dot_finish_strided(partials, nparts, nb, flags, dot, dot_b, batch, dot_stride,
+                                     int64_t(3) * nb * nparts, s);
+}
+
+int launch_dot_finish_strided(const double *partials, int32_t nparts, int32_t nb, uint32_t flags, double *dot,
+                              int32_t dot_b, int64_t batch, int64_t dot_stride, int64_t part_stride,
+                              hipStream_t s) {
+    if (batch < 1 || nparts < 1) return SELL_OK;
+    hipLaunchKernelGGL(dot_finish_kernel, dim3(3 * nb, unsigned(batch)), dim3(256), 0, s, partials, nparts, nb,
+                       flags, dot, dot_b, dot_stride, part_stride);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
@@ -289,17 +325,38 @@ __global__ void __launch_bounds__(256) probe_write(f4 *__restrict__ d, int64_t n
         __builtin_nontemporal_store(v, d + i);
 }
 
+// The same copy and write with ordinary (cached) loads and stores.
+__global__ void __launch_bounds__(256) probe_copy_plain(f4 *__restrict__ d, const f4 *__restrict__ s, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const f4 a = s[i], b = s[i + stride], c = s[i + 2 * stride], e = s[i + 3 * stride];
+        d[i] = a;
+        d[i + stride] = b;
+        d[i + 2 * stride] = c;
+        d[i + 3 * stride] = e;
+    }
+    for (; i < n; i += stride) d[i] = s[i];
+}
+
+__global__ void __launch_bounds__(256) probe_write_plain(f4 *__restrict__ d, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const f4 v = {1.f, 2.f, 3.f, 4.f};
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = v;
+}
+
 int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s) {
     const int64_t n = bytes / 16;
     const unsigned g = 256 * 16;
-    if (kind == 0)
-        hipLaunchKernelGGL(probe_copy, dim3(g), dim3(256), 0, s, static_cast<f4 *>(dst),
-                           static_cast<const f4 *>(src), n);
-    else if (kind == 1)
-        hipLaunchKernelGGL(probe_read, dim3(g), dim3(256), 0, s, static_cast<float *>(dst),
-                           static_cast<const f4 *>(src), n);
-    else
-        hipLaunchKernelGGL(probe_write, dim3(g), dim3(256), 0, s, static_cast<f4 *>(dst), n);
+    f4 *d = static_cast<f4 *>(dst);
+    const f4 *sp = static_cast<const f4 *>(src);
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(probe_copy, dim3(g), dim3(256), 0, s, d, sp, n); break;
+        case 1: hipLaunchKernelGGL(probe_read, dim3(g), dim3(256), 0, s, static_cast<float *>(dst), sp, n); break;
+        case 2: hipLaunchKernelGGL(probe_write, dim3(g), dim3(256), 0, s, d, n); break;
+        case 3: hipLaunchKernelGGL(probe_copy_plain, dim3(g), dim3(256), 0, s, d, sp, n); break;
+        default: hipLaunchKernelGGL(probe_write_plain, dim3(g), dim3(256), 0, s, d, n); break;
+    }
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
