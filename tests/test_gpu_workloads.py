@@ -1,0 +1,106 @@
+"""GPU parity on the full-size synthetic workloads: the 64 x 64 Laplacian with the scalars of
+its workload definition, and the 4M-row irregular matrix (lognormal row lengths) at several
+sorting windows, value types and block widths, checked row by row on samples and through
+properties that hold at any size (dots against exactly rounded sums of the GPU's output)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import abs_product, colwise_relerr, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+
+    import paper_1507_08101_amd as sc
+
+    assert torch.cuda.is_available()
+    sc.lib()
+    return sc
+
+
+@pytest.mark.parametrize("C", [32, 64])
+def test_laplacian64_workload(sc, C):
+    """n = 4096, 20,224 nonzeros (4 / -1), x ~ U[-1,1]; y = A x, then
+    y = 0.5 (A - 0.1 I) x + 1 * y with fused <x,y> and <y,y>."""
+    import torch
+
+    A = synth.laplacian2d(64)
+    assert A.nnz == 20224
+    x = synth.block_vector(A.nrows, 1, synth.SEED_X)
+    y0 = synth.block_vector(A.nrows, 1, synth.SEED_Y)
+    M = sc.SellMatrix.from_csr(A, C=C, sigma=1)
+    xd, yd = dev(x), torch.zeros((A.nrows, 1), dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv(M, xd, yd)
+    assert colwise_relerr(host(yd), oracle.spmmv(A, x), abs_product(A, x)) <= 1e-12
+    yd = dev(y0)
+    dot = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, xd, yd, flags=sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_XY | sc.DOT_YY, alpha=0.5,
+                      gamma=0.1, beta=1.0, dot=dot)
+    ref, _, rd = oracle.spmmv_aug(A, x, Y=y0, flags=oracle.SCALE | oracle.SHIFT | oracle.AXPBY | oracle.DOT_XY
+                                  | oracle.DOT_YY, alpha=0.5, gamma=0.1, beta=1.0)
+    scale = 0.5 * (abs_product(A, x) + 0.1 * np.abs(x)) + np.abs(y0)
+    assert colwise_relerr(host(yd), ref, scale) <= 1e-12
+    d = host(dot)
+    assert abs(d[0] - rd[0]) <= 1e-12 * rd[0]
+    assert abs(d[1] - rd[1]) <= 1e-12 * float(np.sum(np.abs(x * ref)))
+    M.close()
+
+
+_IRR = {}
+
+
+def _irregular():
+    if "A" not in _IRR:
+        _IRR["A"] = synth.irregular(4_000_000)
+    return _IRR["A"]
+
+
+def _check_sampled(A, X, Y, rows, vals, tol):
+    for i in rows:
+        p0, p1 = A.rowptr[i], A.rowptr[i + 1]
+        cols = A.col[p0:p1]
+        ref = vals[p0:p1] @ X[cols]
+        scale = np.abs(vals[p0:p1]) @ np.abs(X[cols])
+        assert np.all(np.abs(Y[i] - ref) <= tol * (scale + 1e-300)), i
+
+
+@pytest.mark.parametrize("sigma,b,dt", [(1, 1, "f64"), (32, 8, "f64"), (1024, 8, "f64"), (10 ** 9, 32, "f64"),
+                                        (1024, 8, "bf16"), (10 ** 9, 4, "f32")])
+def test_irregular_4M_sampled_rows(sc, sigma, b, dt):
+    import torch
+
+    A = _irregular()
+    lens = A.row_lengths()
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=sigma, dtype=dt)
+    info = M.info
+    assert info["nnz"] == A.nnz and info["stored"] >= A.nnz
+    vt = torch.float64 if dt == "f64" else torch.float32
+    X = synth.block_vector(A.ncols, b, synth.SEED_X)
+    if dt != "f64":
+        X = X.astype(np.float32).astype(np.float64)
+    Yd = torch.zeros((A.nrows, b), dtype=vt, device="cuda:0")
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, dev(X, vt), Yd, flags=sc.DOT_YY, dot=dot)
+    Y = host(Yd)
+    rows = np.unique(np.concatenate([synth.randint(78, 3000, 0, A.nrows - 1), [0, A.nrows - 1],
+                                     np.argsort(-lens)[:20]]))  # includes the longest rows
+    if dt == "f64":
+        _check_sampled(A, X, Y, rows, A.val, 1e-12)
+    else:
+        vals = oracle.round_f32(A.val) if dt == "f32" else oracle.round_bf16(A.val)
+        # FP32 accumulation: |err| <= gamma_k |A||x| with k = row length + 1
+        k = int(lens[rows].max()) + 1
+        u = 2.0 ** -24
+        _check_sampled(A, X, Y, rows, vals, k * u / (1 - k * u))
+    d = host(dot)
+    for j in range(min(b, 4)):
+        ref = math.fsum((Y[:, j] * Y[:, j]).tolist())
+        assert abs(d[j] - ref) <= 1e-12 * ref
+    M.close()
