@@ -135,6 +135,82 @@ def cg_compare(sc, torch, synth, edge, nrhs=8, tol=1e-10):
     return out
 
 
+def time_launches(torch, fn, reps=20, warm=3):
+    """Mean and best duration (us) of fn() with HIP events on the current stream."""
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    return float(np.mean(ts)), float(np.min(ts))
+
+
+def other_rows(sc, torch, model, A, Mh, b, s):
+    """The path's other operations on the same matrix: low-precision-value products, the
+    transposed product, the values-only update and the build, each timed with HIP events."""
+    out = {}
+    n = A.nrows
+    info = Mh.info
+    X32 = torch.rand((n, b), dtype=torch.float32, device="cuda") * 2 - 1
+    Y32 = torch.rand((n, b), dtype=torch.float32, device="cuda") * 2 - 1
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda")
+    flags = sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_YY | sc.DOT_XY
+    for dt, vb in (("bf16", 2), ("f32", 4)):
+        Ml = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=dt)
+        mean, best = time_launches(torch, lambda: sc.sell_spmmv_aug(Ml, X32, Y32, flags=flags, alpha=2.0 / s,
+                                                                     beta=-1.0, dot=dot))
+        by = model.bytes_min(A.nnz, n, n, b, vb, 4, read_y=True, nchunks=info["nchunks"])
+        out[f"aug_{dt}_values_f32_vectors"] = {"us": round(mean, 2), "GB/s": round(by / (mean * 1e-6) / 1e9, 1),
+                                               "GFLOP/s": round(model.flops(A.nnz, b) / (mean * 1e-6) / 1e9, 1),
+                                               "bytes": by}
+        Ml.close()
+    X64 = torch.rand((n, b), dtype=torch.float64, device="cuda")
+    Y64 = torch.empty_like(X64)
+    by = model.bytes_min(A.nnz, n, n, b, 8, 8, nchunks=info["nchunks"])
+    for det in (False, True):
+        mean, best = time_launches(torch, lambda: sc.sell_spmmv_T(Mh, X64, Y64, deterministic=det))
+        out["transpose_" + ("deterministic" if det else "atomic")] = {
+            "us": round(mean, 2), "GB/s": round(by / (mean * 1e-6) / 1e9, 1)}
+    x1 = X64[:, :1].contiguous()
+    y1 = torch.empty_like(x1)
+    mean, _ = time_launches(torch, lambda: sc.sell_spmmv(Mh, x1, y1))
+    spmv_us = mean
+    newv = torch.from_numpy(A.val).cuda()
+    upd, _ = time_launches(torch, lambda: Mh.update_values(newv))
+    out["update_values_device"] = {"us": round(upd, 2), "spmv_equivalents": round(upd / spmv_us, 2)}
+    out["plain_spmv_b1_us"] = round(spmv_us, 2)
+    return out
+
+
+def grad_row(sc, torch, synth):
+    """Differentiation workload: loss = sum(T_100(A~(theta)) x)^2 on the 64^3 Anderson
+    matrix, checkpoints every 10 steps; forward + backward time with HIP events."""
+    from paper_1507_08101_amd.autograd import chebyshev
+
+    A = synth.anderson3d(64)
+    s = (6.0 + W_DISORDER / 2) / 0.99
+    out = {"matrix": "3D periodic Anderson 64^3", "n": A.nrows, "nnz": A.nnz, "degree": 100, "checkpoint_every": 10}
+    for dt, vt in (("f64", torch.float64), ("f32", torch.float32)):
+        M = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=dt)
+        theta = torch.tensor(A.val, dtype=torch.float64, device="cuda", requires_grad=True)
+        X = torch.tensor(synth.block_vector(A.nrows, 1, synth.SEED_X), dtype=vt, device="cuda")
+
+        def step():
+            theta.grad = None
+            Y = chebyshev(theta, X, M, 100, s, 0.0, 10)
+            (Y.double() ** 2).sum().backward()
+
+        mean, _ = time_launches(torch, step, reps=5, warm=2)
+        out[dt + "_forward_backward_ms"] = round(mean / 1e3, 3)
+        M.close()
+    return out
+
+
 def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
     """The oracle's augmented product (one KPM step) on the host cores, bounded sample."""
     X = synth.block_vector(A.nrows, b, synth.SEED_X)
@@ -168,6 +244,7 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-b1", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the low-precision/transpose/update timings")
     ap.add_argument("--cg-edge", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one copy probe of this many MiB (calibrates HBM counters) and exit")
@@ -233,6 +310,12 @@ def main():
         del V0d
 
     head = results[args.b]
+    extra = None
+    if not args.no_other:
+        extra = other_rows(sc, torch, model, A, Mh, args.b, s)
+        extra["build_spmv_equivalents"] = round(build_s * 1e6 / extra["plain_spmv_b1_us"], 1)
+        extra["grad_chebyshev"] = grad_row(sc, torch, synth)
+        log(f"[bench] other rows: {json.dumps(extra)}")
     probes = None if args.no_probe else probe_bandwidth(sc, torch)
     if probes:
         log(f"[bench] probes GB/s: {probes}")
@@ -284,6 +367,7 @@ def main():
         "achievable_gbs": probes,
         "frac_of_achievable": None if not probes else round(head["hbm_gbs"] / max(probes["copy"], probes["copy_nt"]), 4),
         "cg_time_to_1e-10": cg,
+        "other_rows_b8": extra,
         "build_s": round(build_s, 3),
         "kernel_source_hash": src_hash,
     }

@@ -263,6 +263,34 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *B, se
                   sell_cg_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------------------------ */
+/* Derivatives with respect to the stored values (used by automatic differentiation)    */
+
+/* dval[p] (+)= alpha * sum_j G[row(p), j] X[col(p), j] for every stored entry p, CSR order:
+ * the gradient of <G, A X> with respect to the values of A (a pattern-restricted outer
+ * product). G: nrows x b, X: ncols x b, row-major with ld = b, the matrix's vector type;
+ * dval: DEVICE array of nnz doubles, overwritten (accumulate = 0) or added to (1).
+ * Asynchronous. */
+int sell_grad_values(const sell_mat *A, const sell_bv *G, const sell_bv *X, double alpha,
+                     int accumulate, double *dval, void *stream);
+
+/* Y = T_N(A~) X with A~ = (A - c I) / s, by the Chebyshev three-term recurrence
+ * v_0 = X, v_1 = A~ v_0, v_m+1 = 2 A~ v_m - v_m-1 (each step one augmented product).
+ * A square; X, Y: n x b row-major with ld = b, b <= 64, the matrix's vector type.
+ * ckpt: NULL, or a DEVICE buffer of 2 * ceil(N / K) * n * b elements of the vector type
+ * that receives the pairs (v_kK, v_kK+1) for the backward pass. N >= 1, K >= 1.
+ * Asynchronous. */
+int sell_cheb_forward(const sell_mat *A, const sell_bv *X, sell_bv *Y, int64_t N, double s,
+                      double c, int64_t K, void *ckpt, void *stream);
+
+/* Adjoint of sell_cheb_forward for a scalar loss L with G = dL/dY: dX = dL/dX and
+ * dval = dL/dval (DEVICE, nnz doubles, CSR order), from the checkpoints of the forward call
+ * with the same (N, s, c, K) and the same matrix values. Each segment of K steps is
+ * recomputed from its checkpoint; A^T products use the SELL copy of A^T (built on the
+ * first call, a synchronous allocating call). Asynchronous otherwise. */
+int sell_cheb_backward(const sell_mat *A, const sell_bv *G, int64_t N, double s, double c,
+                       int64_t K, const void *ckpt, sell_bv *dX, double *dval, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
 /* Measurement helpers                                                                  */
 
 /* Streaming probes of achievable device bandwidth on caller-owned device buffers:

@@ -45,6 +45,9 @@ def lib():
         L.orc_cg.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, _P]
         L.orc_chebyshev.argtypes = [_I64, _P, _P, _P, _P, _I64, _D, _D, _P, _P]
         L.orc_num_threads.restype = ct.c_int
+        L.orc_cheb_apply.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P]
+        L.orc_cheb_grad.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P, _P, _P]
+        L.orc_pattern_outer.argtypes = [_I64, _P, _P, _I64, _P, _P, _P]
         _lib = L
     return _lib
 
@@ -166,3 +169,37 @@ def chebyshev(A, x, M, s, c=0.0):
     _check(lib().orc_chebyshev(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(x), M, s, c, _p(mu),
                                _p(v)), "chebyshev")
     return mu, v
+
+
+def cheb_apply(A, X, N, s, c=0.0):
+    """Y = T_N((A - cI)/s) X for a row-major block X (n x b)."""
+    X = _f64(X)
+    X2 = X.reshape(A.nrows, -1)
+    b = X2.shape[1]
+    Y = np.empty_like(X2)
+    _check(lib().orc_cheb_apply(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), N, s, c, _p(Y)),
+           "cheb_apply")
+    return Y.reshape(X.shape)
+
+
+def cheb_grad(A, X, N, s, c, G):
+    """(dL/dX, dL/dval) for Y = T_N(A~) X and dL/dY = G, by the stored-vector adjoint recurrence."""
+    X = _f64(X)
+    X2 = X.reshape(A.nrows, -1)
+    G2 = _f64(G).reshape(X2.shape)
+    b = X2.shape[1]
+    dX = np.empty_like(X2)
+    dval = np.empty(A.nnz)
+    _check(lib().orc_cheb_grad(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), N, s, c, _p(G2), _p(dX),
+                               _p(dval)), "cheb_grad")
+    return dX.reshape(X.shape), dval
+
+
+def pattern_outer(A, G, X):
+    """dval[p] = sum_j G[row(p), j] X[col(p), j] (CSR order)."""
+    G2 = _f64(G).reshape(A.nrows, -1)
+    X2 = _f64(X).reshape(A.ncols, -1)
+    dval = np.empty(A.nnz)
+    _check(lib().orc_pattern_outer(A.nrows, _p(A.rowptr), _p(A.col), G2.shape[1], _p(G2), _p(X2), _p(dval)),
+           "pattern_outer")
+    return dval

@@ -314,3 +314,111 @@ int orc_chebyshev(int64_t n, const int64_t *rowptr, const int32_t *col, const do
     free(t);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------------
+ * Chebyshev application and its gradient (reverse mode written out by hand).
+ * Forward: v_0 = X, v_1 = A~ v_0, v_{m+1} = 2 A~ v_m - v_{m-1}, Y = v_N, A~ = (A - cI)/s.
+ * Adjoint: with w_m = dL/dv_m, w_N = G; walking m = N-1 .. 1 over v_{m+1} = 2 A~ v_m - v_{m-1}:
+ *   w_m += 2 A~^T w_{m+1},  w_{m-1} -= w_{m+1},  dval += (2/s) outer(w_{m+1}, v_m);
+ * then for v_1 = A~ v_0:  w_0 += A~^T w_1,  dval += (1/s) outer(w_1, v_0); dX = w_0.
+ */
+static void atilde(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                   const double *V, double s, double c, double *out) {
+    orc_spmmv(n, rowptr, col, val, b, V, b, out, b);
+    for (int64_t e = 0; e < n * b; ++e) out[e] = (out[e] - c * V[e]) / s;
+}
+
+static void atilde_T(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                     const double *W, double s, double c, double *out) {
+    orc_spmmv_T(n, n, rowptr, col, val, b, W, b, out, b);
+    for (int64_t e = 0; e < n * b; ++e) out[e] = (out[e] - c * W[e]) / s;
+}
+
+int orc_pattern_outer(int64_t nrows, const int64_t *rowptr, const int32_t *col, int64_t b,
+                      const double *G, const double *X, double *dval) {
+    if (nrows < 0 || b < 1) return -1;
+    for (int64_t i = 0; i < nrows; ++i)
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < b; ++j) acc = acc + G[i * b + j] * X[(int64_t)col[p] * b + j];
+            dval[p] = acc;
+        }
+    return 0;
+}
+
+int orc_cheb_apply(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                   const double *X, int64_t N, double s, double c, double *Y) {
+    if (n < 0 || b < 1 || N < 1 || s == 0.0) return -1;
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1) * (size_t)b;
+    double *prev = (double *)malloc(sz), *cur = (double *)malloc(sz), *nxt = (double *)malloc(sz);
+    if (!prev || !cur || !nxt) {
+        free(prev);
+        free(cur);
+        free(nxt);
+        return -1;
+    }
+    memcpy(prev, X, sizeof(double) * (size_t)(n * b));
+    atilde(n, rowptr, col, val, b, prev, s, c, cur);
+    for (int64_t m = 1; m < N; ++m) {
+        atilde(n, rowptr, col, val, b, cur, s, c, nxt);
+        for (int64_t e = 0; e < n * b; ++e) nxt[e] = 2.0 * nxt[e] - prev[e];
+        double *t = prev;
+        prev = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    memcpy(Y, cur, sizeof(double) * (size_t)(n * b));
+    free(prev);
+    free(cur);
+    free(nxt);
+    return 0;
+}
+
+int orc_cheb_grad(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                  const double *X, int64_t N, double s, double c, const double *G, double *dX,
+                  double *dval) {
+    if (n < 0 || b < 1 || N < 1 || s == 0.0) return -1;
+    const int64_t nb = n * b;
+    const int64_t nnz = rowptr[n];
+    double *V = (double *)malloc(sizeof(double) * (size_t)(N + 1) * (size_t)(nb > 0 ? nb : 1));
+    double *W = (double *)calloc((size_t)(N + 1) * (size_t)(nb > 0 ? nb : 1), sizeof(double));
+    double *t = (double *)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+    double *dv = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!V || !W || !t || !dv) {
+        free(V);
+        free(W);
+        free(t);
+        free(dv);
+        return -1;
+    }
+    /* forward, keeping every v_m */
+    memcpy(V, X, sizeof(double) * (size_t)nb);
+    atilde(n, rowptr, col, val, b, V, s, c, V + nb);
+    for (int64_t m = 1; m < N; ++m) {
+        atilde(n, rowptr, col, val, b, V + m * nb, s, c, V + (m + 1) * nb);
+        for (int64_t e = 0; e < nb; ++e) V[(m + 1) * nb + e] = 2.0 * V[(m + 1) * nb + e] - V[(m - 1) * nb + e];
+    }
+    /* reverse */
+    for (int64_t p = 0; p < nnz; ++p) dval[p] = 0.0;
+    memcpy(W + N * nb, G, sizeof(double) * (size_t)nb);
+    for (int64_t m = N - 1; m >= 1; --m) {
+        const double *wn = W + (m + 1) * nb;
+        atilde_T(n, rowptr, col, val, b, wn, s, c, t);
+        for (int64_t e = 0; e < nb; ++e) {
+            W[m * nb + e] += 2.0 * t[e];
+            W[(m - 1) * nb + e] -= wn[e];
+        }
+        orc_pattern_outer(n, rowptr, col, b, wn, V + m * nb, dv);
+        for (int64_t p = 0; p < nnz; ++p) dval[p] += (2.0 / s) * dv[p];
+    }
+    atilde_T(n, rowptr, col, val, b, W + nb, s, c, t);
+    for (int64_t e = 0; e < nb; ++e) W[e] += t[e];
+    orc_pattern_outer(n, rowptr, col, b, W + nb, V, dv);
+    for (int64_t p = 0; p < nnz; ++p) dval[p] += (1.0 / s) * dv[p];
+    memcpy(dX, W, sizeof(double) * (size_t)nb);
+    free(V);
+    free(W);
+    free(t);
+    free(dv);
+    return 0;
+}

@@ -92,6 +92,22 @@ int orc_cg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *v
 int orc_chebyshev(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                   const double *x, int64_t M, double s, double c, double *mu, double *vlast);
 
+/* Block Chebyshev application Y = T_N(A~) X for A~ = (A - c I) / s (three-term recurrence,
+ * X and Y row-major n x b), and the gradient of a scalar loss L(Y) given G = dL/dY:
+ *   dX   (n x b)  = dL/dX
+ *   dval (nnz)    = dL/dval[p] for every stored entry p of A (CSR order),
+ * by the adjoint (reverse-mode) recurrence with every v_m stored. N >= 1. */
+int orc_cheb_apply(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                   const double *X, int64_t N, double s, double c, double *Y);
+int orc_cheb_grad(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                  const double *X, int64_t N, double s, double c, const double *G, double *dX,
+                  double *dval);
+
+/* dval[p] = sum_j G[row(p), j] * X[col[p], j]: the gradient of <G, A X> with respect to the
+ * stored values (CSR order). */
+int orc_pattern_outer(int64_t nrows, const int64_t *rowptr, const int32_t *col, int64_t b,
+                      const double *G, const double *X, double *dval);
+
 /* Threads the oracle's parallel loops use (OpenMP), for reporting. */
 int orc_num_threads(void);
 

@@ -87,6 +87,9 @@ _SIGNATURES = {
     "sell_cg": ([_P, _P, _P, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_cg_mixed": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_probe_bandwidth": ([_I, _P, _P, _I64, _P], _I),
+    "sell_grad_values": ([_P, _P, _P, _D, _I, _P, _P], _I),
+    "sell_cheb_forward": ([_P, _P, _P, _I64, _D, _D, _I64, _P, _P], _I),
+    "sell_cheb_backward": ([_P, _P, _I64, _D, _D, _I64, _P, _P, _P, _P], _I),
 }
 
 _lib = None
@@ -409,3 +412,33 @@ def sell_probe_bandwidth(kind, dst, src, nbytes, stream=None):
     _ok(lib().sell_probe_bandwidth(int(kind), ct.c_void_p(dst.data_ptr()),
                                    ct.c_void_p(src.data_ptr()) if src is not None else None, int(nbytes),
                                    _stream(stream)), "sell_probe_bandwidth")
+
+
+# ==================================================================== value gradients
+
+
+def sell_grad_values(A, G, X, dval, alpha=1.0, accumulate=False, stream=None):
+    """dval (float64 device tensor of nnz, CSR order) (+)= alpha * sum_j G[row, j] X[col, j]."""
+    g, x = _bv(G), _bv(X)
+    _ok(lib().sell_grad_values(_mat(A), g.handle, x.handle, float(alpha), 1 if accumulate else 0,
+                               ct.c_void_p(dval.data_ptr()) if dval.numel() else None, _stream(stream)),
+        "sell_grad_values")
+
+
+def cheb_ckpt_elems(n, b, N, K):
+    """Elements of the checkpoint buffer of sell_cheb_forward: 2 ceil(N / K) n b."""
+    return 2 * ((N + K - 1) // K) * n * b
+
+
+def sell_cheb_forward(A, X, Y, N, s, c=0.0, K=10, ckpt=None, stream=None):
+    x, y = _bv(X), _bv(Y)
+    _ok(lib().sell_cheb_forward(_mat(A), x.handle, y.handle, int(N), float(s), float(c), int(K),
+                                None if ckpt is None else ct.c_void_p(ckpt.data_ptr()), _stream(stream)),
+        "sell_cheb_forward")
+
+
+def sell_cheb_backward(A, G, N, s, c, K, ckpt, dX, dval, stream=None):
+    g, dx = _bv(G), _bv(dX)
+    _ok(lib().sell_cheb_backward(_mat(A), g.handle, int(N), float(s), float(c), int(K), ct.c_void_p(ckpt.data_ptr()),
+                                 dx.handle, ct.c_void_p(dval.data_ptr()) if dval.numel() else None,
+                                 _stream(stream)), "sell_cheb_backward")

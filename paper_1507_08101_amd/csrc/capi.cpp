@@ -2,6 +2,7 @@
 // Every entry point validates its arguments before issuing any HIP call and converts
 // every failure into a negative error code; no C++ exception leaves this file.
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -45,6 +46,8 @@ void free_device(sell_mat *A) {
     hipFree(A->d_tiles);
     hipFree(A->d_rowslot);
     hipFree(A->d_rowptr);
+    hipFree(A->d_tpos);
+    A->d_tpos = nullptr;
     A->d_col = nullptr;
     A->d_val = nullptr;
     A->d_cl = nullptr;
@@ -159,6 +162,11 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.nrows = A->h.nrows;
     a.alpha = 1.0;
     a.eta = 1.0;
+    static const int xcd_map = [] {
+        const char *e = std::getenv("SELLCS_XCD_MAP");
+        return e ? std::atoi(e) : 1;
+    }();
+    a.xcd_map = xcd_map;
 }
 
 // Split b columns into launches: fixed widths when possible, else up to 64 per launch.
@@ -429,7 +437,10 @@ int sell_export_csr(const sell_mat *A, int64_t *rowptr, int32_t *col, double *va
     return SELL_OK;
 }
 
-static int ensure_update_maps(sell_mat *A, hipStream_t s) {
+}  // extern "C"
+
+namespace sellcs {
+int ensure_update_maps(sell_mat *A, hipStream_t s) {
     if (A->d_rowptr) return SELL_OK;
     const HostSell &h = A->h;
     std::vector<int32_t> rowslot(static_cast<size_t>(h.nrows));
@@ -444,6 +455,9 @@ static int ensure_update_maps(sell_mat *A, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     return SELL_OK;
 }
+}  // namespace sellcs
+
+extern "C" {
 
 int sell_update_values_device(sell_mat *A, const double *val, void *stream) {
     int rc = check_device(A);
@@ -452,10 +466,21 @@ int sell_update_values_device(sell_mat *A, const double *val, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     try {
         if ((rc = ensure_update_maps(A, s))) return rc;
+        if (A->transpose && (rc = ensure_update_maps(A->transpose, s))) return rc;
     } catch (const std::bad_alloc &) {
         return SELL_ERR_OOM;
     }
-    return launch_update_values(A, val, s);
+    if ((rc = launch_update_values(A, val, s))) return rc;
+    if (A->transpose && A->h.nnz > 0) {
+        // keep the SELL copy of A^T in step: permute the values into its CSR order
+        double *tv = nullptr;
+        HIPCHK(hipMallocAsync(reinterpret_cast<void **>(&tv), size_t(A->h.nnz) * sizeof(double), s));
+        rc = launch_scatter(val, A->d_tpos, A->h.nnz, tv, s);
+        if (rc == SELL_OK) rc = launch_update_values(A->transpose, tv, s);
+        hipError_t e = hipFreeAsync(tv, s);
+        if (rc == SELL_OK && e != hipSuccess) rc = hip_err(e);
+    }
+    return rc;
 }
 
 int sell_update_values(sell_mat *A, const double *val, void *stream) {
@@ -597,7 +622,10 @@ int sell_spmmv_aug(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, 
     return aug_impl(A, X, Y, Z, o, !plain, static_cast<hipStream_t>(stream));
 }
 
-static int ensure_transpose(const sell_mat *A, hipStream_t s) {
+}  // extern "C"
+
+namespace sellcs {
+int ensure_transpose(const sell_mat *A, hipStream_t s) {
     if (A->transpose) return SELL_OK;
     const HostSell &h = A->h;
     std::vector<int64_t> rp(size_t(h.nrows) + 1);
@@ -605,26 +633,42 @@ static int ensure_transpose(const sell_mat *A, hipStream_t s) {
     std::vector<double> val(static_cast<size_t>(h.nnz));
     int rc = sell_export_csr(A, rp.data(), col.data(), val.data());
     if (rc) return rc;
-    // CSR of A^T by a counting sort over columns (rows stay ascending inside each column)
+    // CSR of A^T by a counting sort over columns (rows stay ascending inside each column);
+    // tpos[p] records where entry p of A lands, for later value updates
     std::vector<int64_t> trp(size_t(h.ncols) + 1, 0);
     for (int64_t p = 0; p < h.nnz; ++p) trp[size_t(col[p]) + 1]++;
     for (int64_t c = 0; c < h.ncols; ++c) trp[c + 1] += trp[c];
     std::vector<int64_t> fill(trp.begin(), trp.end() - 1);
     std::vector<int32_t> tcol(static_cast<size_t>(h.nnz));
     std::vector<double> tval(static_cast<size_t>(h.nnz));
+    std::vector<int64_t> tpos(static_cast<size_t>(h.nnz));
     for (int64_t i = 0; i < h.nrows; ++i)
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
             const int64_t at = fill[col[p]]++;
             tcol[at] = int32_t(i);
             tval[at] = val[p];
+            tpos[p] = at;
         }
     sell_mat *T = nullptr;
     rc = build_common(&T, h.ncols, h.nrows, trp.data(), tcol.data(), tval.data(), h.C, h.sigma,
                       sell_dtype(h.vdt), true, s);
     if (rc) return rc;
-    const_cast<sell_mat *>(A)->transpose = T;
+    sell_mat *M = const_cast<sell_mat *>(A);
+    rc = dev_upload(&M->d_tpos, tpos.data(), tpos.size(), s);
+    if (rc == SELL_OK && hipStreamSynchronize(s) != hipSuccess) rc = SELL_ERR_HIP;
+    if (rc) {
+        sell_destroy(T);
+        hipFree(M->d_tpos);
+        M->d_tpos = nullptr;
+        return rc;
+    }
+    M->transpose = T;
     return SELL_OK;
 }
+
+}  // namespace sellcs
+
+extern "C" {
 
 int sell_spmmv_T(const sell_mat *A, const sell_bv *X, sell_bv *Y, int deterministic, void *stream) {
     int rc = check_product_operands(A, X, Y);

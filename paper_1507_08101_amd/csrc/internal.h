@@ -63,6 +63,7 @@ struct sell_mat {
     int32_t *d_rowslot = nullptr; // row -> slot, built on first device value update
     int64_t *d_rowptr = nullptr;  // CSR row pointers, built on first device value update
     sell_mat *transpose = nullptr;  // SELL copy of A^T for the deterministic transpose
+    int64_t *d_tpos = nullptr;      // CSR position in A^T of each CSR entry of A (with transpose)
     int64_t matrix_bytes = 0;
 };
 
@@ -92,6 +93,7 @@ struct ProdArgs {
     int32_t nblocks;       // workgroups of the launch (set by the launcher); workgroup g
                            // owns fine tiles [g * ntiles / nblocks, (g + 1) * ntiles / nblocks)
     int32_t cshift;        // log2(C) when C is a power of two, else -1
+    int32_t xcd_map;       // 1: give each XCD one contiguous range of tiles
     int64_t nrows;
     int32_t nb;            // columns in this slice
     const void *X; int64_t xrs, xcs;   // element (i, j) at X[i * xrs + j * xcs]
@@ -160,6 +162,19 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
 // Workgroups of one product launch: as many as the device holds at once (occupancy of the
 // kernel times the compute units), at most the number of fine tiles.
 int32_t resident_grid(const void *kernel, int threads, int32_t ntiles);
+
+// Lazily built device maps (row -> slot, CSR row pointers) and the SELL copy of A^T.
+int ensure_update_maps(sell_mat *A, hipStream_t s);
+int ensure_transpose(const sell_mat *A, hipStream_t s);
+
+// Value-gradient kernels (grad.hip).
+int launch_grad_accum(const sell_mat *A, const void *G, int64_t ldg, const void *X, int64_t ldx, int vec_dt,
+                      int32_t b, double alpha, double *dsell, hipStream_t s);
+int launch_sell_to_csr(const sell_mat *A, const double *dsell, int accumulate, double *dval, hipStream_t s);
+int launch_axpby(int vec_dt, int64_t n, int32_t b, int64_t ld, double alpha, const void *x, double beta, void *y,
+                 hipStream_t s);
+// dst[pos[p]] = src[p] for p < n
+int launch_scatter(const double *src, const int64_t *pos, int64_t n, double *dst, hipStream_t s);
 
 // Per-(device, stream) workspace for reductions.
 struct Workspace {

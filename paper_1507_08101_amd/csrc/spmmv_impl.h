@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
 
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);  // this workgroup's index in the partials
+    const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
     const int C = a.C;
     const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
     const int64_t s_begin = int64_t(a.tiles[t0]) * C;
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(ProdArgs a, int vl_lo
     const int nb = DYN ? a.nb : B;
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);
     const int C = a.C;
     const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
     const int64_t s_begin = int64_t(a.tiles[t0]) * C;

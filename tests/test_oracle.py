@@ -374,3 +374,80 @@ def test_chebyshev_via_eigendecomposition(orc):
     assert np.all(np.abs(t) < 1)
     ref = np.cos(np.arange(41)[:, None] * np.arccos(t)[None, :]) @ w
     assert np.allclose(mu, ref, rtol=0, atol=1e-11 * np.dot(x, x))
+
+
+# ---------------------------------------------------------------- Chebyshev gradient
+
+
+def _loss_half_sq(Y):
+    return 0.5 * float(np.sum(Y * Y))
+
+
+def test_cheb_apply_matches_moment_recurrence(orc):
+    A = synth.anderson3d(4)
+    s = 14.25 / 0.99
+    x = synth.block_vector(A.nrows, 1, 94)
+    for N in (1, 2, 7):
+        Y = orc.cheb_apply(A, x, N, s, 0.2)
+        _, vN = orc.chebyshev(A, x[:, 0], N, s, 0.2)
+        assert np.allclose(Y[:, 0], vN, rtol=0, atol=1e-14 * np.abs(x).sum())
+
+
+@pytest.mark.parametrize("N", [1, 2, 5])
+def test_cheb_grad_against_central_differences(orc, N):
+    A0 = synth.random_sparse(30, 30, 0.15, 95)
+    # symmetric-pattern matrix is not required for the gradient; keep A general
+    A = synth.CSR(30, 30, A0.rowptr, A0.col, A0.val, "g")
+    s, c = 3.0, 0.1
+    X = synth.block_vector(30, 2, 96)
+    W = synth.block_vector(30, 2, 97)  # L = <W, Y>  ->  G = W
+    dX, dval = orc.cheb_grad(A, X, N, s, c, W)
+    h = 1e-6
+    for p in range(0, A.nnz, max(1, A.nnz // 25)):
+        vp, vm = A.val.copy(), A.val.copy()
+        vp[p] += h
+        vm[p] -= h
+        Lp = np.sum(W * orc.cheb_apply(synth.CSR(30, 30, A.rowptr, A.col, vp), X, N, s, c))
+        Lm = np.sum(W * orc.cheb_apply(synth.CSR(30, 30, A.rowptr, A.col, vm), X, N, s, c))
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(dval[p] - fd) <= 1e-6 * max(1.0, abs(fd)), p
+    # L is linear in X: dL/dX is exactly T_N(A~)^T W
+    for i, j in [(0, 0), (7, 1), (29, 0)]:
+        Xp = X.copy()
+        Xp[i, j] += 1.0
+        fd = np.sum(W * orc.cheb_apply(A, Xp, N, s, c)) - np.sum(W * orc.cheb_apply(A, X, N, s, c))
+        assert abs(dX[i, j] - fd) <= 1e-10 * max(1.0, abs(fd))
+
+
+def test_cheb_grad_symmetric_x_gradient_identity(orc):
+    # A~ symmetric and L = |Y|^2 / 2: dL/dX = T_N(A~)^T Y = T_N(A~) T_N(A~) X
+    A = synth.anderson3d(5)
+    s, N = 14.25 / 0.99, 12
+    X = synth.block_vector(A.nrows, 3, 98)
+    Y = orc.cheb_apply(A, X, N, s)
+    dX, _ = orc.cheb_grad(A, X, N, s, 0.0, Y)
+    ref = orc.cheb_apply(A, Y, N, s)
+    assert np.allclose(dX, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_cheb_grad_diagonal_closed_form(orc):
+    # A = diag(d): Y_i = T_N(d_i / s) X_i, dL/dd_i = G_i X_i T_N'(d_i / s) / s with
+    # T_N'(cos t) = N sin(N t) / sin(t)
+    n, N, s = 50, 9, 1.5
+    d = synth.uniform(99, n, -1.2, 1.2)
+    A = synth.CSR(n, n, np.arange(n + 1), np.arange(n, dtype=np.int32), d, "diag")
+    X = synth.block_vector(n, 1, 100)
+    G = synth.block_vector(n, 1, 101)
+    _, dval = orc.cheb_grad(A, X, N, s, 0.0, G)
+    t = np.arccos(d / s)
+    dT = N * np.sin(N * t) / np.sin(t)
+    assert np.allclose(dval, G[:, 0] * X[:, 0] * dT / s, rtol=1e-11, atol=1e-13)
+
+
+def test_pattern_outer_is_gradient_of_bilinear_form(orc):
+    A = synth.random_sparse(40, 25, 0.2, 102, duplicates=True)
+    G = synth.block_vector(40, 3, 103)
+    X = synth.block_vector(25, 3, 104)
+    dval = orc.pattern_outer(A, G, X)
+    rows = np.repeat(np.arange(40), A.row_lengths())
+    assert np.allclose(dval, np.einsum("pj,pj->p", G[rows], X[A.col]), rtol=1e-15, atol=1e-15)
