@@ -291,6 +291,74 @@ int sell_cheb_backward(const sell_mat *A, const sell_bv *G, int64_t N, double s,
                        int64_t K, const void *ckpt, sell_bv *dX, double *dval, void *stream);
 
 /* ------------------------------------------------------------------------------------ */
+/* Tall-skinny block-vector kernels (Sec. 5.2)                                          */
+/* V: n x m, W: n x k block vectors (F64, row-major, 1 <= m, k <= 64); X: small m x k (or
+ * m x m) DEVICE matrix, row-major with leading dimension ldx. Asynchronous. */
+
+/* X = alpha V^T W + beta X (inner product of block vectors; X not read when beta == 0).
+ * Deterministic FP64 reduction over the n rows; kahan != 0 uses compensated (Neumaier)
+ * summation in every partial and in the final sum. */
+int sell_tsmttsm(const sell_bv *V, const sell_bv *W, double alpha, double beta, double *X,
+                 int64_t ldx, int kahan, void *stream);
+
+/* W = alpha V X + beta W (W not read when beta == 0; W must not overlap V). */
+int sell_tsmm(const sell_bv *V, const double *X, int64_t ldx, double alpha, double beta,
+              sell_bv *W, void *stream);
+
+/* V = alpha V X + beta V with X m x m: each row of V is read completely before it is
+ * overwritten. */
+int sell_tsmm_inplace(sell_bv *V, const double *X, int64_t ldx, double alpha, double beta,
+                      void *stream);
+
+/* ------------------------------------------------------------------------------------ */
+/* Batches of independent matrices                                                      */
+/*                                                                                      */
+/* The paper distributes one matrix over heterogeneous devices by work weights which it  */
+/* plans to derive from micro-benchmarks (Sec. 4.1 and the outlook, Sec. 7.2). On one    */
+/* GPU the same idea spreads many small and uneven matrices over the compute units: one  */
+/* launch processes every matrix of a batch, with the device's resident workgroups split  */
+/* in proportion to each matrix's cost (stored entries plus rows).                        */
+
+typedef struct sell_batch sell_batch;
+
+/* Groups count >= 1 device matrices (same value type, current device) into a batch. The
+ * batch refers to the matrices, which must outlive it; it allocates small device tables and
+ * pinned staging memory. The block vectors of a batch hold the operands of its matrices one
+ * after another: matrix m reads rows [c_m, c_m + ncols_m) of X and writes rows
+ * [r_m, r_m + nrows_m) of Y, with r_m, c_m the sums of the earlier matrices' sizes. */
+int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out);
+int sell_batch_destroy(sell_batch *B);
+/* count of matrices and the total rows / columns of the stacked operands (each may be NULL) */
+int sell_batch_info(const sell_batch *B, int32_t *count, int64_t *rows, int64_t *cols);
+
+/* Y_m = alpha (A_m - gamma I) X_m + beta Y_m with dots and chain (opts exactly as for
+ * sell_spmmv_aug, applied to every matrix) in one launch. X: total-columns x b, Y and Z:
+ * total-rows x b, the batch's vector type, 1 <= b <= 64. opts->dot receives 3 b doubles per
+ * matrix: matrix m's group q (yy = 0, xy = 1, xx = 2), column j at dot[(3 m + q) b + j].
+ * Calls on one batch must be ordered (one stream, or synchronised): the launch tables are
+ * reused. Asynchronous. */
+int sell_batch_spmmv_aug(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z,
+                         const sell_spmv_opts *opts, void *stream);
+
+#define SELL_BATCH_GRAPH 0x1u /* capture the iterations in a HIP graph and replay it */
+
+/* Conjugate gradients for every system m of a batch (A_m symmetric positive definite) and
+ * every column of its right-hand sides: B and X are total-rows x b, F64, row-major with
+ * ld = b, 1 <= b <= 64; X holds the initial guesses and receives the solutions. A64: batch
+ * of F64 matrices. Alo: NULL for FP64 CG, else a batch of the same matrices with F32 or
+ * BF16 values, for FP32 iterations refined in FP64 by reliable updates per system (the
+ * scheme of sell_cg_mixed, with inner_tol and inner_maxit per system). A system stops when
+ * every column has ||b - A x|| <= tol ||b|| (true FP64 residual); maxit bounds the
+ * iterations of the batch. All systems advance together, a converged one is skipped by
+ * every kernel. flags: 0 or SELL_BATCH_GRAPH. stats: NULL or a HOST array of count
+ * entries (per system: its iterations, refinements, final relres, converged). Synchronous.
+ * A NULL stream makes the call use a stream of its own (the legacy default stream cannot
+ * be captured), ordered after earlier work on the default stream. */
+int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *B, sell_bv *X, double tol,
+                  int64_t maxit, double inner_tol, int64_t inner_maxit, uint32_t flags,
+                  sell_cg_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
 /* Measurement helpers                                                                  */
 
 /* Streaming probes of achievable device bandwidth on caller-owned device buffers:

@@ -48,6 +48,9 @@ def lib():
         L.orc_cheb_apply.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P]
         L.orc_cheb_grad.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P, _P, _P]
         L.orc_pattern_outer.argtypes = [_I64, _P, _P, _I64, _P, _P, _P]
+        L.orc_tsmttsm.argtypes = [_I64, _I64, _I64, _D, _P, _P, _D, _P, ct.c_int]
+        L.orc_tsmm.argtypes = [_I64, _I64, _I64, _D, _P, _P, _D, _P]
+        L.orc_tsmm_inplace.argtypes = [_I64, _I64, _D, _P, _P, _D]
         _lib = L
     return _lib
 
@@ -203,3 +206,32 @@ def pattern_outer(A, G, X):
     _check(lib().orc_pattern_outer(A.nrows, _p(A.rowptr), _p(A.col), G2.shape[1], _p(G2), _p(X2), _p(dval)),
            "pattern_outer")
     return dval
+
+
+def tsmttsm(V, W, alpha=1.0, beta=0.0, X=None, kahan=False):
+    """X = alpha V^T W + beta X (V: n x m, W: n x k)."""
+    V, W = _f64(V), _f64(W)
+    n, m = V.shape
+    k = W.shape[1]
+    Xo = np.zeros((m, k)) if X is None else _f64(X).copy()
+    _check(lib().orc_tsmttsm(n, m, k, alpha, _p(V), _p(W), beta, _p(Xo), 1 if kahan else 0), "tsmttsm")
+    return Xo
+
+
+def tsmm(V, X, alpha=1.0, beta=0.0, W=None):
+    """W = alpha V X + beta W (V: n x m, X: m x k)."""
+    V, X = _f64(V), _f64(X)
+    n, m = V.shape
+    k = X.shape[1]
+    Wo = np.zeros((n, k)) if W is None else _f64(W).copy()
+    _check(lib().orc_tsmm(n, m, k, alpha, _p(V), _p(X), beta, _p(Wo)), "tsmm")
+    return Wo
+
+
+def tsmm_inplace(V, X, alpha=1.0, beta=0.0):
+    """V = alpha V X + beta V (X: m x m); returns the new V."""
+    Vo = _f64(V).copy()
+    X = _f64(X)
+    n, m = Vo.shape
+    _check(lib().orc_tsmm_inplace(n, m, alpha, _p(Vo), _p(X), beta), "tsmm_inplace")
+    return Vo

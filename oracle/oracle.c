@@ -422,3 +422,61 @@ int orc_cheb_grad(int64_t n, const int64_t *rowptr, const int32_t *col, const do
     free(dv);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------------
+ * Tall-skinny block-vector kernels (Sec. 5.2), plain loops.
+ */
+int orc_tsmttsm(int64_t n, int64_t m, int64_t k, double alpha, const double *V, const double *W, double beta,
+                double *X, int kahan) {
+    if (n < 0 || m < 1 || k < 1) return -1;
+    for (int64_t l = 0; l < m; ++l)
+        for (int64_t j = 0; j < k; ++j) {
+            double s = 0.0, comp = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                const double term = V[i * m + l] * W[i * k + j];
+                if (kahan) {
+                    const double t = s + term;
+                    if (fabs(s) >= fabs(term))
+                        comp += (s - t) + term;
+                    else
+                        comp += (term - t) + s;
+                    s = t;
+                } else {
+                    s = s + term;
+                }
+            }
+            const double v = alpha * (s + comp);
+            X[l * k + j] = beta != 0.0 ? v + beta * X[l * k + j] : v;
+        }
+    return 0;
+}
+
+int orc_tsmm(int64_t n, int64_t m, int64_t k, double alpha, const double *V, const double *X, double beta,
+             double *W) {
+    if (n < 0 || m < 1 || k < 1) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < k; ++j) {
+            double s = 0.0;
+            for (int64_t l = 0; l < m; ++l) s = s + V[i * m + l] * X[l * k + j];
+            const double v = alpha * s;
+            W[i * k + j] = beta != 0.0 ? v + beta * W[i * k + j] : v;
+        }
+    return 0;
+}
+
+int orc_tsmm_inplace(int64_t n, int64_t m, double alpha, double *V, const double *X, double beta) {
+    if (n < 0 || m < 1) return -1;
+    double *row = (double *)malloc(sizeof(double) * (size_t)m);
+    if (!row) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        memcpy(row, V + i * m, sizeof(double) * (size_t)m);
+        for (int64_t j = 0; j < m; ++j) {
+            double s = 0.0;
+            for (int64_t l = 0; l < m; ++l) s = s + row[l] * X[l * m + j];
+            const double v = alpha * s;
+            V[i * m + j] = beta != 0.0 ? v + beta * row[j] : v;
+        }
+    }
+    free(row);
+    return 0;
+}

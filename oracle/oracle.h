@@ -108,6 +108,18 @@ int orc_cheb_grad(int64_t n, const int64_t *rowptr, const int32_t *col, const do
 int orc_pattern_outer(int64_t nrows, const int64_t *rowptr, const int32_t *col, int64_t b,
                       const double *G, const double *X, double *dval);
 
+/* Tall-skinny block-vector kernels (Sec. 5.2); V: n x m, W: n x k row-major, X: m x k
+ * row-major (small).
+ *   tsmttsm:      X = alpha V^T W + beta X   (sums over the n rows in row order; kahan != 0:
+ *                 Neumaier-compensated sums; X not read when beta == 0)
+ *   tsmm:         W = alpha V X + beta W     (W not read when beta == 0)
+ *   tsmm_inplace: V = alpha V X + beta V     (X is m x m; every row uses only its own old row) */
+int orc_tsmttsm(int64_t n, int64_t m, int64_t k, double alpha, const double *V, const double *W, double beta,
+                double *X, int kahan);
+int orc_tsmm(int64_t n, int64_t m, int64_t k, double alpha, const double *V, const double *X, double beta,
+             double *W);
+int orc_tsmm_inplace(int64_t n, int64_t m, double alpha, double *V, const double *X, double beta);
+
 /* Threads the oracle's parallel loops use (OpenMP), for reporting. */
 int orc_num_threads(void);
 

@@ -90,6 +90,14 @@ _SIGNATURES = {
     "sell_grad_values": ([_P, _P, _P, _D, _I, _P, _P], _I),
     "sell_cheb_forward": ([_P, _P, _P, _I64, _D, _D, _I64, _P, _P], _I),
     "sell_cheb_backward": ([_P, _P, _I64, _D, _D, _I64, _P, _P, _P, _P], _I),
+    "sell_tsmttsm": ([_P, _P, _D, _D, _P, _I64, _I, _P], _I),
+    "sell_tsmm": ([_P, _P, _I64, _D, _D, _P, _P], _I),
+    "sell_tsmm_inplace": ([_P, _P, _I64, _D, _D, _P], _I),
+    "sell_batch_create": ([_PP, _I32, _PP], _I),
+    "sell_batch_destroy": ([_P], _I),
+    "sell_batch_info": ([_P, ct.POINTER(_I32), ct.POINTER(_I64), ct.POINTER(_I64)], _I),
+    "sell_batch_spmmv_aug": ([_P, _P, _P, _P, ct.POINTER(sell_spmv_opts), _P], _I),
+    "sell_batch_cg": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.c_uint32, ct.POINTER(sell_cg_stats), _P], _I),
 }
 
 _lib = None
@@ -408,6 +416,62 @@ def sell_cg_mixed(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=0.1, inner_
     return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
 
 
+# ==================================================================== batches
+
+SELL_BATCH_GRAPH = 0x1
+
+
+class SellBatch:
+    """A batch of device matrices processed by single launches. Holds references to the
+    matrices (which must stay open while the batch exists)."""
+
+    def __init__(self, mats):
+        self.mats = list(mats)
+        arr = (ct.c_void_p * len(self.mats))(*[_mat(m).value if isinstance(_mat(m), ct.c_void_p) else _mat(m)
+                                                for m in self.mats])
+        h = ct.c_void_p()
+        _ok(lib().sell_batch_create(arr, len(self.mats), ct.byref(h)), "sell_batch_create")
+        self.handle = h
+        cnt, rows, cols = _I32(), _I64(), _I64()
+        _ok(lib().sell_batch_info(h, ct.byref(cnt), ct.byref(rows), ct.byref(cols)), "sell_batch_info")
+        self.count, self.rows, self.cols = cnt.value, rows.value, cols.value
+
+    def close(self):
+        if self.handle:
+            lib().sell_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sell_batch_spmmv_aug(Bt, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0.0, gamma_v=None, delta=0.0,
+                         eta=1.0, dot=None, stream=None):
+    """The augmented product for every matrix of the batch in one launch; X, Y, Z hold the
+    matrices' operands stacked by rows; ``dot`` receives 3b doubles per matrix."""
+    x, y = _bv(X), _bv(Y)
+    z = _bv(Z) if Z is not None else None
+    o, keep = make_opts(flags, alpha, beta, gamma, gamma_v, delta, eta, dot)
+    _ok(lib().sell_batch_spmmv_aug(Bt.handle, x.handle, y.handle, z.handle if z else None, ct.byref(o),
+                                   _stream(stream)), "sell_batch_spmmv_aug")
+    del keep
+
+
+def sell_batch_cg(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=0.1, inner_maxit=1000, graph=True,
+                  stream=None):
+    """CG for every system of the batch (FP64, or FP32 iterations refined in FP64 when Alo is
+    given); returns one stats dict per system."""
+    st = (sell_cg_stats * A64.count)()
+    b, x = _bv(B), _bv(X)
+    _ok(lib().sell_batch_cg(A64.handle, Alo.handle if Alo is not None else None, b.handle, x.handle, float(tol),
+                            int(maxit), float(inner_tol), int(inner_maxit), SELL_BATCH_GRAPH if graph else 0, st,
+                            _stream(stream)), "sell_batch_cg")
+    return [{k: getattr(e, k) for k, _ in sell_cg_stats._fields_} for e in st]
+
+
 def sell_probe_bandwidth(kind, dst, src, nbytes, stream=None):
     _ok(lib().sell_probe_bandwidth(int(kind), ct.c_void_p(dst.data_ptr()),
                                    ct.c_void_p(src.data_ptr()) if src is not None else None, int(nbytes),
@@ -442,3 +506,27 @@ def sell_cheb_backward(A, G, N, s, c, K, ckpt, dX, dval, stream=None):
     _ok(lib().sell_cheb_backward(_mat(A), g.handle, int(N), float(s), float(c), int(K), ct.c_void_p(ckpt.data_ptr()),
                                  dx.handle, ct.c_void_p(dval.data_ptr()) if dval.numel() else None,
                                  _stream(stream)), "sell_cheb_backward")
+
+
+# ==================================================================== tall-skinny kernels
+
+
+def sell_tsmttsm(V, W, X, alpha=1.0, beta=0.0, kahan=False, stream=None):
+    """X (m x k float64 device tensor) = alpha V^T W + beta X."""
+    v, w = _bv(V), _bv(W)
+    _ok(lib().sell_tsmttsm(v.handle, w.handle, float(alpha), float(beta), ct.c_void_p(X.data_ptr()), X.stride(0),
+                           1 if kahan else 0, _stream(stream)), "sell_tsmttsm")
+
+
+def sell_tsmm(V, X, W, alpha=1.0, beta=0.0, stream=None):
+    """W = alpha V X + beta W (X: m x k float64 device tensor)."""
+    v, w = _bv(V), _bv(W)
+    _ok(lib().sell_tsmm(v.handle, ct.c_void_p(X.data_ptr()), X.stride(0), float(alpha), float(beta), w.handle,
+                        _stream(stream)), "sell_tsmm")
+
+
+def sell_tsmm_inplace(V, X, alpha=1.0, beta=0.0, stream=None):
+    """V = alpha V X + beta V (X: m x m float64 device tensor)."""
+    v = _bv(V)
+    _ok(lib().sell_tsmm_inplace(v.handle, ct.c_void_p(X.data_ptr()), X.stride(0), float(alpha), float(beta),
+                                _stream(stream)), "sell_tsmm_inplace")

@@ -1,0 +1,361 @@
+// batch.cpp -- products over a batch of independent matrices in one kernel launch.
+//
+// The batch's block vectors hold the matrices' operands one after another: matrix m reads
+// rows [col_off[m], col_off[m+1]) of X and writes rows [row_off[m], row_off[m+1]) of Y. One
+// launch of the batched product kernel covers every matrix: the device's resident workgroups
+// are split over the matrices in proportion to their cost (stored entries plus rows), and
+// each workgroup finds its matrix's launch arguments in a table in device memory by a binary
+// search over the workgroup offsets. The tables are staged through pinned host memory into a
+// few device slots; a call whose table equals one already on the device (the same operands
+// and scalars, as in every iteration of a solver) uploads nothing, which keeps repeated calls
+// free of copies and lets them be captured in a HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace sellcs;
+
+namespace sellcs {
+const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok);
+const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok);
+const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok);
+int choose_vpt(int vk, int b);
+}  // namespace sellcs
+
+namespace {
+
+#define HIPCHK(x)                                                                             \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? SELL_ERR_OOM : SELL_ERR_HIP; \
+    } while (0)
+
+constexpr int kSlots = 4;
+
+bool fixed_width(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32; }
+
+bool vec_ok(const void *p, int64_t rs, int64_t cs, int esize, int align) {
+    return cs == 1 && (reinterpret_cast<uintptr_t>(p) % align) == 0 && ((rs * esize) % align) == 0;
+}
+
+}  // namespace
+
+struct sell_batch {
+    std::vector<const sell_mat *> mats;
+    int32_t K = 0;
+    int device = -1;
+    int vdt = SELL_F64;
+    int64_t rows = 0, cols = 0;
+    std::vector<int64_t> row_off, col_off;  // K + 1
+    std::vector<double> cost;               // per matrix
+    int64_t total_tiles = 0;
+    // table slots: K ProdArgs followed by K + 1 int32 workgroup offsets
+    size_t table_bytes = 0;
+    void *d_slot[kSlots] = {};
+    void *h_slot[kSlots] = {};  // pinned staging copies (also the record of the slot content)
+    hipEvent_t ev[kSlots] = {};
+    bool valid[kSlots] = {};
+    int next = 0;
+    std::vector<uint8_t> stage;
+    double *partials = nullptr;
+    size_t partials_cap = 0;  // doubles
+    int64_t *d_row_off = nullptr;  // device copy of row_off (for the batched solvers)
+    int32_t *d_vblk = nullptr;     // vector-kernel workgroup offsets (for the batched solvers)
+    int32_t vgrid = 0;
+};
+
+namespace sellcs {
+
+void batch_free(sell_batch *B) {
+    for (int i = 0; i < kSlots; ++i) {
+        if (B->ev[i]) (void)hipEventSynchronize(B->ev[i]);
+        if (B->ev[i]) (void)hipEventDestroy(B->ev[i]);
+        if (B->d_slot[i]) (void)hipFree(B->d_slot[i]);
+        if (B->h_slot[i]) (void)hipHostFree(B->h_slot[i]);
+    }
+    if (B->partials) (void)hipFree(B->partials);
+    if (B->d_row_off) (void)hipFree(B->d_row_off);
+    if (B->d_vblk) (void)hipFree(B->d_vblk);
+}
+
+const sell_mat *batch_matrix(const sell_batch *B, int m) { return B->mats[size_t(m)]; }
+int32_t batch_count(const sell_batch *B) { return B->K; }
+int64_t batch_rows(const sell_batch *B) { return B->rows; }
+int batch_vdt(const sell_batch *B) { return B->vdt; }
+
+// Segment description of the batch for the vector kernels of the batched solvers.
+BatchSeg batch_seg(const sell_batch *B) {
+    BatchSeg sg;
+    sg.row_off = B->d_row_off;
+    sg.vblk = B->d_vblk;
+    sg.K = B->K;
+    sg.G = B->vgrid;
+    return sg;
+}
+
+// The batched product (no argument checks): y_m = alpha (A_m x_m - gamma x_m) + beta y_m with
+// dots and chain for every matrix m, skipping matrices with active[m] == 0 (active may be
+// null). Dot partials stay in the batch's buffer; *out_blk / *out_partials (may be null)
+// receive the device workgroup offsets and the partials. finish: sum the dots into o.dot
+// (3 b doubles per matrix).
+int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
+                   const int32_t *active, bool finish, hipStream_t s, const int32_t **out_blk,
+                   const double **out_partials) {
+    const int b = X->ncols;
+    const int K = B->K;
+    Workspace *ws = nullptr;
+    int rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const int vk = vec_kind(B->vdt);
+    const int esize = vk == VK_F64F64 ? 8 : 4;
+    const int vpt = choose_vpt(vk, b);
+    const int align = vpt * esize < 16 ? vpt * esize : 16;
+    int64_t xrs, xcs, yrs, ycs, zrs = 0, zcs = 0;
+    bv_strides(X, xrs, xcs);
+    bv_strides(Y, yrs, ycs);
+    const bool chain = aug && (o.flags & SELL_SPMV_CHAIN);
+    if (chain) bv_strides(Z, zrs, zcs);
+    bool fixed_ok = fixed_width(b) && vec_ok(X->ptr, xrs, xcs, esize, align) && vec_ok(Y->ptr, yrs, ycs, esize, align);
+    if (chain) fixed_ok = fixed_ok && vec_ok(Z->ptr, zrs, zcs, esize, align);
+    const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok)
+                       : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok)
+                                         : batch_kernel_bf16(b, vpt, aug, fixed_ok);
+    // workgroups per matrix: the resident grid split in proportion to the cost
+    const int32_t G0 = resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)));
+    double tot = 0.0;
+    for (int m = 0; m < K; ++m) tot += B->cost[size_t(m)];
+    std::vector<int32_t> blk(size_t(K) + 1, 0);
+    for (int m = 0; m < K; ++m) {
+        const sell_mat *A = B->mats[size_t(m)];
+        const int32_t nt = A->ntiles;
+        int32_t n = 0;
+        if (nt > 0) {
+            n = int32_t(std::llround(double(G0) * B->cost[size_t(m)] / (tot > 0 ? tot : 1.0)));
+            n = std::max(1, std::min(n, nt));
+        }
+        blk[size_t(m) + 1] = blk[size_t(m)] + n;
+    }
+    const int32_t G = blk[size_t(K)];
+    const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
+    const size_t need = size_t(3) * b * size_t(std::max(G, 1));
+    if (dots && need > B->partials_cap) {
+        // grows outside any steady state (the first call of a shape)
+        if (B->partials) HIPCHK(hipFree(B->partials));
+        B->partials = nullptr;
+        B->partials_cap = 0;
+        HIPCHK(hipMalloc(&B->partials, need * sizeof(double)));
+        B->partials_cap = need;
+    }
+    // the table
+    B->stage.assign(B->table_bytes, 0);
+    ProdArgs *tab = reinterpret_cast<ProdArgs *>(B->stage.data());
+    for (int m = 0; m < K; ++m) {
+        const sell_mat *A = B->mats[size_t(m)];
+        ProdArgs a;
+        base_args(a, A);
+        a.nb = b;
+        a.nblocks = blk[size_t(m) + 1] - blk[size_t(m)];
+        a.xrs = xrs;
+        a.xcs = xcs;
+        a.yrs = yrs;
+        a.ycs = ycs;
+        a.X = elem_ptr(X, B->col_off[size_t(m)], 0);
+        a.Y = elem_ptr(Y, B->row_off[size_t(m)], 0);
+        a.scratch = ws->scratch;
+        if (chain) {
+            a.zrs = zrs;
+            a.zcs = zcs;
+            a.Z = elem_ptr(Z, B->row_off[size_t(m)], 0);
+        }
+        if (aug) {
+            a.flags = o.flags;
+            a.alpha = o.alpha;
+            a.beta = o.beta;
+            a.delta = o.delta;
+            a.eta = o.eta;
+            a.gamma_s = o.gamma;
+            if (o.flags & SELL_SPMV_VSHIFT) {
+                a.has_gamma_v = 1;
+                for (int j = 0; j < b; ++j) a.gamma_v[j] = o.gamma_v[j];
+            }
+            if (dots) a.partials = B->partials + size_t(3) * b * blk[size_t(m)];
+        }
+        std::memcpy(&tab[m], &a, sizeof(ProdArgs));
+    }
+    std::memcpy(B->stage.data() + sizeof(ProdArgs) * size_t(K), blk.data(), sizeof(int32_t) * (size_t(K) + 1));
+    // find the table on the device, else upload it into the next slot
+    int slot = -1;
+    for (int i = 0; i < kSlots && slot < 0; ++i)
+        if (B->valid[i] && std::memcmp(B->h_slot[i], B->stage.data(), B->table_bytes) == 0) slot = i;
+    if (slot < 0) {
+        slot = B->next;
+        B->next = (B->next + 1) % kSlots;
+        if (B->valid[slot]) HIPCHK(hipEventSynchronize(B->ev[slot]));  // its last upload has been read
+        B->valid[slot] = false;
+        std::memcpy(B->h_slot[slot], B->stage.data(), B->table_bytes);
+        HIPCHK(hipMemcpyAsync(B->d_slot[slot], B->h_slot[slot], B->table_bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventRecord(B->ev[slot], s));
+        B->valid[slot] = true;
+    }
+    const ProdArgs *d_tab = static_cast<const ProdArgs *>(B->d_slot[slot]);
+    const int32_t *d_blk =
+        reinterpret_cast<const int32_t *>(static_cast<const char *>(B->d_slot[slot]) + sizeof(ProdArgs) * size_t(K));
+    if (out_blk) *out_blk = d_blk;
+    if (out_partials) *out_partials = B->partials;
+    if (G > 0) {
+        int vl_log2 = 0;
+        if (!fixed_ok)
+            while ((1 << vl_log2) < b) ++vl_log2;
+        int Karg = K;
+        void *args[] = {&d_tab, &d_blk, &Karg, &active, &vl_log2};
+        HIPCHK(hipLaunchKernel(kern, dim3(unsigned(G)), dim3(kBlock), args, 0, s));
+    }
+    if (dots && finish) {
+        if (G == 0) {
+            for (int m = 0; m < K; ++m)
+                if ((rc = launch_fill(o.dot + size_t(m) * 3 * b, SELL_F64, 1, 3 * b, 3 * b, 1, 0.0, s))) return rc;
+            return SELL_OK;
+        }
+        if ((rc = launch_batch_dot_finish(B->partials, d_blk, K, b, o.flags, o.dot, s))) return rc;
+    }
+    return SELL_OK;
+}
+
+}  // namespace sellcs
+
+extern "C" {
+
+int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
+    if (!out) return SELL_ERR_ARG;
+    *out = nullptr;
+    if (!mats || count < 1) return SELL_ERR_ARG;
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    for (int32_t m = 0; m < count; ++m) {
+        int rc = check_device(mats[m]);
+        if (rc) return rc;
+        if (mats[m]->h.vdt != mats[0]->h.vdt) return SELL_ERR_DTYPE;
+    }
+    sell_batch *B = new (std::nothrow) sell_batch();
+    if (!B) return SELL_ERR_OOM;
+    int rc = SELL_OK;
+    try {
+        B->K = count;
+        B->device = cur;
+        B->vdt = mats[0]->h.vdt;
+        B->mats.assign(mats, mats + count);
+        B->row_off.assign(size_t(count) + 1, 0);
+        B->col_off.assign(size_t(count) + 1, 0);
+        B->cost.assign(size_t(count), 0.0);
+        for (int32_t m = 0; m < count; ++m) {
+            const HostSell &h = mats[m]->h;
+            B->row_off[size_t(m) + 1] = B->row_off[size_t(m)] + h.nrows;
+            B->col_off[size_t(m) + 1] = B->col_off[size_t(m)] + h.ncols;
+            B->cost[size_t(m)] = double(h.stored) + double(h.nrows);
+            B->total_tiles += std::max(0, mats[m]->ntiles);
+        }
+        B->rows = B->row_off[size_t(count)];
+        B->cols = B->col_off[size_t(count)];
+        B->table_bytes = sizeof(ProdArgs) * size_t(count) + sizeof(int32_t) * (size_t(count) + 1);
+    } catch (const std::bad_alloc &) {
+        delete B;
+        return SELL_ERR_OOM;
+    }
+    auto fail = [&](hipError_t e) {
+        batch_free(B);
+        delete B;
+        return e == hipErrorOutOfMemory ? SELL_ERR_OOM : SELL_ERR_HIP;
+    };
+    hipError_t e;
+    for (int i = 0; i < kSlots; ++i) {
+        if ((e = hipMalloc(&B->d_slot[i], B->table_bytes)) != hipSuccess) return fail(e);
+        if ((e = hipHostMalloc(&B->h_slot[i], B->table_bytes, hipHostMallocDefault)) != hipSuccess) return fail(e);
+        if ((e = hipEventCreateWithFlags(&B->ev[i], hipEventDisableTiming)) != hipSuccess) return fail(e);
+    }
+    // vector-kernel workgroups for the batched solvers: about kCgMaxGrid * 2 in total, split
+    // in proportion to the rows (at least one per non-empty system)
+    {
+        const int32_t Gv = 2 * kCgMaxGrid;
+        std::vector<int32_t> vblk(size_t(count) + 1, 0);
+        for (int32_t m = 0; m < count; ++m) {
+            const int64_t n = B->row_off[size_t(m) + 1] - B->row_off[size_t(m)];
+            int32_t g = 0;
+            if (n > 0) {
+                g = int32_t(std::llround(double(Gv) * double(n) / double(std::max<int64_t>(B->rows, 1))));
+                g = std::max(1, g);
+                g = int32_t(std::min<int64_t>(g, (n + 3) / 4));  // keep a few rows per workgroup
+                g = std::max(1, g);
+            }
+            vblk[size_t(m) + 1] = vblk[size_t(m)] + g;
+        }
+        B->vgrid = vblk[size_t(count)];
+        if ((e = hipMalloc(&B->d_row_off, sizeof(int64_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
+        if ((e = hipMalloc(&B->d_vblk, sizeof(int32_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
+        if ((e = hipMemcpy(B->d_row_off, B->row_off.data(), sizeof(int64_t) * (size_t(count) + 1),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e);
+        if ((e = hipMemcpy(B->d_vblk, vblk.data(), sizeof(int32_t) * (size_t(count) + 1), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return fail(e);
+    }
+    (void)rc;
+    *out = B;
+    return SELL_OK;
+}
+
+int sell_batch_destroy(sell_batch *B) {
+    if (!B) return SELL_OK;
+    batch_free(B);
+    delete B;
+    return SELL_OK;
+}
+
+int sell_batch_info(const sell_batch *B, int32_t *count, int64_t *rows, int64_t *cols) {
+    if (!B) return SELL_ERR_ARG;
+    if (count) *count = B->K;
+    if (rows) *rows = B->rows;
+    if (cols) *cols = B->cols;
+    return SELL_OK;
+}
+
+int sell_batch_spmmv_aug(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts *opts,
+                         void *stream) {
+    if (!B) return SELL_ERR_ARG;
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != B->device) return SELL_ERR_STATE;
+    int rc;
+    if ((rc = validate_bv(X)) || (rc = validate_bv(Y))) return rc;
+    const int vdt = vec_dtype_for(B->vdt);
+    if (X->dt != vdt || Y->dt != vdt) return SELL_ERR_DTYPE;
+    if (X->ncols != Y->ncols || X->ncols < 1) return SELL_ERR_SHAPE;
+    if (X->ncols > kMaxSliceCols) return SELL_ERR_UNSUPPORTED;
+    if (X->nrows != B->cols || Y->nrows != B->rows) return SELL_ERR_SHAPE;
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    if (opts) o = *opts;
+    if (o.flags & ~0xFFu) return SELL_ERR_ARG;
+    const uint32_t sq = SELL_SPMV_SHIFT | SELL_SPMV_VSHIFT | SELL_SPMV_DOT_XY | SELL_SPMV_DOT_XX;
+    if (o.flags & sq)
+        for (int m = 0; m < B->K; ++m)
+            if (B->mats[size_t(m)]->h.nrows != B->mats[size_t(m)]->h.ncols) return SELL_ERR_SHAPE;
+    if ((o.flags & SELL_SPMV_VSHIFT) && !o.gamma_v) return SELL_ERR_ARG;
+    if ((o.flags & SELL_SPMV_DOTS) && !o.dot) return SELL_ERR_ARG;
+    if (X->ptr == Y->ptr && B->rows > 0) return SELL_ERR_ARG;
+    if (o.flags & SELL_SPMV_CHAIN) {
+        if ((rc = validate_bv(Z))) return rc;
+        if (Z->dt != Y->dt) return SELL_ERR_DTYPE;
+        if (Z->nrows != Y->nrows || Z->ncols != Y->ncols) return SELL_ERR_SHAPE;
+        if (Z->ptr == Y->ptr && B->rows > 0) return SELL_ERR_ARG;
+    }
+    const bool aug = o.flags != 0;
+    try {
+        return batch_aug_impl(B, X, Y, Z, o, aug, nullptr, true, static_cast<hipStream_t>(stream), nullptr, nullptr);
+    } catch (const std::bad_alloc &) {
+        return SELL_ERR_OOM;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,350 @@
+// batch_solve.cpp -- conjugate gradients for a batch of independent systems, all of them
+// advanced by the same kernel launches.
+//
+// Every system m (matrix A_m of the batch, right-hand sides B_m, one CG per column) keeps its
+// own FP64 scalars on the device. One iteration over the whole batch is five launches:
+//   Q = A P            batched product with the fused <p, A p> per system and column
+//   alpha              one workgroup per system
+//   D += a P, R -= a Q segmented vector kernel with the partials of <r, r>
+//   beta, rho, flags   one workgroup per system (a system whose columns have all converged
+//                      drops out: the product and vector kernels skip it)
+//   P = R + b P        segmented vector kernel
+// Runs of kCheckEvery iterations are captured once in a HIP graph and replayed (or launched
+// directly); the host looks at the scalars between runs.
+//
+// Precision: with a low-precision batch Alo (F32 or BF16 values) the iteration runs in FP32
+// vectors and accumulates a correction D, and the solution is refined in FP64 by reliable
+// updates per system: when the FP32 residual of one of the system's columns has dropped by
+// inner_tol since the system's last update (or after inner_maxit iterations), D is folded into
+// x in FP64 and the residual replaced by the true r = b - A64 x, computed in FP64 with the F64
+// matrix. Without Alo the iteration runs in FP64 on A64; a system's columns retire when their
+// recursive residual meets the tolerance and the true residual then confirms them (or
+// restarts the system from it). In both cases the search direction is kept across updates.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sellcs;
+
+namespace sellcs {
+int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
+                   const int32_t *active, bool finish, hipStream_t s, const int32_t **out_blk,
+                   const double **out_partials);
+const sell_mat *batch_matrix(const sell_batch *B, int m);
+int32_t batch_count(const sell_batch *B);
+int64_t batch_rows(const sell_batch *B);
+int batch_vdt(const sell_batch *B);
+BatchSeg batch_seg(const sell_batch *B);
+}  // namespace sellcs
+
+namespace {
+
+#define HIPCHK(x)                                                                             \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? SELL_ERR_OOM : SELL_ERR_HIP; \
+    } while (0)
+
+constexpr int kCheckEvery = 8;
+
+struct DevBuffers {
+    std::vector<void *> ptrs;
+    ~DevBuffers() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    int alloc(void **p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 16;
+        HIPCHK(hipMalloc(p, bytes));
+        ptrs.push_back(*p);
+        return SELL_OK;
+    }
+};
+
+struct OwnedStream {
+    hipStream_t s = nullptr;
+    bool owned = false;
+    ~OwnedStream() {
+        if (owned) {
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+        }
+    }
+};
+
+struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    ~Graph() {
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+sell_bv view(void *p, int64_t n, int b, int dt) {
+    sell_bv v;
+    v.nrows = n;
+    v.ncols = b;
+    v.dt = dt;
+    v.lay = SELL_ROW_MAJOR;
+    v.ptr = p;
+    v.ld = b;
+    v.owned = false;
+    return v;
+}
+
+int check_batches(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, const sell_bv *X) {
+    if (!A64 || !Bv || !X) return SELL_ERR_ARG;
+    if (batch_vdt(A64) != SELL_F64) return SELL_ERR_DTYPE;
+    const int K = batch_count(A64);
+    for (int m = 0; m < K; ++m) {
+        const sell_mat *A = batch_matrix(A64, m);
+        int rc = check_device(A);
+        if (rc) return rc;
+        if (A->h.nrows != A->h.ncols) return SELL_ERR_SHAPE;
+    }
+    if (Alo) {
+        if (batch_vdt(Alo) == SELL_F64) return SELL_ERR_DTYPE;
+        if (batch_count(Alo) != K) return SELL_ERR_SHAPE;
+        for (int m = 0; m < K; ++m) {
+            const sell_mat *A = batch_matrix(A64, m), *L = batch_matrix(Alo, m);
+            int rc = check_device(L);
+            if (rc) return rc;
+            if (L->h.nrows != A->h.nrows || L->h.ncols != A->h.ncols || L->h.nnz != A->h.nnz) return SELL_ERR_SHAPE;
+        }
+    }
+    if (Bv->dt != SELL_F64 || X->dt != SELL_F64) return SELL_ERR_DTYPE;
+    const int64_t n = batch_rows(A64);
+    if (Bv->nrows != n || X->nrows != n || Bv->ncols != X->ncols) return SELL_ERR_SHAPE;
+    if (Bv->ncols < 1 || Bv->ncols > 64) return SELL_ERR_UNSUPPORTED;
+    if (Bv->lay != SELL_ROW_MAJOR || X->lay != SELL_ROW_MAJOR || Bv->ld != Bv->ncols || X->ld != X->ncols)
+        return SELL_ERR_UNSUPPORTED;
+    if ((!Bv->ptr || !X->ptr) && n > 0) return SELL_ERR_ARG;
+    return SELL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *X, double tol, int64_t maxit,
+                  double inner_tol, int64_t inner_maxit, uint32_t flags, sell_cg_stats *stats, void *stream) {
+    int rc = check_batches(A64, Alo, Bv, X);
+    if (rc) return rc;
+    const bool mixed = Alo != nullptr;
+    if (!(tol > 0) || maxit < 0 || inner_maxit < 1) return SELL_ERR_ARG;
+    if (mixed && !(inner_tol > 0 && inner_tol < 1)) return SELL_ERR_ARG;
+    if (flags & ~uint32_t(SELL_BATCH_GRAPH)) return SELL_ERR_ARG;
+    const bool use_graph = (flags & SELL_BATCH_GRAPH) != 0;
+    const int K = batch_count(A64);
+    const int b = Bv->ncols;
+    const int64_t n = batch_rows(A64);
+    const int idt = mixed ? SELL_F32 : SELL_F64;  // vector type of the iteration
+    const size_t isz = mixed ? sizeof(float) : sizeof(double);
+    sell_batch *Ain = mixed ? Alo : A64;
+    const BatchSeg sg = batch_seg(A64);
+    const size_t Kb = size_t(K) * b;
+
+    // a stream of our own when the caller passes the legacy default stream (which cannot be
+    // captured); created blocking, so it is ordered after the caller's earlier work
+    OwnedStream os;
+    os.s = static_cast<hipStream_t>(stream);
+    if (!os.s) {
+        HIPCHK(hipStreamCreate(&os.s));
+        os.owned = true;
+    }
+    hipStream_t s = os.s;
+
+    DevBuffers DB;
+    void *pr64, *pr, *pd, *pp, *pq, *pscal;
+    const size_t nv = size_t(n) * b;
+    if ((rc = DB.alloc(&pr64, nv * sizeof(double))) || (rc = DB.alloc(&pr, nv * isz)) ||
+        (rc = DB.alloc(&pd, nv * isz)) || (rc = DB.alloc(&pp, nv * isz)) || (rc = DB.alloc(&pq, nv * isz)))
+        return rc;
+    // device scalars: rho alpha beta thresh2 bb rr(3Kb) | vec partials (b G) | int32 flags
+    const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * size_t(std::max(sg.G, 1));
+    const size_t ni = Kb + 3 * size_t(K) + 2 * size_t(K);  // active, sys_active, mask, spare | iters (int64)
+    if ((rc = DB.alloc(&pscal, nd * sizeof(double) + ni * sizeof(int32_t) + 16)))
+        return rc;
+    double *d = static_cast<double *>(pscal);
+    BatchCg sc;
+    sc.rho = d;
+    sc.alpha = d + Kb;
+    sc.beta = d + 2 * Kb;
+    sc.thresh2 = d + 3 * Kb;
+    double *bb_d = d + 4 * Kb;
+    double *rr_d = d + 5 * Kb;
+    double *vparts = d + 8 * Kb;
+    int32_t *ip = reinterpret_cast<int32_t *>(d + nd);
+    sc.active = ip;
+    sc.sys_active = ip + Kb;
+    int32_t *mask_d = ip + Kb + K;
+    int64_t *iters_d = reinterpret_cast<int64_t *>(ip + Kb + 3 * size_t(K));
+    // align the int64 counters
+    iters_d = reinterpret_cast<int64_t *>((reinterpret_cast<uintptr_t>(iters_d) + 7) & ~uintptr_t(7));
+    sc.iters = iters_d;
+
+    sell_bv Bview = *Bv;
+    sell_bv R64 = view(pr64, n, b, SELL_F64), R = view(pr, n, b, idt), D = view(pd, n, b, idt),
+            P = view(pp, n, b, idt), Q = view(pq, n, b, idt);
+    if ((rc = launch_fill(pd, idt, n, b, b, 1, 0.0, s))) return rc;
+    if ((rc = launch_fill(pp, idt, n, b, b, 1, 0.0, s))) return rc;
+    if ((rc = launch_fill(iters_d, SELL_F64, 1, K, K, 1, 0.0, s))) return rc;  // all-zero bits
+    // ||b||^2 per system and column
+    if ((rc = bcg_launch_coldot(SELL_F64, Bv->ptr, Bv->ptr, b, sg, nullptr, vparts, bb_d, nullptr, nullptr, 0.0, s)))
+        return rc;
+    std::vector<double> bb(Kb), rr(3 * Kb), rho(Kb), rho_last(Kb, 0.0), relres(size_t(K), INFINITY);
+    std::vector<int32_t> act(Kb, 1), sysact(size_t(K), 0), conv(size_t(K), 0), mask(size_t(K), 0);
+    std::vector<int64_t> since(size_t(K), 0), refine(size_t(K), 0), its(size_t(K), 0);
+    HIPCHK(hipMemcpyAsync(bb.data(), bb_d, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+
+    // Reliable update of the systems with mask[m] != 0: fold D into x, true residual in FP64,
+    // restart the systems that have not converged from it.
+    auto refresh = [&]() -> int {
+        int r;
+        HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if ((r = bcg_launch_refresh_prep(idt, static_cast<double *>(X->ptr), pd, static_cast<double *>(pr64),
+                                         static_cast<const double *>(Bv->ptr), b, sg, mask_d, s)))
+            return r;
+        sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+        o.flags = SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY;
+        o.alpha = -1.0;
+        o.beta = 1.0;
+        o.dot = rr_d;
+        if ((r = batch_aug_impl(A64, X, &R64, nullptr, o, true, mask_d, true, s, nullptr, nullptr))) return r;
+        HIPCHK(hipMemcpyAsync(rr.data(), rr_d, 3 * Kb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool restart = false;
+        for (int m = 0; m < K; ++m) {
+            if (!mask[size_t(m)]) continue;
+            ++refine[size_t(m)];
+            since[size_t(m)] = 0;
+            double worst = 0.0;
+            bool all = true;
+            for (int j = 0; j < b; ++j) {
+                const size_t q = size_t(m) * b + j;
+                const double r2 = rr[size_t(m) * 3 * b + j];  // group <y, y> of matrix m
+                const double rel = bb[q] > 0 ? std::sqrt(r2 / bb[q]) : std::sqrt(r2);
+                if (!(rel <= worst)) worst = rel;  // NaN propagates
+                act[q] = rel <= tol ? 0 : 1;
+                all = all && !act[q];
+            }
+            relres[size_t(m)] = worst;
+            conv[size_t(m)] = all ? 1 : 0;
+            sysact[size_t(m)] = all ? 0 : 1;
+            if (all) mask[size_t(m)] = 0;  // nothing to restart
+            restart = restart || !all;
+        }
+        HIPCHK(hipMemcpyAsync(sc.active, act.data(), Kb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(sc.sys_active, sysact.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (!restart) return SELL_OK;
+        HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // r = r64 in the iteration's precision, rho = <r, r>; the recursion retires a column
+        // itself only in FP64 (thresh2 = tol^2 ||b||^2), in FP32 only the true residual does
+        if ((r = bcg_launch_convert(idt, pr, static_cast<const double *>(pr64), b, sg, mask_d, vparts, sc.rho,
+                                    sc.thresh2, bb_d, mixed ? 0.0 : tol * tol, s)))
+            return r;
+        HIPCHK(hipMemcpyAsync(rho.data(), sc.rho, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int m = 0; m < K; ++m)
+            if (mask[size_t(m)])
+                for (int j = 0; j < b; ++j) rho_last[size_t(m) * b + j] = rho[size_t(m) * b + j];
+        return SELL_OK;
+    };
+
+    // first update: every system, x0 = X (D = 0); then p = r
+    std::fill(mask.begin(), mask.end(), 1);
+    if ((rc = refresh())) return rc;
+    std::fill(mask.begin(), mask.end(), 1);
+    HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if ((rc = bcg_launch_copy(idt, pp, pr, b, sg, mask_d, s))) return rc;
+
+    sell_spmv_opts po = SELL_SPMV_OPTS_INIT;
+    po.flags = SELL_SPMV_DOT_XY;
+    auto iteration = [&]() -> int {
+        int r;
+        const int32_t *pblk = nullptr;
+        const double *pparts = nullptr;
+        if ((r = batch_aug_impl(Ain, &P, &Q, nullptr, po, true, sc.sys_active, false, s, &pblk, &pparts))) return r;
+        if ((r = bcg_launch_alpha(pparts, pblk, K, b, sc, s))) return r;
+        if ((r = bcg_launch_xr(idt, pd, pr, pp, pq, b, sg, sc, vparts, s))) return r;
+        return bcg_launch_p(idt, pp, pr, b, sg, sc, s);
+    };
+
+    Graph graph;
+    bool done = std::all_of(conv.begin(), conv.end(), [](int32_t c) { return c != 0; });
+    int64_t it = 0;
+    std::vector<int32_t> act_now(Kb), sys_now(static_cast<size_t>(K));
+    while (!done && it < maxit) {
+        const int64_t run = std::min<int64_t>(kCheckEvery, maxit - it);
+        if (use_graph && run == kCheckEvery && it > 0) {
+            // the first run is launched directly (it places the product's table on the
+            // device); the graph is captured from the second run on and replayed
+            if (!graph.ge) {
+                HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                int r = SELL_OK;
+                for (int k = 0; k < run && r == SELL_OK; ++k) r = iteration();
+                hipGraph_t g = nullptr;
+                const hipError_t e = hipStreamEndCapture(s, &g);
+                graph.g = g;
+                if (r) return r;
+                HIPCHK(e);
+                HIPCHK(hipGraphInstantiate(&graph.ge, graph.g, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(graph.ge, s));
+        } else {
+            for (int64_t k = 0; k < run; ++k)
+                if ((rc = iteration())) return rc;
+        }
+        it += run;
+        for (int m = 0; m < K; ++m)
+            if (sysact[size_t(m)]) since[size_t(m)] += run;
+        HIPCHK(hipMemcpyAsync(rho.data(), sc.rho, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(act_now.data(), sc.active, Kb * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(sys_now.data(), sc.sys_active, K * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        bool any = false;
+        for (int m = 0; m < K; ++m) {
+            mask[size_t(m)] = 0;
+            if (conv[size_t(m)]) continue;
+            bool upd = it >= maxit || since[size_t(m)] >= inner_maxit;
+            if (mixed) {
+                for (int j = 0; j < b; ++j) {
+                    const size_t q = size_t(m) * b + j;
+                    if (act[q] && !(rho[q] > inner_tol * inner_tol * rho_last[q])) upd = true;  // NaN too
+                }
+            } else {
+                upd = upd || !sys_now[size_t(m)];  // the recursion retired every column
+            }
+            if (upd) {
+                mask[size_t(m)] = 1;
+                any = true;
+            }
+        }
+        if (!mixed) {
+            // keep the host's view of the column flags in step with the recursion's
+            for (size_t q = 0; q < Kb; ++q) act[q] = act_now[q];
+            for (int m = 0; m < K; ++m) sysact[size_t(m)] = sys_now[size_t(m)];
+        }
+        if (any && (rc = refresh())) return rc;
+        done = std::all_of(conv.begin(), conv.end(), [](int32_t c) { return c != 0; });
+    }
+    HIPCHK(hipMemcpyAsync(its.data(), iters_d, K * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (stats)
+        for (int m = 0; m < K; ++m) {
+            sell_cg_stats st;
+            st.iterations = its[size_t(m)];
+            st.refinements = refine[size_t(m)] > 0 ? refine[size_t(m)] - 1 : 0;
+            st.relres = relres[size_t(m)];
+            st.converged = conv[size_t(m)];
+            stats[m] = st;
+        }
+    (void)Bview;
+    return SELL_OK;
+}
+
+}  // extern "C"

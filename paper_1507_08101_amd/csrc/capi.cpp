@@ -114,7 +114,7 @@ int get_workspace(hipStream_t s, Workspace **ws) {
 
 }  // namespace sellcs
 
-namespace {
+namespace sellcs {
 
 int check_device(const sell_mat *A) {
     if (!A) return SELL_ERR_ARG;
@@ -191,9 +191,6 @@ int validate_bv(const sell_bv *v) {
     return SELL_OK;
 }
 
-}  // namespace
-
-namespace sellcs {
 
 // y = alpha (A x - gamma x) + beta y, dots, chain; no argument checks (callers check).
 int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o,
@@ -466,20 +463,13 @@ int sell_update_values_device(sell_mat *A, const double *val, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     try {
         if ((rc = ensure_update_maps(A, s))) return rc;
-        if (A->transpose && (rc = ensure_update_maps(A->transpose, s))) return rc;
     } catch (const std::bad_alloc &) {
         return SELL_ERR_OOM;
     }
     if ((rc = launch_update_values(A, val, s))) return rc;
-    if (A->transpose && A->h.nnz > 0) {
-        // keep the SELL copy of A^T in step: permute the values into its CSR order
-        double *tv = nullptr;
-        HIPCHK(hipMallocAsync(reinterpret_cast<void **>(&tv), size_t(A->h.nnz) * sizeof(double), s));
-        rc = launch_scatter(val, A->d_tpos, A->h.nnz, tv, s);
-        if (rc == SELL_OK) rc = launch_update_values(A->transpose, tv, s);
-        hipError_t e = hipFreeAsync(tv, s);
-        if (rc == SELL_OK && e != hipSuccess) rc = hip_err(e);
-    }
+    // keep the SELL copy of A^T in step: every value goes straight to its slot there
+    if (A->transpose && A->h.nnz > 0)
+        rc = launch_scatter_values(val, A->d_tpos, A->h.nnz, A->transpose->h.vdt, A->transpose->d_val, s);
     return rc;
 }
 
@@ -653,6 +643,23 @@ int ensure_transpose(const sell_mat *A, hipStream_t s) {
     rc = build_common(&T, h.ncols, h.nrows, trp.data(), tcol.data(), tval.data(), h.C, h.sigma,
                       sell_dtype(h.vdt), true, s);
     if (rc) return rc;
+    // turn the A^T CSR positions into A^T SELL positions, so that a value update of A
+    // refreshes the copy with one scatter
+    {
+        const HostSell &th = T->h;
+        std::vector<int64_t> slot_of(static_cast<size_t>(th.nrows));
+        for (int64_t slot = 0; slot < th.nch * th.C; ++slot) {
+            const int64_t row = th.has_perm ? th.perm[slot] : (slot < th.nrows ? slot : -1);
+            if (row >= 0) slot_of[row] = slot;
+        }
+        std::vector<int64_t> sell_of_q(static_cast<size_t>(h.nnz));
+        for (int64_t t = 0; t < th.nrows; ++t) {
+            const int64_t c = slot_of[t] / th.C, r = slot_of[t] % th.C;
+            for (int64_t q = th.rowptr[t]; q < th.rowptr[t + 1]; ++q)
+                sell_of_q[q] = th.cs[c] + (q - th.rowptr[t]) * th.C + r;
+        }
+        for (int64_t p = 0; p < h.nnz; ++p) tpos[p] = sell_of_q[tpos[p]];
+    }
     sell_mat *M = const_cast<sell_mat *>(A);
     rc = dev_upload(&M->d_tpos, tpos.data(), tpos.size(), s);
     if (rc == SELL_OK && hipStreamSynchronize(s) != hipSuccess) rc = SELL_ERR_HIP;

@@ -152,6 +152,201 @@ __global__ void __launch_bounds__(kVT) axpy_mixed_kernel(double *X, const float 
     }
 }
 
+// ---------------------------------------------------------------- batched variants
+// A batch of K independent systems stores its block vectors one after another (system m owns
+// rows [row_off[m], row_off[m+1])). The workgroups of a vector launch are split over the
+// systems: workgroups [vblk[m], vblk[m+1]) serve system m, so every workgroup works on one
+// system and the per-system column sums stay deterministic. Workgroup partials go to
+// partials[j * G + g] (G workgroups in total); those of system m, column j, are the
+// contiguous range [j * G + vblk[m], j * G + vblk[m+1]). Scalars are indexed m * b + j.
+
+__device__ __forceinline__ int seg_of(int g, const int32_t *blk, int K) {
+    int lo = 0, hi = K;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blk[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Row loop of workgroup g over its system's rows: calls f(row) for the rows of this lane.
+template <class F>
+__device__ __forceinline__ void seg_rows(const BatchSeg &sg, int m, int bpad, F &&f) {
+    const int g = blockIdx.x;
+    const int lb = g - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
+    const int rows_per = kVT / bpad;
+    const int64_t r1 = sg.row_off[m + 1];
+    for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / bpad; i < r1;
+         i += int64_t(nbl) * rows_per)
+        f(i);
+}
+
+// alpha[m, j] = rho[m, j] / <p, A p>[m, j] from the batched product's partials (quantity
+// b + j of matrix m: pparts + 3 b pblk[m] + (b + j) npm, npm = pblk[m+1] - pblk[m]).
+// One workgroup per system.
+__global__ void __launch_bounds__(kVT) bcg_alpha_kernel(const double *pparts, const int32_t *pblk, int b,
+                                                        BatchCg sc) {
+    const int m = blockIdx.x;
+    if (!sc.sys_active[m]) return;
+    const int npm = pblk[m + 1] - pblk[m];
+    const double *base = pparts + size_t(3) * b * pblk[m];
+    for (int j = 0; j < b; ++j) {
+        const double pq = sum_partials(base + size_t(b + j) * npm, npm);
+        if (threadIdx.x == 0) {
+            const int q = m * b + j;
+            sc.alpha[q] = (sc.active[q] && pq != 0.0) ? sc.rho[q] / pq : 0.0;
+        }
+    }
+}
+
+// d += alpha p ; r -= alpha q on the rows of active systems; partials of <r, r>.
+template <class T>
+__global__ void __launch_bounds__(kVT) bcg_xr_kernel(T *D, T *R, const T *P, const T *Q, int b, int bpad,
+                                                     BatchSeg sg, BatchCg sc, double *partials) {
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int j = threadIdx.x & (bpad - 1);
+    double acc = 0.0;
+    if (j < b && sc.sys_active[m]) {
+        const double alpha = sc.alpha[m * b + j];
+        seg_rows(sg, m, bpad, [&](int64_t i) {
+            const int64_t e = i * b + j;
+            const T d = T(double(D[e]) + alpha * double(P[e]));
+            const T r = T(double(R[e]) - alpha * double(Q[e]));
+            D[e] = d;
+            R[e] = r;
+            acc += double(r) * double(r);
+        });
+    }
+    colsum_store(acc, bpad, b, partials);
+}
+
+// rho_new = <r, r>; beta = rho_new / rho; rho = rho_new; active &= rho_new > thresh2;
+// the system stays active while one of its columns is; its iteration counter advances.
+__global__ void __launch_bounds__(kVT) bcg_beta_kernel(const double *partials, int G, BatchSeg sg, int b,
+                                                       BatchCg sc) {
+    const int m = blockIdx.x;
+    if (!sc.sys_active[m]) return;
+    const int v0 = sg.vblk[m], nv = sg.vblk[m + 1] - v0;
+    int any = 0;
+    for (int j = 0; j < b; ++j) {
+        const double rn = sum_partials(partials + size_t(j) * G + v0, nv);
+        if (threadIdx.x == 0) {
+            const int q = m * b + j;
+            const double rho = sc.rho[q];
+            const bool act = sc.active[q] != 0;
+            sc.beta[q] = (act && rho != 0.0) ? rn / rho : 0.0;
+            sc.rho[q] = rn;
+            const int still = (act && rn > sc.thresh2[q]) ? 1 : 0;
+            sc.active[q] = still;
+            any |= still;
+        }
+    }
+    if (threadIdx.x == 0) {
+        sc.sys_active[m] = any;
+        sc.iters[m] += 1;
+    }
+}
+
+// p = r + beta p on the rows of active systems
+template <class T>
+__global__ void __launch_bounds__(kVT) bcg_p_kernel(T *P, const T *R, int b, int bpad, BatchSeg sg, BatchCg sc) {
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int j = threadIdx.x & (bpad - 1);
+    if (j >= b || !sc.sys_active[m]) return;
+    const double beta = sc.beta[m * b + j];
+    seg_rows(sg, m, bpad, [&](int64_t i) {
+        const int64_t e = i * b + j;
+        P[e] = T(double(R[e]) + beta * double(P[e]));
+    });
+}
+
+// Per-workgroup partials of <U_j, V_j> on the rows of the systems with mask[m] != 0
+// (all systems when mask is null).
+template <class T>
+__global__ void __launch_bounds__(kVT) bcoldot_kernel(const T *U, const T *V, int b, int bpad, BatchSeg sg,
+                                                      const int32_t *mask, double *partials) {
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int j = threadIdx.x & (bpad - 1);
+    double acc = 0.0;
+    if (j < b && (!mask || mask[m]))
+        seg_rows(sg, m, bpad, [&](int64_t i) { acc += double(U[i * b + j]) * double(V[i * b + j]); });
+    colsum_store(acc, bpad, b, partials);
+}
+
+// result[m, j] = sum of the partials of system m, column j (systems with mask[m] != 0 only);
+// optionally thresh2[m, j] = f2 * (ref[m, j] or result[m, j]).
+__global__ void __launch_bounds__(kVT) bcoldot_finish_kernel(const double *partials, int G, BatchSeg sg, int b,
+                                                             const int32_t *mask, double *result, double *thresh2,
+                                                             const double *ref, double f2) {
+    const int m = blockIdx.x;
+    if (mask && !mask[m]) return;
+    const int v0 = sg.vblk[m], nv = sg.vblk[m + 1] - v0;
+    for (int j = 0; j < b; ++j) {
+        const double v = sum_partials(partials + size_t(j) * G + v0, nv);
+        if (threadIdx.x == 0) {
+            const int q = m * b + j;
+            result[q] = v;
+            if (thresh2) thresh2[q] = f2 * (ref ? ref[q] : v);
+        }
+    }
+}
+
+// Start of a residual refresh on the systems with mask[m] != 0: x += d, d = 0, r64 = b.
+template <class T>
+__global__ void __launch_bounds__(kVT) brefresh_prep_kernel(double *X, T *D, double *R64, const double *Bv, int b,
+                                                            int bpad, BatchSeg sg, const int32_t *mask) {
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int j = threadIdx.x & (bpad - 1);
+    if (j >= b || !mask[m]) return;
+    seg_rows(sg, m, bpad, [&](int64_t i) {
+        const int64_t e = i * b + j;
+        X[e] += double(D[e]);
+        D[e] = T(0);
+        R64[e] = Bv[e];
+    });
+}
+
+// r = T(r64) (round to nearest) on the systems with mask[m] != 0, with partials of <r, r>.
+template <class T>
+__global__ void __launch_bounds__(kVT) bconvert_kernel(T *R, const double *R64, int b, int bpad, BatchSeg sg,
+                                                       const int32_t *mask, double *partials) {
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int j = threadIdx.x & (bpad - 1);
+    double acc = 0.0;
+    if (j < b && mask[m])
+        seg_rows(sg, m, bpad, [&](int64_t i) {
+            const T r = T(R64[i * b + j]);
+            R[i * b + j] = r;
+            acc += double(r) * double(r);
+        });
+    colsum_store(acc, bpad, b, partials);
+}
+
+// p = r on the systems with mask[m] != 0
+template <class T>
+__global__ void __launch_bounds__(kVT) bcopy_kernel(T *P, const T *R, int b, int bpad, BatchSeg sg,
+                                                    const int32_t *mask) {
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int j = threadIdx.x & (bpad - 1);
+    if (j >= b || !mask[m]) return;
+    seg_rows(sg, m, bpad, [&](int64_t i) { P[i * b + j] = R[i * b + j]; });
+}
+
+// Dots of a batched product: dot[m * 3 nb + q] = sum of the partials of quantity q of matrix m
+// (partials + 3 nb blk[m] + q npm, npm = blk[m+1] - blk[m]) for the requested groups.
+__global__ void __launch_bounds__(kVT) batch_dot_finish_kernel(const double *partials, const int32_t *blk,
+                                                               int32_t nb, uint32_t flags, double *dot) {
+    const int q = blockIdx.x, m = blockIdx.y, g = q / nb;
+    const uint32_t want = g == 0 ? SELL_SPMV_DOT_YY : g == 1 ? SELL_SPMV_DOT_XY : SELL_SPMV_DOT_XX;
+    if (!(flags & want)) return;
+    const int npm = blk[m + 1] - blk[m];
+    const double v = sum_partials(partials + size_t(3) * nb * blk[m] + size_t(q) * npm, npm);
+    if (threadIdx.x == 0) dot[size_t(m) * 3 * nb + q] = v;
+}
+
 static unsigned vgrid(int64_t work, unsigned cap) {
     int64_t g = (work + kVT - 1) / kVT;
     if (g < 1) g = 1;
@@ -229,6 +424,105 @@ int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int6
 int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
                          hipStream_t s) {
     hipLaunchKernelGGL(axpy_mixed_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, X, D, n, b, ld, scale);
+    return ok();
+}
+
+// ---------------------------------------------------------------- batched launchers
+namespace {
+template <class T>
+T *tp(void *p) { return static_cast<T *>(p); }
+template <class T>
+const T *ctp(const void *p) { return static_cast<const T *>(p); }
+}  // namespace
+
+int bcg_launch_alpha(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s) {
+    hipLaunchKernelGGL(bcg_alpha_kernel, dim3(K), dim3(kVT), 0, s, pparts, pblk, b, sc);
+    return ok();
+}
+
+int bcg_launch_xr(int dt, void *D, void *R, const void *P, const void *Q, int b, const BatchSeg &sg,
+                  const BatchCg &sc, double *partials, hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(bcg_xr_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(D), tp<double>(R),
+                           ctp<double>(P), ctp<double>(Q), b, bpad, sg, sc, partials);
+    else
+        hipLaunchKernelGGL(bcg_xr_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(D), tp<float>(R),
+                           ctp<float>(P), ctp<float>(Q), b, bpad, sg, sc, partials);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(bcg_beta_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, sc);
+    return ok();
+}
+
+int bcg_launch_p(int dt, void *P, const void *R, int b, const BatchSeg &sg, const BatchCg &sc, hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(bcg_p_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), ctp<double>(R), b, bpad,
+                           sg, sc);
+    else
+        hipLaunchKernelGGL(bcg_p_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(P), ctp<float>(R), b, bpad,
+                           sg, sc);
+    return ok();
+}
+
+int bcg_launch_coldot(int dt, const void *U, const void *V, int b, const BatchSeg &sg, const int32_t *mask,
+                      double *partials, double *result, double *thresh2, const double *ref, double f2,
+                      hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(bcoldot_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, ctp<double>(U), ctp<double>(V), b,
+                           bpad, sg, mask, partials);
+    else
+        hipLaunchKernelGGL(bcoldot_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, ctp<float>(U), ctp<float>(V), b,
+                           bpad, sg, mask, partials);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(bcoldot_finish_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, mask, result,
+                       thresh2, ref, f2);
+    return ok();
+}
+
+int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const double *Bv, int b, const BatchSeg &sg,
+                            const int32_t *mask, hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(brefresh_prep_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, X, tp<double>(D), R64, Bv, b,
+                           bpad, sg, mask);
+    else
+        hipLaunchKernelGGL(brefresh_prep_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, X, tp<float>(D), R64, Bv, b,
+                           bpad, sg, mask);
+    return ok();
+}
+
+int bcg_launch_convert(int dt, void *R, const double *R64, int b, const BatchSeg &sg, const int32_t *mask,
+                       double *partials, double *rho, double *thresh2, const double *ref, double f2, hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(bconvert_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), R64, b, bpad, sg,
+                           mask, partials);
+    else
+        hipLaunchKernelGGL(bconvert_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(R), R64, b, bpad, sg,
+                           mask, partials);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(bcoldot_finish_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, mask, rho,
+                       thresh2, ref, f2);
+    return ok();
+}
+
+int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, const int32_t *mask, hipStream_t s) {
+    const int bpad = pow2_at_least(b);
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(bcopy_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), ctp<double>(R), b, bpad,
+                           sg, mask);
+    else
+        hipLaunchKernelGGL(bcopy_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(P), ctp<float>(R), b, bpad,
+                           sg, mask);
+    return ok();
+}
+
+int launch_batch_dot_finish(const double *partials, const int32_t *blk, int K, int32_t nb, uint32_t flags,
+                            double *dot, hipStream_t s) {
+    if (K < 1) return SELL_OK;
+    hipLaunchKernelGGL(batch_dot_finish_kernel, dim3(3 * nb, K), dim3(kVT), 0, s, partials, blk, nb, flags, dot);
     return ok();
 }
 

@@ -5,6 +5,7 @@
 // the sparsity pattern. It is accumulated here in SELL-C-sigma order (entry k of slot r of
 // chunk c at cs[c] + k*C + r), so consecutive lanes touch consecutive addresses, and mapped
 // to the caller's CSR order once at the end.
+#include "convert.h"
 #include "internal.h"
 
 namespace sellcs {
@@ -67,9 +68,10 @@ __global__ void __launch_bounds__(256) axpby_kernel(int64_t n, int32_t b, int64_
     }
 }
 
-__global__ void __launch_bounds__(256) scatter_kernel(const double *src, const int64_t *pos, int64_t n, double *dst) {
+template <class V>
+__global__ void __launch_bounds__(256) scatter_kernel(const double *src, const int64_t *pos, int64_t n, V *dst) {
     for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < n; p += int64_t(gridDim.x) * blockDim.x)
-        dst[pos[p]] = src[p];
+        dst[pos[p]] = Conv<V, double>::go(src[p]);
 }
 
 static unsigned ggrid(int64_t n) {
@@ -115,9 +117,17 @@ int launch_axpby(int vec_dt, int64_t n, int32_t b, int64_t ld, double alpha, con
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
-int launch_scatter(const double *src, const int64_t *pos, int64_t n, double *dst, hipStream_t s) {
+int launch_scatter_values(const double *src, const int64_t *pos, int64_t n, int vdt, void *dst, hipStream_t s) {
     if (n == 0) return SELL_OK;
-    hipLaunchKernelGGL(scatter_kernel, dim3(ggrid(n)), dim3(256), 0, s, src, pos, n, dst);
+    if (vdt == SELL_F64)
+        hipLaunchKernelGGL(scatter_kernel<double>, dim3(ggrid(n)), dim3(256), 0, s, src, pos, n,
+                           static_cast<double *>(dst));
+    else if (vdt == SELL_F32)
+        hipLaunchKernelGGL(scatter_kernel<float>, dim3(ggrid(n)), dim3(256), 0, s, src, pos, n,
+                           static_cast<float *>(dst));
+    else
+        hipLaunchKernelGGL(scatter_kernel<uint16_t>, dim3(ggrid(n)), dim3(256), 0, s, src, pos, n,
+                           static_cast<uint16_t *>(dst));
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 

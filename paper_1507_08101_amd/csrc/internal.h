@@ -63,7 +63,7 @@ struct sell_mat {
     int32_t *d_rowslot = nullptr; // row -> slot, built on first device value update
     int64_t *d_rowptr = nullptr;  // CSR row pointers, built on first device value update
     sell_mat *transpose = nullptr;  // SELL copy of A^T for the deterministic transpose
-    int64_t *d_tpos = nullptr;      // CSR position in A^T of each CSR entry of A (with transpose)
+    int64_t *d_tpos = nullptr;      // position in the SELL arrays of A^T of each CSR entry of A
     int64_t matrix_bytes = 0;
 };
 
@@ -151,6 +151,33 @@ int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int6
 int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
                          hipStream_t s);
 
+// Batched CG (cg.hip): K systems stored one after another in the block vectors.
+struct BatchSeg {
+    const int64_t *row_off;  // K + 1 row offsets (device)
+    const int32_t *vblk;     // K + 1 workgroup offsets of the vector kernels (device)
+    int32_t K, G;            // systems; workgroups of a vector launch (vblk[K])
+};
+struct BatchCg {
+    double *rho, *alpha, *beta, *thresh2;  // K * b each, index m * b + j
+    int32_t *active;                       // K * b column flags
+    int32_t *sys_active;                   // K system flags (some column active)
+    int64_t *iters;                        // K iteration counters
+};
+int bcg_launch_alpha(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s);
+int bcg_launch_xr(int dt, void *D, void *R, const void *P, const void *Q, int b, const BatchSeg &sg,
+                  const BatchCg &sc, double *partials, hipStream_t s);
+int bcg_launch_p(int dt, void *P, const void *R, int b, const BatchSeg &sg, const BatchCg &sc, hipStream_t s);
+int bcg_launch_coldot(int dt, const void *U, const void *V, int b, const BatchSeg &sg, const int32_t *mask,
+                      double *partials, double *result, double *thresh2, const double *ref, double f2,
+                      hipStream_t s);
+int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const double *Bv, int b, const BatchSeg &sg,
+                            const int32_t *mask, hipStream_t s);
+int bcg_launch_convert(int dt, void *R, const double *R64, int b, const BatchSeg &sg, const int32_t *mask,
+                       double *partials, double *rho, double *thresh2, const double *ref, double f2, hipStream_t s);
+int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, const int32_t *mask, hipStream_t s);
+int launch_batch_dot_finish(const double *partials, const int32_t *blk, int K, int32_t nb, uint32_t flags,
+                            double *dot, hipStream_t s);
+
 // The fused product of capi.cpp (no argument checks): y = alpha (A x - gamma x) + beta y,
 // dots, chain; aug = false runs the plain product y = A x.
 // partials_out == nullptr: the dots are summed into o.dot right away (workspace partials and
@@ -173,8 +200,17 @@ int launch_grad_accum(const sell_mat *A, const void *G, int64_t ldg, const void 
 int launch_sell_to_csr(const sell_mat *A, const double *dsell, int accumulate, double *dval, hipStream_t s);
 int launch_axpby(int vec_dt, int64_t n, int32_t b, int64_t ld, double alpha, const void *x, double beta, void *y,
                  hipStream_t s);
-// dst[pos[p]] = src[p] for p < n
-int launch_scatter(const double *src, const int64_t *pos, int64_t n, double *dst, hipStream_t s);
+// dst[pos[p]] = convert(src[p]) for p < n, dst of storage type vdt
+int launch_scatter_values(const double *src, const int64_t *pos, int64_t n, int vdt, void *dst, hipStream_t s);
+
+// Argument helpers of the entry points (capi.cpp).
+int check_device(const sell_mat *A);     // on the device and the current one
+int validate_bv(const sell_bv *v);
+int vec_kind(int vdt);                   // VecKind of a value type
+int vec_dtype_for(int vdt);              // block-vector type for a value type
+void bv_strides(const sell_bv *v, int64_t &rs, int64_t &cs);
+char *elem_ptr(const sell_bv *v, int64_t i, int64_t j);
+void base_args(ProdArgs &a, const sell_mat *A);  // matrix fields of a product launch
 
 // Per-(device, stream) workspace for reductions.
 struct Workspace {

@@ -124,8 +124,9 @@ constexpr int batch_len() {
 //        the block vectors are row-major with rows aligned for vector accesses (VEC).
 // B == 0: run-time width nb <= 64, one column per lane, VL = next power of two >= nb,
 //         any strides.
+// The product over the tiles of workgroup `tile` (one of a.nblocks) of one matrix.
 template <int VK, int B, int VPT, bool AUG>
-__global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
+__device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, const int vl_log2) {
     using V = typename KTypes<VK>::V;
     using X = typename KTypes<VK>::X;
     using Acc = typename KTypes<VK>::Acc;
@@ -136,8 +137,12 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
 
-    const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
     const int C = a.C;
+    const int32_t cshift = a.cshift;
+    const int32_t *__restrict__ perm = a.perm;
+    const int32_t *__restrict__ clp = a.cl;
+    const int64_t *__restrict__ csp = a.cs;
+    const int64_t nrows = a.nrows;
     const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
     const int64_t s_begin = int64_t(a.tiles[t0]) * C;
     const int64_t s_end = int64_t(a.tiles[t1]) * C;
@@ -163,6 +168,8 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const bool chain = AUG && (a.flags & SELL_SPMV_CHAIN);
     const bool read_z = chain && a.delta != 0.0;
     const double alpha = (AUG && (a.flags & SELL_SPMV_SCALE)) ? a.alpha : 1.0;
+    const double beta = a.beta, delta = a.delta, eta = a.eta;
+    X *const scratch_base = static_cast<X *>(a.scratch);
 
     double dyy[VPT], dxy[VPT], dxx[VPT];
 #pragma unroll
@@ -179,10 +186,10 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     // overlaps the current pass.
     auto load_meta = [&](int64_t ss, int &clv, int64_t &csv, int &pv) {
         const int64_t sc = ss < s_end ? ss : s_end - 1;
-        const int64_t c = a.cshift >= 0 ? (sc >> a.cshift) : int64_t(uint32_t(sc) / uint32_t(C));
-        const int32_t *pp = a.perm ? a.perm + sc : a.cl + c;
-        clv = a.cl[c];
-        csv = a.cs[c];
+        const int64_t c = cshift >= 0 ? (sc >> cshift) : int64_t(uint32_t(sc) / uint32_t(C));
+        const int32_t *pp = perm ? perm + sc : clp + c;
+        clv = clp[c];
+        csv = csp[c];
         pv = *pp;
     };
 
@@ -195,10 +202,10 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     // held up behind them.
     __builtin_amdgcn_s_waitcnt(0);
     for (; s < s_end; s += rows_per_pass) {
-        const int64_t c = a.cshift >= 0 ? (s >> a.cshift) : int64_t(uint32_t(s) / uint32_t(C));
+        const int64_t c = cshift >= 0 ? (s >> cshift) : int64_t(uint32_t(s) / uint32_t(C));
         const int len = cl_n;
         const int64_t base = cs_n + (s - c * C);
-        const int64_t row = s < a.nrows ? (a.perm ? int64_t(pv_n) : s) : -1;
+        const int64_t row = s < nrows ? (perm ? int64_t(pv_n) : s) : -1;
         load_meta(s + rows_per_pass, cl_n, cs_n, pv_n);  // one pass ahead
         const bool live = row >= 0 && col_ok;
         // Lanes without an output row (slots past the last row, or unused columns of the
@@ -252,7 +259,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
             }
         }
 
-        X *scratch = static_cast<X *>(a.scratch) + size_t(tid) * VPT;
+        X *scratch = scratch_base + size_t(tid) * VPT;
         X *ydst = live ? Yp + row * yrs + int64_t(jb) * ycs : scratch;
         const int64_t ysd = live ? ycs : 1;
         X out[VPT];
@@ -268,7 +275,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
                 double tv = double(acc[t]);
                 if (shift) tv = tv - gam[t] * xv;
                 double y = alpha * tv;
-                if (read_y) y = y + a.beta * double(yin[t]);
+                if (read_y) y = y + beta * double(yin[t]);
                 out[t] = X(y);
                 const double yd = double(out[t]);
                 if (want_dots && live) {
@@ -276,8 +283,8 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
                     dxy[t] += xv * yd;
                     dxx[t] += xv * xv;
                 }
-                double z = a.eta * yd;
-                if (read_z) z = a.delta * double(zin[t]) + z;
+                double z = eta * yd;
+                if (read_z) z = delta * double(zin[t]) + z;
                 zout[t] = X(z);
             }
             store_row<X, VPT, VEC>(ydst, ysd, out);
@@ -319,6 +326,38 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         for (int ww = 0; ww < kBlock / 64; ++ww) sum += red[ww][q];
         a.partials[size_t(q) * a.nblocks + tile] = sum;
     }
+}
+
+template <int VK, int B, int VPT, bool AUG>
+__global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
+    const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
+    prod_body<VK, B, VPT, AUG>(a, tile, vl_log2);
+}
+
+// One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
+// (XCD-remapped) grid work on matrix m, whose launch arguments are table[m].
+template <int VK, int B, int VPT, bool AUG>
+// A matrix m with active != null and active[m] == 0 is skipped (its dot partials are zeroed).
+__global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__restrict__ table,
+                                                            const int32_t *__restrict__ blk_start, int K,
+                                                            const int32_t *__restrict__ active, int vl_log2) {
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = K;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blk_start[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const ProdArgs &a = table[lo];
+    const int tile = g - blk_start[lo];
+    if (active && !active[lo]) {
+        if (AUG && (a.flags & SELL_SPMV_DOTS))
+            for (int q = threadIdx.x; q < 3 * a.nb; q += kBlock) a.partials[size_t(q) * a.nblocks + tile] = 0.0;
+        return;
+    }
+    prod_body<VK, B, VPT, AUG>(a, tile, vl_log2);
 }
 
 // Transposed product by scattering with floating-point atomics: Y[col, j] += v * X[row, j].
@@ -415,6 +454,30 @@ int dispatch_prod(ProdArgs &a, hipStream_t s, bool fixed_ok) {
         }
     }
     return go_prod<VK, 0, 1, AUG>(a, s);
+}
+
+template <int VK, int B, int VPT, bool AUG>
+inline const void *bk() {
+    return reinterpret_cast<const void *>(prod_batch_kernel<VK, B, VPT, AUG>);
+}
+
+// The batched kernel for (width, columns per lane); fixed_ok as in dispatch_prod.
+template <int VK, bool AUG>
+const void *batch_kernel_for(int b, int vpt, bool fixed_ok) {
+    if (fixed_ok) {
+        switch (b) {
+            case 1: return bk<VK, 1, 1, AUG>();
+            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>() : bk<VK, 2, 1, AUG>();
+            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>() : vpt == 2 ? bk<VK, 4, 2, AUG>() : bk<VK, 4, 1, AUG>();
+            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>() : vpt == 2 ? bk<VK, 8, 2, AUG>() : bk<VK, 8, 1, AUG>();
+            case 16:
+                return vpt >= 4 ? bk<VK, 16, 4, AUG>() : vpt == 2 ? bk<VK, 16, 2, AUG>() : bk<VK, 16, 1, AUG>();
+            case 32:
+                return vpt >= 4 ? bk<VK, 32, 4, AUG>() : vpt == 2 ? bk<VK, 32, 2, AUG>() : bk<VK, 32, 1, AUG>();
+            default: break;
+        }
+    }
+    return bk<VK, 0, 1, AUG>();
 }
 
 template <int VK>

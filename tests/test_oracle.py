@@ -451,3 +451,35 @@ def test_pattern_outer_is_gradient_of_bilinear_form(orc):
     dval = orc.pattern_outer(A, G, X)
     rows = np.repeat(np.arange(40), A.row_lengths())
     assert np.allclose(dval, np.einsum("pj,pj->p", G[rows], X[A.col]), rtol=1e-15, atol=1e-15)
+
+
+# ---------------------------------------------------------------- tall-skinny kernels
+
+
+def test_tsm_kernels_against_dense(orc):
+    V = synth.block_vector(500, 5, 150)
+    W = synth.block_vector(500, 3, 151)
+    X0 = synth.block_vector(5, 3, 152)
+    assert np.allclose(orc.tsmttsm(V, W, 2.0, -1.0, X0), 2.0 * V.T @ W - X0, rtol=0, atol=1e-12)
+    assert np.allclose(orc.tsmm(V, X0, 0.5, 2.0, W), 0.5 * V @ X0 + 2.0 * W, rtol=0, atol=1e-13)
+    S = synth.block_vector(5, 5, 153)
+    assert np.allclose(orc.tsmm_inplace(V, S, 1.5, -0.5), 1.5 * V @ S - 0.5 * V, rtol=0, atol=1e-13)
+    # integer data: exact in any order
+    Vi, Wi = synth.int_block_vector(300, 4, 154), synth.int_block_vector(300, 2, 155)
+    assert np.array_equal(orc.tsmttsm(Vi, Wi), Vi.T @ Wi)
+    assert np.array_equal(orc.tsmttsm(Vi, Wi, kahan=True), Vi.T @ Wi)
+
+
+def test_tsmttsm_kahan_is_accurate(orc):
+    # ill-conditioned inner products: the compensated sum stays within a few ulps of the
+    # correctly rounded result, the plain sum does not
+    n = 100000
+    a = synth.normal(156, n) * np.exp(synth.uniform(157, n, -15, 15))
+    V = np.stack([a, np.ones(n)], axis=1)
+    W = np.stack([synth.normal(158, n), -np.ones(n) * 1e-3], axis=1)
+    exact = [[math.fsum((V[:, l] * W[:, j]).tolist()) for j in range(2)] for l in range(2)]
+    Xk = orc.tsmttsm(V, W, kahan=True)
+    for l in range(2):
+        for j in range(2):
+            bound = 4.5e-16 * abs(exact[l][j]) + 1.2e-16 * float(np.sum(np.abs(V[:, l] * W[:, j])))
+            assert abs(Xk[l, j] - exact[l][j]) <= bound
