@@ -135,6 +135,90 @@ def cg_compare(sc, torch, synth, edge, nrhs=8, tol=1e-10):
     return out
 
 
+def batch_row(sc, torch, synth, model, nmat=64, b=8, tol=1e-10):
+    """Batched workload: nmat 3D Laplacians with edges ~ U{20..100}, b right-hand sides each.
+    Formats and launch shapes from the autotuner; one batched product launch (FP64) against
+    the same products launched matrix by matrix; CG to tol for the whole batch in FP64 and
+    with FP32 iterations on BF16 / FP32 values refined in FP64 (HIP graph on)."""
+    t0 = time.perf_counter()
+    edges = synth.laplacian3d_batch(nmat)
+    mats = [synth.laplacian3d(e) for e in edges]
+    gen_s = time.perf_counter() - t0
+    n_tot = sum(A.nrows for A in mats)
+    nnz_tot = sum(A.nnz for A in mats)
+    out = {"matrices": f"{nmat} 3D 7-point Dirichlet Laplacians, edge ~ U{{20..100}}", "n_total": n_tot,
+           "nnz_total": nnz_tot, "b": b, "generate_s": round(gen_s, 1)}
+    t0 = time.perf_counter()
+    tunes = {}
+    M = {}
+    for dt in ("f64", "bf16", "f32"):
+        Ms = []
+        for A in mats:
+            t = sc.sell_autotune(A, b, "bf16" if dt == "f32" else dt)
+            Mk = sc.SellMatrix.from_csr(A, C=t["C"], sigma=t["sigma"], dtype=dt)
+            Mk.set_launch(t["vpt"], t["blocks_per_cu"])
+            Ms.append(Mk)
+            key = (dt, t["C"], t["sigma"], t["vpt"], t["blocks_per_cu"])
+            tunes[key] = tunes.get(key, 0) + 1
+        M[dt] = Ms
+    out["tune_and_build_s"] = round(time.perf_counter() - t0, 1)
+    out["tuned_choices"] = [dict(dtype=k[0], C=k[1], sigma=k[2], vpt=k[3], blocks_per_cu=k[4], matrices=v)
+                            for k, v in sorted(tunes.items())]
+    log(f"[bench] batch: {n_tot} rows, {nnz_tot} nnz, tuned {out['tuned_choices']}")
+    B64 = sc.SellBatch(M["f64"])
+    Bbf = sc.SellBatch(M["bf16"])
+    B32 = sc.SellBatch(M["f32"])
+    Xd = torch.rand((n_tot, b), dtype=torch.float64, device="cuda") * 2 - 1
+    Yd = torch.empty_like(Xd)
+    dots = torch.zeros(3 * b * nmat, dtype=torch.float64, device="cuda")
+    alg_bytes = 0
+    for A, Mk in zip(mats, M["f64"]):
+        alg_bytes += model.bytes_min(A.nnz, A.nrows, A.ncols, b, 8, 8, read_y=False, nchunks=Mk.info["nchunks"])
+    us, us_min = time_launches(torch, lambda: sc.sell_batch_spmmv_aug(B64, Xd, Yd, flags=sc.DOT_XY, dot=dots),
+                               reps=20)
+    out["batched_product_f64"] = {"us": round(us, 1), "GB/s": round(alg_bytes / (us * 1e-6) / 1e9, 1),
+                                  "GFLOP/s": round(2.0 * nnz_tot * b / (us * 1e-6) / 1e9, 1),
+                                  "bytes": int(alg_bytes)}
+    offs = np.cumsum([0] + [A.nrows for A in mats])
+    dsingle = torch.zeros(3 * b, dtype=torch.float64, device="cuda")
+
+    def one_by_one():
+        for k, Mk in enumerate(M["f64"]):
+            sc.sell_spmmv_aug(Mk, Xd[offs[k]:offs[k + 1]], Yd[offs[k]:offs[k + 1]], flags=sc.DOT_XY, dot=dsingle)
+
+    us1, _ = time_launches(torch, one_by_one, reps=5)
+    out["per_matrix_launches_f64_us"] = round(us1, 1)
+    log(f"[bench] batch product: {out['batched_product_f64']}, one by one {us1:.0f} us")
+    Bd = torch.from_numpy(np.concatenate([synth.block_vector(A.nrows, b, synth.SEED_Y + 1000 * k)
+                                          for k, A in enumerate(mats)])).cuda()
+
+    def solve(name, lo, graph=True):
+        for rep in range(2):  # the first run also warms the kernels and tables
+            X = torch.zeros_like(Bd)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st = sc.sell_batch_cg(B64, lo, Bd, X, tol=tol, maxit=20000, graph=graph)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t1
+        its = [e["iterations"] for e in st]
+        out[name] = {"seconds": round(dt_s, 4), "all_converged": all(e["converged"] for e in st),
+                     "max_relres": max(e["relres"] for e in st), "iterations_min": min(its),
+                     "iterations_max": max(its), "refinements_max": max(e["refinements"] for e in st)}
+        log(f"[bench] batch CG {name}: {out[name]}")
+
+    solve("cg_fp64", None)
+    solve("cg_mixed_bf16", Bbf)
+    solve("cg_mixed_f32", B32)
+    solve("cg_mixed_bf16_no_graph", Bbf, graph=False)
+    out["speedup_bf16_vs_fp64"] = round(out["cg_fp64"]["seconds"] / out["cg_mixed_bf16"]["seconds"], 3)
+    for Bt in (B64, Bbf, B32):
+        Bt.close()
+    for Ms in M.values():
+        for Mk in Ms:
+            Mk.close()
+    return out
+
+
 def time_launches(torch, fn, reps=20, warm=3):
     """Mean and best duration (us) of fn() with HIP events on the current stream."""
     for _ in range(warm):
@@ -249,6 +333,8 @@ def main():
     ap.add_argument("--no-b1", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the low-precision/transpose/update timings")
     ap.add_argument("--cg-edge", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched Laplacian workload")
+    ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one copy probe of this many MiB (calibrates HBM counters) and exit")
     args = ap.parse_args()
@@ -330,6 +416,9 @@ def main():
         except sc.SellError as e:
             cg = {"error": str(e)}
             log(f"[bench] CG skipped: {e}")
+    batch = None
+    if not args.no_batch:
+        batch = batch_row(sc, torch, synth, model, nmat=args.batch_count)
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -371,6 +460,7 @@ def main():
         "frac_of_achievable": None if not probes else round(head["hbm_gbs"] / max(probes["copy"], probes["copy_nt"]), 4),
         "cg_time_to_1e-10": cg,
         "other_rows_b8": extra,
+        "batch_laplacians": batch,
         "build_s": round(build_s, 3),
         "kernel_source_hash": src_hash,
     }

@@ -311,6 +311,44 @@ int sell_tsmm_inplace(sell_bv *V, const double *X, int64_t ldx, double alpha, do
                       void *stream);
 
 /* ------------------------------------------------------------------------------------ */
+/* Parameter choice                                                                     */
+/*                                                                                      */
+/* The paper chooses C from the hardware's vector width and sigma between padding and    */
+/* right-hand-side locality (Sec. 5.1); the best values depend on the device and on the  */
+/* matrix, so they are found here by timed trials on the device (micro-benchmarks, as    */
+/* planned for device-dependent choices in Sec. 7.2).                                    */
+
+/* Launch parameters of the product kernels for this matrix: columns per lane of the
+ * fixed-width kernels (1, 2 or 4, at most the block width; 0 = default: 4 for b >= 4, else b)
+ * and workgroups per compute unit (1..64, capped at the occupancy limit; 0 = the limit).
+ * Results do not depend on them (every row is computed the same way); dot products may
+ * differ in the last bits (another split of the partial sums). */
+int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu);
+
+typedef struct {
+    int32_t C;             /* chosen chunk height                                      */
+    int64_t sigma;         /* chosen sorting window                                    */
+    int32_t vpt;           /* chosen columns per lane (0 = default)                    */
+    int32_t blocks_per_cu; /* chosen workgroups per compute unit (0 = occupancy limit) */
+    double us;             /* time of one product with the choice (microseconds)       */
+    double default_us;     /* the same for C = 32, sigma = 1 and the default launch    */
+    int32_t trials;        /* configurations timed; 0 when answered from the cache     */
+} sell_tune_result;
+
+#define SELL_TUNE_NO_CACHE 0x1u /* time the candidates even if the shape class is cached */
+
+/* Times candidate formats of the CSR matrix (same arguments as sell_build) for products
+ * with block width b (1..64) on the current device: C in {16, 32, 64} with sigma in
+ * {1, 8 C, 256 C}, then columns per lane {1, 2, 4} and workgroups per CU {limit, 1, 2} for the
+ * best pair. The trial product is the one a CG iteration issues (fused <x, y>; plain for a
+ * rectangular matrix). Results are cached per process for the matrix's shape class (value
+ * type, b, order of magnitude of the row count, mean row length, row-length histogram over
+ * power-of-two bins). Synchronous; allocates and frees its own trial matrices and vectors. */
+int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
+                  const double *val, sell_dtype vdt, int32_t b, uint32_t flags,
+                  sell_tune_result *out, void *stream);
+
+/* ------------------------------------------------------------------------------------ */
 /* Batches of independent matrices                                                      */
 /*                                                                                      */
 /* The paper distributes one matrix over heterogeneous devices by work weights which it  */

@@ -52,6 +52,11 @@ class sell_info_t(ct.Structure):
                 ("matrix_bytes", ct.c_int64)]
 
 
+class sell_tune_result(ct.Structure):
+    _fields_ = [("C", ct.c_int32), ("sigma", ct.c_int64), ("vpt", ct.c_int32), ("blocks_per_cu", ct.c_int32),
+                ("us", ct.c_double), ("default_us", ct.c_double), ("trials", ct.c_int32)]
+
+
 class sell_cg_stats(ct.Structure):
     _fields_ = [("iterations", ct.c_int64), ("refinements", ct.c_int64), ("relres", ct.c_double),
                 ("converged", ct.c_int32)]
@@ -93,6 +98,8 @@ _SIGNATURES = {
     "sell_tsmttsm": ([_P, _P, _D, _D, _P, _I64, _I, _P], _I),
     "sell_tsmm": ([_P, _P, _I64, _D, _D, _P, _P], _I),
     "sell_tsmm_inplace": ([_P, _P, _I64, _D, _D, _P], _I),
+    "sell_set_launch": ([_P, _I32, _I32], _I),
+    "sell_autotune": ([_I64, _I64, _P, _P, _P, _I, _I32, ct.c_uint32, ct.POINTER(sell_tune_result), _P], _I),
     "sell_batch_create": ([_PP, _I32, _PP], _I),
     "sell_batch_destroy": ([_P], _I),
     "sell_batch_info": ([_P, ct.POINTER(_I32), ct.POINTER(_I64), ct.POINTER(_I64)], _I),
@@ -255,6 +262,20 @@ class SellMatrix:
 
         return torch.float64 if self.info["vdtype"] == SELL_F64 else torch.float32
 
+    def set_launch(self, vpt=0, blocks_per_cu=0):
+        """Launch parameters of the product kernels for this matrix (0 = defaults)."""
+        _ok(lib().sell_set_launch(self.handle, int(vpt), int(blocks_per_cu)), "sell_set_launch")
+
+    @classmethod
+    def from_csr_tuned(cls, A, b, dtype="f64", stream=None, cache=True):
+        """Build with the format and launch parameters chosen by ``sell_autotune``; the choice
+        is kept in ``self.tune``."""
+        t = sell_autotune(A, b, dtype, stream=stream, cache=cache)
+        M = cls.from_csr(A, C=t["C"], sigma=t["sigma"], dtype=dtype, stream=stream)
+        M.set_launch(t["vpt"], t["blocks_per_cu"])
+        M.tune = t
+        return M
+
     def export_csr(self):
         return sell_export_csr(self.handle)
 
@@ -414,6 +435,24 @@ def sell_cg_mixed(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=0.1, inner_
     _ok(lib().sell_cg_mixed(_mat(A64), _mat(Alo), b.handle, x.handle, float(tol), int(maxit), float(inner_tol),
                             int(inner_maxit), ct.byref(st), _stream(stream)), "sell_cg_mixed")
     return {k: getattr(st, k) for k, _ in sell_cg_stats._fields_}
+
+
+# ==================================================================== parameter choice
+
+SELL_TUNE_NO_CACHE = 0x1
+
+
+def sell_autotune(A, b, dtype="f64", stream=None, cache=True):
+    """Time candidate (C, sigma, columns per lane, workgroups per CU) for products of width
+    ``b`` with the CSR matrix ``A``; returns the choice and its timings as a dict."""
+    rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val, dtype=np.float64)
+    r = sell_tune_result()
+    _ok(lib().sell_autotune(int(A.nrows), int(A.ncols), _np_ptr(rowptr), _np_ptr(col), _np_ptr(val),
+                            _dtype_code(dtype), int(b), 0 if cache else SELL_TUNE_NO_CACHE, ct.byref(r),
+                            _stream(stream)), "sell_autotune")
+    return {k: getattr(r, k) for k, _ in sell_tune_result._fields_}
 
 
 # ==================================================================== batches

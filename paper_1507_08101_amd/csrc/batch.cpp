@@ -22,7 +22,6 @@ namespace sellcs {
 const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok);
 const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok);
 const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok);
-int choose_vpt(int vk, int b);
 }  // namespace sellcs
 
 namespace {
@@ -111,7 +110,9 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     if (rc) return rc;
     const int vk = vec_kind(B->vdt);
     const int esize = vk == VK_F64F64 ? 8 : 4;
-    const int vpt = choose_vpt(vk, b);
+    // launch parameters: those chosen for the first matrix (a batch is usually one family)
+    const sell_mat *A0 = B->mats[0];
+    const int vpt = choose_vpt(vk, b, A0->vpt_hint);
     const int align = vpt * esize < 16 ? vpt * esize : 16;
     int64_t xrs, xcs, yrs, ycs, zrs = 0, zcs = 0;
     bv_strides(X, xrs, xcs);
@@ -124,7 +125,8 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
                        : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok)
                                          : batch_kernel_bf16(b, vpt, aug, fixed_ok);
     // workgroups per matrix: the resident grid split in proportion to the cost
-    const int32_t G0 = resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)));
+    const int32_t G0 =
+        resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), A0->bpc_hint);
     double tot = 0.0;
     for (int m = 0; m < K; ++m) tot += B->cost[size_t(m)];
     std::vector<int32_t> blk(size_t(K) + 1, 0);

@@ -19,7 +19,10 @@
 // x in FP64 and the residual replaced by the true r = b - A64 x, computed in FP64 with the F64
 // matrix. Without Alo the iteration runs in FP64 on A64; a system's columns retire when their
 // recursive residual meets the tolerance and the true residual then confirms them (or
-// restarts the system from it). In both cases the search direction is kept across updates.
+// restarts the system from it). In both cases the search direction is kept across updates,
+// except in a column whose recursive residual has drifted below a tenth of the true one (FP32
+// CG that has exhausted a small system, or a retired column): the kept direction no longer
+// fits the new residual there, and the column restarts from p = r.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -146,6 +149,11 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     sell_batch *Ain = mixed ? Alo : A64;
     const BatchSeg sg = batch_seg(A64);
     const size_t Kb = size_t(K) * b;
+    if (n == 0) {  // only empty systems: nothing to solve
+        if (stats)
+            for (int m = 0; m < K; ++m) stats[m] = sell_cg_stats{0, 0, 0.0, 1};
+        return SELL_OK;
+    }
 
     // a stream of our own when the caller passes the legacy default stream (which cannot be
     // captured); created blocking, so it is ordered after the caller's earlier work
@@ -165,7 +173,8 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         return rc;
     // device scalars: rho alpha beta thresh2 bb rr(3Kb) | vec partials (b G) | int32 flags
     const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * size_t(std::max(sg.G, 1));
-    const size_t ni = Kb + 3 * size_t(K) + 2 * size_t(K);  // active, sys_active, mask, spare | iters (int64)
+    // active, sys_active, mask, spare | iters (int64) | column mask
+    const size_t ni = Kb + 3 * size_t(K) + 2 * size_t(K) + 2 + Kb;
     if ((rc = DB.alloc(&pscal, nd * sizeof(double) + ni * sizeof(int32_t) + 16)))
         return rc;
     double *d = static_cast<double *>(pscal);
@@ -185,6 +194,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     // align the int64 counters
     iters_d = reinterpret_cast<int64_t *>((reinterpret_cast<uintptr_t>(iters_d) + 7) & ~uintptr_t(7));
     sc.iters = iters_d;
+    int32_t *colmask_d = reinterpret_cast<int32_t *>(iters_d + K);
 
     sell_bv Bview = *Bv;
     sell_bv R64 = view(pr64, n, b, SELL_F64), R = view(pr, n, b, idt), D = view(pd, n, b, idt),
@@ -196,7 +206,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     if ((rc = bcg_launch_coldot(SELL_F64, Bv->ptr, Bv->ptr, b, sg, nullptr, vparts, bb_d, nullptr, nullptr, 0.0, s)))
         return rc;
     std::vector<double> bb(Kb), rr(3 * Kb), rho(Kb), rho_last(Kb, 0.0), relres(size_t(K), INFINITY);
-    std::vector<int32_t> act(Kb, 1), sysact(size_t(K), 0), conv(size_t(K), 0), mask(size_t(K), 0);
+    std::vector<int32_t> act(Kb, 1), sysact(size_t(K), 0), conv(size_t(K), 0), mask(size_t(K), 0), reset(Kb, 0);
     std::vector<int64_t> since(size_t(K), 0), refine(size_t(K), 0), its(size_t(K), 0);
     HIPCHK(hipMemcpyAsync(bb.data(), bb_d, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -241,12 +251,26 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         HIPCHK(hipMemcpyAsync(sc.active, act.data(), Kb * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(sc.sys_active, sysact.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
         if (!restart) return SELL_OK;
+        // columns whose recursion drifted from the true residual restart from p = r (rho holds
+        // the recursive residuals of the last check; 0 before the first iteration)
+        bool any_reset = false;
+        for (int m = 0; m < K; ++m)
+            for (int j = 0; j < b; ++j) {
+                const size_t q = size_t(m) * b + j;
+                const double r2 = rr[size_t(m) * 3 * b + j];
+                reset[q] = (mask[size_t(m)] && act[q] && !(rho[q] >= 0.01 * r2)) ? 1 : 0;
+                any_reset = any_reset || reset[q];
+            }
         HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
         // r = r64 in the iteration's precision, rho = <r, r>; the recursion retires a column
         // itself only in FP64 (thresh2 = tol^2 ||b||^2), in FP32 only the true residual does
         if ((r = bcg_launch_convert(idt, pr, static_cast<const double *>(pr64), b, sg, mask_d, vparts, sc.rho,
                                     sc.thresh2, bb_d, mixed ? 0.0 : tol * tol, s)))
             return r;
+        if (any_reset) {
+            HIPCHK(hipMemcpyAsync(colmask_d, reset.data(), Kb * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            if ((r = bcg_launch_copy(idt, pp, pr, b, sg, colmask_d, s))) return r;
+        }
         HIPCHK(hipMemcpyAsync(rho.data(), sc.rho, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int m = 0; m < K; ++m)
@@ -255,12 +279,10 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         return SELL_OK;
     };
 
-    // first update: every system, x0 = X (D = 0); then p = r
+    // first update: every system, x0 = X (D = 0, P = 0); rho = 0 makes every active column
+    // start from p = r
     std::fill(mask.begin(), mask.end(), 1);
     if ((rc = refresh())) return rc;
-    std::fill(mask.begin(), mask.end(), 1);
-    HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    if ((rc = bcg_launch_copy(idt, pp, pr, b, sg, mask_d, s))) return rc;
 
     sell_spmv_opts po = SELL_SPMV_OPTS_INIT;
     po.flags = SELL_SPMV_DOT_XY;

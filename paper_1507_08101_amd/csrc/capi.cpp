@@ -167,6 +167,8 @@ void base_args(ProdArgs &a, const sell_mat *A) {
         return e ? std::atoi(e) : 1;
     }();
     a.xcd_map = xcd_map;
+    a.vpt_hint = A->vpt_hint;
+    a.bpc_hint = A->bpc_hint;
 }
 
 // Split b columns into launches: fixed widths when possible, else up to 64 per launch.

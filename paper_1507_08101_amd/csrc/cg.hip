@@ -141,6 +141,18 @@ __global__ void __launch_bounds__(kVT) scale_to_f32_kernel(float *dst, const dou
     }
 }
 
+// p = r in the columns with colmask[j] != 0 (one system)
+template <class T>
+__global__ void __launch_bounds__(kVT) copy_cols_kernel(T *P, const T *R, int64_t n, int b, int64_t ld,
+                                                        const int32_t *colmask) {
+    const int64_t N = n * b;
+    for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
+        const int64_t i = e / b;
+        const int j = int(e - i * b);
+        if (colmask[j]) P[i * ld + j] = R[i * ld + j];
+    }
+}
+
 // x += scale_j * d  (scale_j = 1 when scale is null)
 __global__ void __launch_bounds__(kVT) axpy_mixed_kernel(double *X, const float *D, int64_t n, int b, int64_t ld,
                                                          const double *scale) {
@@ -325,13 +337,13 @@ __global__ void __launch_bounds__(kVT) bconvert_kernel(T *R, const double *R64, 
     colsum_store(acc, bpad, b, partials);
 }
 
-// p = r on the systems with mask[m] != 0
+// p = r in the columns with colmask[m * b + j] != 0
 template <class T>
 __global__ void __launch_bounds__(kVT) bcopy_kernel(T *P, const T *R, int b, int bpad, BatchSeg sg,
-                                                    const int32_t *mask) {
+                                                    const int32_t *colmask) {
     const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
     const int j = threadIdx.x & (bpad - 1);
-    if (j >= b || !mask[m]) return;
+    if (j >= b || !colmask[m * b + j]) return;
     seg_rows(sg, m, bpad, [&](int64_t i) { P[i * b + j] = R[i * b + j]; });
 }
 
@@ -418,6 +430,18 @@ int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int6
                            const double *thresh2, double *scale, hipStream_t s) {
     hipLaunchKernelGGL(scale_to_f32_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, dst, src, n, b, ld, rr,
                        thresh2, scale);
+    return ok();
+}
+
+int cg_launch_copy_cols(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const int32_t *colmask,
+                        hipStream_t s) {
+    if (n * b == 0) return SELL_OK;
+    if (dt == SELL_F64)
+        hipLaunchKernelGGL(copy_cols_kernel<double>, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s,
+                           static_cast<double *>(P), static_cast<const double *>(R), n, b, ld, colmask);
+    else
+        hipLaunchKernelGGL(copy_cols_kernel<float>, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s,
+                           static_cast<float *>(P), static_cast<const float *>(R), n, b, ld, colmask);
     return ok();
 }
 

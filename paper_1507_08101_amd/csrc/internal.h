@@ -65,6 +65,8 @@ struct sell_mat {
     sell_mat *transpose = nullptr;  // SELL copy of A^T for the deterministic transpose
     int64_t *d_tpos = nullptr;      // position in the SELL arrays of A^T of each CSR entry of A
     int64_t matrix_bytes = 0;
+    int32_t vpt_hint = 0;           // launch parameters chosen for this matrix (0: defaults)
+    int32_t bpc_hint = 0;
 };
 
 struct sell_bv {
@@ -94,6 +96,8 @@ struct ProdArgs {
                            // owns fine tiles [g * ntiles / nblocks, (g + 1) * ntiles / nblocks)
     int32_t cshift;        // log2(C) when C is a power of two, else -1
     int32_t xcd_map;       // 1: give each XCD one contiguous range of tiles
+    int32_t vpt_hint;      // columns per lane requested for the matrix (0: default)
+    int32_t bpc_hint;      // workgroups per compute unit requested (0: occupancy limit)
     int64_t nrows;
     int32_t nb;            // columns in this slice
     const void *X; int64_t xrs, xcs;   // element (i, j) at X[i * xrs + j * xcs]
@@ -148,6 +152,9 @@ int cg_launch_coldot(int dt, const void *U, const void *V, int64_t n, int b, int
                      hipStream_t s);
 int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int64_t ld, const double *rr,
                            const double *thresh2, double *scale, hipStream_t s);
+// P = R in the columns with colmask[j] != 0 (device flags)
+int cg_launch_copy_cols(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const int32_t *colmask,
+                        hipStream_t s);
 int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
                          hipStream_t s);
 
@@ -174,7 +181,9 @@ int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const doubl
                             const int32_t *mask, hipStream_t s);
 int bcg_launch_convert(int dt, void *R, const double *R64, int b, const BatchSeg &sg, const int32_t *mask,
                        double *partials, double *rho, double *thresh2, const double *ref, double f2, hipStream_t s);
-int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, const int32_t *mask, hipStream_t s);
+// P = R in the columns with colmask[m * b + j] != 0
+int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, const int32_t *colmask,
+                    hipStream_t s);
 int launch_batch_dot_finish(const double *partials, const int32_t *blk, int K, int32_t nb, uint32_t flags,
                             double *dot, hipStream_t s);
 
@@ -188,7 +197,11 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
              hipStream_t s, double *partials_out = nullptr, int32_t *nblocks_out = nullptr);
 // Workgroups of one product launch: as many as the device holds at once (occupancy of the
 // kernel times the compute units), at most the number of fine tiles.
-int32_t resident_grid(const void *kernel, int threads, int32_t ntiles);
+// blocks_per_cu > 0 lowers the workgroups per compute unit to at most that many.
+int32_t resident_grid(const void *kernel, int threads, int32_t ntiles, int32_t blocks_per_cu = 0);
+// Columns per lane of the fixed-width product kernels: hint (1, 2 or 4, at most b) when
+// given, else 4 for b >= 4 and b otherwise.
+int choose_vpt(int vk, int b, int hint = 0);
 
 // Lazily built device maps (row -> slot, CSR row pointers) and the SELL copy of A^T.
 int ensure_update_maps(sell_mat *A, hipStream_t s);

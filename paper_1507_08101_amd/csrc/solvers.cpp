@@ -15,7 +15,10 @@
 //                 correction is folded into x in FP64 and the residual is replaced by the
 //                 true r = b - A x, formed in FP64 with the FP64 matrix (one augmented product:
 //                 y = b preloaded, alpha = -1, beta = 1, fused <r, r>). The search direction is
-//                 kept across updates, so the Krylov space is not restarted.
+//                 kept across updates, so the Krylov space is not restarted, unless the FP32
+//                 recursion has drifted away from the true residual (its residual norm below a
+//                 tenth of the true one, as when FP32 CG has exhausted a small system): then that
+//                 column restarts from p = r, since the kept direction no longer fits the new r.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -63,6 +66,7 @@ sell_bv view(void *p, int64_t n, int b, int dt) {
 struct Scalars {
     double *rho, *pq, *alpha, *beta, *thresh2, *bb, *rr, *scale, *thresh_out;
     int32_t *active;
+    int32_t *colmask;     // per-column flags handed to the device (b)
     double *prod_parts;   // tile partials of the product's dots (3 b ntiles)
     double *vec_parts;    // workgroup partials of the vector kernels (b kCgMaxGrid)
     int32_t prod_tiles;
@@ -85,6 +89,7 @@ int alloc_scalars(Buffers &B, Scalars &S, int b, int32_t max_tiles) {
     S.scale = d + 9 * b;
     S.thresh_out = d + 10 * b;
     S.active = reinterpret_cast<int32_t *>(d + 11 * b);
+    S.colmask = reinterpret_cast<int32_t *>(d + 13 * b);
     S.prod_parts = d + 16 * b;
     S.vec_parts = S.prod_parts + 3 * size_t(b) * nt;
     S.prod_tiles = max_tiles;
@@ -252,7 +257,8 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
                                0.0, s)))
         return rc;
     double bb[64], rr[64], rho[64], rho_last[64];
-    int32_t act[64];
+    int32_t act[64], reset[64];
+    for (int j = 0; j < b; ++j) rho[j] = 0.0;
     HIPCHK(hipMemcpyAsync(bb, S.bb, sizeof(double) * b, hipMemcpyDeviceToHost, s));
 
     // Reliable update: fold the FP32 correction into x (FP64), recompute the true residual
@@ -277,6 +283,11 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
         st.relres = worst;
         *done = all;
         if (all) return SELL_OK;
+        bool any_reset = false;
+        for (int j = 0; j < b; ++j) {
+            reset[j] = (act[j] && !(rho[j] >= 0.01 * rr[j])) ? 1 : 0;  // recursion drifted (or first update)
+            any_reset = any_reset || reset[j];
+        }
         if ((r = launch_copy(&R, &R64, s))) return r;  // FP64 -> FP32, round to nearest
         if ((r = launch_fill(D.ptr, SELL_F32, n, b, b, 1, 0.0, s))) return r;
         // rho = <r32, r32>; thresh2 = 0 so the FP32 recursion never retires a column itself
@@ -284,14 +295,21 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
                                   0.0, s)))
             return r;
         HIPCHK(hipMemcpyAsync(S.active, act, sizeof(int32_t) * b, hipMemcpyHostToDevice, s));
+        if (any_reset) {
+            HIPCHK(hipMemcpyAsync(S.colmask, reset, sizeof(int32_t) * b, hipMemcpyHostToDevice, s));
+            if ((r = cg_launch_copy_cols(SELL_F32, P.ptr, R.ptr, n, b, b, S.colmask, s))) return r;
+        }
         HIPCHK(hipMemcpyAsync(rho_last, S.rho, sizeof(double) * b, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        for (int j = 0; j < b; ++j) rho[j] = rho_last[j];
         return SELL_OK;
     };
 
     bool done = false;
+    // p = 0 in every column (a converged column keeps it); the first update sets p = r in the
+    // active columns (rho = 0 there marks the recursion as drifted)
+    if ((rc = launch_fill(P.ptr, SELL_F32, n, b, b, 1, 0.0, s))) return rc;
     if ((rc = reliable_update(false, &done))) return rc;
-    if (!done && (rc = launch_copy(&P, &R, s))) return rc;
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
     o.flags = SELL_SPMV_DOT_XY;
     int64_t since = 0;

@@ -410,7 +410,7 @@ inline int go_prod(ProdArgs &a, hipStream_t s) {
         while ((1 << vl_log2) < a.nb) ++vl_log2;
     }
     auto k = prod_kernel<VK, B, VPT, AUG>;
-    a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles);
+    a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles, a.bpc_hint);
     hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
@@ -427,13 +427,11 @@ inline int go_transpose(ProdArgs &a, hipStream_t s) {
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
-// Columns per lane for a compile-time width (tunable through SELLCS_VPT for experiments).
-int choose_vpt(int vk, int b);
 
 template <int VK, bool AUG>
 int dispatch_prod(ProdArgs &a, hipStream_t s, bool fixed_ok) {
     const int b = a.nb;
-    const int vpt = choose_vpt(VK, b);
+    const int vpt = choose_vpt(VK, b, a.vpt_hint);
     if (fixed_ok) {
         switch (b) {
             case 1: return go_prod<VK, 1, 1, AUG>(a, s);

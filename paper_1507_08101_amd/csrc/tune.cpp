@@ -1,0 +1,223 @@
+// tune.cpp -- choice of the SELL-C-sigma parameters and launch shape by timed trials.
+//
+// The paper picks C from the hardware (the SIMD width or the warp size) and sigma as a
+// compromise between padding and the locality of the right-hand side (Sec. 5.1), and plans
+// micro-benchmarks for decisions that depend on the device (Sec. 7.2). Here the candidates are
+// timed on the device itself: first (C, sigma) pairs with the default launch, then, for the
+// best pair, the columns per lane of the fixed-width kernels and the workgroups per compute
+// unit. Each trial times the augmented product that a CG iteration issues (y = A x with the
+// fused <x, y>, or the plain product for a rectangular matrix) with HIP events.
+//
+// Results are cached for the process under a key that describes the matrix's shape class: the
+// value type, the block width, the binary order of magnitude of the row count, the mean row
+// length and the histogram of row lengths over power-of-two bins (fractions rounded to 1/32).
+// Matrices of one family and similar size therefore share one tuning run.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sellcs;
+
+namespace {
+
+#define HIPCHK(x)                                                                             \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? SELL_ERR_OOM : SELL_ERR_HIP; \
+    } while (0)
+
+std::mutex g_mu;
+std::map<std::string, sell_tune_result> g_cache;
+
+std::string shape_key(int64_t nrows, int64_t ncols, const int64_t *rowptr, int vdt, int b) {
+    std::vector<int64_t> hist(34, 0);
+    for (int64_t i = 0; i < nrows; ++i) {
+        const int64_t len = rowptr[i + 1] - rowptr[i];
+        int bin = 0;
+        while (bin < 33 && (int64_t(1) << bin) <= len) ++bin;  // 0: empty, k: [2^(k-1), 2^k)
+        hist[size_t(bin)]++;
+    }
+    std::string key = std::to_string(vdt) + "/" + std::to_string(b) + "/" + (nrows == ncols ? "sq" : "rect") + "/";
+    int mag = 0;
+    while ((int64_t(1) << mag) < nrows) ++mag;
+    key += std::to_string(mag) + "/";
+    const double mean = nrows > 0 ? double(rowptr[nrows] - rowptr[0]) / double(nrows) : 0.0;
+    key += std::to_string(int(std::lround(mean * 2))) + "/";
+    for (int64_t h : hist) key += std::to_string(nrows > 0 ? std::lround(32.0 * double(h) / double(nrows)) : 0) + ",";
+    return key;
+}
+
+struct Trial {
+    int32_t C;
+    int64_t sigma;
+    int32_t vpt, bpc;
+    double us;
+};
+
+// Average time of one product on A (after warm-up launches).
+int time_product(sell_mat *A, const sell_bv *X, sell_bv *Y, double *dot, int reps, hipStream_t s, double *us) {
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    const bool square = A->h.nrows == A->h.ncols;
+    o.flags = square ? SELL_SPMV_DOT_XY : 0;
+    o.dot = dot;
+    int rc;
+    for (int w = 0; w < 3; ++w)
+        if ((rc = aug_impl(A, X, Y, nullptr, o, square, s))) return rc;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SELL_ERR_HIP;
+    }
+    rc = SELL_OK;
+    if (hipEventRecord(e0, s) != hipSuccess) rc = SELL_ERR_HIP;
+    for (int r = 0; r < reps && rc == SELL_OK; ++r) rc = aug_impl(A, X, Y, nullptr, o, square, s);
+    if (rc == SELL_OK && hipEventRecord(e1, s) != hipSuccess) rc = SELL_ERR_HIP;
+    float ms = 0.f;
+    if (rc == SELL_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = SELL_ERR_HIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *us = 1000.0 * double(ms) / reps;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu) {
+    if (!A) return SELL_ERR_ARG;
+    if (!(vpt == 0 || vpt == 1 || vpt == 2 || vpt == 4)) return SELL_ERR_ARG;
+    if (blocks_per_cu < 0 || blocks_per_cu > 64) return SELL_ERR_ARG;
+    A->vpt_hint = vpt;
+    A->bpc_hint = blocks_per_cu;
+    return SELL_OK;
+}
+
+int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col, const double *val,
+                  sell_dtype vdt, int32_t b, uint32_t flags, sell_tune_result *out, void *stream) {
+    if (!out || !rowptr || nrows < 0 || ncols < 0) return SELL_ERR_ARG;
+    if (b < 1 || b > kMaxSliceCols) return SELL_ERR_UNSUPPORTED;
+    if (flags & ~uint32_t(SELL_TUNE_NO_CACHE)) return SELL_ERR_ARG;
+    if (vdt != SELL_F64 && vdt != SELL_F32 && vdt != SELL_BF16) return SELL_ERR_DTYPE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::string key;
+    try {
+        key = shape_key(nrows, ncols, rowptr, int(vdt), b);
+    } catch (...) {
+        return SELL_ERR_OOM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (!(flags & SELL_TUNE_NO_CACHE) && it != g_cache.end()) {
+            *out = it->second;
+            out->trials = 0;
+            return SELL_OK;
+        }
+    }
+    // operands of the trials: X = 1, Y = 0 in the matrix's vector type
+    const int vt = vdt == SELL_F64 ? SELL_F64 : SELL_F32;
+    const size_t es = vt == SELL_F64 ? 8 : 4;
+    void *px = nullptr, *py = nullptr;
+    double *pdot = nullptr;
+    HIPCHK(hipMalloc(&px, std::max<size_t>(16, size_t(ncols) * b * es)));
+    auto cleanup = [&]() {
+        if (px) (void)hipFree(px);
+        if (py) (void)hipFree(py);
+        if (pdot) (void)hipFree(pdot);
+    };
+    if (hipMalloc(&py, std::max<size_t>(16, size_t(nrows) * b * es)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&pdot), 3 * kMaxSliceCols * sizeof(double)) != hipSuccess) {
+        cleanup();
+        return SELL_ERR_OOM;
+    }
+    int rc = launch_fill(px, vt, ncols, b, b, 1, 1.0, s);
+    if (!rc) rc = launch_fill(py, vt, nrows, b, b, 1, 0.0, s);
+    sell_bv X, Y;
+    X.nrows = ncols;
+    X.ncols = b;
+    X.dt = vt;
+    X.lay = SELL_ROW_MAJOR;
+    X.ptr = px;
+    X.ld = b;
+    Y = X;
+    Y.nrows = nrows;
+    Y.ptr = py;
+
+    std::vector<Trial> trials;
+    const int reps = 10;
+    auto run = [&](int32_t C, int64_t sigma, int32_t vpt, int32_t bpc, sell_mat *reuse, Trial *res) -> int {
+        sell_mat *A = reuse;
+        int r = SELL_OK;
+        if (!A && (r = sell_build(&A, nrows, ncols, rowptr, col, val, C, sigma, vdt, s))) return r;
+        A->vpt_hint = vpt;
+        A->bpc_hint = bpc;
+        double us = 0.0;
+        r = time_product(A, &X, &Y, pdot, reps, s, &us);
+        if (!reuse) sell_destroy(A);
+        if (r) return r;
+        *res = Trial{C, sigma, vpt, bpc, us};
+        trials.push_back(*res);
+        return SELL_OK;
+    };
+
+    // stage 1: (C, sigma) with the default launch
+    const int32_t Cs[] = {16, 32, 64};
+    Trial best{32, 1, 0, 0, INFINITY}, deflt{32, 1, 0, 0, INFINITY};
+    for (int32_t C : Cs) {
+        const int64_t sigmas[] = {1, 8 * int64_t(C), 256 * int64_t(C)};
+        for (int64_t sg : sigmas) {
+            if (rc) break;
+            if (sg > 1 && sg >= nrows && sg != sigmas[1]) continue;  // one whole-matrix window suffices
+            Trial t;
+            rc = run(C, sg, 0, 0, nullptr, &t);
+            if (rc) break;
+            if (C == 32 && sg == 1) deflt = t;
+            if (t.us < best.us) best = t;
+        }
+    }
+    // stage 2: launch shape for the best pair
+    if (!rc) {
+        sell_mat *A = nullptr;
+        rc = sell_build(&A, nrows, ncols, rowptr, col, val, best.C, best.sigma, vdt, s);
+        if (!rc) {
+            std::vector<int32_t> vpts;
+            for (int v : {1, 2, 4})
+                if (v <= b && (b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32)) vpts.push_back(v);
+            for (int32_t v : vpts)
+                for (int32_t bpc : {0, 1, 2}) {
+                    if (rc) break;
+                    if (v == choose_vpt(vdt == SELL_F64 ? VK_F64F64 : VK_F32F32, b) && bpc == 0) continue;  // stage 1
+                    Trial t;
+                    rc = run(best.C, best.sigma, v, bpc, A, &t);
+                    if (!rc && t.us < best.us) best = t;
+                }
+            sell_destroy(A);
+        }
+    }
+    cleanup();
+    if (rc) return rc;
+    sell_tune_result res;
+    res.C = best.C;
+    res.sigma = best.sigma;
+    res.vpt = best.vpt;
+    res.blocks_per_cu = best.bpc;
+    res.us = best.us;
+    res.default_us = deflt.us;
+    res.trials = int32_t(trials.size());
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_cache[key] = res;
+    }
+    *out = res;
+    return SELL_OK;
+}
+
+}  // extern "C"

@@ -20,7 +20,8 @@ int transpose_bf16(ProdArgs &a, hipStream_t s);
 // Columns per lane of the fixed-width kernels: up to four (16 bytes of a row per lane for
 // FP32 vectors, two 16-byte pieces for FP64; measured fastest for FP64 at b = 8 on the
 // 128^3 Anderson workload). SELLCS_VPT overrides the choice (1, 2 or 4) for tuning.
-int choose_vpt(int vk, int b) {
+int choose_vpt(int vk, int b, int hint) {
+    if ((hint == 1 || hint == 2 || hint == 4) && hint <= b) return hint;
     int v = b >= 4 ? 4 : b;
     if (const char *e = std::getenv("SELLCS_VPT")) {
         int x = std::atoi(e);
@@ -29,16 +30,17 @@ int choose_vpt(int vk, int b) {
     return v;
 }
 
-int32_t resident_grid(const void *kernel, int threads, int32_t ntiles) {
+int32_t resident_grid(const void *kernel, int threads, int32_t ntiles, int32_t blocks_per_cu) {
     if (ntiles <= 0) return 0;
-    static thread_local std::map<std::pair<int, const void *>, int32_t> cache;
+    // (workgroups per CU, CUs) of each kernel on each device
+    static thread_local std::map<std::pair<int, const void *>, std::pair<int32_t, int32_t>> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     auto key = std::make_pair(dev, kernel);
     auto it = cache.find(key);
-    int32_t full;
+    std::pair<int32_t, int32_t> occ;
     if (it != cache.end()) {
-        full = it->second;
+        occ = it->second;
     } else {
         int per_cu = 0, ncu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
@@ -49,9 +51,11 @@ int32_t resident_grid(const void *kernel, int threads, int32_t ntiles) {
             const int v = std::atoi(e);
             if (v >= 1 && v <= 64) per_cu = v;
         }
-        full = int32_t(per_cu) * ncu;
-        cache.emplace(key, full);
+        occ = std::make_pair(int32_t(per_cu), int32_t(ncu));
+        cache.emplace(key, occ);
     }
+    const int32_t per = (blocks_per_cu > 0 && blocks_per_cu < occ.first) ? blocks_per_cu : occ.first;
+    const int32_t full = per * occ.second;
     return full < ntiles ? full : ntiles;
 }
 
@@ -64,7 +68,7 @@ static bool vec_ok(const void *p, int64_t rs, int64_t cs, int esize, int align) 
 int launch_product(ProdArgs &a, int vk, bool aug, hipStream_t s) {
     if (a.ntiles == 0) return SELL_OK;
     const int esize = vk == VK_F64F64 ? 8 : 4;
-    const int vpt = choose_vpt(vk, a.nb);
+    const int vpt = choose_vpt(vk, a.nb, a.vpt_hint);
     const int align = vpt * esize < 16 ? vpt * esize : 16;
     bool fixed_ok = fixed_width(a.nb) && vec_ok(a.X, a.xrs, a.xcs, esize, align) &&
                     vec_ok(a.Y, a.yrs, a.ycs, esize, align);

@@ -97,6 +97,26 @@ def test_cg_mixed_on_matrix_not_exact_in_bf16(sc):
     Alo.close()
 
 
+@pytest.mark.parametrize("e", [2, 3, 5])
+@pytest.mark.parametrize("lo", ["bf16", "f32"])
+def test_cg_mixed_small_systems(sc, e, lo):
+    """FP32 CG exhausts a system of e^3 unknowns within a few checks: its recursive residual
+    falls far below the true one, and the refinement must restart those columns from p = r
+    rather than keep a direction of vanishing size."""
+    A = synth.laplacian3d(e)
+    b = 4
+    B = synth.block_vector(A.nrows, b, 12 + e)
+    A64 = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    Alo = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=lo)
+    Xd = dev(np.zeros_like(B))
+    st = sc.sell_cg_mixed(A64, Alo, dev(B), Xd, tol=TOL, maxit=2000)
+    rr = _true_relres(A, B, host(Xd))
+    assert st["converged"] == 1 and rr.max() <= TOL * 1.001, (st, rr)
+    assert st["iterations"] < 400, st
+    A64.close()
+    Alo.close()
+
+
 def test_cg_rejects_bad_operands(sc):
     import torch
 

@@ -1,0 +1,80 @@
+"""GPU tests of the parameter choice: the autotuner returns a valid configuration that is at
+least as fast as the default one it timed, answers a matrix of the same shape class from its
+cache, and the launch parameters it may choose leave every row's result unchanged."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import abs_product, colwise_relerr, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+
+    import paper_1507_08101_amd as sc
+
+    assert torch.cuda.is_available()
+    sc.lib()
+    return sc
+
+
+def test_autotune_choice_and_cache(sc):
+    A = synth.laplacian3d(40)
+    t = sc.sell_autotune(A, 8, "f64", cache=False)
+    assert t["C"] in (16, 32, 64) and t["sigma"] >= 1 and t["vpt"] in (0, 1, 2, 4)
+    assert 0 <= t["blocks_per_cu"] <= 2 and t["trials"] > 5
+    assert 0 < t["us"] <= t["default_us"]
+    # same family and order of magnitude: answered from the cache
+    t2 = sc.sell_autotune(synth.laplacian3d(38), 8, "f64")
+    assert t2["trials"] == 0 and (t2["C"], t2["sigma"], t2["vpt"]) == (t["C"], t["sigma"], t["vpt"])
+    # another block width is another class
+    t3 = sc.sell_autotune(A, 1, "f64")
+    assert t3["trials"] > 0
+
+
+def test_tuned_matrix_parity(sc):
+    import torch
+
+    A = synth.irregular(20000, band=2000, max_len=500, seed=61)
+    M = sc.SellMatrix.from_csr_tuned(A, 4, "f64")
+    X = synth.block_vector(A.ncols, 4, 62)
+    Y = torch.zeros((A.nrows, 4), dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv(M, dev(X), Y)
+    assert colwise_relerr(host(Y), oracle.spmmv(A, X), abs_product(A, X)) <= 1e-12
+    M.close()
+
+
+@pytest.mark.parametrize("b", [1, 2, 8, 32])
+def test_launch_parameters_do_not_change_rows(sc, b):
+    import torch
+
+    A = synth.random_sparse(3000, 3000, 0.004, 63, empty_rows=30, long_row=2000)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=128)
+    X = dev(synth.block_vector(A.ncols, b, 64))
+    ref = None
+    for vpt in (0, 1, 2, 4):
+        if vpt > b:
+            continue
+        for bpc in (0, 1, 2, 5):
+            M.set_launch(vpt, bpc)
+            Y = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
+            dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+            sc.sell_spmmv_aug(M, X, Y, flags=sc.SHIFT | sc.DOTS, gamma=0.25, dot=dot)
+            got = host(Y)
+            if ref is None:
+                ref = got
+                Xh = host(X)
+                dref = oracle.spmmv_aug(A, Xh, flags=oracle.SHIFT | oracle.DOT_YY | oracle.DOT_XY | oracle.DOT_XX,
+                                        gamma=0.25)[2]
+            assert np.array_equal(got, ref), (vpt, bpc)
+            den = np.concatenate([np.sum(got * got, 0), np.sum(np.abs(Xh * got), 0), np.sum(Xh * Xh, 0)])
+            assert np.all(np.abs(host(dot) - dref) <= 1e-12 * den), (vpt, bpc)
+    with pytest.raises(sc.SellError):
+        M.set_launch(3, 0)
+    with pytest.raises(sc.SellError):
+        M.set_launch(0, 65)
+    M.close()
