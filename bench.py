@@ -274,6 +274,23 @@ def other_rows(sc, torch, model, A, Mh, b, s):
     return out
 
 
+def device_build_row(sc, torch, A, C, sigma, spmv_us):
+    """Construction on the GPU from a device-resident CSR (mean of 3 after one warm-up), in
+    seconds and in units of one plain SpMV (b = 1)."""
+    rp = torch.from_numpy(A.rowptr).cuda()
+    co = torch.from_numpy(A.col).cuda()
+    va = torch.from_numpy(A.val).cuda()
+    ts = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = sc.SellMatrix.from_device_csr(A.nrows, A.ncols, rp, co, va, C=C, sigma=sigma)
+        ts.append(time.perf_counter() - t0)
+        M.close()
+    t = float(np.mean(ts[1:]))
+    return {"seconds": round(t, 5), "spmv_equivalents": round(t * 1e6 / spmv_us, 1)}
+
+
 def grad_row(sc, torch, synth):
     """Differentiation workload: loss = sum(T_100(A~(theta)) x)^2 on the 64^3 Anderson
     matrix, checkpoints every 10 steps; forward + backward time with HIP events."""
@@ -403,6 +420,7 @@ def main():
     if not args.no_other:
         extra = other_rows(sc, torch, model, A, Mh, args.b, s)
         extra["build_spmv_equivalents"] = round(build_s * 1e6 / extra["plain_spmv_b1_us"], 1)
+        extra["build_device"] = device_build_row(sc, torch, A, args.C, args.sigma, extra["plain_spmv_b1_us"])
         extra["grad_chebyshev"] = grad_row(sc, torch, synth)
         log(f"[bench] other rows: {json.dumps(extra)}")
     probes = None if args.no_probe else probe_bandwidth(sc, torch)

@@ -90,6 +90,18 @@ int sell_build(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr
                const int32_t *col, const double *val, int32_t C, int64_t sigma,
                sell_dtype vdt, void *stream);
 
+/* Same as sell_build for a CSR matrix already in DEVICE memory (rowptr, col, val are device
+ * pointers on the current device): every step of the construction runs on the GPU (row
+ * lengths, the stable sort inside sigma windows, chunk lengths and starts, the column-major
+ * fill with padding and value conversion), and the result is identical to sell_build's entry
+ * for entry. The small per-chunk arrays, the permutation and the row pointers are also kept in
+ * host memory, as for sell_build. The input arrays are only read. Invalid CSR input (row
+ * pointers not starting at 0 or decreasing, column indices out of range) gives SELL_ERR_ARG.
+ * Synchronous (returns when the matrix is ready). */
+int sell_build_device(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr,
+                      const int32_t *col, const double *val, int32_t C, int64_t sigma,
+                      sell_dtype vdt, void *stream);
+
 /* Same as sell_build but keeps the SELL arrays in host memory only and touches no GPU.
  * The result serves sell_info, sell_export_csr, sell_export_sell and sell_destroy; the
  * compute calls reject it with SELL_ERR_STATE. */
@@ -363,7 +375,9 @@ typedef struct sell_batch sell_batch;
  * batch refers to the matrices, which must outlive it; it allocates small device tables and
  * pinned staging memory. The block vectors of a batch hold the operands of its matrices one
  * after another: matrix m reads rows [c_m, c_m + ncols_m) of X and writes rows
- * [r_m, r_m + nrows_m) of Y, with r_m, c_m the sums of the earlier matrices' sizes. */
+ * [r_m, r_m + nrows_m) of Y, with r_m, c_m the sums of the earlier matrices' sizes. Launch
+ * parameters set with sell_set_launch apply to the batch when all its matrices have the same
+ * ones (read at creation); otherwise the defaults are used. */
 int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out);
 int sell_batch_destroy(sell_batch *B);
 /* count of matrices and the total rows / columns of the stacked operands (each may be NULL) */

@@ -74,6 +74,7 @@ _SIGNATURES = {
     "sell_version": ([], _I),
     "sell_build": ([_PP, _I64, _I64, _P, _P, _P, _I32, _I64, _I, _P], _I),
     "sell_build_host": ([_PP, _I64, _I64, _P, _P, _P, _I32, _I64, _I], _I),
+    "sell_build_device": ([_PP, _I64, _I64, _P, _P, _P, _I32, _I64, _I, _P], _I),
     "sell_update_values": ([_P, _P, _P], _I),
     "sell_update_values_device": ([_P, _P, _P], _I),
     "sell_export_csr": ([_P, _P, _P, _P], _I),
@@ -189,6 +190,24 @@ def sell_build(nrows, ncols, rowptr, col, val, C, sigma, vdt=SELL_F64, stream=No
     return h
 
 
+def sell_build_device(nrows, ncols, rowptr, col, val, C, sigma, vdt=SELL_F64, stream=None):
+    """Build on the GPU from CSR arrays in device memory (torch tensors: int64 rowptr, int32
+    col, float64 val, contiguous, on the current device); returns the opaque handle."""
+    import torch
+
+    for t, dt in ((rowptr, torch.int64), (col, torch.int32), (val, torch.float64)):
+        if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise SellError(SELL_ERR_ARG, "sell_build_device: rowptr int64, col int32, val float64 device tensors")
+    if rowptr.numel() != nrows + 1:
+        raise SellError(SELL_ERR_ARG, "sell_build_device: rowptr must have nrows + 1 entries")
+    h = ct.c_void_p()
+    _ok(lib().sell_build_device(ct.byref(h), int(nrows), int(ncols), ct.c_void_p(rowptr.data_ptr()),
+                                ct.c_void_p(col.data_ptr()) if col.numel() else None,
+                                ct.c_void_p(val.data_ptr()) if val.numel() else None, int(C), int(sigma),
+                                _dtype_code(vdt), _stream(stream)), "sell_build_device")
+    return h
+
+
 def sell_info(h) -> dict:
     info = sell_info_t()
     _ok(lib().sell_info(h, ct.byref(info)), "sell_info")
@@ -265,6 +284,11 @@ class SellMatrix:
     def set_launch(self, vpt=0, blocks_per_cu=0):
         """Launch parameters of the product kernels for this matrix (0 = defaults)."""
         _ok(lib().sell_set_launch(self.handle, int(vpt), int(blocks_per_cu)), "sell_set_launch")
+
+    @classmethod
+    def from_device_csr(cls, nrows, ncols, rowptr, col, val, C=32, sigma=1, dtype="f64", stream=None):
+        """Build on the GPU from CSR arrays that are device tensors."""
+        return cls(sell_build_device(nrows, ncols, rowptr, col, val, C, sigma, _dtype_code(dtype), stream))
 
     @classmethod
     def from_csr_tuned(cls, A, b, dtype="f64", stream=None, cache=True):

@@ -64,6 +64,7 @@ struct sell_batch {
     int64_t *d_row_off = nullptr;  // device copy of row_off (for the batched solvers)
     int32_t *d_vblk = nullptr;     // vector-kernel workgroup offsets (for the batched solvers)
     int32_t vgrid = 0;
+    int32_t vpt_hint = 0, bpc_hint = 0;  // launch parameters shared by all matrices (else 0)
 };
 
 namespace sellcs {
@@ -110,9 +111,7 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     if (rc) return rc;
     const int vk = vec_kind(B->vdt);
     const int esize = vk == VK_F64F64 ? 8 : 4;
-    // launch parameters: those chosen for the first matrix (a batch is usually one family)
-    const sell_mat *A0 = B->mats[0];
-    const int vpt = choose_vpt(vk, b, A0->vpt_hint);
+    const int vpt = choose_vpt(vk, b, B->vpt_hint);
     const int align = vpt * esize < 16 ? vpt * esize : 16;
     int64_t xrs, xcs, yrs, ycs, zrs = 0, zcs = 0;
     bv_strides(X, xrs, xcs);
@@ -126,7 +125,7 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
                                          : batch_kernel_bf16(b, vpt, aug, fixed_ok);
     // workgroups per matrix: the resident grid split in proportion to the cost
     const int32_t G0 =
-        resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), A0->bpc_hint);
+        resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
     double tot = 0.0;
     for (int m = 0; m < K; ++m) tot += B->cost[size_t(m)];
     std::vector<int32_t> blk(size_t(K) + 1, 0);
@@ -260,6 +259,13 @@ int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
             B->total_tiles += std::max(0, mats[m]->ntiles);
         }
         B->rows = B->row_off[size_t(count)];
+        // launch parameters chosen for the matrices apply to the batch when they all agree
+        B->vpt_hint = mats[0]->vpt_hint;
+        B->bpc_hint = mats[0]->bpc_hint;
+        for (int32_t m = 1; m < count; ++m) {
+            if (mats[m]->vpt_hint != B->vpt_hint) B->vpt_hint = 0;
+            if (mats[m]->bpc_hint != B->bpc_hint) B->bpc_hint = 0;
+        }
         B->cols = B->col_off[size_t(count)];
         B->table_bytes = sizeof(ProdArgs) * size_t(count) + sizeof(int32_t) * (size_t(count) + 1);
     } catch (const std::bad_alloc &) {

@@ -11,10 +11,12 @@
 // Padding entries carry column -1 and value 0, so the kernels can skip them exactly
 // (no gather, no arithmetic) and the original CSR can be recovered bit for bit.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <numeric>
 #include <thread>
+#include <utility>
 
 #include "convert.h"
 #include "internal.h"
@@ -102,17 +104,28 @@ int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *ro
     if (vdt != SELL_F64 && vdt != SELL_F32 && vdt != SELL_BF16) return SELL_ERR_DTYPE;
     if (!rowptr) return SELL_ERR_ARG;
     if (rowptr[0] != 0) return SELL_ERR_ARG;
-    for (int64_t i = 0; i < nrows; ++i)
-        if (rowptr[i + 1] < rowptr[i]) return SELL_ERR_ARG;
+    {
+        std::atomic<bool> bad{false};
+        parallel_for(nrows, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i)
+                if (rowptr[i + 1] < rowptr[i]) {
+                    bad = true;
+                    return;
+                }
+        });
+        if (bad) return SELL_ERR_ARG;
+    }
     const int64_t nnz = rowptr[nrows];
     if (nnz > 0 && (!col || !val)) return SELL_ERR_ARG;
     {
-        bool bad = false;
-        for (int64_t p = 0; p < nnz; ++p)
-            if (col[p] < 0 || int64_t(col[p]) >= ncols) {
-                bad = true;
-                break;
-            }
+        std::atomic<bool> bad{false};
+        parallel_for(nnz, [&](int64_t lo, int64_t hi) {
+            for (int64_t p = lo; p < hi; ++p)
+                if (col[p] < 0 || int64_t(col[p]) >= ncols) {
+                    bad = true;
+                    return;
+                }
+        });
         if (bad) return SELL_ERR_ARG;
     }
 
@@ -129,11 +142,15 @@ int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *ro
 
     // row lengths
     std::vector<int64_t> len(static_cast<size_t>(nrows));
-    for (int64_t i = 0; i < nrows; ++i) len[i] = rowptr[i + 1] - rowptr[i];
+    parallel_for(nrows, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) len[i] = rowptr[i + 1] - rowptr[i];
+    });
 
     // sigma-window sort (descending length, stable)
     std::vector<int32_t> slot_row(static_cast<size_t>(nslots));
-    for (int64_t s = 0; s < nslots; ++s) slot_row[s] = s < nrows ? int32_t(s) : -1;
+    parallel_for(nslots, [&](int64_t lo, int64_t hi) {
+        for (int64_t s = lo; s < hi; ++s) slot_row[s] = s < nrows ? int32_t(s) : -1;
+    });
     const int64_t win = std::min<int64_t>(sigma, std::max<int64_t>(nrows, 1));
     if (win > 1) {
         const int64_t nwin = (nrows + win - 1) / win;
@@ -149,39 +166,53 @@ int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *ro
         h.has_perm = !ident;
     }
 
-    // chunk lengths and starts
+    // chunk lengths (in parallel) and starts (a prefix sum)
     h.cl.assign(size_t(nch), 0);
     h.cs.assign(size_t(nch) + 1, 0);
-    for (int64_t c = 0; c < nch; ++c) {
-        int64_t m = 0;
-        for (int32_t r = 0; r < C; ++r) {
-            int32_t row = slot_row[c * C + r];
-            if (row >= 0) m = std::max(m, len[row]);
+    std::vector<int64_t> clen(static_cast<size_t>(nch));
+    parallel_for(nch, [&](int64_t lo, int64_t hi) {
+        for (int64_t c = lo; c < hi; ++c) {
+            int64_t m = 0;
+            for (int32_t r = 0; r < C; ++r) {
+                const int32_t row = slot_row[c * C + r];
+                if (row >= 0) m = std::max(m, len[row]);
+            }
+            clen[c] = m;
         }
-        if (m >= (int64_t(1) << 31)) return SELL_ERR_ARG;
-        h.cl[c] = int32_t(m);
-        h.cs[c + 1] = h.cs[c] + int64_t(C) * m;
+    });
+    for (int64_t c = 0; c < nch; ++c) {
+        if (clen[c] >= (int64_t(1) << 31)) return SELL_ERR_ARG;
+        h.cl[c] = int32_t(clen[c]);
+        h.cs[c + 1] = h.cs[c] + int64_t(C) * clen[c];
     }
     h.stored = h.cs[nch];
 
-    // column-major fill with padding (col -1, val 0)
-    h.col.assign(size_t(h.stored), -1);
-    std::vector<double> sval(size_t(h.stored), 0.0);
-    parallel_for(nch, [&](int64_t lo, int64_t hi) {
-        for (int64_t c = lo; c < hi; ++c)
-            for (int32_t r = 0; r < C; ++r) {
-                const int32_t row = slot_row[c * C + r];
-                if (row < 0) continue;
-                const int64_t p0 = rowptr[row];
-                for (int64_t k = 0; k < len[row]; ++k) {
-                    const int64_t at = h.cs[c] + k * C + r;
-                    h.col[at] = col[p0 + k];
-                    sval[at] = val[p0 + k];
-                }
-            }
-    });
+    // column-major fill, padding (col -1, value 0) written in the same pass; values are
+    // converted to the storage type on the way (round to nearest even from the double)
+    h.col.resize(size_t(h.stored));
     h.val.resize(size_t(h.stored) * dtype_bytes(vdt));
-    convert_values(sval.data(), h.stored, vdt, h.val.data());
+    auto fill = [&](auto *dst, auto conv) {
+        parallel_for(nch, [&](int64_t lo, int64_t hi) {
+            for (int64_t c = lo; c < hi; ++c)
+                for (int32_t r = 0; r < C; ++r) {
+                    const int32_t row = slot_row[c * C + r];
+                    const int64_t n = row >= 0 ? len[row] : 0;
+                    const int64_t p0 = row >= 0 ? rowptr[row] : 0;
+                    for (int64_t k = 0; k < h.cl[c]; ++k) {
+                        const int64_t at = h.cs[c] + k * C + r;
+                        const bool real = k < n;
+                        h.col[at] = real ? col[p0 + k] : -1;
+                        dst[at] = conv(real ? val[p0 + k] : 0.0);
+                    }
+                }
+        });
+    };
+    if (vdt == SELL_F64)
+        fill(reinterpret_cast<double *>(h.val.data()), [](double v) { return v; });
+    else if (vdt == SELL_F32)
+        fill(reinterpret_cast<float *>(h.val.data()), [](double v) { return float(v); });
+    else
+        fill(reinterpret_cast<uint16_t *>(h.val.data()), [](double v) { return f64_to_bf16_bits(v); });
 
     if (h.has_perm) h.perm = std::move(slot_row);
     h.rowptr.assign(rowptr, rowptr + nrows + 1);

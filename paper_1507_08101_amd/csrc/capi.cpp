@@ -76,8 +76,8 @@ int upload(sell_mat *A, hipStream_t s) {
     A->matrix_bytes = int64_t(h.col.size() * 4 + h.val.size() + h.cl.size() * 4 + h.cs.size() * 8 +
                               h.perm.size() * 4 + h.tiles.size() * 4);
     // the device now holds the big arrays; keep only the small metadata on the host
-    std::vector<int32_t>().swap(h.col);
-    std::vector<uint8_t>().swap(h.val);
+    raw_vector<int32_t>().swap(h.col);
+    raw_vector<uint8_t>().swap(h.val);
     A->on_device = true;
     return SELL_OK;
 }
@@ -326,6 +326,28 @@ int sell_build(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr
                const double *val, int32_t C, int64_t sigma, sell_dtype vdt, void *stream) {
     return build_common(A, nrows, ncols, rowptr, col, val, C, sigma, vdt, true,
                         static_cast<hipStream_t>(stream));
+}
+
+int sell_build_device(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
+                      const double *val, int32_t C, int64_t sigma, sell_dtype vdt, void *stream) {
+    if (!A) return SELL_ERR_ARG;
+    *A = nullptr;
+    sell_mat *M = new (std::nothrow) sell_mat();
+    if (!M) return SELL_ERR_OOM;
+    int rc;
+    try {
+        rc = build_device_sell(M, nrows, ncols, rowptr, col, val, C, sigma, int(vdt), static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc &) {
+        rc = SELL_ERR_OOM;
+    }
+    if (rc) {
+        M->on_device = true;  // release whatever device arrays the build made
+        free_device(M);
+        delete M;
+        return rc;
+    }
+    *A = M;
+    return SELL_OK;
 }
 
 int sell_build_host(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr,

@@ -18,6 +18,29 @@ constexpr int kBlock = 512;         // threads per block of the product kernels
 
 inline int dtype_bytes(int dt) { return dt == SELL_F64 ? 8 : dt == SELL_F32 ? 4 : 2; }
 
+// Allocator that leaves new elements uninitialised (the builder writes every element itself,
+// in parallel, so a serial zero fill of hundreds of MB is saved).
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept {
+        ::new (static_cast<void *>(p)) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new (static_cast<void *>(p)) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using raw_vector = std::vector<T, NoInitAlloc<T>>;
+
 // Host-side SELL-C-sigma arrays (the build result before upload).
 struct HostSell {
     int64_t nrows = 0, ncols = 0, nnz = 0, stored = 0, nch = 0, sigma = 1;
@@ -27,8 +50,8 @@ struct HostSell {
     std::vector<int32_t> perm;    // slot -> row (-1 past the end); empty when identity
     std::vector<int32_t> cl;      // chunk lengths
     std::vector<int64_t> cs;      // chunk starts (nch + 1)
-    std::vector<int32_t> col;     // stored column indices (-1 = padding)
-    std::vector<uint8_t> val;     // stored values in storage type
+    raw_vector<int32_t> col;      // stored column indices (-1 = padding)
+    raw_vector<uint8_t> val;      // stored values in storage type
     std::vector<int32_t> tiles;   // ntiles + 1 chunk boundaries
     std::vector<int64_t> rowptr;  // CSR row pointers of the input (for export and updates)
 };
@@ -41,6 +64,14 @@ void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
 // Validates CSR input and builds the host SELL arrays. Returns SELL_OK or an error.
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
                     const int32_t *col, const double *val, int32_t C, int64_t sigma, int vdt);
+
+}  // namespace sellcs
+struct sell_mat;
+namespace sellcs {
+// Builds the SELL arrays on the device from a CSR matrix in device memory (devbuild.hip);
+// fills the device arrays and the host metadata of M. On error M may hold device arrays.
+int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
+                      const double *val, int32_t C, int64_t sigma, int vdt, hipStream_t s);
 
 // Value conversion (round to nearest, ties to even, from the double).
 uint16_t f64_to_bf16_bits(double v);

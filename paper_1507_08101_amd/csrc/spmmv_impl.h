@@ -68,22 +68,33 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks) {
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
+// Pointers into global memory. Pointers read from memory (the argument tables of the batched
+// kernel) are generic to the compiler, which would access them with flat instructions (that
+// also count against the LDS counter and so lengthen every wait); typed as global pointers
+// they are accessed with global loads and stores, as pointers passed as kernel arguments are.
+#define SELL_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ SELL_GLOBAL T *to_global(T *p) {
+    return (SELL_GLOBAL T *)p;
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // VPT consecutive elements at p (element stride cs). VEC: cs == 1 and p aligned to
 // min(16, VPT * sizeof(X)) bytes, so the row piece moves as 8- or 16-byte vector accesses.
 template <class X, int VPT, bool VEC>
-__device__ __forceinline__ void load_row(const X *p, int64_t cs, X (&o)[VPT]) {
+__device__ __forceinline__ void load_row(const SELL_GLOBAL X *p, int64_t cs, X (&o)[VPT]) {
     constexpr int bytes = VPT * int(sizeof(X));
     if constexpr (VEC && bytes % 16 == 0) {
 #pragma unroll
         for (int q = 0; q < bytes / 16; ++q) {
-            const u32x4 v = reinterpret_cast<const u32x4 *>(p)[q];
+            const u32x4 v = reinterpret_cast<const SELL_GLOBAL u32x4 *>(p)[q];
             __builtin_memcpy(reinterpret_cast<char *>(o) + 16 * q, &v, 16);
         }
     } else if constexpr (VEC && bytes == 8) {
-        const u32x2 v = *reinterpret_cast<const u32x2 *>(p);
+        const u32x2 v = *reinterpret_cast<const SELL_GLOBAL u32x2 *>(p);
         __builtin_memcpy(o, &v, 8);
     } else {
 #pragma unroll
@@ -92,19 +103,19 @@ __device__ __forceinline__ void load_row(const X *p, int64_t cs, X (&o)[VPT]) {
 }
 
 template <class X, int VPT, bool VEC>
-__device__ __forceinline__ void store_row(X *p, int64_t cs, const X (&o)[VPT]) {
+__device__ __forceinline__ void store_row(SELL_GLOBAL X *p, int64_t cs, const X (&o)[VPT]) {
     constexpr int bytes = VPT * int(sizeof(X));
     if constexpr (VEC && bytes % 16 == 0) {
 #pragma unroll
         for (int q = 0; q < bytes / 16; ++q) {
             u32x4 v;
             __builtin_memcpy(&v, reinterpret_cast<const char *>(o) + 16 * q, 16);
-            reinterpret_cast<u32x4 *>(p)[q] = v;
+            reinterpret_cast<SELL_GLOBAL u32x4 *>(p)[q] = v;
         }
     } else if constexpr (VEC && bytes == 8) {
         u32x2 v;
         __builtin_memcpy(&v, o, 8);
-        *reinterpret_cast<u32x2 *>(p) = v;
+        *reinterpret_cast<SELL_GLOBAL u32x2 *>(p) = v;
     } else {
 #pragma unroll
         for (int t = 0; t < VPT; ++t) p[t * cs] = o[t];
@@ -139,24 +150,25 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
 
     const int C = a.C;
     const int32_t cshift = a.cshift;
-    const int32_t *__restrict__ perm = a.perm;
-    const int32_t *__restrict__ clp = a.cl;
-    const int64_t *__restrict__ csp = a.cs;
+    const SELL_GLOBAL int32_t *__restrict__ perm = to_global(a.perm);
+    const SELL_GLOBAL int32_t *__restrict__ clp = to_global(a.cl);
+    const SELL_GLOBAL int64_t *__restrict__ csp = to_global(a.cs);
+    const SELL_GLOBAL int32_t *__restrict__ tiles = to_global(a.tiles);
     const int64_t nrows = a.nrows;
     const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
-    const int64_t s_begin = int64_t(a.tiles[t0]) * C;
-    const int64_t s_end = int64_t(a.tiles[t1]) * C;
+    const int64_t s_begin = int64_t(tiles[t0]) * C;
+    const int64_t s_end = int64_t(tiles[t1]) * C;
     const int tid = threadIdx.x;
     const int vg = tid & (VL - 1);
     const int rows_per_pass = kBlock >> vls;
     const int jb = vg * VPT;
     const bool col_ok = DYN ? (vg < nb) : true;
 
-    const V *__restrict__ val = static_cast<const V *>(a.val);
-    const int32_t *__restrict__ col = a.col;
-    const X *__restrict__ Xp = static_cast<const X *>(a.X);
-    X *__restrict__ Yp = static_cast<X *>(a.Y);
-    X *__restrict__ Zp = static_cast<X *>(a.Z);
+    const SELL_GLOBAL V *__restrict__ val = to_global(static_cast<const V *>(a.val));
+    const SELL_GLOBAL int32_t *__restrict__ col = to_global(a.col);
+    const SELL_GLOBAL X *__restrict__ Xp = to_global(static_cast<const X *>(a.X));
+    SELL_GLOBAL X *__restrict__ Yp = to_global(static_cast<X *>(a.Y));
+    SELL_GLOBAL X *__restrict__ Zp = to_global(static_cast<X *>(a.Z));
     const int64_t xrs = a.xrs, xcs = VEC ? 1 : a.xcs;
     const int64_t yrs = a.yrs, ycs = VEC ? 1 : a.ycs;
     const int64_t zrs = a.zrs, zcs = VEC ? 1 : a.zcs;
@@ -169,7 +181,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     const bool read_z = chain && a.delta != 0.0;
     const double alpha = (AUG && (a.flags & SELL_SPMV_SCALE)) ? a.alpha : 1.0;
     const double beta = a.beta, delta = a.delta, eta = a.eta;
-    X *const scratch_base = static_cast<X *>(a.scratch);
+    SELL_GLOBAL X *const scratch_base = to_global(static_cast<X *>(a.scratch));
 
     double dyy[VPT], dxy[VPT], dxx[VPT];
 #pragma unroll
@@ -187,7 +199,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     auto load_meta = [&](int64_t ss, int &clv, int64_t &csv, int &pv) {
         const int64_t sc = ss < s_end ? ss : s_end - 1;
         const int64_t c = cshift >= 0 ? (sc >> cshift) : int64_t(uint32_t(sc) / uint32_t(C));
-        const int32_t *pp = perm ? perm + sc : clp + c;
+        const SELL_GLOBAL int32_t *pp = perm ? perm + sc : clp + c;
         clv = clp[c];
         csv = csp[c];
         pv = *pp;
@@ -259,8 +271,8 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
             }
         }
 
-        X *scratch = scratch_base + size_t(tid) * VPT;
-        X *ydst = live ? Yp + row * yrs + int64_t(jb) * ycs : scratch;
+        SELL_GLOBAL X *scratch = scratch_base + size_t(tid) * VPT;
+        SELL_GLOBAL X *ydst = live ? Yp + row * yrs + int64_t(jb) * ycs : scratch;
         const int64_t ysd = live ? ycs : 1;
         X out[VPT];
         if (!AUG) {
@@ -289,7 +301,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
             }
             store_row<X, VPT, VEC>(ydst, ysd, out);
             if (chain) {
-                X *zdst = live ? Zp + row * zrs + int64_t(jb) * zcs : scratch;
+                SELL_GLOBAL X *zdst = live ? Zp + row * zrs + int64_t(jb) * zcs : scratch;
                 store_row<X, VPT, VEC>(zdst, live ? zcs : 1, zout);
             }
         }
@@ -324,7 +336,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
         double sum = 0.0;
 #pragma unroll
         for (int ww = 0; ww < kBlock / 64; ++ww) sum += red[ww][q];
-        a.partials[size_t(q) * a.nblocks + tile] = sum;
+        to_global(a.partials)[size_t(q) * a.nblocks + tile] = sum;
     }
 }
 
@@ -354,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__re
     const int tile = g - blk_start[lo];
     if (active && !active[lo]) {
         if (AUG && (a.flags & SELL_SPMV_DOTS))
-            for (int q = threadIdx.x; q < 3 * a.nb; q += kBlock) a.partials[size_t(q) * a.nblocks + tile] = 0.0;
+            for (int q = threadIdx.x; q < 3 * a.nb; q += kBlock) to_global(a.partials)[size_t(q) * a.nblocks + tile] = 0.0;
         return;
     }
     prod_body<VK, B, VPT, AUG>(a, tile, vl_log2);
