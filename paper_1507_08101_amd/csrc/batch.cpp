@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 
 #include "internal.h"
@@ -32,7 +33,8 @@ namespace {
         if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? SELL_ERR_OOM : SELL_ERR_HIP; \
     } while (0)
 
-constexpr int kSlots = 4;
+constexpr int kRing = 4;            // table slots shared by all calls, reused round robin
+constexpr int kSlots = kRing + 1;   // plus one reserved for a solver's repeated product
 
 bool fixed_width(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32; }
 
@@ -65,6 +67,7 @@ struct sell_batch {
     int32_t *d_vblk = nullptr;     // vector-kernel workgroup offsets (for the batched solvers)
     int32_t vgrid = 0;
     int32_t vpt_hint = 0, bpc_hint = 0;  // launch parameters shared by all matrices (else 0)
+    std::map<int32_t, std::vector<int32_t>> blk_cache;  // workgroup offsets per resident grid size
 };
 
 namespace sellcs {
@@ -96,14 +99,84 @@ BatchSeg batch_seg(const sell_batch *B) {
     return sg;
 }
 
+// Splits G0 workgroups over K items in proportion to their weights (largest remainders), at
+// least one for every item with work (cap > 0) and at most cap; blk receives the K + 1 offsets.
+// Used so that a launch stays one wave of resident workgroups: a workgroup beyond the resident
+// ones would start only when another finishes and double the time of its share. The total
+// exceeds G0 only when more items have work than G0.
+void apportion(const std::vector<double> &w, const std::vector<int64_t> &cap, int32_t G0,
+               std::vector<int32_t> &blk) {
+    const size_t K = w.size();
+    double tot = 0.0;
+    for (size_t m = 0; m < K; ++m)
+        if (cap[m] > 0) tot += w[m];
+    std::vector<int64_t> n(K, 0);
+    std::vector<double> ideal(K, 0.0);
+    int64_t sum = 0;
+    for (size_t m = 0; m < K; ++m) {
+        if (cap[m] <= 0) continue;
+        ideal[m] = double(G0) * w[m] / (tot > 0 ? tot : 1.0);
+        n[m] = std::max<int64_t>(1, std::min<int64_t>(cap[m], int64_t(ideal[m])));
+        sum += n[m];
+    }
+    // what is left goes to the largest remainders, one at a time
+    while (sum < G0) {
+        int64_t best = -1;
+        double rem = -1e300;
+        for (size_t m = 0; m < K; ++m) {
+            if (cap[m] <= 0 || n[m] >= cap[m]) continue;
+            const double r = ideal[m] - double(n[m]);
+            if (r > rem) {
+                rem = r;
+                best = int64_t(m);
+            }
+        }
+        if (best < 0) break;
+        ++n[size_t(best)];
+        ++sum;
+    }
+    // too many (the minimum of one per item): take from the most over-served
+    while (sum > G0) {
+        int64_t best = -1;
+        double over = -1e300;
+        for (size_t m = 0; m < K; ++m) {
+            if (n[m] <= 1) continue;
+            const double o = double(n[m]) - ideal[m];
+            if (o > over) {
+                over = o;
+                best = int64_t(m);
+            }
+        }
+        if (best < 0) break;
+        --n[size_t(best)];
+        --sum;
+    }
+    blk.assign(K + 1, 0);
+    for (size_t m = 0; m < K; ++m) blk[m + 1] = blk[m] + int32_t(n[m]);
+}
+
+// Workgroups of the product launches per matrix: weights = cost, cap = fine tiles; matrices
+// with host_active[m] == 0 get none (host_active may be null: all matrices).
+void apportion_products(const sell_batch *B, int32_t G0, const int32_t *host_active, std::vector<int32_t> &blk) {
+    std::vector<int64_t> cap(static_cast<size_t>(B->K));
+    for (int m = 0; m < B->K; ++m)
+        cap[size_t(m)] = (host_active && !host_active[m]) ? 0 : B->mats[size_t(m)]->ntiles;
+    apportion(B->cost, cap, G0, blk);
+}
+
 // The batched product (no argument checks): y_m = alpha (A_m x_m - gamma x_m) + beta y_m with
-// dots and chain for every matrix m, skipping matrices with active[m] == 0 (active may be
-// null). Dot partials stay in the batch's buffer; *out_blk / *out_partials (may be null)
-// receive the device workgroup offsets and the partials. finish: sum the dots into o.dot
-// (3 b doubles per matrix).
+// dots and chain for every matrix m, skipping matrices with active[m] == 0 (device flags read
+// by the kernel; may be null). host_active (K host flags, may be null) restricts the launch to
+// the flagged matrices: the others get no workgroups and are not touched, and the resident
+// grid is split over the flagged ones only. Dot partials stay in the batch's buffer;
+// *out_blk / *out_partials (may be null) receive the device workgroup offsets and the partials.
+// finish: sum the dots into o.dot (3 b doubles per matrix; those of unlaunched matrices are
+// left as they are). reserved: keep the launch table in the batch's reserved slot, which only
+// other reserved calls replace (a solver's repeated product, whose table a captured graph
+// refers to, is not evicted by its other products).
 int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
-                   const int32_t *active, bool finish, hipStream_t s, const int32_t **out_blk,
-                   const double **out_partials) {
+                   const int32_t *active, const int32_t *host_active, bool finish, hipStream_t s,
+                   const int32_t **out_blk, const double **out_partials, bool reserved) {
     const int b = X->ncols;
     const int K = B->K;
     Workspace *ws = nullptr;
@@ -126,22 +199,26 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     // workgroups per matrix: the resident grid split in proportion to the cost
     const int32_t G0 =
         resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
-    double tot = 0.0;
-    for (int m = 0; m < K; ++m) tot += B->cost[size_t(m)];
-    std::vector<int32_t> blk(size_t(K) + 1, 0);
-    for (int m = 0; m < K; ++m) {
-        const sell_mat *A = B->mats[size_t(m)];
-        const int32_t nt = A->ntiles;
-        int32_t n = 0;
-        if (nt > 0) {
-            n = int32_t(std::llround(double(G0) * B->cost[size_t(m)] / (tot > 0 ? tot : 1.0)));
-            n = std::max(1, std::min(n, nt));
+    std::vector<int32_t> sub_blk;
+    const std::vector<int32_t> *pblk_h = nullptr;
+    if (host_active) {
+        apportion_products(B, G0, host_active, sub_blk);
+        pblk_h = &sub_blk;
+    } else {
+        auto hit = B->blk_cache.find(G0);
+        if (hit == B->blk_cache.end()) {
+            std::vector<int32_t> v;
+            apportion_products(B, G0, nullptr, v);
+            hit = B->blk_cache.emplace(G0, std::move(v)).first;
         }
-        blk[size_t(m) + 1] = blk[size_t(m)] + n;
+        pblk_h = &hit->second;
     }
+    const std::vector<int32_t> &blk = *pblk_h;
     const int32_t G = blk[size_t(K)];
     const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
-    const size_t need = size_t(3) * b * size_t(std::max(G, 1));
+    // room for any block width and any split of this grid, so later calls (possibly captured
+    // in a graph) never move the buffer
+    const size_t need = size_t(3) * kMaxSliceCols * size_t(std::max<int64_t>(std::max(G, G0), K));
     if (dots && need > B->partials_cap) {
         // grows outside any steady state (the first call of a shape)
         if (B->partials) HIPCHK(hipFree(B->partials));
@@ -187,13 +264,21 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
         std::memcpy(&tab[m], &a, sizeof(ProdArgs));
     }
     std::memcpy(B->stage.data() + sizeof(ProdArgs) * size_t(K), blk.data(), sizeof(int32_t) * (size_t(K) + 1));
-    // find the table on the device, else upload it into the next slot
+    // find the table on the device, else upload it (into the reserved slot, or the next ring slot)
     int slot = -1;
-    for (int i = 0; i < kSlots && slot < 0; ++i)
-        if (B->valid[i] && std::memcmp(B->h_slot[i], B->stage.data(), B->table_bytes) == 0) slot = i;
+    if (reserved) {
+        if (B->valid[kRing] && std::memcmp(B->h_slot[kRing], B->stage.data(), B->table_bytes) == 0) slot = kRing;
+    } else {
+        for (int i = 0; i < kRing && slot < 0; ++i)
+            if (B->valid[i] && std::memcmp(B->h_slot[i], B->stage.data(), B->table_bytes) == 0) slot = i;
+    }
     if (slot < 0) {
-        slot = B->next;
-        B->next = (B->next + 1) % kSlots;
+        if (reserved) {
+            slot = kRing;
+        } else {
+            slot = B->next;
+            B->next = (B->next + 1) % kRing;
+        }
         if (B->valid[slot]) HIPCHK(hipEventSynchronize(B->ev[slot]));  // its last upload has been read
         B->valid[slot] = false;
         std::memcpy(B->h_slot[slot], B->stage.data(), B->table_bytes);
@@ -218,6 +303,19 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
         if (G == 0) {
             for (int m = 0; m < K; ++m)
                 if ((rc = launch_fill(o.dot + size_t(m) * 3 * b, SELL_F64, 1, 3 * b, 3 * b, 1, 0.0, s))) return rc;
+            return SELL_OK;
+        }
+        if (host_active) {
+            // only the launched matrices have partials (a matrix without rows: zero dots)
+            for (int m = 0; m < K; ++m) {
+                if (!host_active[m]) continue;
+                const int32_t np = blk[size_t(m) + 1] - blk[size_t(m)];
+                double *dm = o.dot + size_t(m) * 3 * b;
+                rc = np > 0 ? launch_dot_finish(B->partials + size_t(3) * b * blk[size_t(m)], np, b, o.flags, dm, b,
+                                                1, 0, s)
+                            : launch_fill(dm, SELL_F64, 1, 3 * b, 3 * b, 1, 0.0, s);
+                if (rc) return rc;
+            }
             return SELL_OK;
         }
         if ((rc = launch_batch_dot_finish(B->partials, d_blk, K, b, o.flags, o.dot, s))) return rc;
@@ -283,22 +381,19 @@ int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
         if ((e = hipHostMalloc(&B->h_slot[i], B->table_bytes, hipHostMallocDefault)) != hipSuccess) return fail(e);
         if ((e = hipEventCreateWithFlags(&B->ev[i], hipEventDisableTiming)) != hipSuccess) return fail(e);
     }
-    // vector-kernel workgroups for the batched solvers: about kCgMaxGrid * 2 in total, split
-    // in proportion to the rows (at least one per non-empty system)
+    // vector-kernel workgroups for the batched solvers: 2 * kCgMaxGrid in total, split in
+    // proportion to the rows (at least one per non-empty system, a few rows per workgroup)
     {
         const int32_t Gv = 2 * kCgMaxGrid;
-        std::vector<int32_t> vblk(size_t(count) + 1, 0);
+        std::vector<int32_t> vblk;
+        std::vector<double> w(static_cast<size_t>(count));
+        std::vector<int64_t> cap(static_cast<size_t>(count));
         for (int32_t m = 0; m < count; ++m) {
             const int64_t n = B->row_off[size_t(m) + 1] - B->row_off[size_t(m)];
-            int32_t g = 0;
-            if (n > 0) {
-                g = int32_t(std::llround(double(Gv) * double(n) / double(std::max<int64_t>(B->rows, 1))));
-                g = std::max(1, g);
-                g = int32_t(std::min<int64_t>(g, (n + 3) / 4));  // keep a few rows per workgroup
-                g = std::max(1, g);
-            }
-            vblk[size_t(m) + 1] = vblk[size_t(m)] + g;
+            w[size_t(m)] = double(n);
+            cap[size_t(m)] = n > 0 ? std::max<int64_t>(1, (n + 3) / 4) : 0;
         }
+        apportion(w, cap, Gv, vblk);
         B->vgrid = vblk[size_t(count)];
         if ((e = hipMalloc(&B->d_row_off, sizeof(int64_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
         if ((e = hipMalloc(&B->d_vblk, sizeof(int32_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
@@ -360,7 +455,8 @@ int sell_batch_spmmv_aug(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z
     }
     const bool aug = o.flags != 0;
     try {
-        return batch_aug_impl(B, X, Y, Z, o, aug, nullptr, true, static_cast<hipStream_t>(stream), nullptr, nullptr);
+        return batch_aug_impl(B, X, Y, Z, o, aug, nullptr, nullptr, true, static_cast<hipStream_t>(stream), nullptr,
+                              nullptr, false);
     } catch (const std::bad_alloc &) {
         return SELL_ERR_OOM;
     }

@@ -9,8 +9,12 @@
 //   beta, rho, flags   one workgroup per system (a system whose columns have all converged
 //                      drops out: the product and vector kernels skip it)
 //   P = R + b P        segmented vector kernel
-// Runs of kCheckEvery iterations are captured once in a HIP graph and replayed (or launched
-// directly); the host looks at the scalars between runs.
+// Runs of kCheckEvery iterations are captured in a HIP graph and replayed (or launched
+// directly); the host looks at the scalars between runs. The launches of an iteration are
+// spread over the systems that still iterate only: whenever that set changes, the resident
+// workgroups of the product and of the vector kernels are split anew over the remaining
+// systems (and the graph is captured again), so that the last, largest systems still get the
+// whole GPU. A residual update likewise spreads its FP64 product over the updated systems.
 //
 // Precision: with a low-precision batch Alo (F32 or BF16 values) the iteration runs in FP32
 // vectors and accumulates a correction D, and the solution is refined in FP64 by reliable
@@ -33,8 +37,10 @@ using namespace sellcs;
 
 namespace sellcs {
 int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
-                   const int32_t *active, bool finish, hipStream_t s, const int32_t **out_blk,
-                   const double **out_partials);
+                   const int32_t *active, const int32_t *host_active, bool finish, hipStream_t s,
+                   const int32_t **out_blk, const double **out_partials, bool reserved);
+void apportion(const std::vector<double> &w, const std::vector<int64_t> &cap, int32_t G0,
+               std::vector<int32_t> &blk);
 const sell_mat *batch_matrix(const sell_batch *B, int m);
 int32_t batch_count(const sell_batch *B);
 int64_t batch_rows(const sell_batch *B);
@@ -147,7 +153,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     const int idt = mixed ? SELL_F32 : SELL_F64;  // vector type of the iteration
     const size_t isz = mixed ? sizeof(float) : sizeof(double);
     sell_batch *Ain = mixed ? Alo : A64;
-    const BatchSeg sg = batch_seg(A64);
+    const BatchSeg sg = batch_seg(A64);  // every system (for ||b||^2 and the residual updates)
     const size_t Kb = size_t(K) * b;
     if (n == 0) {  // only empty systems: nothing to solve
         if (stats)
@@ -172,9 +178,11 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         (rc = DB.alloc(&pd, nv * isz)) || (rc = DB.alloc(&pp, nv * isz)) || (rc = DB.alloc(&pq, nv * isz)))
         return rc;
     // device scalars: rho alpha beta thresh2 bb rr(3Kb) | vec partials (b G) | int32 flags
-    const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * size_t(std::max(sg.G, 1));
-    // active, sys_active, mask, spare | iters (int64) | column mask
-    const size_t ni = Kb + 3 * size_t(K) + 2 * size_t(K) + 2 + Kb;
+    const int32_t Gv = 2 * kCgMaxGrid;  // vector-kernel workgroups of an iteration
+    const size_t gmax = size_t(std::max(std::max(sg.G, Gv), K));
+    const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * gmax;
+    // active, sys_active, mask, spare | iters (int64) | column mask | iteration workgroup offsets
+    const size_t ni = Kb + 3 * size_t(K) + 2 * size_t(K) + 2 + Kb + size_t(K) + 1;
     if ((rc = DB.alloc(&pscal, nd * sizeof(double) + ni * sizeof(int32_t) + 16)))
         return rc;
     double *d = static_cast<double *>(pscal);
@@ -195,6 +203,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     iters_d = reinterpret_cast<int64_t *>((reinterpret_cast<uintptr_t>(iters_d) + 7) & ~uintptr_t(7));
     sc.iters = iters_d;
     int32_t *colmask_d = reinterpret_cast<int32_t *>(iters_d + K);
+    int32_t *vblk_d = colmask_d + Kb;
 
     sell_bv Bview = *Bv;
     sell_bv R64 = view(pr64, n, b, SELL_F64), R = view(pr, n, b, idt), D = view(pd, n, b, idt),
@@ -224,7 +233,8 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         o.alpha = -1.0;
         o.beta = 1.0;
         o.dot = rr_d;
-        if ((r = batch_aug_impl(A64, X, &R64, nullptr, o, true, mask_d, true, s, nullptr, nullptr))) return r;
+        if ((r = batch_aug_impl(A64, X, &R64, nullptr, o, true, mask_d, mask.data(), true, s, nullptr, nullptr, false)))
+            return r;
         HIPCHK(hipMemcpyAsync(rr.data(), rr_d, 3 * Kb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         bool restart = false;
@@ -284,27 +294,62 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     std::fill(mask.begin(), mask.end(), 1);
     if ((rc = refresh())) return rc;
 
+    // the split of an iteration's launches over the systems that iterate (appo_active)
+    std::vector<int32_t> appo_active(static_cast<size_t>(K), -1), vblk;
+    BatchSeg sgi = sg;
+    sgi.vblk = vblk_d;
+    std::vector<double> wrows(static_cast<size_t>(K));
+    for (int m = 0; m < K; ++m) wrows[size_t(m)] = double(batch_matrix(A64, m)->h.nrows);
+    auto resplit = [&](bool *changed) -> int {
+        *changed = appo_active != sysact;
+        if (!*changed) return SELL_OK;
+        appo_active = sysact;
+        std::vector<int64_t> cap(static_cast<size_t>(K));
+        for (int m = 0; m < K; ++m) {
+            const int64_t nr = batch_matrix(A64, m)->h.nrows;
+            cap[size_t(m)] = (sysact[size_t(m)] && nr > 0) ? std::max<int64_t>(1, (nr + 3) / 4) : 0;
+        }
+        apportion(wrows, cap, Gv, vblk);
+        sgi.G = vblk[size_t(K)];
+        HIPCHK(hipMemcpyAsync(vblk_d, vblk.data(), (size_t(K) + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));  // vblk is reused by the next split
+        return SELL_OK;
+    };
+
     sell_spmv_opts po = SELL_SPMV_OPTS_INIT;
     po.flags = SELL_SPMV_DOT_XY;
     auto iteration = [&]() -> int {
         int r;
         const int32_t *pblk = nullptr;
         const double *pparts = nullptr;
-        if ((r = batch_aug_impl(Ain, &P, &Q, nullptr, po, true, sc.sys_active, false, s, &pblk, &pparts))) return r;
+        if ((r = batch_aug_impl(Ain, &P, &Q, nullptr, po, true, sc.sys_active, appo_active.data(), false, s, &pblk,
+                                &pparts, true)))
+            return r;
         if ((r = bcg_launch_alpha(pparts, pblk, K, b, sc, s))) return r;
-        if ((r = bcg_launch_xr(idt, pd, pr, pp, pq, b, sg, sc, vparts, s))) return r;
-        return bcg_launch_p(idt, pp, pr, b, sg, sc, s);
+        if (sgi.G == 0) return SELL_OK;
+        if ((r = bcg_launch_xr(idt, pd, pr, pp, pq, b, sgi, sc, vparts, s))) return r;
+        return bcg_launch_p(idt, pp, pr, b, sgi, sc, s);
     };
 
     Graph graph;
     bool done = std::all_of(conv.begin(), conv.end(), [](int32_t c) { return c != 0; });
     int64_t it = 0;
+    bool fresh = true;  // the split changed since the last run: launch directly once
     std::vector<int32_t> act_now(Kb), sys_now(static_cast<size_t>(K));
     while (!done && it < maxit) {
+        bool changed = false;
+        if ((rc = resplit(&changed))) return rc;
+        if (changed) {
+            fresh = true;
+            if (graph.ge) (void)hipGraphExecDestroy(graph.ge);
+            if (graph.g) (void)hipGraphDestroy(graph.g);
+            graph.ge = nullptr;
+            graph.g = nullptr;
+        }
         const int64_t run = std::min<int64_t>(kCheckEvery, maxit - it);
-        if (use_graph && run == kCheckEvery && it > 0) {
-            // the first run is launched directly (it places the product's table on the
-            // device); the graph is captured from the second run on and replayed
+        if (use_graph && run == kCheckEvery && !fresh) {
+            // the first run after a new split is launched directly (it places the product's
+            // table on the device); the graph is captured from the next run on and replayed
             if (!graph.ge) {
                 HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 int r = SELL_OK;
@@ -320,6 +365,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         } else {
             for (int64_t k = 0; k < run; ++k)
                 if ((rc = iteration())) return rc;
+            fresh = false;
         }
         it += run;
         for (int m = 0; m < K; ++m)

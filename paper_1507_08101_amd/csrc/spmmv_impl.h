@@ -123,12 +123,13 @@ __device__ __forceinline__ void store_row(SELL_GLOBAL X *p, int64_t cs, const X 
 }
 
 // Entries gathered per batch: all index/value loads of a batch are issued before its
-// gathers, and all gathers before the FMAs (bounded so the gathered values fit in about
-// 32 VGPRs).
+// gathers, and all gathers before the FMAs, so a row of up to U entries costs one round of
+// index loads and one round of gathers. The gathered values take U * VPT * sizeof(X) / 4
+// VGPRs (up to 64); an 8-wave workgroup still runs one per CU below 256 VGPRs.
 template <class X, int VPT>
 constexpr int batch_len() {
     constexpr int regs = VPT * int(sizeof(X)) / 4;  // VGPRs per gathered row piece
-    return regs <= 4 ? 8 : (regs <= 8 ? 4 : 2);
+    return regs <= 8 ? 8 : 4;
 }
 
 // B > 0: compile-time slice width with VPT columns per lane (VL = B / VPT lanes per row);

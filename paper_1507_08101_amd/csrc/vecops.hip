@@ -55,8 +55,8 @@ int32_t resident_grid(const void *kernel, int threads, int32_t ntiles, int32_t b
         cache.emplace(key, occ);
     }
     const int32_t per = (blocks_per_cu > 0 && blocks_per_cu < occ.first) ? blocks_per_cu : occ.first;
-    const int32_t full = per * occ.second;
-    return full < ntiles ? full : ntiles;
+    const int64_t full = int64_t(per) * occ.second;
+    return full < ntiles ? int32_t(full) : ntiles;
 }
 
 static bool fixed_width(int b) { return b == 1 || b == 2 || b == 4 || b == 8 || b == 16 || b == 32; }
