@@ -366,8 +366,8 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
 /* The paper distributes one matrix over heterogeneous devices by work weights which it  */
 /* plans to derive from micro-benchmarks (Sec. 4.1 and the outlook, Sec. 7.2). On one    */
 /* GPU the same idea spreads many small and uneven matrices over the compute units: one  */
-/* launch processes every matrix of a batch, with the device's resident workgroups split  */
-/* in proportion to each matrix's cost (stored entries plus rows).                        */
+/* launch processes every matrix of a batch, with the workgroups split by each matrix's   */
+/* cost (stored entries plus rows) so that the busiest workgroup has the least work.      */
 
 typedef struct sell_batch sell_batch;
 

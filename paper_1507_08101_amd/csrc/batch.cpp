@@ -2,18 +2,21 @@
 //
 // The batch's block vectors hold the matrices' operands one after another: matrix m reads
 // rows [col_off[m], col_off[m+1]) of X and writes rows [row_off[m], row_off[m+1]) of Y. One
-// launch of the batched product kernel covers every matrix: the device's resident workgroups
-// are split over the matrices in proportion to their cost (stored entries plus rows), and
-// each workgroup finds its matrix's launch arguments in a table in device memory by a binary
+// launch of the batched product kernel covers every matrix: two waves of the device's resident
+// workgroups are split over the matrices by their cost (stored entries plus rows) so that the
+// busiest workgroup has as little work as possible, and each workgroup finds its matrix's launch arguments in a table in device memory by a binary
 // search over the workgroup offsets. The tables are staged through pinned host memory into a
 // few device slots; a call whose table equals one already on the device (the same operands
 // and scalars, as in every iteration of a solver) uploads nothing, which keeps repeated calls
 // free of copies and lets them be captured in a HIP graph.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
+#include <queue>
+#include <utility>
 
 #include "internal.h"
 
@@ -99,57 +102,30 @@ BatchSeg batch_seg(const sell_batch *B) {
     return sg;
 }
 
-// Splits G0 workgroups over K items in proportion to their weights (largest remainders), at
-// least one for every item with work (cap > 0) and at most cap; blk receives the K + 1 offsets.
-// Used so that a launch stays one wave of resident workgroups: a workgroup beyond the resident
-// ones would start only when another finishes and double the time of its share. The total
-// exceeds G0 only when more items have work than G0.
+// Splits G0 workgroups over K items so that the largest work per workgroup is as small as
+// possible: one for every item with work (cap > 0), then one at a time to the item whose work
+// per workgroup is largest (ties to the lower index), never more than cap. A launch takes as long
+// as its busiest workgroup, so this is the split that finishes first (a proportional split
+// rounds an item of 1.4 workgroups' worth down to one and leaves that workgroup 40 % over).
+// blk receives the K + 1 offsets; the total exceeds G0 only when more items have work than G0.
 void apportion(const std::vector<double> &w, const std::vector<int64_t> &cap, int32_t G0,
                std::vector<int32_t> &blk) {
     const size_t K = w.size();
-    double tot = 0.0;
-    for (size_t m = 0; m < K; ++m)
-        if (cap[m] > 0) tot += w[m];
     std::vector<int64_t> n(K, 0);
-    std::vector<double> ideal(K, 0.0);
+    std::priority_queue<std::pair<double, int64_t>> q;  // (work per workgroup, -index)
     int64_t sum = 0;
     for (size_t m = 0; m < K; ++m) {
         if (cap[m] <= 0) continue;
-        ideal[m] = double(G0) * w[m] / (tot > 0 ? tot : 1.0);
-        n[m] = std::max<int64_t>(1, std::min<int64_t>(cap[m], int64_t(ideal[m])));
-        sum += n[m];
-    }
-    // what is left goes to the largest remainders, one at a time
-    while (sum < G0) {
-        int64_t best = -1;
-        double rem = -1e300;
-        for (size_t m = 0; m < K; ++m) {
-            if (cap[m] <= 0 || n[m] >= cap[m]) continue;
-            const double r = ideal[m] - double(n[m]);
-            if (r > rem) {
-                rem = r;
-                best = int64_t(m);
-            }
-        }
-        if (best < 0) break;
-        ++n[size_t(best)];
+        n[m] = 1;
         ++sum;
+        if (cap[m] > 1) q.emplace(w[m], -int64_t(m));
     }
-    // too many (the minimum of one per item): take from the most over-served
-    while (sum > G0) {
-        int64_t best = -1;
-        double over = -1e300;
-        for (size_t m = 0; m < K; ++m) {
-            if (n[m] <= 1) continue;
-            const double o = double(n[m]) - ideal[m];
-            if (o > over) {
-                over = o;
-                best = int64_t(m);
-            }
-        }
-        if (best < 0) break;
-        --n[size_t(best)];
-        --sum;
+    while (sum < G0 && !q.empty()) {
+        const size_t m = size_t(-q.top().second);
+        q.pop();
+        ++n[m];
+        ++sum;
+        if (n[m] < cap[m]) q.emplace(w[m] / double(n[m]), -int64_t(m));
     }
     blk.assign(K + 1, 0);
     for (size_t m = 0; m < K; ++m) blk[m + 1] = blk[m] + int32_t(n[m]);
@@ -196,9 +172,15 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok)
                        : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok)
                                          : batch_kernel_bf16(b, vpt, aug, fixed_ok);
-    // workgroups per matrix: the resident grid split in proportion to the cost
+    // workgroups per matrix: waves of the resident grid split so that the busiest workgroup
+    // has as little work as possible
+    static const int32_t waves = [] {
+        const char *e = std::getenv("SELLCS_BATCH_WAVES");
+        const int v = e ? std::atoi(e) : 2;
+        return int32_t(v >= 1 && v <= 8 ? v : 2);
+    }();
     const int32_t G0 =
-        resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
+        waves * resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
     std::vector<int32_t> sub_blk;
     const std::vector<int32_t> *pblk_h = nullptr;
     if (host_active) {
@@ -381,8 +363,8 @@ int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
         if ((e = hipHostMalloc(&B->h_slot[i], B->table_bytes, hipHostMallocDefault)) != hipSuccess) return fail(e);
         if ((e = hipEventCreateWithFlags(&B->ev[i], hipEventDisableTiming)) != hipSuccess) return fail(e);
     }
-    // vector-kernel workgroups for the batched solvers: 2 * kCgMaxGrid in total, split in
-    // proportion to the rows (at least one per non-empty system, a few rows per workgroup)
+    // vector-kernel workgroups for the batched solvers: 2 * kCgMaxGrid in total, split by the
+    // rows (at least one per non-empty system, a few rows per workgroup)
     {
         const int32_t Gv = 2 * kCgMaxGrid;
         std::vector<int32_t> vblk;

@@ -78,6 +78,7 @@ struct OwnedStream {
     ~OwnedStream() {
         if (owned) {
             (void)hipStreamSynchronize(s);
+            drop_workspace(s);
             (void)hipStreamDestroy(s);
         }
     }

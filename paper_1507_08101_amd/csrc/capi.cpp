@@ -112,6 +112,17 @@ int get_workspace(hipStream_t s, Workspace **ws) {
     return SELL_OK;
 }
 
+void drop_workspace(hipStream_t s) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find(std::make_pair(dev, s));
+    if (it == g_ws.end()) return;
+    (void)hipFree(it->second.partials);
+    (void)hipFree(it->second.scratch);
+    g_ws.erase(it);
+}
+
 }  // namespace sellcs
 
 namespace sellcs {

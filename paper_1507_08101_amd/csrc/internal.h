@@ -263,5 +263,7 @@ struct Workspace {
 };
 constexpr size_t kScratchBytes = size_t(kBlock) * 64;
 int get_workspace(hipStream_t s, Workspace **ws);
+// Frees the workspace of a stream that is about to be destroyed (after its work has finished).
+void drop_workspace(hipStream_t s);
 
 }  // namespace sellcs
