@@ -352,10 +352,12 @@ typedef struct {
 /* Times candidate formats of the CSR matrix (same arguments as sell_build) for products
  * with block width b (1..64) on the current device: C in {16, 32, 64} with sigma in
  * {1, 8 C, 256 C}, then columns per lane {1, 2, 4} and workgroups per CU {limit, 1, 2} for the
- * best pair. The trial product is the one a CG iteration issues (fused <x, y>; plain for a
- * rectangular matrix). Results are cached per process for the matrix's shape class (value
- * type, b, order of magnitude of the row count, mean row length, row-length histogram over
- * power-of-two bins). Synchronous; allocates and frees its own trial matrices and vectors. */
+ * best pair; a candidate replaces the best so far only when more than 3 % faster (the default,
+ * C = 32, sigma = 1, is timed first). The trial product is the one a CG iteration issues (fused
+ * <x, y>; plain for a rectangular matrix). Results are cached per process for the matrix's
+ * shape class (value type, b, order of magnitude of the row count, mean row length,
+ * row-length histogram over power-of-two bins). Synchronous; allocates and frees its own trial
+ * matrices and vectors. */
 int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
                   const double *val, sell_dtype vdt, int32_t b, uint32_t flags,
                   sell_tune_result *out, void *stream);

@@ -757,15 +757,21 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
     const int b = V->ncols;
     if (b > kMaxSliceCols) return SELL_ERR_UNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // timing events come from a per-thread, per-device pool that lives as long as the process,
+    // so a timed call creates none (creating a few hundred events costs about a millisecond of
+    // host time, during which the device would wait)
     std::vector<hipEvent_t> ev;
     if (step_ms) {
-        ev.resize(size_t(M) + 1, nullptr);
-        for (auto &e : ev)
-            if (hipEventCreate(&e) != hipSuccess) {
-                for (auto &f : ev)
-                    if (f) hipEventDestroy(f);
-                return SELL_ERR_HIP;
-            }
+        static thread_local std::map<int, std::vector<hipEvent_t>> pools;
+        int dev = 0;
+        HIPCHK(hipGetDevice(&dev));
+        std::vector<hipEvent_t> &pool = pools[dev];
+        while (pool.size() < size_t(M) + 1) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        ev.assign(pool.begin(), pool.begin() + (size_t(M) + 1));
     }
     // per-step tile partials of the dots, summed once after the recurrence
     const int32_t nt = A->ntiles;
@@ -818,7 +824,6 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
             if (e != hipSuccess) rc = hip_err(e);
             step_ms[m] = ms;
         }
-        for (auto &f : ev) hipEventDestroy(f);
     }
     if (last_in_w) *last_in_w = (x == W) ? 1 : 0;
     return rc;
