@@ -315,6 +315,24 @@ def grad_row(sc, torch, synth):
     return out
 
 
+def tsm_row(sc, torch, n=1 << 22, m=8, k=8):
+    """Tall-skinny block kernels on n x m / n x k FP64 blocks (the block-Krylov building blocks):
+    time with HIP events and the bytes each must move (n (m + k) 8; in place 2 n m 8)."""
+    V = torch.rand((n, m), dtype=torch.float64, device="cuda")
+    W = torch.rand((n, k), dtype=torch.float64, device="cuda")
+    X = torch.rand((m, k), dtype=torch.float64, device="cuda")
+    Xs = torch.rand((m, m), dtype=torch.float64, device="cuda")
+    out = {"n": n, "m": m, "k": k}
+    rows = [("tsmttsm", lambda: sc.sell_tsmttsm(V, W, X), n * (m + k) * 8),
+            ("tsmttsm_kahan", lambda: sc.sell_tsmttsm(V, W, X, kahan=True), n * (m + k) * 8),
+            ("tsmm", lambda: sc.sell_tsmm(V, X, W, beta=0.5), n * (m + 2 * k) * 8),
+            ("tsmm_inplace", lambda: sc.sell_tsmm_inplace(V, Xs, beta=0.5), 2 * n * m * 8)]
+    for name, fn, by in rows:
+        us, _ = time_launches(torch, fn, reps=10)
+        out[name] = {"us": round(us, 1), "GB/s": round(by / (us * 1e-6) / 1e9, 1)}
+    return out
+
+
 def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
     """The oracle's augmented product (one KPM step) on the host cores, bounded sample."""
     X = synth.block_vector(A.nrows, b, synth.SEED_X)
@@ -422,6 +440,7 @@ def main():
         extra["build_spmv_equivalents"] = round(build_s * 1e6 / extra["plain_spmv_b1_us"], 1)
         extra["build_device"] = device_build_row(sc, torch, A, args.C, args.sigma, extra["plain_spmv_b1_us"])
         extra["grad_chebyshev"] = grad_row(sc, torch, synth)
+        extra["tall_skinny"] = tsm_row(sc, torch)
         log(f"[bench] other rows: {json.dumps(extra)}")
     probes = None if args.no_probe else probe_bandwidth(sc, torch)
     if probes:

@@ -2,18 +2,17 @@
 //   tsmttsm:      X = alpha V^T W + beta X   (V: n x m, W: n x k, X: m x k small)
 //   tsmm:         W = alpha V X + beta W     (X: m x k small)
 //   tsmm_inplace: V = alpha V X + beta V     (X: m x m small)
-// m, k <= 64. They are streaming kernels (bandwidth-bound for small m, k): rows are staged
-// through LDS with coalesced loads, the small matrix X sits in LDS. The inner product
-// tsmttsm reduces deterministically (per-workgroup partials, then a fixed-order sum), with an
-// optional Neumaier-compensated summation (the paper adds a Kahan-summed variant of this
-// reduction for accuracy on long vectors).
+// m, k <= 64. They are streaming kernels (bandwidth-bound for small m, k). tsmttsm keeps 4 x 4
+// blocks of the result in registers per thread and reduces deterministically (per-workgroup
+// partials, then a fixed-order sum), with an optional Neumaier-compensated summation (the
+// paper adds a Kahan-summed variant of this reduction for accuracy on long vectors); tsmm and
+// tsmm_inplace keep the small matrix X in LDS.
 #include "devutil.h"
 #include "internal.h"
 
 namespace sellcs {
 
 constexpr int kTT = 256;     // threads per workgroup
-constexpr int kRowTile = 32; // rows staged per LDS tile in tsmttsm
 
 __device__ __forceinline__ void neumaier_add(double &s, double &comp, double term) {
     const double t = s + term;
@@ -24,45 +23,60 @@ __device__ __forceinline__ void neumaier_add(double &s, double &comp, double ter
     s = t;
 }
 
-// Partial sums of V^T W over this workgroup's row range; output entry q = l * k + j is
-// handled by threads q, q + 256, ...; partials[q * G + g].
+// Partial sums of V^T W over this workgroup's row range [g n / G, (g + 1) n / G). The m x k
+// result is cut into 4 x 4 blocks; thread t accumulates block t % nblk in registers over the
+// rows t / nblk, + groups, ... of the range (groups = 256 / nblk row groups), so every loaded
+// row piece feeds 16 multiply-adds. The row groups' blocks are then added in group order
+// through LDS; output q = l * k + j lands in partials[q * G + g]. KAHAN: Neumaier-compensated
+// sums in both stages.
+template <bool KAHAN>
 __global__ void __launch_bounds__(kTT) tsmttsm_partial_kernel(const double *__restrict__ V, int64_t ldv,
                                                               const double *__restrict__ W, int64_t ldw, int64_t n,
-                                                              int m, int k, int kahan, double *partials) {
-    __shared__ double sv[kRowTile][64];
-    __shared__ double sw[kRowTile][64];
+                                                              int m, int k, double *partials) {
+    __shared__ double red[kTT][17];
     const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
     const int64_t r0 = int64_t(g) * n / G, r1 = int64_t(g + 1) * n / G;
-    const int mk = m * k;
-    constexpr int QPT = (64 * 64 + kTT - 1) / kTT;  // outputs per thread at most
-    double s[QPT], comp[QPT];
+    const int nbk = (k + 3) / 4, nblk = ((m + 3) / 4) * nbk;  // at most 256 blocks
+    const int groups = kTT / nblk;
+    const int blk = tid % nblk, grp = tid / nblk;
+    const int l0 = (blk / nbk) * 4, j0 = (blk % nbk) * 4;
+    double acc[16], comp[16];
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) s[u] = comp[u] = 0.0;
-    for (int64_t t0 = r0; t0 < r1; t0 += kRowTile) {
-        const int rows = int(min<int64_t>(kRowTile, r1 - t0));
-        __syncthreads();
-        for (int e = tid; e < rows * m; e += kTT) sv[e / m][e % m] = V[(t0 + e / m) * ldv + e % m];
-        for (int e = tid; e < rows * k; e += kTT) sw[e / k][e % k] = W[(t0 + e / k) * ldw + e % k];
-        __syncthreads();
+    for (int e = 0; e < 16; ++e) acc[e] = comp[e] = 0.0;
+    if (grp < groups) {
+        for (int64_t i = r0 + grp; i < r1; i += groups) {
+            double v[4], w[4];
 #pragma unroll
-        for (int u = 0; u < QPT; ++u) {
-            const int q = tid + u * kTT;
-            if (q < mk) {
-                const int l = q / k, j = q - l * k;
-                for (int r = 0; r < rows; ++r) {
-                    const double term = sv[r][l] * sw[r][j];
-                    if (kahan)
-                        neumaier_add(s[u], comp[u], term);
-                    else
-                        s[u] += term;
-                }
+            for (int t = 0; t < 4; ++t) {
+                v[t] = l0 + t < m ? V[i * ldv + l0 + t] : 0.0;
+                w[t] = j0 + t < k ? W[i * ldw + j0 + t] : 0.0;
             }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if (KAHAN)
+                        neumaier_add(acc[a * 4 + c], comp[a * 4 + c], v[a] * w[c]);
+                    else
+                        acc[a * 4 + c] = fma(v[a], w[c], acc[a * 4 + c]);
+                }
         }
     }
 #pragma unroll
-    for (int u = 0; u < QPT; ++u) {
-        const int q = tid + u * kTT;
-        if (q < mk) partials[size_t(q) * G + g] = s[u] + comp[u];
+    for (int e = 0; e < 16; ++e) red[tid][e] = acc[e] + comp[e];
+    __syncthreads();
+    for (int o = tid; o < nblk * 16; o += kTT) {
+        const int b = o >> 4, e = o & 15;
+        const int l = (b / nbk) * 4 + (e >> 2), j = (b % nbk) * 4 + (e & 3);
+        if (l >= m || j >= k) continue;
+        double sum = 0.0, c2 = 0.0;
+        for (int gg = 0; gg < groups; ++gg) {
+            if (KAHAN)
+                neumaier_add(sum, c2, red[gg * nblk + b][e]);
+            else
+                sum += red[gg * nblk + b][e];
+        }
+        partials[size_t(l * k + j) * G + g] = sum + c2;
     }
 }
 
@@ -144,8 +158,12 @@ int launch_tsmttsm(const double *V, int64_t ldv, const double *W, int64_t ldw, i
     if (G > 1024) G = 1024;
     if (G > max_partials / mk) G = max_partials / mk;
     if (G < 1) G = 1;
-    hipLaunchKernelGGL(tsmttsm_partial_kernel, dim3(unsigned(G)), dim3(kTT), 0, s, V, ldv, W, ldw, n, m, k, kahan,
-                       partials);
+    if (kahan)
+        hipLaunchKernelGGL(tsmttsm_partial_kernel<true>, dim3(unsigned(G)), dim3(kTT), 0, s, V, ldv, W, ldw, n, m, k,
+                           partials);
+    else
+        hipLaunchKernelGGL(tsmttsm_partial_kernel<false>, dim3(unsigned(G)), dim3(kTT), 0, s, V, ldv, W, ldw, n, m,
+                           k, partials);
     if (hipGetLastError() != hipSuccess) return SELL_ERR_HIP;
     hipLaunchKernelGGL(tsmttsm_finish_kernel, dim3(mk), dim3(kTT), 0, s, partials, int(G), k, kahan, alpha, beta, X,
                        ldx);
