@@ -44,6 +44,7 @@ __global__ void __launch_bounds__(kTT) tsmttsm_partial_kernel(const double *__re
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] = comp[e] = 0.0;
     if (grp < groups) {
+#pragma unroll 2
         for (int64_t i = r0 + grp; i < r1; i += groups) {
             double v[4], w[4];
 #pragma unroll
@@ -101,31 +102,46 @@ __global__ void __launch_bounds__(kTT) tsmttsm_finish_kernel(const double *parti
     }
 }
 
-// W = alpha V X + beta W: one thread per output element; X staged in LDS.
+// W = alpha V X + beta W: a tile of R rows of V is staged in LDS with coalesced loads (consecutive
+// lanes read consecutive entries), then thread (r, j) of the tile forms output (r, j) from the
+// staged row and X, also staged in LDS. The LDS holds exactly m k + R m doubles (dynamic), so
+// small blocks do not limit the workgroups per compute unit.
+__host__ __device__ inline int tsmm_rows(int m, int k) {
+    const int r = kTT / k;
+    return r * m > 2048 ? 2048 / m : r;
+}
+
 __global__ void __launch_bounds__(kTT) tsmm_kernel(const double *__restrict__ V, int64_t ldv, const double *Xs,
                                                    int64_t ldx, int m, int k, int64_t n, double alpha, double beta,
                                                    double *W, int64_t ldw) {
-    __shared__ double sx[64 * 64];
+    extern __shared__ double lds[];
+    double *sx = lds, *sv = lds + m * k;
     for (int e = threadIdx.x; e < m * k; e += kTT) sx[e] = Xs[int64_t(e / k) * ldx + e % k];
-    __syncthreads();
-    const int64_t N = n * k;
-    for (int64_t e = int64_t(blockIdx.x) * kTT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kTT) {
-        const int64_t i = e / k;
-        const int j = int(e - i * k);
-        const double *v = V + i * ldv;
-        double s = 0.0;
-        for (int l = 0; l < m; ++l) s += v[l] * sx[l * k + j];
-        double *w = W + i * ldw + j;
-        const double r = alpha * s;
-        *w = beta != 0.0 ? r + beta * *w : r;
+    const int R = tsmm_rows(m, k);
+    const int r = threadIdx.x / k, j = threadIdx.x - r * k;
+    for (int64_t t0 = int64_t(blockIdx.x) * R; t0 < n; t0 += int64_t(gridDim.x) * R) {
+        const int rows = n - t0 < R ? int(n - t0) : R;
+        __syncthreads();
+        for (int e = threadIdx.x; e < rows * m; e += kTT) {
+            const int rr = e / m;
+            sv[e] = V[(t0 + rr) * ldv + (e - rr * m)];
+        }
+        __syncthreads();
+        if (r < rows) {
+            double s = 0.0;
+            for (int l = 0; l < m; ++l) s = fma(sv[r * m + l], sx[l * k + j], s);
+            double *w = W + (t0 + r) * ldw + j;
+            const double v = alpha * s;
+            *w = beta != 0.0 ? v + beta * *w : v;
+        }
     }
 }
 
 // V = alpha V X + beta V: rows staged in LDS before any of them is overwritten.
 __global__ void __launch_bounds__(kTT) tsmm_inplace_kernel(double *V, int64_t ldv, const double *Xs, int64_t ldx,
                                                            int m, int64_t n, double alpha, double beta) {
-    __shared__ double sx[64 * 64];
-    __shared__ double sv[kTT];
+    extern __shared__ double lds[];
+    double *sv = lds, *sx = lds + kTT;  // LDS: kTT + m m doubles (dynamic)
     for (int e = threadIdx.x; e < m * m; e += kTT) sx[e] = Xs[int64_t(e / m) * ldx + e % m];
     const int rows = kTT / m;  // rows per tile
     for (int64_t t0 = int64_t(blockIdx.x) * rows; t0 < n; t0 += int64_t(gridDim.x) * rows) {
@@ -173,8 +189,10 @@ int launch_tsmttsm(const double *V, int64_t ldv, const double *W, int64_t ldw, i
 int launch_tsmm(const double *V, int64_t ldv, const double *X, int64_t ldx, int m, int k, int64_t n, double alpha,
                 double beta, double *W, int64_t ldw, hipStream_t s) {
     if (n == 0) return SELL_OK;
-    hipLaunchKernelGGL(tsmm_kernel, dim3(tgrid(n * k, 8192)), dim3(kTT), 0, s, V, ldv, X, ldx, m, k, n, alpha, beta,
-                       W, ldw);
+    const int R = tsmm_rows(m, k);
+    const size_t lds = size_t(m * k + R * m) * sizeof(double);
+    hipLaunchKernelGGL(tsmm_kernel, dim3(tgrid((n + R - 1) / R * kTT, 8192)), dim3(kTT), lds, s, V, ldv, X, ldx, m,
+                       k, n, alpha, beta, W, ldw);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
@@ -182,8 +200,8 @@ int launch_tsmm_inplace(double *V, int64_t ldv, const double *X, int64_t ldx, in
                         double beta, hipStream_t s) {
     if (n == 0) return SELL_OK;
     const int rows = kTT / m;
-    hipLaunchKernelGGL(tsmm_inplace_kernel, dim3(tgrid((n + rows - 1) / rows * kTT, 8192)), dim3(kTT), 0, s, V, ldv,
-                       X, ldx, m, n, alpha, beta);
+    hipLaunchKernelGGL(tsmm_inplace_kernel, dim3(tgrid((n + rows - 1) / rows * kTT, 8192)), dim3(kTT),
+                       size_t(kTT + m * m) * sizeof(double), s, V, ldv, X, ldx, m, n, alpha, beta);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
 
