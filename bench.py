@@ -333,6 +333,86 @@ def tsm_row(sc, torch, n=1 << 22, m=8, k=8):
     return out
 
 
+def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
+    """The irregular matrix (lognormal row lengths, mean 15, half banded / half uniform
+    columns): plain products y = A X for every sorting window, value type and block width,
+    with algorithmic (true nonzeros) and SELL (stored entries, padding included) GB/s.
+    SELL-C-sigma is built on the device from a device CSR. At b = 8, FP64, the row-major
+    templated kernel is compared with column-major vectors and with rows whose leading
+    dimension b + 1 breaks the 16-byte alignment (both run the run-time-width kernel)."""
+    t0 = time.perf_counter()
+    A = synth.irregular(n)
+    out = {"matrix": "irregular, lognormal row lengths (mean 15, clip 1..2000), half +-5000 band, half uniform",
+           "n": A.nrows, "nnz": A.nnz, "C": C, "generate_s": round(time.perf_counter() - t0, 1)}
+    rp = torch.from_numpy(A.rowptr).cuda()
+    co = torch.from_numpy(A.col).cuda()
+    va = torch.from_numpy(A.val).cuda()
+    widths = (1, 4, 8, 16, 32)
+    res = {}
+    for dt, vb in (("f64", 8), ("f32", 4), ("bf16", 2)):
+        xs = 8 if dt == "f64" else 4
+        vt = torch.float64 if dt == "f64" else torch.float32
+        res[dt] = {}
+        for sg in (1, 32, 1024, A.nrows):
+            M = sc.SellMatrix.from_device_csr(A.nrows, A.ncols, rp, co, va, C=C, sigma=sg, dtype=dt)
+            info = M.info
+            row = {"stored_over_nnz": round(info["stored"] / A.nnz, 3)}
+            for b in widths:
+                X = torch.rand((A.ncols, b), dtype=vt, device="cuda")
+                Y = torch.empty((A.nrows, b), dtype=vt, device="cuda")
+                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, X, Y), reps=10)
+                bmin = model.bytes_min(A.nnz, A.nrows, A.ncols, b, vb, xs, nchunks=info["nchunks"],
+                                       has_perm=sg > 1)
+                bsell = model.bytes_sell(info["stored"], A.nrows, A.ncols, b, vb, xs, nchunks=info["nchunks"],
+                                         has_perm=sg > 1)
+                row[f"b{b}"] = {"us": round(us, 1), "GFLOP/s": round(model.flops(A.nnz, b) / (us * 1e-6) / 1e9, 1),
+                                "GB/s": round(bmin / (us * 1e-6) / 1e9, 1),
+                                "GB/s_sell": round(bsell / (us * 1e-6) / 1e9, 1)}
+                del X, Y
+            if dt == "f64" and sg == 1024:
+                b = 8
+                bmin = model.bytes_min(A.nnz, A.nrows, A.ncols, b, 8, 8, nchunks=info["nchunks"], has_perm=True)
+                lay = {"row_major_templated_us": row["b8"]["us"]}
+                Xc = torch.rand((b, A.ncols), dtype=torch.float64, device="cuda").T
+                Yc = torch.empty((b, A.nrows), dtype=torch.float64, device="cuda").T
+                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, Xc, Yc), reps=10)
+                lay["col_major_us"] = round(us, 1)
+                lay["col_major_GB/s"] = round(bmin / (us * 1e-6) / 1e9, 1)
+                del Xc, Yc
+                Xp = torch.rand((A.ncols, b + 1), dtype=torch.float64, device="cuda")[:, :b]
+                Yp = torch.empty((A.nrows, b + 1), dtype=torch.float64, device="cuda")[:, :b]
+                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, Xp, Yp), reps=10)
+                lay["row_major_ld9_runtime_width_us"] = round(us, 1)
+                lay["row_major_ld9_runtime_width_GB/s"] = round(bmin / (us * 1e-6) / 1e9, 1)
+                del Xp, Yp
+                out["layouts_f64_b8_sigma1024"] = lay
+            M.close()
+            res[dt]["sigma_n" if sg == A.nrows else f"sigma_{sg}"] = row
+            log(f"[bench] irregular {dt} sigma={sg}: {row}")
+    out["products"] = res
+    # achievable rate of scattered row gathers (the library's gather probe): as many uniform
+    # random rows as the matrix has uniform columns (half its nonzeros), and as many as nonzeros
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(synth.SEED_X)
+    idx = torch.randint(0, A.ncols, (A.nnz,), dtype=torch.int32, device="cuda", generator=gen)
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
+    probe = {}
+    for b in (1, 8):
+        x = torch.rand((A.ncols, b), dtype=torch.float64, device="cuda")
+        for name, cnt in (("half_nnz", A.nnz // 2), ("nnz", A.nnz)):
+            ix = idx[:cnt]
+            # five back-to-back launches per timed call (a single call's host overhead would count)
+            us, _ = time_launches(torch, lambda: [sc.sell_probe_gather(x, ix, sink) for _ in range(5)], reps=4)
+            us /= 5
+            probe[f"b{b}_{name}"] = {"gathers": cnt, "us": round(us, 1), "Ggathers/s": round(cnt / us / 1e3, 2)}
+        del x
+    out["gather_probe_f64"] = probe
+    log(f"[bench] gather probe: {probe}")
+    del rp, co, va, idx
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
     """The oracle's augmented product (one KPM step) on the host cores, bounded sample."""
     X = synth.block_vector(A.nrows, b, synth.SEED_X)
@@ -370,6 +450,7 @@ def main():
     ap.add_argument("--cg-edge", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Laplacian workload")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--no-irregular", action="store_true", help="skip the 4M-row irregular matrix sweep")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run one copy probe of this many MiB (calibrates HBM counters) and exit")
     args = ap.parse_args()
@@ -456,6 +537,9 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_row(sc, torch, synth, model, nmat=args.batch_count)
+    irregular = None
+    if not args.no_irregular:
+        irregular = irregular_row(sc, torch, synth, model)
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -498,6 +582,7 @@ def main():
         "cg_time_to_1e-10": cg,
         "other_rows_b8": extra,
         "batch_laplacians": batch,
+        "irregular_4M": irregular,
         "build_s": round(build_s, 3),
         "kernel_source_hash": src_hash,
     }

@@ -425,6 +425,19 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *B, sell_bv *X
  * by kinds 2 and 4 (may be NULL). Asynchronous. */
 int sell_probe_bandwidth(int kind, void *dst, const void *src, int64_t bytes, void *stream);
 
+/* Random-gather probe: for i < count, reads row idx[i] of x (nrows rows of row_bytes bytes,
+ * row_bytes in {8, 16, 32, 64}; x 8-byte aligned for 8, else 16-byte aligned), 8 gathers in
+ * flight per thread. It gives the achievable rate of the scattered row gathers that a product
+ * with scattered column indices performs (a row of X per nonzero; Sec. 5.2 notes that SpMMV
+ * gathers whole rows of a row-major block vector).
+ * idx: device int32[count] (may be NULL when count is 0); entries outside [0, nrows) read
+ * row 0. out: device memory of at least 8 bytes, 8-byte aligned (not normally written).
+ * Moves count * (row_bytes + 4) bytes of algorithmic data. Asynchronous.
+ * Errors: SELL_ERR_ARG for NULL x or out, NULL idx with count > 0, nrows < 1, count < 0,
+ * another row_bytes or a misaligned pointer. */
+int sell_probe_gather(const void *x, int64_t nrows, int32_t row_bytes, const int32_t *idx, int64_t count,
+                      void *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "sell_cg": ([_P, _P, _P, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_cg_mixed": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_probe_bandwidth": ([_I, _P, _P, _I64, _P], _I),
+    "sell_probe_gather": ([_P, _I64, _I32, _P, _I64, _P, _P], _I),
     "sell_grad_values": ([_P, _P, _P, _D, _I, _P, _P], _I),
     "sell_cheb_forward": ([_P, _P, _P, _I64, _D, _D, _I64, _P, _P], _I),
     "sell_cheb_backward": ([_P, _P, _I64, _D, _D, _I64, _P, _P, _P, _P], _I),
@@ -539,6 +540,19 @@ def sell_probe_bandwidth(kind, dst, src, nbytes, stream=None):
     _ok(lib().sell_probe_bandwidth(int(kind), ct.c_void_p(dst.data_ptr()),
                                    ct.c_void_p(src.data_ptr()) if src is not None else None, int(nbytes),
                                    _stream(stream)), "sell_probe_bandwidth")
+
+
+def sell_probe_gather(x, idx, out, stream=None):
+    """Random-gather probe: reads row idx[i] of x (a contiguous device tensor of rows of 8, 16,
+    32 or 64 bytes) for every i; idx is a device int32 tensor, out a device float64 tensor."""
+    import torch
+
+    if not (x.is_contiguous() and idx.is_contiguous() and idx.dtype == torch.int32):
+        raise SellError(-1, "sell_probe_gather: x and idx must be contiguous, idx int32")
+    row_bytes = x.element_size() * (x.shape[1] if x.dim() == 2 else 1)
+    _ok(lib().sell_probe_gather(ct.c_void_p(x.data_ptr()), int(x.shape[0]), int(row_bytes),
+                                ct.c_void_p(idx.data_ptr()), int(idx.numel()), ct.c_void_p(out.data_ptr()),
+                                _stream(stream)), "sell_probe_gather")
 
 
 # ==================================================================== value gradients
