@@ -501,7 +501,18 @@ def main():
         b1 = model.bytes_min(A.nnz, A.nrows, A.ncols, b, 8, 8, read_y=True, nchunks=info["nchunks"])
         bytes_launch = (b0 + (args.M - 1) * b1) / args.M
         launch_avg_ms = float(np.mean(launch_ms))
+        dos = None
+        if b == args.b:
+            # density of states from the block moments (Jackson damping) on 2001 energies
+            Ed = torch.linspace(-s, s, 2001, dtype=torch.float64, device="cuda")
+            us_dos, _ = time_launches(torch, lambda: sc.sell_kpm_dos(mu, b, Ed, s, 0.0), reps=5)
+            rho = sc.sell_kpm_dos(mu, b, Ed, s, 0.0).cpu().numpy()
+            Eh = Ed.cpu().numpy()
+            dos = {"energies": int(Ed.numel()), "moments": 2 * args.M + 1, "kernel": "jackson", "us": round(us_dos, 1),
+                   "integral": round(float(np.sum(0.5 * (rho[1:] + rho[:-1]) * np.diff(Eh))), 4),
+                   "rho_at_0": round(float(rho[1000]), 5)}
         results[b] = dict(
+            dos=dos,
             ms_per_step=float(np.mean(step_ms)),
             gflops=flops_step / (float(np.mean(step_ms)) * 1e-3) / 1e9,
             gflops_pmax=flops_step / (float(np.min(step_ms)) * 1e-3) / 1e9,
@@ -567,6 +578,7 @@ def main():
                                f"Anderson {args.L}^3 (n={A.nrows}, nnz={A.nnz}), SELL-{args.C}-{args.sigma}",
                    "n": A.nrows, "nnz": A.nnz, "b": args.b, "C": args.C, "sigma": args.sigma,
                    "kpm_steps": args.M},
+        "kpm_dos": head.get("dos"),
         "roofline": {"bound": "hbm", "achieved": round(head["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(frac, 4), "traffic": traffic,
                      "kernel": f"prod_kernel (FP64 values and vectors, b={args.b}, augmented, fused dots)",
@@ -576,7 +588,7 @@ def main():
         "hbm_gbs": round(head["hbm_gbs"], 1),
         "pmax_gflops": round(head["gflops_pmax"], 2),
         "b1": None if 1 not in results or args.b == 1 else {k: (round(v, 3) if isinstance(v, float) else v)
-                                                            for k, v in results[1].items()},
+                                                            for k, v in results[1].items() if k != "dos"},
         "achievable_gbs": probes,
         "frac_of_achievable": None if not probes else round(head["hbm_gbs"] / max(probes["copy"], probes["copy_nt"]), 4),
         "cg_time_to_1e-10": cg,

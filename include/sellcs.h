@@ -249,6 +249,24 @@ int sell_spmmv_T(const sell_mat *A, const sell_bv *X, sell_bv *Y, int determinis
 int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double s, double c,
              double *mu, int *last_in_w, float *step_ms, void *stream);
 
+/* Density of states from block KPM moments (the kernel polynomial method that the fused
+ * block product serves, Sec. 5.3; the reconstruction is the standard one): the b columns'
+ * moments are summed and normalised, mu~_m = sum_j mu[m * b + j] / sum_j mu[j] (a stochastic
+ * trace estimate when the columns are random vectors), damped with kernel (SELL_KPM_JACKSON:
+ * g_m = ((N - m + 1) cos(pi m / (N + 1)) + sin(pi m / (N + 1)) cot(pi / (N + 1))) / (N + 1)
+ * with N = nmom; SELL_KPM_NONE: g_m = 1), and summed as a Chebyshev series:
+ *   rho[k] = (g_0 mu~_0 + 2 sum_{m=1}^{nmom-1} g_m mu~_m T_m(x)) / (pi sqrt(1 - x^2) s),
+ *   x = (E[k] - c) / s,  rho[k] = 0 where |x| >= 1,
+ * the density per unit energy of A when A~ = (A - c I) / s (the scaling of sell_kpm).
+ * mu: DEVICE, nmom * b doubles in sell_kpm's layout (nmom = 2M + 1 there). E, rho: DEVICE,
+ * K doubles each (may be NULL when K = 0). sum_j mu[j] must be nonzero (else rho is not
+ * finite). Deterministic (fixed summation order). Asynchronous.
+ * Errors: SELL_ERR_ARG for nmom < 1, b < 1, K < 0, another kernel, s not positive or not
+ * finite, c not finite, or a NULL pointer that is needed. */
+enum { SELL_KPM_NONE = 0, SELL_KPM_JACKSON = 1 };
+int sell_kpm_dos(const double *mu, int64_t nmom, int32_t b, int32_t kernel, double s, double c,
+                 const double *E, int64_t K, double *rho, void *stream);
+
 typedef struct {
     int64_t iterations;       /* total inner (low-precision) or plain CG iterations  */
     int64_t refinements;      /* outer FP64 residual corrections (0 for plain CG)     */

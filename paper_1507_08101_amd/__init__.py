@@ -94,6 +94,7 @@ _SIGNATURES = {
     "sell_cg_mixed": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_probe_bandwidth": ([_I, _P, _P, _I64, _P], _I),
     "sell_probe_gather": ([_P, _I64, _I32, _P, _I64, _P, _P], _I),
+    "sell_kpm_dos": ([_P, _I64, _I32, _I32, _D, _D, _P, _I64, _P, _P], _I),
     "sell_grad_values": ([_P, _P, _P, _D, _I, _P, _P], _I),
     "sell_cheb_forward": ([_P, _P, _P, _I64, _D, _D, _I64, _P, _P], _I),
     "sell_cheb_backward": ([_P, _P, _I64, _D, _D, _I64, _P, _P, _P, _P], _I),
@@ -442,6 +443,28 @@ def sell_kpm(A, V, W, M, s, c, mu, step_ms=None, stream=None):
     _ok(lib().sell_kpm(_mat(A), v.handle, w.handle, int(M), float(s), float(c), ct.c_void_p(mu.data_ptr()),
                        ct.byref(last), _np_ptr(step_ms), _stream(stream)), "sell_kpm")
     return bool(last.value)
+
+
+SELL_KPM_NONE, SELL_KPM_JACKSON = 0, 1
+
+
+def sell_kpm_dos(mu, b, E, s, c=0.0, kernel="jackson", rho=None, stream=None):
+    """Density of states at the energies E (float64 device tensor) from block KPM moments mu
+    (float64 device tensor of nmom * b entries in sell_kpm's layout); returns rho (a new
+    tensor unless given)."""
+    import torch
+
+    if mu.dtype != torch.float64 or E.dtype != torch.float64 or not (mu.is_contiguous() and E.is_contiguous()):
+        raise SellError(-1, "sell_kpm_dos: mu and E must be contiguous float64")
+    if mu.numel() % b:
+        raise SellError(-1, "sell_kpm_dos: mu does not hold whole rows of b moments")
+    if rho is None:
+        rho = torch.empty_like(E)
+    kern = {"jackson": SELL_KPM_JACKSON, "none": SELL_KPM_NONE}[kernel]
+    _ok(lib().sell_kpm_dos(ct.c_void_p(mu.data_ptr()), int(mu.numel() // b), int(b), kern, float(s), float(c),
+                           ct.c_void_p(E.data_ptr()) if E.numel() else None, int(E.numel()),
+                           ct.c_void_p(rho.data_ptr()) if rho.numel() else None, _stream(stream)), "sell_kpm_dos")
+    return rho
 
 
 def sell_cg(A, B, X, tol=1e-10, maxit=100000, stream=None):

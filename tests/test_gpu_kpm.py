@@ -131,3 +131,68 @@ def test_full_size_anderson_128_sampled_rows(sc, b):
             ref = math.fsum((u[:, j] * v[:, j]).tolist())
             assert abs(d[g * b + j] - ref) <= 1e-12 * float(np.sum(np.abs(u[:, j] * v[:, j]))), (j, g)
     Mx.close()
+
+
+def _dos_tol(mu_h, b, E, s, c, kernel):
+    # forward error of the three-term recurrence for T_m grows at worst like m^2 eps; bound
+    # each energy's error by 4 eps nmom^2 times the sum of the absolute series terms
+    mu2 = mu_h.reshape(-1, b).sum(axis=1)
+    mt = mu2 / mu2[0]
+    N = mt.shape[0]
+    g = oracle.jackson(N) if kernel == "jackson" else np.ones(N)
+    terms = np.abs(g * mt) * np.where(np.arange(N) == 0, 1.0, 2.0)
+    x = (E - c) / s
+    w = np.where(np.abs(x) < 1, np.pi * np.sqrt(np.maximum(1 - x * x, 1e-300)) * s, np.inf)
+    return 4 * np.finfo(float).eps * N * N * terms.sum() / w
+
+
+@pytest.mark.parametrize("b", [1, 8])
+@pytest.mark.parametrize("kernel", ["jackson", "none"])
+def test_kpm_dos_matches_oracle(sc, b, kernel):
+    import torch
+
+    A = synth.anderson3d(12)
+    M = 60
+    s, c = _scale(), 0.25
+    Vd = dev(synth.block_vector(A.nrows, b, synth.SEED_X))
+    Wd = torch.zeros_like(Vd)
+    mu = torch.zeros((2 * M + 1) * b, dtype=torch.float64, device="cuda:0")
+    Mx = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    sc.sell_kpm(Mx, Vd, Wd, M, s, c, mu)
+    E = np.concatenate([np.linspace(c - 1.1 * s, c + 1.1 * s, 333), [c - s, c + s, c]])
+    rho = host(sc.sell_kpm_dos(mu, b, dev(E), s, c, kernel=kernel))
+    mu_h = host(mu)
+    ref = oracle.kpm_dos(mu_h, b, E, s, c, kernel=kernel)
+    tol = _dos_tol(mu_h, b, E, s, c, kernel)
+    assert np.all(np.abs(rho - ref) <= tol), np.max(np.abs(rho - ref) / np.where(tol > 0, tol, 1))
+    assert np.all(rho[np.abs((E - c) / s) >= 1] == 0.0)
+    Mx.close()
+
+
+def test_kpm_dos_many_moments_and_edges(sc):
+    # more moments than one LDS chunk holds (2048), two columns, synthetic moments
+    import torch
+
+    rng = np.random.default_rng(91)
+    d = rng.uniform(-0.97, 0.97, 400)
+    nmom, b = 5000, 2
+    mom = np.cos(np.outer(np.arange(nmom), np.arccos(d))).mean(axis=1)
+    mu_h = np.stack([0.7 * mom, 1.9 * mom], axis=1).ravel()
+    E = np.linspace(-1.2, 1.2, 1001)
+    rho = host(sc.sell_kpm_dos(dev(mu_h), b, dev(E), 1.0))
+    ref = oracle.kpm_dos(mu_h, b, E, 1.0)
+    assert np.all(np.abs(rho - ref) <= _dos_tol(mu_h, b, E, 1.0, 0.0, "jackson"))
+    # one moment: the bare weight 1 / (pi sqrt(1 - x^2) s)
+    one = host(sc.sell_kpm_dos(dev(np.array([3.0, 5.0])), 2, dev(E), 2.0))
+    x = E / 2.0
+    assert np.allclose(one, 1.0 / (np.pi * np.sqrt(1 - x * x) * 2.0), rtol=1e-14, atol=0)
+    # no energies: nothing to do
+    empty = torch.zeros(0, dtype=torch.float64, device="cuda:0")
+    assert sc.sell_kpm_dos(dev(mu_h), b, empty, 1.0).numel() == 0
+    for bad in (dict(s=0.0), dict(s=-1.0), dict(s=float("inf")), dict(c=float("nan"))):
+        kw = dict(s=1.0, c=0.0)
+        kw.update(bad)
+        with pytest.raises(sc.SellError):
+            sc.sell_kpm_dos(dev(mu_h), b, dev(E), kw["s"], kw["c"])
+    with pytest.raises(sc.SellError):
+        sc.sell_kpm_dos(dev(mu_h[:-1]), b, dev(E), 1.0)  # not whole rows of b moments
