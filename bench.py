@@ -189,6 +189,53 @@ def batch_row(sc, torch, synth, model, nmat=64, b=8, tol=1e-10):
     us1, _ = time_launches(torch, one_by_one, reps=5)
     out["per_matrix_launches_f64_us"] = round(us1, 1)
     log(f"[bench] batch product: {out['batched_product_f64']}, one by one {us1:.0f} us")
+    # block widths 1..32 mixed over the matrices in one launch (operands packed per matrix at its
+    # own width), against one launch per matrix and one batch per width
+    wlist = [(1, 2, 4, 8, 16, 32)[k % 6] for k in range(nmat)]
+    B64.set_widths(wlist)
+    nx, ny, nd = B64.packed_sizes()
+    Xp = torch.rand(nx, dtype=torch.float64, device="cuda") * 2 - 1
+    Yp = torch.empty(ny, dtype=torch.float64, device="cuda")
+    dp = torch.zeros(nd, dtype=torch.float64, device="cuda")
+    usw, _ = time_launches(torch, lambda: sc.sell_batch_spmmv_aug_packed(B64, Xp, Yp, flags=sc.DOT_XY, dot=dp),
+                           reps=10)
+    B64.set_widths(None)
+    xo = np.cumsum([0] + [A.ncols * wlist[k] for k, A in enumerate(mats)])
+    yo = np.cumsum([0] + [A.nrows * wlist[k] for k, A in enumerate(mats)])
+    views = [(Xp[xo[k]:xo[k + 1]].view(A.ncols, wlist[k]), Yp[yo[k]:yo[k + 1]].view(A.nrows, wlist[k]))
+             for k, A in enumerate(mats)]
+    dw1 = torch.zeros(3 * max(wlist), dtype=torch.float64, device="cuda")
+
+    def one_by_one_w():
+        for k, Mk in enumerate(M["f64"]):
+            sc.sell_spmmv_aug(Mk, views[k][0], views[k][1], flags=sc.DOT_XY, dot=dw1)
+
+    usw1, _ = time_launches(torch, one_by_one_w, reps=5)
+    classes = []
+    for w in sorted(set(wlist)):
+        ks = [k for k in range(nmat) if wlist[k] == w]
+        Bw = sc.SellBatch([M["f64"][k] for k in ks])
+        Xc = torch.cat([views[k][0] for k in ks]).contiguous()
+        classes.append((Bw, Xc, torch.empty((Bw.rows, w), dtype=torch.float64, device="cuda"),
+                        torch.zeros(3 * w * len(ks), dtype=torch.float64, device="cuda")))
+
+    def per_class():
+        for Bw, Xc, Yc, dc in classes:
+            sc.sell_batch_spmmv_aug(Bw, Xc, Yc, flags=sc.DOT_XY, dot=dc)
+
+    usc, _ = time_launches(torch, per_class, reps=10)
+    for Bw, _, _, _ in classes:
+        Bw.close()
+    del classes, views, Xp, Yp
+    wbytes = sum(model.bytes_min(A.nnz, A.nrows, A.ncols, wlist[k], 8, 8, nchunks=M["f64"][k].info["nchunks"])
+                 for k, A in enumerate(mats))
+    wflops = sum(2.0 * A.nnz * wlist[k] for k, A in enumerate(mats))
+    out["mixed_widths_f64"] = {"widths": "1,2,4,8,16,32 in turn, packed operands", "us": round(usw, 1),
+                               "GB/s": round(wbytes / (usw * 1e-6) / 1e9, 1),
+                               "GFLOP/s": round(wflops / (usw * 1e-6) / 1e9, 1),
+                               "per_matrix_launches_us": round(usw1, 1),
+                               "one_batch_per_width_us": round(usc, 1)}
+    log(f"[bench] mixed widths: {out['mixed_widths_f64']}")
     Bd = torch.from_numpy(np.concatenate([synth.block_vector(A.nrows, b, synth.SEED_Y + 1000 * k)
                                           for k, A in enumerate(mats)])).cuda()
 

@@ -407,10 +407,41 @@ int sell_batch_info(const sell_batch *B, int32_t *count, int64_t *rows, int64_t 
  * sell_spmmv_aug, applied to every matrix) in one launch. X: total-columns x b, Y and Z:
  * total-rows x b, the batch's vector type, 1 <= b <= 64. opts->dot receives 3 b doubles per
  * matrix: matrix m's group q (yy = 0, xy = 1, xx = 2), column j at dot[(3 m + q) b + j].
+ * SELL_ERR_UNSUPPORTED while block widths other than b are set (sell_batch_set_widths).
  * Calls on one batch must be ordered (one stream, or synchronised): the launch tables are
  * reused. Asynchronous. */
 int sell_batch_spmmv_aug(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z,
                          const sell_spmv_opts *opts, void *stream);
+
+/* Block widths of the batch's matrices, for batches whose systems have different numbers of
+ * vectors (block widths 1..64 in one launch): widths is a HOST array of count entries, each in
+ * [1, 64], or NULL to clear them. The widths define the packed operand layout of
+ * sell_batch_spmmv_aug_packed. While widths other than b are set, sell_batch_spmmv_aug with
+ * operands of width b returns SELL_ERR_UNSUPPORTED, and so does sell_batch_cg (both need one
+ * width for all). Synchronous (waits for the device). Errors: SELL_ERR_ARG (NULL batch, width
+ * out of range), SELL_ERR_STATE (another device is current). */
+int sell_batch_set_widths(sell_batch *B, const int32_t *widths);
+
+/* Sizes of the packed operands for the widths set (0 when none are set), each may be NULL:
+ * elements of X (sum of ncols_m w_m), of Y and Z (sum of nrows_m w_m), and doubles of the dots
+ * (3 sum of w_m). */
+int sell_batch_packed_sizes(const sell_batch *B, int64_t *x_elems, int64_t *y_elems, int64_t *dots);
+
+/* The product of sell_batch_spmmv_aug over packed operands of per-matrix widths, in one launch:
+ * matrix m's X_m (ncols_m x w_m, row-major, leading dimension w_m) starts at element
+ * sum_{k<m} ncols_k w_k of X, and its Y_m and Z_m (nrows_m x w_m) at element
+ * sum_{k<m} nrows_k w_k of Y and Z. X, Y, Z: DEVICE, the batch's vector type (F64 for F64
+ * values, else F32), aligned to the element size. opts as for sell_spmmv_aug, applied to every
+ * matrix (gamma_v: at least max w_m entries, matrix m uses the first w_m); opts->dot receives
+ * matrix m's dots packed at dot + 3 sum_{k<m} w_k, as [yy (w_m) | xy (w_m) | xx (w_m)].
+ * Every workgroup runs the kernel body compiled for its matrix's width (run-time width for
+ * widths outside 1, 2, 4, 8, 16, 32 or rows not aligned for 16-byte accesses); the workgroups
+ * are split by each matrix's bytes at its own width. Asynchronous; calls on one batch must be
+ * ordered. Errors: SELL_ERR_STATE (no widths set, or another device is current),
+ * SELL_ERR_ARG (NULL or misaligned operand that is needed, X == Y, bad flags or missing
+ * gamma_v / dot), SELL_ERR_SHAPE (shifts or x-dots with a non-square matrix). */
+int sell_batch_spmmv_aug_packed(sell_batch *B, const void *X, void *Y, void *Z, const sell_spmv_opts *opts,
+                                void *stream);
 
 #define SELL_BATCH_GRAPH 0x1u /* capture the iterations in a HIP graph and replay it */
 

@@ -107,6 +107,9 @@ _SIGNATURES = {
     "sell_batch_destroy": ([_P], _I),
     "sell_batch_info": ([_P, ct.POINTER(_I32), ct.POINTER(_I64), ct.POINTER(_I64)], _I),
     "sell_batch_spmmv_aug": ([_P, _P, _P, _P, ct.POINTER(sell_spmv_opts), _P], _I),
+    "sell_batch_set_widths": ([_P, _P], _I),
+    "sell_batch_packed_sizes": ([_P, ct.POINTER(_I64), ct.POINTER(_I64), ct.POINTER(_I64)], _I),
+    "sell_batch_spmmv_aug_packed": ([_P, _P, _P, _P, ct.POINTER(sell_spmv_opts), _P], _I),
     "sell_batch_cg": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.c_uint32, ct.POINTER(sell_cg_stats), _P], _I),
 }
 
@@ -523,6 +526,26 @@ class SellBatch:
         _ok(lib().sell_batch_info(h, ct.byref(cnt), ct.byref(rows), ct.byref(cols)), "sell_batch_info")
         self.count, self.rows, self.cols = cnt.value, rows.value, cols.value
 
+    def set_widths(self, widths=None):
+        """Block width of each matrix, for the packed operands of sell_batch_spmmv_aug_packed
+        (None clears them)."""
+        if widths is None:
+            _ok(lib().sell_batch_set_widths(self.handle, None), "sell_batch_set_widths")
+            self.widths = None
+            return
+        w = np.ascontiguousarray(widths, dtype=np.int32)
+        if w.shape != (self.count,):
+            raise SellError(-1, "sell_batch_set_widths: one width per matrix")
+        _ok(lib().sell_batch_set_widths(self.handle, w.ctypes.data_as(ct.c_void_p)), "sell_batch_set_widths")
+        self.widths = w.copy()
+
+    def packed_sizes(self):
+        """(elements of packed X, elements of packed Y / Z, doubles of packed dots)."""
+        x, y, d = _I64(), _I64(), _I64()
+        _ok(lib().sell_batch_packed_sizes(self.handle, ct.byref(x), ct.byref(y), ct.byref(d)),
+            "sell_batch_packed_sizes")
+        return x.value, y.value, d.value
+
     def close(self):
         if self.handle:
             lib().sell_batch_destroy(self.handle)
@@ -544,6 +567,28 @@ def sell_batch_spmmv_aug(Bt, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0
     o, keep = make_opts(flags, alpha, beta, gamma, gamma_v, delta, eta, dot)
     _ok(lib().sell_batch_spmmv_aug(Bt.handle, x.handle, y.handle, z.handle if z else None, ct.byref(o),
                                    _stream(stream)), "sell_batch_spmmv_aug")
+    del keep
+
+
+def sell_batch_spmmv_aug_packed(Bt, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0.0, gamma_v=None, delta=0.0,
+                                eta=1.0, dot=None, stream=None):
+    """The batched product over packed operands of per-matrix widths (set with
+    ``SellBatch.set_widths``): X, Y, Z are contiguous device tensors holding the matrices'
+    blocks one after another, each at its own width; ``dot`` receives the packed dots."""
+    import torch
+
+    nx, ny, _ = Bt.packed_sizes()
+    want = torch.float64 if Bt.mats[0].info["vdtype"] == SELL_F64 else torch.float32
+    for t, need in ((X, nx), (Y, ny), (Z, ny)):
+        if t is not None and (not t.is_contiguous() or t.numel() != need):
+            raise SellError(-2, "sell_batch_spmmv_aug_packed: operand is not the packed size")
+        if t is not None and t.dtype != want:
+            raise SellError(-3, "sell_batch_spmmv_aug_packed: operand is not the batch's vector type")
+    o, keep = make_opts(flags, alpha, beta, gamma, gamma_v, delta, eta, dot)
+    _ok(lib().sell_batch_spmmv_aug_packed(Bt.handle, ct.c_void_p(X.data_ptr()) if X.numel() else None,
+                                          ct.c_void_p(Y.data_ptr()) if Y.numel() else None,
+                                          ct.c_void_p(Z.data_ptr()) if Z is not None and Z.numel() else None,
+                                          ct.byref(o), _stream(stream)), "sell_batch_spmmv_aug_packed")
     del keep
 
 

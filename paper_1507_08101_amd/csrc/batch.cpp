@@ -26,6 +26,9 @@ namespace sellcs {
 const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok);
 const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok);
 const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok);
+const void *batch_mixed_kernel_f64(bool aug);
+const void *batch_mixed_kernel_f32(bool aug);
+const void *batch_mixed_kernel_bf16(bool aug);
 }  // namespace sellcs
 
 namespace {
@@ -71,6 +74,16 @@ struct sell_batch {
     int32_t vgrid = 0;
     int32_t vpt_hint = 0, bpc_hint = 0;  // launch parameters shared by all matrices (else 0)
     std::map<int32_t, std::vector<int32_t>> blk_cache;  // workgroup offsets per resident grid size
+    // block widths of the matrices for packed operands (empty: not set)
+    std::vector<int32_t> widths;
+    std::vector<int64_t> xoff, yoff;                       // element offsets of the packed blocks
+    int64_t x_elems = 0, y_elems = 0, sum_w = 0;
+    int32_t wmax = 0;
+    int32_t *d_widths = nullptr;
+    int64_t *d_dotoff = nullptr;                           // sum of the earlier widths, per matrix
+    std::vector<int32_t> porder;                           // launch-table position -> matrix, by width
+    std::vector<double> cost_w;                            // per matrix, at its own width
+    std::map<int32_t, std::vector<int32_t>> blk_cache_w;   // offsets for the widths' costs
 };
 
 namespace sellcs {
@@ -85,6 +98,15 @@ void batch_free(sell_batch *B) {
     if (B->partials) (void)hipFree(B->partials);
     if (B->d_row_off) (void)hipFree(B->d_row_off);
     if (B->d_vblk) (void)hipFree(B->d_vblk);
+    if (B->d_widths) (void)hipFree(B->d_widths);
+    if (B->d_dotoff) (void)hipFree(B->d_dotoff);
+}
+
+// True when the matrices have widths of their own that differ from the operands' width b.
+bool batch_ragged(const sell_batch *B, int b) {
+    for (int32_t w : B->widths)
+        if (w != b) return true;
+    return false;
 }
 
 const sell_mat *batch_matrix(const sell_batch *B, int m) { return B->mats[size_t(m)]; }
@@ -133,12 +155,95 @@ void apportion(const std::vector<double> &w, const std::vector<int64_t> &cap, in
 
 // Workgroups of the product launches per matrix: weights = cost, cap = fine tiles; matrices
 // with host_active[m] == 0 get none (host_active may be null: all matrices).
-void apportion_products(const sell_batch *B, int32_t G0, const int32_t *host_active, std::vector<int32_t> &blk) {
+void apportion_products(const sell_batch *B, int32_t G0, const int32_t *host_active, std::vector<int32_t> &blk,
+                        bool ragged = false) {
     std::vector<int64_t> cap(static_cast<size_t>(B->K));
     for (int m = 0; m < B->K; ++m)
         cap[size_t(m)] = (host_active && !host_active[m]) ? 0 : B->mats[size_t(m)]->ntiles;
-    apportion(B->cost, cap, G0, blk);
+    apportion(ragged ? B->cost_w : B->cost, cap, G0, blk);
 }
+
+namespace {
+
+// Workgroups of a product launch with kernel kern: waves of the resident grid, 2 by default for
+// one width and 16 for mixed widths (whose workgroups differ more in speed, so a finer split
+// balances better: 2.85 ms against 4.06 ms with 2 waves for 64 Laplacians of widths 1..32).
+int32_t product_grid(const sell_batch *B, const void *kern, bool mixed = false) {
+    static const int32_t waves = [] {
+        const char *e = std::getenv("SELLCS_BATCH_WAVES");
+        const int v = e ? std::atoi(e) : 2;
+        return int32_t(v >= 1 && v <= 8 ? v : 2);
+    }();
+    static const int32_t mixed_waves = [] {
+        const char *e = std::getenv("SELLCS_PACKED_WAVES");
+        const int v = e ? std::atoi(e) : 16;
+        return int32_t(v >= 1 && v <= 32 ? v : 16);
+    }();
+    return (mixed ? mixed_waves : waves) *
+           resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
+}
+
+// Room for 3 * kMaxSliceCols partials per workgroup of any split of this grid, so that later
+// calls (possibly captured in a graph) never move the buffer.
+int ensure_partials(sell_batch *B, int32_t G, int32_t G0) {
+    const size_t need = size_t(3) * kMaxSliceCols * size_t(std::max<int64_t>(std::max(G, G0), B->K));
+    if (need <= B->partials_cap) return SELL_OK;
+    // grows outside any steady state (the first call of a shape)
+    if (B->partials) HIPCHK(hipFree(B->partials));
+    B->partials = nullptr;
+    B->partials_cap = 0;
+    HIPCHK(hipMalloc(&B->partials, need * sizeof(double)));
+    B->partials_cap = need;
+    return SELL_OK;
+}
+
+// Appends the workgroup offsets to the staged table (K ProdArgs already in B->stage) and finds
+// the table on the device, else uploads it (into the reserved slot, or the next ring slot).
+int place_table(sell_batch *B, const std::vector<int32_t> &blk, bool reserved, hipStream_t s,
+                const ProdArgs **d_tab, const int32_t **d_blk) {
+    const int K = B->K;
+    std::memcpy(B->stage.data() + sizeof(ProdArgs) * size_t(K), blk.data(), sizeof(int32_t) * (size_t(K) + 1));
+    int slot = -1;
+    if (reserved) {
+        if (B->valid[kRing] && std::memcmp(B->h_slot[kRing], B->stage.data(), B->table_bytes) == 0) slot = kRing;
+    } else {
+        for (int i = 0; i < kRing && slot < 0; ++i)
+            if (B->valid[i] && std::memcmp(B->h_slot[i], B->stage.data(), B->table_bytes) == 0) slot = i;
+    }
+    if (slot < 0) {
+        if (reserved) {
+            slot = kRing;
+        } else {
+            slot = B->next;
+            B->next = (B->next + 1) % kRing;
+        }
+        if (B->valid[slot]) HIPCHK(hipEventSynchronize(B->ev[slot]));  // its last upload has been read
+        B->valid[slot] = false;
+        std::memcpy(B->h_slot[slot], B->stage.data(), B->table_bytes);
+        HIPCHK(hipMemcpyAsync(B->d_slot[slot], B->h_slot[slot], B->table_bytes, hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventRecord(B->ev[slot], s));
+        B->valid[slot] = true;
+    }
+    *d_tab = static_cast<const ProdArgs *>(B->d_slot[slot]);
+    *d_blk = reinterpret_cast<const int32_t *>(static_cast<const char *>(B->d_slot[slot]) + sizeof(ProdArgs) * size_t(K));
+    return SELL_OK;
+}
+
+// The epilogue fields of a launch-table entry (nb columns of the shifts).
+void set_epilogue(ProdArgs &a, const sell_spmv_opts &o) {
+    a.flags = o.flags;
+    a.alpha = o.alpha;
+    a.beta = o.beta;
+    a.delta = o.delta;
+    a.eta = o.eta;
+    a.gamma_s = o.gamma;
+    if (o.flags & SELL_SPMV_VSHIFT) {
+        a.has_gamma_v = 1;
+        for (int j = 0; j < a.nb; ++j) a.gamma_v[j] = o.gamma_v[j];
+    }
+}
+
+}  // namespace
 
 // The batched product (no argument checks): y_m = alpha (A_m x_m - gamma x_m) + beta y_m with
 // dots and chain for every matrix m, skipping matrices with active[m] == 0 (device flags read
@@ -155,6 +260,7 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
                    const int32_t **out_blk, const double **out_partials, bool reserved) {
     const int b = X->ncols;
     const int K = B->K;
+    if (batch_ragged(B, b)) return SELL_ERR_UNSUPPORTED;  // mixed widths take packed operands
     Workspace *ws = nullptr;
     int rc = get_workspace(s, &ws);
     if (rc) return rc;
@@ -174,13 +280,7 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
                                          : batch_kernel_bf16(b, vpt, aug, fixed_ok);
     // workgroups per matrix: waves of the resident grid split so that the busiest workgroup
     // has as little work as possible
-    static const int32_t waves = [] {
-        const char *e = std::getenv("SELLCS_BATCH_WAVES");
-        const int v = e ? std::atoi(e) : 2;
-        return int32_t(v >= 1 && v <= 8 ? v : 2);
-    }();
-    const int32_t G0 =
-        waves * resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
+    const int32_t G0 = product_grid(B, kern);
     std::vector<int32_t> sub_blk;
     const std::vector<int32_t> *pblk_h = nullptr;
     if (host_active) {
@@ -198,17 +298,7 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     const std::vector<int32_t> &blk = *pblk_h;
     const int32_t G = blk[size_t(K)];
     const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
-    // room for any block width and any split of this grid, so later calls (possibly captured
-    // in a graph) never move the buffer
-    const size_t need = size_t(3) * kMaxSliceCols * size_t(std::max<int64_t>(std::max(G, G0), K));
-    if (dots && need > B->partials_cap) {
-        // grows outside any steady state (the first call of a shape)
-        if (B->partials) HIPCHK(hipFree(B->partials));
-        B->partials = nullptr;
-        B->partials_cap = 0;
-        HIPCHK(hipMalloc(&B->partials, need * sizeof(double)));
-        B->partials_cap = need;
-    }
+    if (dots && (rc = ensure_partials(B, G, G0))) return rc;
     // the table
     B->stage.assign(B->table_bytes, 0);
     ProdArgs *tab = reinterpret_cast<ProdArgs *>(B->stage.data());
@@ -231,46 +321,14 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
             a.Z = elem_ptr(Z, B->row_off[size_t(m)], 0);
         }
         if (aug) {
-            a.flags = o.flags;
-            a.alpha = o.alpha;
-            a.beta = o.beta;
-            a.delta = o.delta;
-            a.eta = o.eta;
-            a.gamma_s = o.gamma;
-            if (o.flags & SELL_SPMV_VSHIFT) {
-                a.has_gamma_v = 1;
-                for (int j = 0; j < b; ++j) a.gamma_v[j] = o.gamma_v[j];
-            }
+            set_epilogue(a, o);
             if (dots) a.partials = B->partials + size_t(3) * b * blk[size_t(m)];
         }
         std::memcpy(&tab[m], &a, sizeof(ProdArgs));
     }
-    std::memcpy(B->stage.data() + sizeof(ProdArgs) * size_t(K), blk.data(), sizeof(int32_t) * (size_t(K) + 1));
-    // find the table on the device, else upload it (into the reserved slot, or the next ring slot)
-    int slot = -1;
-    if (reserved) {
-        if (B->valid[kRing] && std::memcmp(B->h_slot[kRing], B->stage.data(), B->table_bytes) == 0) slot = kRing;
-    } else {
-        for (int i = 0; i < kRing && slot < 0; ++i)
-            if (B->valid[i] && std::memcmp(B->h_slot[i], B->stage.data(), B->table_bytes) == 0) slot = i;
-    }
-    if (slot < 0) {
-        if (reserved) {
-            slot = kRing;
-        } else {
-            slot = B->next;
-            B->next = (B->next + 1) % kRing;
-        }
-        if (B->valid[slot]) HIPCHK(hipEventSynchronize(B->ev[slot]));  // its last upload has been read
-        B->valid[slot] = false;
-        std::memcpy(B->h_slot[slot], B->stage.data(), B->table_bytes);
-        HIPCHK(hipMemcpyAsync(B->d_slot[slot], B->h_slot[slot], B->table_bytes, hipMemcpyHostToDevice, s));
-        HIPCHK(hipEventRecord(B->ev[slot], s));
-        B->valid[slot] = true;
-    }
-    const ProdArgs *d_tab = static_cast<const ProdArgs *>(B->d_slot[slot]);
-    const int32_t *d_blk =
-        reinterpret_cast<const int32_t *>(static_cast<const char *>(B->d_slot[slot]) + sizeof(ProdArgs) * size_t(K));
+    const ProdArgs *d_tab = nullptr;
+    const int32_t *d_blk = nullptr;
+    if ((rc = place_table(B, blk, reserved, s, &d_tab, &d_blk))) return rc;
     if (out_blk) *out_blk = d_blk;
     if (out_partials) *out_partials = B->partials;
     if (G > 0) {
@@ -301,6 +359,94 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
             return SELL_OK;
         }
         if ((rc = launch_batch_dot_finish(B->partials, d_blk, K, b, o.flags, o.dot, s))) return rc;
+    }
+    return SELL_OK;
+}
+
+// The batched product over packed operands of per-matrix widths (no argument checks):
+// matrix m's X block starts at element xoff[m] of X (ncols_m x w_m, row-major, ld = w_m), its
+// Y and Z blocks at yoff[m]; its dots land packed at o.dot + 3 dotoff[m]. One launch of the
+// mixed-width kernel; the launch table lists the matrices by width, and the workgroups are
+// split by each matrix's cost at its own width.
+int batch_aug_packed_impl(sell_batch *B, const void *X, void *Y, void *Z, const sell_spmv_opts &o, bool aug,
+                          hipStream_t s) {
+    const int K = B->K;
+    Workspace *ws = nullptr;
+    int rc = get_workspace(s, &ws);
+    if (rc) return rc;
+    const int vk = vec_kind(B->vdt);
+    const int esize = vk == VK_F64F64 ? 8 : 4;
+    const bool chain = aug && (o.flags & SELL_SPMV_CHAIN);
+    const void *kern = vk == VK_F64F64   ? batch_mixed_kernel_f64(aug)
+                       : vk == VK_F32F32 ? batch_mixed_kernel_f32(aug)
+                                         : batch_mixed_kernel_bf16(aug);
+    const int32_t G0 = product_grid(B, kern, true);
+    auto hit = B->blk_cache_w.find(G0);
+    if (hit == B->blk_cache_w.end()) {
+        // workgroups per table position (matrices in width order)
+        std::vector<double> w(static_cast<size_t>(K));
+        std::vector<int64_t> cap(static_cast<size_t>(K));
+        for (int p = 0; p < K; ++p) {
+            const int32_t m = B->porder[size_t(p)];
+            w[size_t(p)] = B->cost_w[size_t(m)];
+            cap[size_t(p)] = B->mats[size_t(m)]->ntiles;
+        }
+        std::vector<int32_t> v;
+        apportion(w, cap, G0, v);
+        hit = B->blk_cache_w.emplace(G0, std::move(v)).first;
+    }
+    const std::vector<int32_t> &blk = hit->second;
+    const int32_t G = blk[size_t(K)];
+    const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
+    if (dots && (rc = ensure_partials(B, G, G0))) return rc;
+    const char *xb = static_cast<const char *>(X);
+    char *yb = static_cast<char *>(Y), *zb = static_cast<char *>(Z);
+    B->stage.assign(B->table_bytes, 0);
+    ProdArgs *tab = reinterpret_cast<ProdArgs *>(B->stage.data());
+    for (int p = 0; p < K; ++p) {
+        const int32_t m = B->porder[size_t(p)];
+        const sell_mat *A = B->mats[size_t(m)];
+        const int w = B->widths[size_t(m)];
+        ProdArgs a;
+        base_args(a, A);
+        a.nb = w;
+        a.nblocks = blk[size_t(p) + 1] - blk[size_t(p)];
+        a.X = xb + B->xoff[size_t(m)] * esize;
+        a.Y = yb + B->yoff[size_t(m)] * esize;
+        a.xrs = a.yrs = w;
+        a.xcs = a.ycs = 1;
+        if (chain) {
+            a.Z = zb + B->yoff[size_t(m)] * esize;
+            a.zrs = w;
+            a.zcs = 1;
+        }
+        // the compiled body needs rows aligned to its vector accesses
+        const int vpt = w >= 4 ? 4 : w;
+        const int al = vpt * esize < 16 ? vpt * esize : 16;
+        bool vec = fixed_width(w) && vec_ok(a.X, w, 1, esize, al) && vec_ok(a.Y, w, 1, esize, al);
+        if (chain) vec = vec && vec_ok(a.Z, w, 1, esize, al);
+        a.runtime_width = vec ? 0 : 1;
+        a.scratch = ws->scratch;
+        if (aug) {
+            set_epilogue(a, o);
+            if (dots) a.partials = B->partials + size_t(3) * B->wmax * blk[size_t(p)];
+        }
+        std::memcpy(&tab[p], &a, sizeof(ProdArgs));
+    }
+    const ProdArgs *d_tab = nullptr;
+    const int32_t *d_blk = nullptr;
+    if ((rc = place_table(B, blk, false, s, &d_tab, &d_blk))) return rc;
+    if (G > 0) {
+        int vl_log2 = 0;  // unused by the mixed-width kernel
+        int Karg = K;
+        const int32_t *active = nullptr;
+        void *args[] = {&d_tab, &d_blk, &Karg, &active, &vl_log2};
+        HIPCHK(hipLaunchKernel(kern, dim3(unsigned(G)), dim3(kBlock), args, 0, s));
+    }
+    if (dots) {
+        if (G == 0) return launch_fill(o.dot, SELL_F64, 1, int32_t(3 * B->sum_w), 3 * B->sum_w, 1, 0.0, s);
+        return launch_batch_dot_finish_packed(B->partials, d_blk, B->d_widths, B->d_dotoff, K, B->wmax, o.flags,
+                                              o.dot, s);
     }
     return SELL_OK;
 }
@@ -406,6 +552,118 @@ int sell_batch_info(const sell_batch *B, int32_t *count, int64_t *rows, int64_t 
     return SELL_OK;
 }
 
+int sell_batch_set_widths(sell_batch *B, const int32_t *widths) {
+    if (!B) return SELL_ERR_ARG;
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != B->device) return SELL_ERR_STATE;
+    if (widths)
+        for (int32_t m = 0; m < B->K; ++m)
+            if (widths[m] < 1 || widths[m] > kMaxSliceCols) return SELL_ERR_ARG;
+    // earlier launches may still read the device copies of the widths and offsets
+    HIPCHK(hipDeviceSynchronize());
+    std::vector<int64_t> dotoff, off_ord;
+    std::vector<int32_t> w_ord;
+    try {
+        B->blk_cache_w.clear();
+        if (!widths) {
+            B->widths.clear();
+            B->porder.clear();
+            B->cost_w.clear();
+            B->xoff.clear();
+            B->yoff.clear();
+            B->x_elems = B->y_elems = B->sum_w = 0;
+            B->wmax = 0;
+            return SELL_OK;
+        }
+        const size_t K = size_t(B->K);
+        B->widths.assign(widths, widths + K);
+        B->xoff.assign(K + 1, 0);
+        B->yoff.assign(K + 1, 0);
+        dotoff.assign(K, 0);
+        B->wmax = 0;
+        B->sum_w = 0;
+        // cost at the matrix's own width: its stored entries, the rows of X they gather (weighted
+        // 0.7: mostly served by the caches; the factor reproduces the measured ratio of width-32
+        // to width-1 batched products on 7-point Laplacians, 13x), and the rows of X and Y
+        const double vb = B->vdt == SELL_F64 ? 8.0 : B->vdt == SELL_F32 ? 4.0 : 2.0;
+        const double eb = B->vdt == SELL_F64 ? 8.0 : 4.0;
+        B->cost_w.assign(K, 0.0);
+        for (size_t m = 0; m < K; ++m) {
+            const HostSell &h = B->mats[m]->h;
+            const int64_t w = widths[m];
+            B->xoff[m + 1] = B->xoff[m] + h.ncols * w;
+            B->yoff[m + 1] = B->yoff[m] + h.nrows * w;
+            dotoff[m] = B->sum_w;
+            B->sum_w += w;
+            B->wmax = std::max<int32_t>(B->wmax, int32_t(w));
+            B->cost_w[m] = double(h.stored) * (vb + 4.0 + 0.7 * double(w) * eb) + double(h.nrows + h.ncols) * double(w) * eb;
+        }
+        B->x_elems = B->xoff[K];
+        B->y_elems = B->yoff[K];
+        // the launch table lists the matrices by width (stable), so that the contiguous ranges
+        // of workgroups that the XCDs receive hold matrices of one width where possible
+        B->porder.resize(K);
+        for (size_t m = 0; m < K; ++m) B->porder[m] = int32_t(m);
+        std::stable_sort(B->porder.begin(), B->porder.end(),
+                         [&](int32_t a, int32_t c) { return widths[a] < widths[c]; });
+        w_ord.resize(K);
+        off_ord.resize(K);
+        for (size_t p = 0; p < K; ++p) {
+            w_ord[p] = widths[B->porder[p]];
+            off_ord[p] = dotoff[size_t(B->porder[p])];
+        }
+    } catch (const std::bad_alloc &) {
+        return SELL_ERR_OOM;
+    }
+    if (!B->d_widths) HIPCHK(hipMalloc(&B->d_widths, sizeof(int32_t) * size_t(B->K)));
+    if (!B->d_dotoff) HIPCHK(hipMalloc(&B->d_dotoff, sizeof(int64_t) * size_t(B->K)));
+    HIPCHK(hipMemcpy(B->d_widths, w_ord.data(), sizeof(int32_t) * size_t(B->K), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(B->d_dotoff, off_ord.data(), sizeof(int64_t) * size_t(B->K), hipMemcpyHostToDevice));
+    return SELL_OK;
+}
+
+int sell_batch_packed_sizes(const sell_batch *B, int64_t *x_elems, int64_t *y_elems, int64_t *dots) {
+    if (!B) return SELL_ERR_ARG;
+    if (x_elems) *x_elems = B->x_elems;
+    if (y_elems) *y_elems = B->y_elems;
+    if (dots) *dots = 3 * B->sum_w;
+    return SELL_OK;
+}
+
+int sell_batch_spmmv_aug_packed(sell_batch *B, const void *X, void *Y, void *Z, const sell_spmv_opts *opts,
+                                void *stream) {
+    if (!B) return SELL_ERR_ARG;
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != B->device) return SELL_ERR_STATE;
+    if (B->widths.empty()) return SELL_ERR_STATE;
+    const size_t esize = B->vdt == SELL_F64 ? 8 : 4;
+    if ((B->x_elems > 0 && !X) || (B->y_elems > 0 && !Y)) return SELL_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) % esize) return SELL_ERR_ARG;
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    if (opts) o = *opts;
+    if (o.flags & ~0xFFu) return SELL_ERR_ARG;
+    const uint32_t sq = SELL_SPMV_SHIFT | SELL_SPMV_VSHIFT | SELL_SPMV_DOT_XY | SELL_SPMV_DOT_XX;
+    if (o.flags & sq)
+        for (int m = 0; m < B->K; ++m)
+            if (B->mats[size_t(m)]->h.nrows != B->mats[size_t(m)]->h.ncols) return SELL_ERR_SHAPE;
+    if ((o.flags & SELL_SPMV_VSHIFT) && !o.gamma_v) return SELL_ERR_ARG;
+    if ((o.flags & SELL_SPMV_DOTS) && !o.dot) return SELL_ERR_ARG;
+    if (X == Y && B->y_elems > 0) return SELL_ERR_ARG;
+    if (o.flags & SELL_SPMV_CHAIN) {
+        if (B->y_elems > 0 && !Z) return SELL_ERR_ARG;
+        if (reinterpret_cast<uintptr_t>(Z) % esize) return SELL_ERR_ARG;
+        if (Z == Y && B->y_elems > 0) return SELL_ERR_ARG;
+    }
+    const bool aug = o.flags != 0;
+    try {
+        return batch_aug_packed_impl(B, X, Y, Z, o, aug, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc &) {
+        return SELL_ERR_OOM;
+    }
+}
+
 int sell_batch_spmmv_aug(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts *opts,
                          void *stream) {
     if (!B) return SELL_ERR_ARG;
@@ -419,6 +677,7 @@ int sell_batch_spmmv_aug(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z
     if (X->ncols != Y->ncols || X->ncols < 1) return SELL_ERR_SHAPE;
     if (X->ncols > kMaxSliceCols) return SELL_ERR_UNSUPPORTED;
     if (X->nrows != B->cols || Y->nrows != B->rows) return SELL_ERR_SHAPE;
+    if (batch_ragged(B, X->ncols)) return SELL_ERR_UNSUPPORTED;  // mixed widths take packed operands
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
     if (opts) o = *opts;
     if (o.flags & ~0xFFu) return SELL_ERR_ARG;

@@ -46,6 +46,7 @@ int32_t batch_count(const sell_batch *B);
 int64_t batch_rows(const sell_batch *B);
 int batch_vdt(const sell_batch *B);
 BatchSeg batch_seg(const sell_batch *B);
+bool batch_ragged(const sell_batch *B, int b);
 }  // namespace sellcs
 
 namespace {
@@ -150,6 +151,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     const bool use_graph = (flags & SELL_BATCH_GRAPH) != 0;
     const int K = batch_count(A64);
     const int b = Bv->ncols;
+    if (batch_ragged(A64, b) || (mixed && batch_ragged(Alo, b))) return SELL_ERR_UNSUPPORTED;
     const int64_t n = batch_rows(A64);
     const int idt = mixed ? SELL_F32 : SELL_F64;  // vector type of the iteration
     const size_t isz = mixed ? sizeof(float) : sizeof(double);

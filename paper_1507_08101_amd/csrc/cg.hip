@@ -359,6 +359,22 @@ __global__ void __launch_bounds__(kVT) batch_dot_finish_kernel(const double *par
     if (threadIdx.x == 0) dot[size_t(m) * 3 * nb + q] = v;
 }
 
+// The same for a batch whose matrices have widths of their own (packed operands), per launch
+// table position m: its partials start at 3 wmax blk[m] and hold 3 nbm[m] quantities (group g,
+// column j at g * nbm[m] + j); its dots land packed at dot[3 dot_off[m] + g * nbm[m] + j].
+__global__ void __launch_bounds__(kVT) batch_dot_finish_packed_kernel(const double *partials, const int32_t *blk,
+                                                                      const int32_t *nbm, const int64_t *dot_off,
+                                                                      int32_t wmax, uint32_t flags, double *dot) {
+    const int q = blockIdx.x, m = blockIdx.y, g = q / wmax, j = q - g * wmax;
+    const int w = nbm[m];
+    if (j >= w) return;
+    const uint32_t want = g == 0 ? SELL_SPMV_DOT_YY : g == 1 ? SELL_SPMV_DOT_XY : SELL_SPMV_DOT_XX;
+    if (!(flags & want)) return;
+    const int npm = blk[m + 1] - blk[m];
+    const double v = sum_partials(partials + size_t(3) * wmax * blk[m] + size_t(g * w + j) * npm, npm);
+    if (threadIdx.x == 0) dot[size_t(3) * dot_off[m] + size_t(g) * w + j] = v;
+}
+
 static unsigned vgrid(int64_t work, unsigned cap) {
     int64_t g = (work + kVT - 1) / kVT;
     if (g < 1) g = 1;
@@ -540,6 +556,15 @@ int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, c
     else
         hipLaunchKernelGGL(bcopy_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(P), ctp<float>(R), b, bpad,
                            sg, mask);
+    return ok();
+}
+
+int launch_batch_dot_finish_packed(const double *partials, const int32_t *blk, const int32_t *nbm,
+                                   const int64_t *dot_off, int K, int32_t wmax, uint32_t flags, double *dot,
+                                   hipStream_t s) {
+    if (K < 1) return SELL_OK;
+    hipLaunchKernelGGL(batch_dot_finish_packed_kernel, dim3(3 * wmax, K), dim3(kVT), 0, s, partials, blk, nbm, dot_off,
+                       wmax, flags, dot);
     return ok();
 }
 

@@ -129,6 +129,8 @@ struct ProdArgs {
     int32_t xcd_map;       // 1: give each XCD one contiguous range of tiles
     int32_t vpt_hint;      // columns per lane requested for the matrix (0: default)
     int32_t bpc_hint;      // workgroups per compute unit requested (0: occupancy limit)
+    int32_t runtime_width; // batched launch of mixed widths: 1 = this matrix's rows do not
+                           // allow vector accesses, use the run-time-width body
     int64_t nrows;
     int32_t nb;            // columns in this slice
     const void *X; int64_t xrs, xcs;   // element (i, j) at X[i * xrs + j * xcs]
@@ -217,6 +219,9 @@ int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, c
                     hipStream_t s);
 int launch_batch_dot_finish(const double *partials, const int32_t *blk, int K, int32_t nb, uint32_t flags,
                             double *dot, hipStream_t s);
+int launch_batch_dot_finish_packed(const double *partials, const int32_t *blk, const int32_t *nbm,
+                                   const int64_t *dot_off, int K, int32_t wmax, uint32_t flags, double *dot,
+                                   hipStream_t s);
 
 // The fused product of capi.cpp (no argument checks): y = alpha (A x - gamma x) + beta y,
 // dots, chain; aug = false runs the plain product y = A x.

@@ -13,4 +13,8 @@ const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok) {
     return aug ? batch_kernel_for<VK_F64F64, true>(b, vpt, fixed_ok) : batch_kernel_for<VK_F64F64, false>(b, vpt, fixed_ok);
 }
 
+const void *batch_mixed_kernel_f64(bool aug) {
+    return aug ? batch_mixed_kernel_for<VK_F64F64, true>() : batch_mixed_kernel_for<VK_F64F64, false>();
+}
+
 }  // namespace sellcs

@@ -344,13 +344,20 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
 template <int VK, int B, int VPT, bool AUG>
 __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
-    prod_body<VK, B, VPT, AUG>(a, tile, vl_log2);
+    int vls = vl_log2;
+    if (B == 0 && vls < 0) {
+        vls = 0;
+        while ((1 << vls) < a.nb) ++vls;
+    }
+    prod_body<VK, B, VPT, AUG>(a, tile, vls);
 }
 
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
-// (XCD-remapped) grid work on matrix m, whose launch arguments are table[m].
+// (XCD-remapped) grid work on matrix m, whose launch arguments are table[m]. A matrix m with
+// active != null and active[m] == 0 is skipped (its dot partials are zeroed). With the
+// run-time-width kernel (B == 0) and vl_log2 < 0 every matrix gets the lanes per row of its
+// own width (table[m].nb), so matrices of different block widths share the launch.
 template <int VK, int B, int VPT, bool AUG>
-// A matrix m with active != null and active[m] == 0 is skipped (its dot partials are zeroed).
 __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__restrict__ table,
                                                             const int32_t *__restrict__ blk_start, int K,
                                                             const int32_t *__restrict__ active, int vl_log2) {
@@ -370,7 +377,52 @@ __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__re
             for (int q = threadIdx.x; q < 3 * a.nb; q += kBlock) to_global(a.partials)[size_t(q) * a.nblocks + tile] = 0.0;
         return;
     }
-    prod_body<VK, B, VPT, AUG>(a, tile, vl_log2);
+    int vls = vl_log2;
+    if (B == 0 && vls < 0) {
+        vls = 0;
+        while ((1 << vls) < a.nb) ++vls;
+    }
+    prod_body<VK, B, VPT, AUG>(a, tile, vls);
+}
+
+// A batch whose matrices have block widths of their own, in one launch: every workgroup runs
+// the body compiled for its matrix's width (1, 2, 4, 8, 16 or 32, with the default columns
+// per lane), or the run-time-width body for any other width or for operands whose rows do
+// not allow vector accesses (runtime_width). The branch depends only on the workgroup's
+// matrix, so it is uniform over the workgroup.
+template <int VK, bool AUG>
+__global__ void __launch_bounds__(kBlock) prod_batch_mixed_kernel(const ProdArgs *__restrict__ table,
+                                                                  const int32_t *__restrict__ blk_start, int K,
+                                                                  const int32_t *__restrict__ active, int) {
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = K;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (blk_start[mid] <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const ProdArgs &a = table[lo];
+    const int tile = g - blk_start[lo];
+    if (active && !active[lo]) {
+        if (AUG && (a.flags & SELL_SPMV_DOTS))
+            for (int q = threadIdx.x; q < 3 * a.nb; q += kBlock) to_global(a.partials)[size_t(q) * a.nblocks + tile] = 0.0;
+        return;
+    }
+    switch (a.runtime_width ? 0 : a.nb) {
+        case 1: prod_body<VK, 1, 1, AUG>(a, tile, 0); break;
+        case 2: prod_body<VK, 2, 2, AUG>(a, tile, 0); break;
+        case 4: prod_body<VK, 4, 4, AUG>(a, tile, 0); break;
+        case 8: prod_body<VK, 8, 4, AUG>(a, tile, 0); break;
+        case 16: prod_body<VK, 16, 4, AUG>(a, tile, 0); break;
+        case 32: prod_body<VK, 32, 4, AUG>(a, tile, 0); break;
+        default: {
+            int vls = 0;
+            while ((1 << vls) < a.nb) ++vls;
+            prod_body<VK, 0, 1, AUG>(a, tile, vls);
+        }
+    }
 }
 
 // Transposed product by scattering with floating-point atomics: Y[col, j] += v * X[row, j].
@@ -489,6 +541,11 @@ const void *batch_kernel_for(int b, int vpt, bool fixed_ok) {
         }
     }
     return bk<VK, 0, 1, AUG>();
+}
+
+template <int VK, bool AUG>
+const void *batch_mixed_kernel_for() {
+    return reinterpret_cast<const void *>(prod_batch_mixed_kernel<VK, AUG>);
 }
 
 template <int VK>

@@ -272,3 +272,137 @@ def test_batch_cg_initial_guess_exact_and_maxit(sc):
     B64.close()
     for M in M64:
         M.close()
+
+
+def _pack(blocks):
+    return np.concatenate([np.ascontiguousarray(v).ravel() for v in blocks]) if blocks else np.zeros(0)
+
+
+@pytest.mark.parametrize("dt", ["f64", "bf16"])
+@pytest.mark.parametrize("flags_name", ["plain", "shift_scale_axpby_dots", "vshift_chain_dots"])
+@pytest.mark.parametrize("widths", [(1, 5, 8, 32, 3, 16), (2, 2, 4, 1, 8, 32)])
+def test_batch_packed_widths_vs_oracle(sc, dt, flags_name, widths):
+    """Matrices of different block widths in one launch, operands packed per matrix at its own
+    width (the second set also puts 2-wide FP64 rows at offsets that break 16-byte alignment,
+    which runs the run-time-width body for those matrices)."""
+    import torch
+
+    mats = _square_mats()
+    flags = {"plain": 0,
+             "shift_scale_axpby_dots": sc.SHIFT | sc.SCALE | sc.AXPBY | sc.DOTS,
+             "vshift_chain_dots": sc.VSHIFT | sc.SCALE | sc.AXPBY | sc.DOTS | sc.CHAIN}[flags_name]
+    wmax = max(widths)
+    gv = np.linspace(-1, 1, wmax)
+    kw = dict(alpha=0.5, beta=-1.25, gamma=0.1, delta=0.3, eta=-2.0)
+    Ms = [sc.SellMatrix.from_csr(A, C=32 if k % 2 == 0 else 8, sigma=[1, 64, 7][k % 3], dtype=dt)
+          for k, A in enumerate(mats)]
+    Bt = sc.SellBatch(Ms)
+    Bt.set_widths(widths)
+    nx, ny, nd = Bt.packed_sizes()
+    assert nx == sum(A.ncols * w for A, w in zip(mats, widths)) and nd == 3 * sum(widths)
+    vt = torch.float64 if dt == "f64" else torch.float32
+    Xs = [synth.block_vector(A.ncols, w, synth.SEED_X + 1000 * k) for k, (A, w) in enumerate(zip(mats, widths))]
+    Ys = [synth.block_vector(A.nrows, w, synth.SEED_Y + 1000 * k) for k, (A, w) in enumerate(zip(mats, widths))]
+    Zs = [synth.block_vector(A.nrows, w, synth.SEED_Y + 7 + 1000 * k) for k, (A, w) in enumerate(zip(mats, widths))]
+    if dt != "f64":
+        Xs, Ys, Zs = [[oracle.round_f32(v) for v in L] for L in (Xs, Ys, Zs)]
+    Xd, Yd, Zd = dev(_pack(Xs), vt), dev(_pack(Ys), vt), dev(_pack(Zs), vt)
+    dot = torch.full((nd,), float("nan"), dtype=torch.float64, device="cuda:0")
+    sc.sell_batch_spmmv_aug_packed(Bt, Xd, Yd, Zd if flags & sc.CHAIN else None, flags=flags,
+                                   dot=dot if flags & sc.DOTS else None,
+                                   gamma_v=gv if flags & sc.VSHIFT else None, **kw)
+    Yg, Zg, dg = host(Yd), host(Zd), host(dot)
+    if dt == "f64":
+        tol = 1e-12
+    else:
+        k = max(int(np.diff(A.rowptr).max()) for A in mats if A.nrows) + 3
+        tol = k * 2.0 ** -24 / (1 - k * 2.0 ** -24)
+    gmax = 1.0 if flags & sc.VSHIFT else 0.1
+    esize = 8 if dt == "f64" else 4
+    xo = yo = do = 0
+    for k, (A, w) in enumerate(zip(mats, widths)):
+        Yk = Yg[yo: yo + A.nrows * w].reshape(A.nrows, w)
+        Zk = Zg[yo: yo + A.nrows * w].reshape(A.nrows, w)
+        got = dg[3 * do: 3 * (do + w)]
+        # the batch runs the body compiled for w when the packed rows allow its vector accesses
+        al = min(16, (4 if w >= 4 else w) * esize)
+        same_body = w not in (1, 2, 4, 8, 16, 32) or all((o * esize) % al == 0 for o in (xo, yo, w))
+        xo += A.ncols * w
+        yo += A.nrows * w
+        do += w
+        if A.nrows == 0:
+            if flags & sc.DOTS:
+                assert np.all(got == 0.0)
+            continue
+        Ar = _value_ref(A, dt)
+        if flags:
+            Yr, Zr, dr = oracle.spmmv_aug(Ar, Xs[k], Ys[k], Zs[k], flags=to_oracle_flags(flags),
+                                          gamma_v=gv[:w] if flags & sc.VSHIFT else None, **kw)
+        else:
+            Yr, Zr, dr = oracle.spmmv(Ar, Xs[k]), None, None
+        scale = 0.5 * (abs_product(Ar, Xs[k]) + gmax * np.abs(Xs[k])) + 1.25 * np.abs(Ys[k]) if flags else \
+            abs_product(Ar, Xs[k])
+        assert colwise_relerr(Yk, Yr, scale) <= tol, (k, "y")
+        if flags & sc.CHAIN:
+            assert colwise_relerr(Zk, Zr, 0.3 * np.abs(Zs[k]) + 2.0 * np.abs(Yr) + 2 * scale) <= tol, (k, "z")
+        if flags & sc.DOTS:
+            den = np.concatenate([np.sum(Yk * Yk + 2 * np.abs(Yk) * scale, axis=0),
+                                  np.sum(np.abs(Xs[k]) * (np.abs(Yk) + scale), axis=0), np.sum(Xs[k] * Xs[k], axis=0)])
+            assert np.all(np.abs(got - dr) <= tol * den + 1e-300), (k, "dots")
+        # every row is computed the same way as by the single-matrix entry point (same body)
+        if same_body and not flags & sc.CHAIN:
+            Y1 = dev(Ys[k], vt)
+            d1 = torch.zeros(3 * w, dtype=torch.float64, device="cuda:0")
+            sc.sell_spmmv_aug(Ms[k], dev(Xs[k], vt), Y1, flags=flags, dot=d1 if flags & sc.DOTS else None,
+                              gamma_v=gv[:w] if flags & sc.VSHIFT else None, **kw)
+            assert np.array_equal(host(Y1), Yk), (k, "single")
+    Bt.close()
+    for M in Ms:
+        M.close()
+
+
+def test_batch_widths_state_and_errors(sc):
+    import torch
+
+    mats = _square_mats()
+    Ms = [sc.SellMatrix.from_csr(A) for A in mats]
+    Bt = sc.SellBatch(Ms)
+    b = 8
+    Xd = dev(np.concatenate([synth.block_vector(A.ncols, b, 11 + k) for k, A in enumerate(mats)]))
+    Y0 = dev(np.concatenate([synth.block_vector(A.nrows, b, 21 + k) for k, A in enumerate(mats)]))
+    fl = sc.SHIFT | sc.AXPBY | sc.DOTS
+    dot = torch.zeros(3 * b * len(mats), dtype=torch.float64, device="cuda:0")
+    Yref = Y0.clone()
+    sc.sell_batch_spmmv_aug(Bt, Xd, Yref, flags=fl, beta=0.5, gamma=0.2, dot=dot)
+    # packed operands with every width b are the stacked operands: the same rows, bit for bit
+    Bt.set_widths([b] * len(mats))
+    Yp = Y0.clone().ravel()
+    dp = torch.zeros(3 * b * len(mats), dtype=torch.float64, device="cuda:0")
+    sc.sell_batch_spmmv_aug_packed(Bt, Xd.ravel(), Yp, flags=fl, beta=0.5, gamma=0.2, dot=dp)
+    assert np.array_equal(host(Yp), host(Yref).ravel())
+    assert np.allclose(host(dp), host(dot), rtol=1e-13, atol=0)
+    # with every width equal to b the stacked entry point still works
+    Y2 = Y0.clone()
+    sc.sell_batch_spmmv_aug(Bt, Xd, Y2, flags=fl, beta=0.5, gamma=0.2, dot=dot)
+    assert np.array_equal(host(Y2), host(Yref))
+    with pytest.raises(sc.SellError):
+        Bt.set_widths([0] * len(mats))
+    with pytest.raises(sc.SellError):
+        Bt.set_widths([65] * len(mats))
+    Bt.set_widths([1, 2, 3, 4, 5, 6])
+    with pytest.raises(sc.SellError):  # stacked operands need one width
+        sc.sell_batch_spmmv_aug(Bt, Xd, Y0.clone())
+    with pytest.raises(sc.SellError):  # so does the batched solver
+        sc.sell_batch_cg(Bt, None, Y0.clone(), torch.zeros_like(Y0), tol=1e-8, maxit=10)
+    with pytest.raises(sc.SellError):  # operands of the wrong packed size
+        sc.sell_batch_spmmv_aug_packed(Bt, Xd.ravel(), Y0.clone().ravel())
+    Bt.set_widths(None)
+    with pytest.raises(sc.SellError):  # no widths set
+        sc.lib()  # keep the library loaded; the raw call below must fail on the state
+        sc._ok(sc.lib().sell_batch_spmmv_aug_packed(Bt.handle, None, None, None, None, None), "packed")
+    Y3 = Y0.clone()
+    sc.sell_batch_spmmv_aug(Bt, Xd, Y3, flags=fl, beta=0.5, gamma=0.2, dot=dot)
+    assert np.array_equal(host(Y3), host(Yref))
+    Bt.close()
+    for M in Ms:
+        M.close()
