@@ -455,6 +455,12 @@ def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
         del x
     out["gather_probe_f64"] = probe
     log(f"[bench] gather probe: {probe}")
+    # the autotuner on this matrix at b = 32, FP64: (C, sigma), launch shape and slice width
+    t0 = time.perf_counter()
+    tune = sc.sell_autotune(A, 32, "f64", cache=False)
+    out["autotune_f64_b32"] = {k: (round(v, 1) if isinstance(v, float) else v) for k, v in tune.items()}
+    out["autotune_f64_b32"]["seconds"] = round(time.perf_counter() - t0, 1)
+    log(f"[bench] irregular autotune b=32: {out['autotune_f64_b32']}")
     del rp, co, va, idx
     torch.cuda.empty_cache()
     return out

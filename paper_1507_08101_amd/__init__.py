@@ -54,7 +54,7 @@ class sell_info_t(ct.Structure):
 
 class sell_tune_result(ct.Structure):
     _fields_ = [("C", ct.c_int32), ("sigma", ct.c_int64), ("vpt", ct.c_int32), ("blocks_per_cu", ct.c_int32),
-                ("us", ct.c_double), ("default_us", ct.c_double), ("trials", ct.c_int32)]
+                ("us", ct.c_double), ("default_us", ct.c_double), ("trials", ct.c_int32), ("slice", ct.c_int32)]
 
 
 class sell_cg_stats(ct.Structure):
@@ -102,6 +102,7 @@ _SIGNATURES = {
     "sell_tsmm": ([_P, _P, _I64, _D, _D, _P, _P], _I),
     "sell_tsmm_inplace": ([_P, _P, _I64, _D, _D, _P], _I),
     "sell_set_launch": ([_P, _I32, _I32], _I),
+    "sell_set_slice": ([_P, _I32], _I),
     "sell_autotune": ([_I64, _I64, _P, _P, _P, _I, _I32, ct.c_uint32, ct.POINTER(sell_tune_result), _P], _I),
     "sell_batch_create": ([_PP, _I32, _PP], _I),
     "sell_batch_destroy": ([_P], _I),
@@ -290,6 +291,10 @@ class SellMatrix:
         """Launch parameters of the product kernels for this matrix (0 = defaults)."""
         _ok(lib().sell_set_launch(self.handle, int(vpt), int(blocks_per_cu)), "sell_set_launch")
 
+    def set_slice(self, slice_width=0):
+        """Process wider blocks in launches over column slices of this width (0 = whole block)."""
+        _ok(lib().sell_set_slice(self.handle, int(slice_width)), "sell_set_slice")
+
     @classmethod
     def from_device_csr(cls, nrows, ncols, rowptr, col, val, C=32, sigma=1, dtype="f64", stream=None):
         """Build on the GPU from CSR arrays that are device tensors."""
@@ -302,6 +307,7 @@ class SellMatrix:
         t = sell_autotune(A, b, dtype, stream=stream, cache=cache)
         M = cls.from_csr(A, C=t["C"], sigma=t["sigma"], dtype=dtype, stream=stream)
         M.set_launch(t["vpt"], t["blocks_per_cu"])
+        M.set_slice(t["slice"])
         M.tune = t
         return M
 

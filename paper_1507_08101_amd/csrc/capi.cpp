@@ -182,9 +182,14 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.bpc_hint = A->bpc_hint;
 }
 
-// Split b columns into launches: fixed widths when possible, else up to 64 per launch.
-std::vector<std::pair<int, int>> slices(int b) {
+// Split b columns into launches: slices of width `hint` when it divides b (a width chosen for
+// the matrix, e.g. by the autotuner), else fixed widths when possible, else up to 64 per launch.
+std::vector<std::pair<int, int>> slices(int b, int hint = 0) {
     std::vector<std::pair<int, int>> out;
+    if (hint > 0 && hint < b && b % hint == 0) {
+        for (int j = 0; j < b; j += hint) out.emplace_back(j, hint);
+        return out;
+    }
     auto fixed = [](int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16 || w == 32; };
     if (fixed(b) || b <= kMaxSliceCols) {
         out.emplace_back(0, b);
@@ -229,7 +234,8 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
         }
         return SELL_OK;
     }
-    auto sl_list = slices(b);
+    // the solvers (partials_out) need one slice: they ignore the matrix's slice width
+    auto sl_list = slices(b, partials_out ? 0 : A->slice_hint);
     if (partials_out && sl_list.size() != 1) return SELL_ERR_UNSUPPORTED;
     for (auto sl : sl_list) {
         ProdArgs a;

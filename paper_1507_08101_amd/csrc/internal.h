@@ -98,6 +98,7 @@ struct sell_mat {
     int64_t matrix_bytes = 0;
     int32_t vpt_hint = 0;           // launch parameters chosen for this matrix (0: defaults)
     int32_t bpc_hint = 0;
+    int32_t slice_hint = 0;         // process wider blocks in slices of this width (0: whole)
 };
 
 struct sell_bv {

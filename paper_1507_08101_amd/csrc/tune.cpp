@@ -9,7 +9,8 @@
 // fused <x, y>, or the plain product for a rectangular matrix) with HIP events.
 //
 // The default (C = 32, sigma = 1, default launch) is timed first; a candidate must beat the best
-// so far by 3 % to replace it.
+// so far by 3 % to replace it. A last stage times the block in slices of 8, 16 or 32 columns
+// (several launches of a narrower width can beat one wide launch).
 //
 // Results are cached for the process under a key that describes the matrix's shape class: the
 // value type, the block width, the binary order of magnitude of the row count, the mean row
@@ -64,6 +65,7 @@ struct Trial {
     int64_t sigma;
     int32_t vpt, bpc;
     double us;
+    int32_t slice = 0;
 };
 
 // Average time of one product on A (after warm-up launches).
@@ -104,6 +106,14 @@ int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu) {
     if (blocks_per_cu < 0 || blocks_per_cu > 64) return SELL_ERR_ARG;
     A->vpt_hint = vpt;
     A->bpc_hint = blocks_per_cu;
+    return SELL_OK;
+}
+
+int sell_set_slice(sell_mat *A, int32_t slice) {
+    if (!A) return SELL_ERR_ARG;
+    if (!(slice == 0 || slice == 1 || slice == 2 || slice == 4 || slice == 8 || slice == 16 || slice == 32))
+        return SELL_ERR_ARG;
+    A->slice_hint = slice;
     return SELL_OK;
 }
 
@@ -210,6 +220,20 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
                     rc = run(best.C, best.sigma, v, bpc, A, &t);
                     if (!rc && t.us < kMargin * best.us) best = t;
                 }
+            // stage 3: the block in slices of 8, 16 or 32 columns (the b packing), timed as the
+            // whole sliced call with the best launch shape
+            for (int32_t sl : {8, 16, 32}) {
+                if (rc || sl >= b || b % sl != 0) continue;
+                A->slice_hint = sl;
+                Trial t;
+                rc = run(best.C, best.sigma, best.vpt, best.bpc, A, &t);
+                A->slice_hint = 0;
+                t.slice = sl;
+                if (!rc) {
+                    trials.back().slice = sl;
+                    if (t.us < kMargin * best.us) best = t;
+                }
+            }
             sell_destroy(A);
         }
     }
@@ -220,6 +244,7 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
     res.sigma = best.sigma;
     res.vpt = best.vpt;
     res.blocks_per_cu = best.bpc;
+    res.slice = best.slice;
     res.us = best.us;
     res.default_us = deflt.us;
     res.trials = int32_t(trials.size());

@@ -78,3 +78,58 @@ def test_launch_parameters_do_not_change_rows(sc, b):
     with pytest.raises(sc.SellError):
         M.set_launch(0, 65)
     M.close()
+
+
+@pytest.mark.parametrize("b,slices", [(32, (0, 8, 16)), (24, (0, 8, 16))])
+def test_slices_do_not_change_rows(sc, b, slices):
+    """A block processed in column slices (the autotuner's b packing) gives every row bit for bit,
+    with per-column shifts, chain and dots landing in their columns."""
+    import torch
+
+    A = synth.random_sparse(3000, 3000, 0.004, 65, empty_rows=30, long_row=2000)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=128)
+    Xh = synth.block_vector(A.ncols, b, 66)
+    Y0 = synth.block_vector(A.nrows, b, 67)
+    Z0 = synth.block_vector(A.nrows, b, 68)
+    gv = np.linspace(-0.5, 0.5, b)
+    fl = sc.VSHIFT | sc.SCALE | sc.AXPBY | sc.DOTS | sc.CHAIN
+    kw = dict(alpha=0.75, beta=-0.5, delta=0.25, eta=1.5)
+    ref = None
+    for sl in slices:
+        M.set_slice(sl)
+        Y, Z = dev(Y0), dev(Z0)
+        dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+        sc.sell_spmmv_aug(M, dev(Xh), Y, Z, flags=fl, gamma_v=gv, dot=dot, **kw)
+        got = (host(Y), host(Z), host(dot))
+        if ref is None:
+            ref = got
+            Yr, Zr, dr = oracle.spmmv_aug(A, Xh, Y0, Z0, flags=oracle.VSHIFT | oracle.SCALE | oracle.AXPBY
+                                          | oracle.DOT_YY | oracle.DOT_XY | oracle.DOT_XX | oracle.CHAIN,
+                                          gamma_v=gv, **kw)
+            scale = 0.75 * (abs_product(A, Xh) + 0.5 * np.abs(Xh)) + 0.5 * np.abs(Y0)
+            assert colwise_relerr(got[0], Yr, scale) <= 1e-12
+            assert colwise_relerr(got[1], Zr, 0.25 * np.abs(Z0) + 1.5 * np.abs(Yr) + 1.5 * scale) <= 1e-12
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), sl
+        Yq = got[0]
+        den = np.concatenate([np.sum(Yq * Yq, 0), np.sum(np.abs(Xh * Yq), 0), np.sum(Xh * Xh, 0)])
+        assert np.all(np.abs(got[2] - dr) <= 1e-12 * den), sl
+    with pytest.raises(sc.SellError):
+        M.set_slice(3)
+    with pytest.raises(sc.SellError):
+        M.set_slice(64)
+    M.close()
+
+
+def test_autotune_reports_slice(sc):
+    A = synth.irregular(30000, band=3000, max_len=400, seed=69)
+    t = sc.sell_autotune(A, 32, "f64", cache=False)
+    assert t["slice"] in (0, 8, 16) and t["us"] <= t["default_us"]
+    M = sc.SellMatrix.from_csr_tuned(A, 32, "f64", cache=True)
+    assert M.tune["slice"] == t["slice"]
+    import torch
+
+    X = synth.block_vector(A.ncols, 32, 70)
+    Y = torch.zeros((A.nrows, 32), dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv(M, dev(X), Y)
+    assert colwise_relerr(host(Y), oracle.spmmv(A, X), abs_product(A, X)) <= 1e-12
+    M.close()
