@@ -318,6 +318,62 @@ def other_rows(sc, torch, model, A, Mh, b, s):
     upd, _ = time_launches(torch, lambda: Mh.update_values(newv))
     out["update_values_device_with_transpose_copy"] = {"us": round(upd, 2),
                                                         "spmv_equivalents": round(upd / spmv_us, 2)}
+    # kernel fusion (Sec. 5.3): one KPM step as the fused augmented product, against the plain
+    # product followed by separate passes for scale/shift/axpby and the two dots
+    Yf = torch.rand((n, b), dtype=torch.float64, device="cuda")
+    T = torch.empty_like(Yf)
+    dotf = torch.zeros(3 * b, dtype=torch.float64, device="cuda")
+    alpha, gamma = 2.0 / s, 0.1
+    fl = sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_YY | sc.DOT_XY
+    fused, _ = time_launches(torch, lambda: sc.sell_spmmv_aug(Mh, X64, Yf, flags=fl, alpha=alpha, gamma=gamma,
+                                                               beta=-1.0, dot=dotf))
+
+    def unfused():
+        sc.sell_spmmv(Mh, X64, T)
+        Yf.mul_(-1.0).add_(T, alpha=alpha).add_(X64, alpha=-alpha * gamma)
+        torch.linalg.vecdot(Yf, Yf, dim=0)
+        torch.linalg.vecdot(X64, Yf, dim=0)
+
+    unf, _ = time_launches(torch, unfused)
+    out["fusion_kpm_step_b8"] = {"fused_us": round(fused, 2), "unfused_us": round(unf, 2),
+                                 "speedup": round(unf / fused, 2)}
+    return out
+
+
+def latency_row(sc, torch, synth):
+    """The 64 x 64 Dirichlet Laplacian (n = 4096, 20,224 nonzeros, b = 1, SELL-32-1): time per
+    call of the plain product and of the augmented one (alpha = 0.5, gamma = 0.1, beta = 1, <x,y>
+    and <y,y>), back to back (HIP events over 100 calls) and one call at a time (host clock
+    around a call and a synchronisation)."""
+    A = synth.laplacian2d(64)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    x = torch.tensor(synth.block_vector(A.nrows, 1, synth.SEED_X), device="cuda")
+    y = torch.tensor(synth.block_vector(A.nrows, 1, synth.SEED_Y), device="cuda")
+    dot = torch.zeros(3, dtype=torch.float64, device="cuda")
+    fl = sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_XY | sc.DOT_YY
+    calls = {"plain": lambda: sc.sell_spmmv(M, x, y),
+             "augmented": lambda: sc.sell_spmmv_aug(M, x, y, flags=fl, alpha=0.5, gamma=0.1, beta=1.0, dot=dot)}
+    out = {"matrix": "2D 5-point Dirichlet Laplacian 64x64", "n": A.nrows, "nnz": A.nnz, "b": 1}
+    for name, fn in calls.items():
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(100):
+            fn()
+        e1.record()
+        e1.synchronize()
+        back_to_back = e0.elapsed_time(e1) * 1e3 / 100
+        ts = []
+        for _ in range(100):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        out[name] = {"us_back_to_back": round(back_to_back, 2), "us_synchronous_median": round(
+            float(np.median(ts)) * 1e6, 1)}
+    M.close()
     return out
 
 
@@ -586,6 +642,7 @@ def main():
         extra["build_device"] = device_build_row(sc, torch, A, args.C, args.sigma, extra["plain_spmv_b1_us"])
         extra["grad_chebyshev"] = grad_row(sc, torch, synth)
         extra["tall_skinny"] = tsm_row(sc, torch)
+        extra["latency_laplacian64"] = latency_row(sc, torch, synth)
         log(f"[bench] other rows: {json.dumps(extra)}")
     probes = None if args.no_probe else probe_bandwidth(sc, torch)
     if probes:
