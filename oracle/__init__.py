@@ -48,6 +48,7 @@ def lib():
         L.orc_cheb_apply.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P]
         L.orc_cheb_grad.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P, _P, _P]
         L.orc_pattern_outer.argtypes = [_I64, _P, _P, _I64, _P, _P, _P]
+        L.orc_cheb_filter.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _P, _D, _D, _P]
         L.orc_tsmttsm.argtypes = [_I64, _I64, _I64, _D, _P, _P, _D, _P, ct.c_int]
         L.orc_tsmm.argtypes = [_I64, _I64, _I64, _D, _P, _P, _D, _P]
         L.orc_tsmm_inplace.argtypes = [_I64, _I64, _D, _P, _P, _D]
@@ -183,6 +184,18 @@ def cheb_apply(A, X, N, s, c=0.0):
     _check(lib().orc_cheb_apply(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), N, s, c, _p(Y)),
            "cheb_apply")
     return Y.reshape(X.shape)
+
+
+def cheb_filter(A, X, coef, s, c=0.0):
+    """Z = sum_m coef[m] T_m((A - cI)/s) X for a row-major block X (n x b); N = len(coef) - 1."""
+    X = _f64(X)
+    X2 = X.reshape(A.nrows, -1)
+    b = X2.shape[1]
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    Z = np.empty_like(X2)
+    _check(lib().orc_cheb_filter(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), len(coef) - 1, _p(coef),
+                                 s, c, _p(Z)), "cheb_filter")
+    return Z.reshape(X.shape)
 
 
 def cheb_grad(A, X, N, s, c, G):

@@ -374,6 +374,45 @@ int orc_cheb_apply(int64_t n, const int64_t *rowptr, const int32_t *col, const d
     return 0;
 }
 
+/* Chebyshev filter Z = sum_{m=0}^{N} coef[m] T_m(A~) X: the recurrence as in orc_cheb_apply,
+ * with every v_m added into Z, scaled by its coefficient, right after it is formed. N >= 0. */
+int orc_cheb_filter(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                    const double *X, int64_t N, const double *coef, double s, double c, double *Z) {
+    if (n < 0 || b < 1 || N < 0 || s == 0.0 || !coef) return -1;
+    const size_t ne = (size_t)n * (size_t)b;
+    size_t sz = sizeof(double) * (ne > 0 ? ne : 1);
+    double *prev = (double *)malloc(sz), *cur = (double *)malloc(sz), *nxt = (double *)malloc(sz);
+    if (!prev || !cur || !nxt) {
+        free(prev);
+        free(cur);
+        free(nxt);
+        return -1;
+    }
+    for (size_t e = 0; e < ne; ++e) {
+        prev[e] = X[e];
+        Z[e] = coef[0] * X[e];
+    }
+    if (N >= 1) {
+        atilde(n, rowptr, col, val, b, prev, s, c, cur);
+        for (size_t e = 0; e < ne; ++e) Z[e] += coef[1] * cur[e];
+    }
+    for (int64_t m = 1; m < N; ++m) {
+        atilde(n, rowptr, col, val, b, cur, s, c, nxt);
+        for (size_t e = 0; e < ne; ++e) {
+            nxt[e] = 2.0 * nxt[e] - prev[e];
+            Z[e] += coef[m + 1] * nxt[e];
+        }
+        double *t = prev;
+        prev = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    free(prev);
+    free(cur);
+    free(nxt);
+    return 0;
+}
+
 int orc_cheb_grad(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
                   const double *X, int64_t N, double s, double c, const double *G, double *dX,
                   double *dval) {

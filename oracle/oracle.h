@@ -103,6 +103,10 @@ int orc_cheb_grad(int64_t n, const int64_t *rowptr, const int32_t *col, const do
                   const double *X, int64_t N, double s, double c, const double *G, double *dX,
                   double *dval);
 
+/* Chebyshev filter Z = sum_{m=0}^{N} coef[m] T_m(A~) X (X, Z row-major n x b), N >= 0. */
+int orc_cheb_filter(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int64_t b,
+                    const double *X, int64_t N, const double *coef, double s, double c, double *Z);
+
 /* dval[p] = sum_j G[row(p), j] * X[col[p], j]: the gradient of <G, A X> with respect to the
  * stored values (CSR order). */
 int orc_pattern_outer(int64_t nrows, const int64_t *rowptr, const int32_t *col, int64_t b,

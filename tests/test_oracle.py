@@ -483,3 +483,40 @@ def test_tsmttsm_kahan_is_accurate(orc):
         for j in range(2):
             bound = 4.5e-16 * abs(exact[l][j]) + 1.2e-16 * float(np.sum(np.abs(V[:, l] * W[:, j])))
             assert abs(Xk[l, j] - exact[l][j]) <= bound
+
+
+def test_cheb_filter_is_matrix_exponential():
+    """exp(t x) = I_0(t) + 2 sum_m I_m(t) T_m(x) (the Chebyshev expansion of the exponential);
+    with 41 terms at t = 1.7 the truncation is far below rounding, so the filter with these
+    coefficients equals the dense matrix exponential of A~ applied to X."""
+    import scipy.linalg
+    import scipy.special
+
+    A = synth.anderson3d(5, W=4.0)
+    s = (6 + 2.0) / 0.9
+    D = sp.csr_matrix((A.val, A.col, A.rowptr), shape=(A.nrows, A.ncols)).toarray()
+    X = synth.block_vector(A.nrows, 3, 5)
+    t, N = 1.7, 40
+    coef = np.array([scipy.special.iv(m, t) * (1.0 if m == 0 else 2.0) for m in range(N + 1)])
+    for c in (0.0, 0.4):
+        Z = oracle.cheb_filter(A, X, coef, s, c)
+        ref = scipy.linalg.expm(t * (D - c * np.eye(A.nrows)) / s) @ X
+        assert np.abs(Z - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_cheb_filter_diagonal_closed_form_and_degenerate_cases():
+    rng = np.random.default_rng(8)
+    n = 50
+    d = rng.uniform(-3, 3, n)
+    A = synth.CSR(n, n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32), d, "diag")
+    s, c = 3.5, 0.25
+    X = synth.block_vector(n, 2, 9)
+    coef = rng.normal(size=31)
+    th = np.arccos((d - c) / s)
+    ref = (np.cos(np.outer(th, np.arange(31))) @ coef)[:, None] * X
+    assert np.abs(oracle.cheb_filter(A, X, coef, s, c) - ref).max() <= 1e-13 * np.abs(ref).max()
+    # degree 0 is the scaled input; a unit coefficient vector picks one Chebyshev term
+    assert np.array_equal(oracle.cheb_filter(A, X, [2.5], s, c), 2.5 * X)
+    e = np.zeros(8)
+    e[7] = 1.0
+    assert np.abs(oracle.cheb_filter(A, X, e, s, c) - oracle.cheb_apply(A, X, 7, s, c)).max() <= 1e-14
