@@ -485,7 +485,7 @@ def test_tsmttsm_kahan_is_accurate(orc):
             assert abs(Xk[l, j] - exact[l][j]) <= bound
 
 
-def test_cheb_filter_is_matrix_exponential():
+def test_cheb_filter_is_matrix_exponential(orc):
     """exp(t x) = I_0(t) + 2 sum_m I_m(t) T_m(x) (the Chebyshev expansion of the exponential);
     with 41 terms at t = 1.7 the truncation is far below rounding, so the filter with these
     coefficients equals the dense matrix exponential of A~ applied to X."""
@@ -499,12 +499,12 @@ def test_cheb_filter_is_matrix_exponential():
     t, N = 1.7, 40
     coef = np.array([scipy.special.iv(m, t) * (1.0 if m == 0 else 2.0) for m in range(N + 1)])
     for c in (0.0, 0.4):
-        Z = oracle.cheb_filter(A, X, coef, s, c)
+        Z = orc.cheb_filter(A, X, coef, s, c)
         ref = scipy.linalg.expm(t * (D - c * np.eye(A.nrows)) / s) @ X
         assert np.abs(Z - ref).max() <= 1e-14 * np.abs(ref).max()
 
 
-def test_cheb_filter_diagonal_closed_form_and_degenerate_cases():
+def test_cheb_filter_diagonal_closed_form_and_degenerate_cases(orc):
     rng = np.random.default_rng(8)
     n = 50
     d = rng.uniform(-3, 3, n)
@@ -514,9 +514,9 @@ def test_cheb_filter_diagonal_closed_form_and_degenerate_cases():
     coef = rng.normal(size=31)
     th = np.arccos((d - c) / s)
     ref = (np.cos(np.outer(th, np.arange(31))) @ coef)[:, None] * X
-    assert np.abs(oracle.cheb_filter(A, X, coef, s, c) - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(orc.cheb_filter(A, X, coef, s, c) - ref).max() <= 1e-13 * np.abs(ref).max()
     # degree 0 is the scaled input; a unit coefficient vector picks one Chebyshev term
-    assert np.array_equal(oracle.cheb_filter(A, X, [2.5], s, c), 2.5 * X)
+    assert np.array_equal(orc.cheb_filter(A, X, [2.5], s, c), 2.5 * X)
     e = np.zeros(8)
     e[7] = 1.0
-    assert np.abs(oracle.cheb_filter(A, X, e, s, c) - oracle.cheb_apply(A, X, 7, s, c)).max() <= 1e-14
+    assert np.abs(orc.cheb_filter(A, X, e, s, c) - orc.cheb_apply(A, X, 7, s, c)).max() <= 1e-14
