@@ -337,6 +337,29 @@ def other_rows(sc, torch, model, A, Mh, b, s):
     unf, _ = time_launches(torch, unfused)
     out["fusion_kpm_step_b8"] = {"fused_us": round(fused, 2), "unfused_us": round(unf, 2),
                                  "speedup": round(unf / fused, 2)}
+    # Chebyshev filter of degree 100 (the chained axpby): every step one augmented product that
+    # also accumulates z, against the same recurrence with a separate z += c v pass per step
+    N = 100
+    coef = np.random.default_rng(5).normal(size=N + 1) / np.arange(1, N + 2)
+    Zf = torch.empty_like(X64)
+    chained, _ = time_launches(torch, lambda: sc.sell_cheb_filter(Mh, X64, coef, s, 0.0, Z=Zf), reps=3, warm=1)
+    V0, V1 = torch.empty_like(X64), torch.empty_like(X64)
+
+    def separate():
+        V0.copy_(X64)
+        torch.mul(X64, coef[0], out=Zf)
+        sc.sell_spmmv_aug(Mh, V0, V1, flags=sc.SCALE | sc.SHIFT, alpha=1.0 / s, gamma=0.0)
+        Zf.add_(V1, alpha=coef[1])
+        a, c2 = V0, V1
+        for m in range(1, N):
+            sc.sell_spmmv_aug(Mh, c2, a, flags=sc.SCALE | sc.SHIFT | sc.AXPBY, alpha=2.0 / s, gamma=0.0, beta=-1.0)
+            a, c2 = c2, a
+            Zf.add_(c2, alpha=coef[m + 1])
+
+    sep, _ = time_launches(torch, separate, reps=3, warm=1)
+    out["cheb_filter_deg100_b8"] = {"chained_us_per_step": round(chained / N, 2),
+                                    "separate_axpy_us_per_step": round(sep / N, 2),
+                                    "speedup": round(sep / chained, 2)}
     return out
 
 

@@ -312,6 +312,15 @@ int sell_grad_values(const sell_mat *A, const sell_bv *G, const sell_bv *X, doub
 int sell_cheb_forward(const sell_mat *A, const sell_bv *X, sell_bv *Y, int64_t N, double s,
                       double c, int64_t K, void *ckpt, void *stream);
 
+/* Chebyshev filter Z = sum_{m=0}^{N} coef[m] T_m(A~) X with A~ = (A - c I) / s (polynomial
+ * filters and expansions such as exp(t A~); Sec. 5.3's chained axpby): z = coef[0] x, then
+ * every step of the recurrence is one augmented product that forms v_m+1 and, chained in the
+ * same kernel, z = z + coef[m+1] v_m+1. A square; X, Z: n x b row-major with ld = b, b <= 64,
+ * the matrix's vector type, Z != X. coef: HOST array of N + 1 doubles, N >= 0. Two work blocks
+ * are allocated in stream order. Asynchronous. */
+int sell_cheb_filter(const sell_mat *A, const sell_bv *X, sell_bv *Z, int64_t N, const double *coef,
+                     double s, double c, void *stream);
+
 /* Adjoint of sell_cheb_forward for a scalar loss L with G = dL/dY: dX = dL/dX and
  * dval = dL/dval (DEVICE, nnz doubles, CSR order), from the checkpoints of the forward call
  * with the same (N, s, c, K) and the same matrix values. Each segment of K steps is

@@ -97,6 +97,7 @@ _SIGNATURES = {
     "sell_kpm_dos": ([_P, _I64, _I32, _I32, _D, _D, _P, _I64, _P, _P], _I),
     "sell_grad_values": ([_P, _P, _P, _D, _I, _P, _P], _I),
     "sell_cheb_forward": ([_P, _P, _P, _I64, _D, _D, _I64, _P, _P], _I),
+    "sell_cheb_filter": ([_P, _P, _P, _I64, _P, _D, _D, _P], _I),
     "sell_cheb_backward": ([_P, _P, _I64, _D, _D, _I64, _P, _P, _P, _P], _I),
     "sell_tsmttsm": ([_P, _P, _D, _D, _P, _I64, _I, _P], _I),
     "sell_tsmm": ([_P, _P, _I64, _D, _D, _P, _P], _I),
@@ -630,6 +631,22 @@ def sell_probe_gather(x, idx, out, stream=None):
 
 
 # ==================================================================== value gradients
+
+
+def sell_cheb_filter(A, X, coef, s, c=0.0, Z=None, stream=None):
+    """Z = sum_m coef[m] T_m((A - cI)/s) X (each recurrence step one augmented product with the
+    chained accumulation); returns Z (a new tensor unless given)."""
+    import torch
+
+    coef = np.ascontiguousarray(coef, dtype=np.float64)
+    if coef.ndim != 1 or coef.size < 1:
+        raise SellError(-1, "sell_cheb_filter: coef must hold at least one coefficient")
+    if Z is None:
+        Z = torch.empty_like(X)
+    x, z = _bv(X), _bv(Z)
+    _ok(lib().sell_cheb_filter(_mat(A), x.handle, z.handle, int(coef.size - 1), coef.ctypes.data_as(ct.c_void_p),
+                               float(s), float(c), _stream(stream)), "sell_cheb_filter")
+    return Z
 
 
 def sell_grad_values(A, G, X, dval, alpha=1.0, accumulate=False, stream=None):

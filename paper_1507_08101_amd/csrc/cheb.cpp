@@ -1,6 +1,8 @@
 // cheb.cpp -- derivatives with respect to the stored matrix values.
 //
 //  * sell_grad_values: dL/dval for Y = A X given G = dL/dY (pattern-restricted outer product).
+//  * sell_cheb_filter: Z = sum_m coef_m T_m(A~) X, the chained axpby of the augmented product
+//    accumulating z = z + coef_m+1 v_m+1 in the step that forms v_m+1.
 //  * sell_cheb_forward / sell_cheb_backward: Y = T_N(A~) X with A~ = (A - c I) / s by the
 //    three-term Chebyshev recurrence (each step one augmented product), and its adjoint.
 //    The forward pass keeps the pair (v_kK, v_kK+1) every K steps; the backward pass walks
@@ -143,6 +145,50 @@ int sell_cheb_forward(const sell_mat *A, const sell_bv *X, sell_bv *Y, int64_t N
         if (m % K == 0 && (rc = save(m / K))) return rc;
     }
     return launch_copy(Y, &V1, s);
+}
+
+int sell_cheb_filter(const sell_mat *A, const sell_bv *X, sell_bv *Z, int64_t N, const double *coef, double scale,
+                     double c, void *stream) {
+    int rc = check_matrix(A);
+    if (rc) return rc;
+    if (A->h.nrows != A->h.ncols) return SELL_ERR_SHAPE;
+    if (!X || !Z || !coef) return SELL_ERR_ARG;
+    const int64_t n = A->h.nrows;
+    const int b = X->ncols;
+    if ((rc = check_block(A, X, n, b)) || (rc = check_block(A, Z, n, b))) return rc;
+    if (b > kMaxSliceCols) return SELL_ERR_UNSUPPORTED;
+    if (N < 0 || !(scale != 0.0) || !std::isfinite(scale) || !std::isfinite(c)) return SELL_ERR_ARG;
+    if (X->ptr == Z->ptr && n > 0) return SELL_ERR_ARG;
+    if (n == 0) return SELL_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int dt = vec_dt_of(A);
+    // z = coef_0 x
+    if ((rc = launch_axpby(dt, n, b, b, coef[0], X->ptr, 0.0, Z->ptr, s))) return rc;
+    if (N == 0) return SELL_OK;
+    const size_t vb = size_t(n) * b * (dt == SELL_F64 ? 8 : 4);
+    Temps T(s);
+    void *p0, *p1;
+    if ((rc = T.alloc(&p0, vb)) || (rc = T.alloc(&p1, vb))) return rc;
+    sell_bv V0 = block(p0, n, b, dt), V1 = block(p1, n, b, dt);
+    if ((rc = launch_copy(&V0, X, s))) return rc;
+    // every step: one augmented product forming v_m+1 with the chained z = z + coef_m+1 v_m+1
+    sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
+    o.flags = SELL_SPMV_SCALE | SELL_SPMV_SHIFT | SELL_SPMV_CHAIN;
+    o.alpha = 1.0 / scale;
+    o.gamma = c;
+    o.delta = 1.0;
+    o.eta = coef[1];
+    if ((rc = aug_impl(A, &V0, &V1, Z, o, true, s))) return rc;  // v_1 = A~ v_0
+    o.flags |= SELL_SPMV_AXPBY;
+    o.alpha = 2.0 / scale;
+    o.beta = -1.0;
+    for (int64_t m = 1; m < N; ++m) {
+        // v_m+1 = 2 A~ v_m - v_m-1, written over v_m-1
+        o.eta = coef[m + 1];
+        if ((rc = aug_impl(A, &V1, &V0, Z, o, true, s))) return rc;
+        std::swap(V0, V1);  // (V0, V1) = (v_m, v_m+1)
+    }
+    return SELL_OK;
 }
 
 int sell_cheb_backward(const sell_mat *A, const sell_bv *G, int64_t N, double scale, double c, int64_t K,

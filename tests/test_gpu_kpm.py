@@ -196,3 +196,53 @@ def test_kpm_dos_many_moments_and_edges(sc):
             sc.sell_kpm_dos(dev(mu_h), b, dev(E), kw["s"], kw["c"])
     with pytest.raises(sc.SellError):
         sc.sell_kpm_dos(dev(mu_h[:-1]), b, dev(E), 1.0)  # not whole rows of b moments
+
+
+@pytest.mark.parametrize("b", [1, 8])
+@pytest.mark.parametrize("N", [0, 1, 2, 60])
+def test_cheb_filter_matches_oracle(sc, b, N):
+    """Z = sum_m c_m T_m(A~) X with the chained accumulation of the augmented product. The
+    three-term recurrence keeps |T_m(A~)| <= 1 on the scaled spectrum, so each step adds at most
+    a few ulps of ||X|| per coefficient; the bound below allows 1e-13 N sum|c| ||X|| per column."""
+    A = synth.anderson3d(10)
+    s, c = _scale(), 0.3
+    rng = np.random.default_rng(40 + N)
+    coef = rng.normal(size=N + 1)
+    X = synth.block_vector(A.nrows, b, synth.SEED_X)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    Z = host(sc.sell_cheb_filter(M, dev(X), coef, s, c))
+    ref = oracle.cheb_filter(A, X, coef, s, c)
+    err = np.linalg.norm(Z - ref, axis=0)
+    bound = 1e-13 * max(N, 1) * np.abs(coef).sum() * np.linalg.norm(X, axis=0)
+    assert np.all(err <= bound), (err, bound)
+    if N == 0:
+        assert np.array_equal(Z, coef[0] * X)
+    M.close()
+
+
+def test_cheb_filter_exponential_f32_and_errors(sc):
+    import scipy.special
+    import torch
+
+    A = synth.anderson3d(8)
+    s = _scale()
+    t, N = 2.0, 30
+    coef = np.array([scipy.special.iv(m, t) * (1.0 if m == 0 else 2.0) for m in range(N + 1)])
+    X = synth.block_vector(A.nrows, 4, 41)
+    ref = oracle.cheb_filter(A, X, coef, s)  # exp(t A~) X, pinned against a dense expm
+    # FP32 values and vectors: each step rounds to FP32 (relative 2^-24 per step of a stable
+    # recurrence); the sum of |c_m| = e^t bounds the growth
+    M32 = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype="f32")
+    Z = host(sc.sell_cheb_filter(M32, dev(X, torch.float32), coef, s)).astype(np.float64)
+    rel = np.linalg.norm(Z - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert rel.max() <= 50 * N * 2.0 ** -24 * np.abs(coef).sum(), rel
+    Xd = dev(X)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    with pytest.raises(sc.SellError):
+        sc.sell_cheb_filter(M, Xd, coef, s, Z=Xd)  # Z must not be X
+    with pytest.raises(sc.SellError):
+        sc.sell_cheb_filter(M, Xd, coef, 0.0)
+    with pytest.raises(sc.SellError):
+        sc.sell_cheb_filter(M, Xd, [], s)
+    M.close()
+    M32.close()
