@@ -12,8 +12,10 @@ torch tensors.
 """
 from __future__ import annotations
 
+import collections
 import ctypes as ct
 import os
+import threading
 
 import numpy as np
 
@@ -376,8 +378,42 @@ class BlockVector:
             pass
 
 
+class _CachedView:
+    """A block-vector descriptor from the view cache (owned by the cache, not by this object)."""
+
+    __slots__ = ("handle", "tensor")
+
+    def __init__(self, handle, tensor):
+        self.handle = handle
+        self.tensor = tensor
+
+
+# Descriptors of tensor views, keyed by what they describe (address, shape, strides, type): a
+# descriptor does not own the memory, so one made for an earlier tensor with the same key
+# describes the same memory. One cache per thread (an entry is only evicted by the thread that
+# uses it); least recently used entries are destroyed beyond the bound.
+_VIEW_TLS = threading.local()
+_VIEW_CACHE_MAX = 512
+
+
 def _bv(x):
-    return x if isinstance(x, BlockVector) else BlockVector.view(x)
+    if isinstance(x, (BlockVector, _CachedView)):
+        return x
+    cache = getattr(_VIEW_TLS, "cache", None)
+    if cache is None:
+        cache = _VIEW_TLS.cache = collections.OrderedDict()
+    key = (x.data_ptr(), tuple(x.shape), tuple(x.stride()), x.dtype)
+    h = cache.get(key)
+    if h is None:
+        v = BlockVector.view(x)
+        h, v.handle = v.handle, None  # the cache takes the descriptor over
+        cache[key] = h
+        if len(cache) > _VIEW_CACHE_MAX:
+            _, old = cache.popitem(last=False)
+            lib().sell_bv_destroy(old)
+    else:
+        cache.move_to_end(key)
+    return _CachedView(h, x)
 
 
 def sell_bv_create(nrows, ncols, dtype, layout=SELL_ROW_MAJOR, data=None, ld=0):

@@ -142,3 +142,62 @@ def test_batch_64_laplacians_full(sc):
         assert np.all(rel <= 1.001e-10), (k, rel.max())
     for obj in [B64, Bbf] + M64 + Mbf:
         obj.close()
+
+
+def test_irregular_4M_autotuned_configuration(sc):
+    """The irregular matrix in the configuration the autotuner chooses for b = 32 in FP64
+    (C = 16, sigma = 4096, the block in two 16-column slices), checked on sampled rows with the
+    fused <y, y> of every column against a compensated sum of the returned y."""
+    import torch
+
+    A = _irregular()
+    lens = A.row_lengths()
+    b = 32
+    M = sc.SellMatrix.from_csr(A, C=16, sigma=4096)
+    M.set_slice(16)
+    X = synth.block_vector(A.ncols, b, synth.SEED_X)
+    Yd = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, dev(X), Yd, flags=sc.DOT_YY, dot=dot)
+    Y = host(Yd)
+    rows = np.unique(np.concatenate([synth.randint(79, 2000, 0, A.nrows - 1), [0, A.nrows - 1],
+                                     np.argsort(-lens)[:20]]))
+    _check_sampled(A, X, Y, rows, A.val, 1e-12)
+    d = host(dot)
+    for j in (0, 15, 16, 31):  # both slices
+        ref = math.fsum((Y[:, j] * Y[:, j]).tolist())
+        assert abs(d[j] - ref) <= 1e-12 * ref
+    M.close()
+
+
+def test_batch_64_laplacians_mixed_widths_full(sc):
+    """The 64 Laplacians with block widths 1, 2, 4, 8, 16, 32 in turn, packed operands, one
+    launch (the benchmark's mixed-width row), checked on sampled rows of every matrix."""
+    import torch
+
+    edges = synth.laplacian3d_batch(64)
+    mats = [synth.laplacian3d(e) for e in edges]
+    widths = [(1, 2, 4, 8, 16, 32)[k % 6] for k in range(64)]
+    Ms = [sc.SellMatrix.from_csr(A, C=32, sigma=1) for A in mats]
+    Bt = sc.SellBatch(Ms)
+    Bt.set_widths(widths)
+    nx, ny, nd = Bt.packed_sizes()
+    Xs = [synth.block_vector(A.ncols, w, synth.SEED_X + 1000 * k) for k, (A, w) in enumerate(zip(mats, widths))]
+    Xd = dev(np.concatenate([v.ravel() for v in Xs]))
+    Yd = torch.zeros(ny, dtype=torch.float64, device="cuda:0")
+    dot = torch.zeros(nd, dtype=torch.float64, device="cuda:0")
+    sc.sell_batch_spmmv_aug_packed(Bt, Xd, Yd, flags=sc.DOT_YY, dot=dot)
+    Yh, dh = host(Yd), host(dot)
+    yo = do = 0
+    for k, (A, w) in enumerate(zip(mats, widths)):
+        Yk = Yh[yo: yo + A.nrows * w].reshape(A.nrows, w)
+        rows = np.unique(np.concatenate([synth.randint(90 + k, 40, 0, A.nrows - 1), [0, A.nrows - 1]]))
+        _check_sampled(A, Xs[k], Yk, rows, A.val, 1e-12)
+        for j in range(w):
+            ref = math.fsum((Yk[:, j] * Yk[:, j]).tolist())
+            assert abs(dh[3 * do + j] - ref) <= 1e-12 * ref, (k, j)
+        yo += A.nrows * w
+        do += w
+    Bt.close()
+    for M in Ms:
+        M.close()
