@@ -335,8 +335,22 @@ def other_rows(sc, torch, model, A, Mh, b, s):
         torch.linalg.vecdot(X64, Yf, dim=0)
 
     unf, _ = time_launches(torch, unfused)
+    # the same step one vector at a time, unfused: the paper's KPM comparison (block vectors
+    # together with the augmented product against single-vector steps with separate passes)
+    x1u = X64[:, :1].contiguous()
+    y1u = torch.rand((n, 1), dtype=torch.float64, device="cuda")
+    t1u = torch.empty_like(y1u)
+
+    def unfused_b1():
+        sc.sell_spmmv(Mh, x1u, t1u)
+        y1u.mul_(-1.0).add_(t1u, alpha=alpha).add_(x1u, alpha=-alpha * gamma)
+        torch.linalg.vecdot(y1u, y1u, dim=0)
+        torch.linalg.vecdot(x1u, y1u, dim=0)
+
+    unf1, _ = time_launches(torch, unfused_b1)
     out["fusion_kpm_step_b8"] = {"fused_us": round(fused, 2), "unfused_us": round(unf, 2),
-                                 "speedup": round(unf / fused, 2)}
+                                 "speedup": round(unf / fused, 2), "unfused_b1_us": round(unf1, 2),
+                                 "block_and_fusion_speedup": round(b * unf1 / fused, 2)}
     # Chebyshev filter of degree 100 (the chained axpby): every step one augmented product that
     # also accumulates z, against the same recurrence with a separate z += c v pass per step
     N = 100
@@ -553,22 +567,43 @@ def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
 
 
 def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
-    """The oracle's augmented product (one KPM step) on the host cores, bounded sample."""
+    """The oracle's augmented product (one KPM step) on the host cores, bounded sample; returns
+    the baseline and the oracle's output of the first call (for the parity figure)."""
     X = synth.block_vector(A.nrows, b, synth.SEED_X)
     Y = synth.block_vector(A.nrows, b, synth.SEED_Y)
     flags = oracle.SCALE | oracle.SHIFT | oracle.AXPBY | oracle.DOT_YY | oracle.DOT_XY
     calls = 0
+    first = None
     t0 = time.perf_counter()
     while True:
-        oracle.spmmv_aug(A, X, Y=Y, flags=flags, alpha=2.0 / s, beta=-1.0, gamma=0.0)
+        r = oracle.spmmv_aug(A, X, Y=Y, flags=flags, alpha=2.0 / s, beta=-1.0, gamma=0.0)
+        if first is None:
+            first = r
         calls += 1
         el = time.perf_counter() - t0
         if el >= target_s or calls >= 200:
             break
     gf = calls * 2 * A.nnz * b / el / 1e9
-    return {"value": gf, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{calls} augmented products (one KPM step each, b={b}) on the full "
-                      f"{A.name} matrix, {el:.1f} s"}
+    return ({"value": gf, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"{calls} augmented products (one KPM step each, b={b}) on the full "
+                       f"{A.name} matrix, {el:.1f} s"}, (X, Y, first))
+
+
+def parity_row(sc, torch, A, Mh, b, s, ref):
+    """The timed product (one KPM step: alpha = 2/s, beta = -1, <y,y> and <x,y>) on the full
+    matrix against the oracle's result on the same inputs: the largest per-column normwise
+    relative error of y and the largest relative error of the dots."""
+    X, Y, (Yr, _, dr) = ref
+    Yd = torch.from_numpy(Y).cuda()
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda")
+    sc.sell_spmmv_aug(Mh, torch.from_numpy(X).cuda(), Yd, flags=sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_YY
+                      | sc.DOT_XY, alpha=2.0 / s, beta=-1.0, gamma=0.0, dot=dot)
+    Yg = Yd.cpu().numpy()
+    dg = dot.cpu().numpy()
+    err = np.linalg.norm(Yg - Yr, axis=0) / np.linalg.norm(Yr, axis=0)
+    derr = np.abs(dg[:2 * b] - dr[:2 * b]) / np.abs(dr[:2 * b])
+    return {"y_max_colwise_relerr": float(err.max()), "dots_max_relerr": float(derr.max()),
+            "what": f"one augmented product of the benchmark, b={b}, full matrix, against the FP64 oracle"}
 
 
 def main():
@@ -692,11 +727,14 @@ def main():
     if not args.no_irregular:
         irregular = irregular_row(sc, torch, synth, model)
     cpu = None
+    parity = None
     if not args.no_cpu:
         import oracle
 
-        cpu = cpu_baseline(oracle, synth, A, args.b, s)
+        cpu, ref = cpu_baseline(oracle, synth, A, args.b, s)
         log(f"[bench] cpu baseline: {cpu}")
+        parity = parity_row(sc, torch, A, Mh, args.b, s, ref)
+        log(f"[bench] parity against the oracle: {parity}")
 
     src_hash = kernel_source_hash()
     traffic = load_traffic(f"traffic_anderson{args.L}_b{args.b}.json", src_hash)
@@ -725,6 +763,7 @@ def main():
                      "bytes_per_launch": int(head["bytes_per_launch"]),
                      "launch_avg_us": round(head["launch_avg_us"], 2)},
         "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
         "hbm_gbs": round(head["hbm_gbs"], 1),
         "pmax_gflops": round(head["gflops_pmax"], 2),
         "b1": None if 1 not in results or args.b == 1 else {k: (round(v, 3) if isinstance(v, float) else v)
