@@ -2,7 +2,7 @@
 //
 // The batch's block vectors hold the matrices' operands one after another: matrix m reads
 // rows [col_off[m], col_off[m+1]) of X and writes rows [row_off[m], row_off[m+1]) of Y. One
-// launch of the batched product kernel covers every matrix: two waves of the device's resident
+// launch of the batched product kernel covers every matrix: sixteen waves of the device's resident
 // workgroups are split over the matrices by their cost (stored entries plus rows) so that the
 // busiest workgroup has as little work as possible, and each workgroup finds its matrix's launch arguments in a table in device memory by a binary
 // search over the workgroup offsets. The tables are staged through pinned host memory into a
@@ -165,22 +165,17 @@ void apportion_products(const sell_batch *B, int32_t G0, const int32_t *host_act
 
 namespace {
 
-// Workgroups of a product launch with kernel kern: waves of the resident grid, 2 by default for
-// one width and 16 for mixed widths (whose workgroups differ more in speed, so a finer split
-// balances better: 2.85 ms against 4.06 ms with 2 waves for 64 Laplacians of widths 1..32).
-int32_t product_grid(const sell_batch *B, const void *kern, bool mixed = false) {
+// Workgroups of a product launch with kernel kern: 16 waves of the resident grid by default. A
+// finer split than one wave balances uneven matrices better, since workgroups that finish early
+// take the next ones (64 Laplacians of edges 20..100 at b = 8: 1.42 ms with 16 waves, 1.68 ms
+// with 2, 1.83 ms with 1; mixed widths 1..32: 2.85 ms against 4.06 ms with 2).
+int32_t product_grid(const sell_batch *B, const void *kern) {
     static const int32_t waves = [] {
         const char *e = std::getenv("SELLCS_BATCH_WAVES");
-        const int v = e ? std::atoi(e) : 2;
-        return int32_t(v >= 1 && v <= 8 ? v : 2);
-    }();
-    static const int32_t mixed_waves = [] {
-        const char *e = std::getenv("SELLCS_PACKED_WAVES");
         const int v = e ? std::atoi(e) : 16;
         return int32_t(v >= 1 && v <= 32 ? v : 16);
     }();
-    return (mixed ? mixed_waves : waves) *
-           resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
+    return waves * resident_grid(kern, kBlock, int32_t(std::min<int64_t>(B->total_tiles, 1 << 30)), B->bpc_hint);
 }
 
 // Room for 3 * kMaxSliceCols partials per workgroup of any split of this grid, so that later
@@ -380,7 +375,7 @@ int batch_aug_packed_impl(sell_batch *B, const void *X, void *Y, void *Z, const 
     const void *kern = vk == VK_F64F64   ? batch_mixed_kernel_f64(aug)
                        : vk == VK_F32F32 ? batch_mixed_kernel_f32(aug)
                                          : batch_mixed_kernel_bf16(aug);
-    const int32_t G0 = product_grid(B, kern, true);
+    const int32_t G0 = product_grid(B, kern);
     auto hit = B->blk_cache_w.find(G0);
     if (hit == B->blk_cache_w.end()) {
         // workgroups per table position (matrices in width order)
