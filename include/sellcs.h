@@ -364,6 +364,13 @@ int sell_tsmm_inplace(sell_bv *V, const double *X, int64_t ldx, double alpha, do
  * differ in the last bits (another split of the partial sums). */
 int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu);
 
+/* Grid of the product launches of A in waves of resident workgroups: waves in {0, 1, 2, 4, 8,
+ * 16} (0 and 1: one wave, the default). Several waves let workgroups that finish early take the
+ * next ones, which balances matrices whose tiles differ in speed (scattered gathers); the grid
+ * never exceeds the matrix's fine tiles. Results per row are the same; dots may differ in the
+ * last bits. */
+int sell_set_waves(sell_mat *A, int32_t waves);
+
 /* Processes blocks wider than `slice` columns (slice in {1, 2, 4, 8, 16, 32}; 0 = the whole
  * block in one launch) as consecutive launches over column slices of that width, when slice
  * divides the block width (else the default split). Applies to sell_spmmv and
@@ -380,6 +387,7 @@ typedef struct {
     double default_us;     /* the same for C = 32, sigma = 1 and the default launch    */
     int32_t trials;        /* configurations timed; 0 when answered from the cache     */
     int32_t slice;         /* chosen slice width for the block (0 = whole block)       */
+    int32_t waves;         /* chosen grid in waves of resident workgroups (0 = one)    */
 } sell_tune_result;
 
 #define SELL_TUNE_NO_CACHE 0x1u /* time the candidates even if the shape class is cached */
@@ -387,7 +395,8 @@ typedef struct {
 /* Times candidate formats of the CSR matrix (same arguments as sell_build) for products
  * with block width b (1..64) on the current device: C in {16, 32, 64} with sigma in
  * {1, 8 C, 256 C}, then columns per lane {1, 2, 4} and workgroups per CU {limit, 1, 2} for the
- * best pair, then slices of 8, 16 or 32 columns that divide b (the b packing, sell_set_slice);
+ * best pair, then grids of 2, 4 or 8 waves (sell_set_waves), then slices of 8, 16 or 32 columns
+ * that divide b (the b packing, sell_set_slice);
  * a candidate replaces the best so far only when more than 3 % faster (the default,
  * C = 32, sigma = 1, is timed first). The trial product is the one a CG iteration issues (fused
  * <x, y>; plain for a rectangular matrix). Results are cached per process for the matrix's

@@ -56,7 +56,8 @@ class sell_info_t(ct.Structure):
 
 class sell_tune_result(ct.Structure):
     _fields_ = [("C", ct.c_int32), ("sigma", ct.c_int64), ("vpt", ct.c_int32), ("blocks_per_cu", ct.c_int32),
-                ("us", ct.c_double), ("default_us", ct.c_double), ("trials", ct.c_int32), ("slice", ct.c_int32)]
+                ("us", ct.c_double), ("default_us", ct.c_double), ("trials", ct.c_int32), ("slice", ct.c_int32),
+                ("waves", ct.c_int32)]
 
 
 class sell_cg_stats(ct.Structure):
@@ -106,6 +107,7 @@ _SIGNATURES = {
     "sell_tsmm_inplace": ([_P, _P, _I64, _D, _D, _P], _I),
     "sell_set_launch": ([_P, _I32, _I32], _I),
     "sell_set_slice": ([_P, _I32], _I),
+    "sell_set_waves": ([_P, _I32], _I),
     "sell_autotune": ([_I64, _I64, _P, _P, _P, _I, _I32, ct.c_uint32, ct.POINTER(sell_tune_result), _P], _I),
     "sell_batch_create": ([_PP, _I32, _PP], _I),
     "sell_batch_destroy": ([_P], _I),
@@ -294,6 +296,10 @@ class SellMatrix:
         """Launch parameters of the product kernels for this matrix (0 = defaults)."""
         _ok(lib().sell_set_launch(self.handle, int(vpt), int(blocks_per_cu)), "sell_set_launch")
 
+    def set_waves(self, waves=0):
+        """Grid of the product launches in waves of resident workgroups (0 = one wave)."""
+        _ok(lib().sell_set_waves(self.handle, int(waves)), "sell_set_waves")
+
     def set_slice(self, slice_width=0):
         """Process wider blocks in launches over column slices of this width (0 = whole block)."""
         _ok(lib().sell_set_slice(self.handle, int(slice_width)), "sell_set_slice")
@@ -311,6 +317,7 @@ class SellMatrix:
         M = cls.from_csr(A, C=t["C"], sigma=t["sigma"], dtype=dtype, stream=stream)
         M.set_launch(t["vpt"], t["blocks_per_cu"])
         M.set_slice(t["slice"])
+        M.set_waves(t["waves"])
         M.tune = t
         return M
 

@@ -180,6 +180,7 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.xcd_map = xcd_map;
     a.vpt_hint = A->vpt_hint;
     a.bpc_hint = A->bpc_hint;
+    a.waves_hint = A->waves_hint;
 }
 
 // Split b columns into launches: slices of width `hint` when it divides b (a width chosen for

@@ -99,6 +99,7 @@ struct sell_mat {
     int32_t vpt_hint = 0;           // launch parameters chosen for this matrix (0: defaults)
     int32_t bpc_hint = 0;
     int32_t slice_hint = 0;         // process wider blocks in slices of this width (0: whole)
+    int32_t waves_hint = 0;         // product grid in waves of the resident workgroups (0, 1: one)
 };
 
 struct sell_bv {
@@ -130,6 +131,7 @@ struct ProdArgs {
     int32_t xcd_map;       // 1: give each XCD one contiguous range of tiles
     int32_t vpt_hint;      // columns per lane requested for the matrix (0: default)
     int32_t bpc_hint;      // workgroups per compute unit requested (0: occupancy limit)
+    int32_t waves_hint;    // product grid in waves of resident workgroups (0, 1: one wave)
     int32_t runtime_width; // batched launch of mixed widths: 1 = this matrix's rows do not
                            // allow vector accesses, use the run-time-width body
     int64_t nrows;

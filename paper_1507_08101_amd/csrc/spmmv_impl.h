@@ -26,6 +26,8 @@
 //     needs writes back and invalidates the L2 once per workgroup.
 #pragma once
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace sellcs {
@@ -476,6 +478,8 @@ inline int go_prod(ProdArgs &a, hipStream_t s) {
     }
     auto k = prod_kernel<VK, B, VPT, AUG>;
     a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles, a.bpc_hint);
+    // several waves: workgroups that finish early take the next ones (uneven tiles)
+    if (a.waves_hint > 1) a.nblocks = int32_t(std::min<int64_t>(int64_t(a.nblocks) * a.waves_hint, a.ntiles));
     hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }

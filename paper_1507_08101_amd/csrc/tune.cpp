@@ -4,8 +4,8 @@
 // compromise between padding and the locality of the right-hand side (Sec. 5.1), and plans
 // micro-benchmarks for decisions that depend on the device (Sec. 7.2). Here the candidates are
 // timed on the device itself: first (C, sigma) pairs with the default launch, then, for the
-// best pair, the columns per lane of the fixed-width kernels and the workgroups per compute
-// unit. Each trial times the augmented product that a CG iteration issues (y = A x with the
+// best pair, the columns per lane of the fixed-width kernels, the workgroups per compute unit
+// and the grid size in waves of resident workgroups. Each trial times the augmented product that a CG iteration issues (y = A x with the
 // fused <x, y>, or the plain product for a rectangular matrix) with HIP events.
 //
 // The default (C = 32, sigma = 1, default launch) is timed first; a candidate must beat the best
@@ -66,6 +66,7 @@ struct Trial {
     int32_t vpt, bpc;
     double us;
     int32_t slice = 0;
+    int32_t waves = 0;
 };
 
 // Average time of one product on A (after warm-up launches).
@@ -106,6 +107,13 @@ int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu) {
     if (blocks_per_cu < 0 || blocks_per_cu > 64) return SELL_ERR_ARG;
     A->vpt_hint = vpt;
     A->bpc_hint = blocks_per_cu;
+    return SELL_OK;
+}
+
+int sell_set_waves(sell_mat *A, int32_t waves) {
+    if (!A) return SELL_ERR_ARG;
+    if (!(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16)) return SELL_ERR_ARG;
+    A->waves_hint = waves;
     return SELL_OK;
 }
 
@@ -220,17 +228,34 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
                     rc = run(best.C, best.sigma, v, bpc, A, &t);
                     if (!rc && t.us < kMargin * best.us) best = t;
                 }
+            // grids of several waves of resident workgroups (uneven tiles balance dynamically)
+            for (int32_t wv : {2, 4, 8}) {
+                if (rc) break;
+                A->waves_hint = wv;
+                Trial t;
+                rc = run(best.C, best.sigma, best.vpt, best.bpc, A, &t);
+                A->waves_hint = 0;
+                t.waves = wv;
+                if (!rc) {
+                    trials.back().waves = wv;
+                    if (t.us < kMargin * best.us) best = t;
+                }
+            }
             // stage 3: the block in slices of 8, 16 or 32 columns (the b packing), timed as the
             // whole sliced call with the best launch shape
             for (int32_t sl : {8, 16, 32}) {
                 if (rc || sl >= b || b % sl != 0) continue;
                 A->slice_hint = sl;
+                A->waves_hint = best.waves;
                 Trial t;
                 rc = run(best.C, best.sigma, best.vpt, best.bpc, A, &t);
                 A->slice_hint = 0;
+                A->waves_hint = 0;
                 t.slice = sl;
+                t.waves = best.waves;
                 if (!rc) {
                     trials.back().slice = sl;
+                    trials.back().waves = best.waves;
                     if (t.us < kMargin * best.us) best = t;
                 }
             }
@@ -245,6 +270,7 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
     res.vpt = best.vpt;
     res.blocks_per_cu = best.bpc;
     res.slice = best.slice;
+    res.waves = best.waves;
     res.us = best.us;
     res.default_us = deflt.us;
     res.trials = int32_t(trials.size());

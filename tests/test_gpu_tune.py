@@ -59,8 +59,9 @@ def test_launch_parameters_do_not_change_rows(sc, b):
     for vpt in (0, 1, 2, 4):
         if vpt > b:
             continue
-        for bpc in (0, 1, 2, 5):
+        for bpc, waves in ((0, 0), (1, 0), (2, 0), (5, 0), (0, 2), (0, 8), (1, 16)):
             M.set_launch(vpt, bpc)
+            M.set_waves(waves)
             Y = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
             dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
             sc.sell_spmmv_aug(M, X, Y, flags=sc.SHIFT | sc.DOTS, gamma=0.25, dot=dot)
@@ -70,9 +71,11 @@ def test_launch_parameters_do_not_change_rows(sc, b):
                 Xh = host(X)
                 dref = oracle.spmmv_aug(A, Xh, flags=oracle.SHIFT | oracle.DOT_YY | oracle.DOT_XY | oracle.DOT_XX,
                                         gamma=0.25)[2]
-            assert np.array_equal(got, ref), (vpt, bpc)
+            assert np.array_equal(got, ref), (vpt, bpc, waves)
             den = np.concatenate([np.sum(got * got, 0), np.sum(np.abs(Xh * got), 0), np.sum(Xh * Xh, 0)])
-            assert np.all(np.abs(host(dot) - dref) <= 1e-12 * den), (vpt, bpc)
+            assert np.all(np.abs(host(dot) - dref) <= 1e-12 * den), (vpt, bpc, waves)
+    with pytest.raises(sc.SellError):
+        M.set_waves(3)
     with pytest.raises(sc.SellError):
         M.set_launch(3, 0)
     with pytest.raises(sc.SellError):
@@ -123,9 +126,9 @@ def test_slices_do_not_change_rows(sc, b, slices):
 def test_autotune_reports_slice(sc):
     A = synth.irregular(30000, band=3000, max_len=400, seed=69)
     t = sc.sell_autotune(A, 32, "f64", cache=False)
-    assert t["slice"] in (0, 8, 16) and t["us"] <= t["default_us"]
+    assert t["slice"] in (0, 8, 16) and t["waves"] in (0, 2, 4, 8) and t["us"] <= t["default_us"]
     M = sc.SellMatrix.from_csr_tuned(A, 32, "f64", cache=True)
-    assert M.tune["slice"] == t["slice"]
+    assert M.tune["slice"] == t["slice"] and M.tune["waves"] == t["waves"]
     import torch
 
     X = synth.block_vector(A.ncols, 32, 70)

@@ -144,17 +144,19 @@ def test_batch_64_laplacians_full(sc):
         obj.close()
 
 
-def test_irregular_4M_autotuned_configuration(sc):
-    """The irregular matrix in the configuration the autotuner chooses for b = 32 in FP64
-    (C = 16, sigma = 4096, the block in two 16-column slices), checked on sampled rows with the
-    fused <y, y> of every column against a compensated sum of the returned y."""
+@pytest.mark.parametrize("waves,slice_width", [(8, 0), (0, 16)])
+def test_irregular_4M_autotuned_configuration(sc, waves, slice_width):
+    """The irregular matrix in the configurations the autotuner chooses for b = 32 in FP64
+    (C = 16, sigma = 4096, a grid of 8 waves; and the block in two 16-column slices), checked on
+    sampled rows with the fused <y, y> of every column against a compensated sum of y."""
     import torch
 
     A = _irregular()
     lens = A.row_lengths()
     b = 32
     M = sc.SellMatrix.from_csr(A, C=16, sigma=4096)
-    M.set_slice(16)
+    M.set_waves(waves)
+    M.set_slice(slice_width)
     X = synth.block_vector(A.ncols, b, synth.SEED_X)
     Yd = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
     dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
