@@ -67,6 +67,15 @@ const char *sell_strerror(int code);
 /* Library version as 10000*major + 100*minor + patch. */
 int sell_version(void);
 
+/* Test hooks for the error paths (not for production use). sell_debug_fail_alloc(k): the k-th
+ * device or pinned host allocation the library makes from now on fails as out of memory
+ * (k >= 1; 0 clears; the hook is process-wide). sell_debug_live_allocs: the number of device
+ * and pinned host allocations the library holds (its workspaces and the objects alive), so that
+ * a test can check that a failed call left nothing behind. Errors: SELL_ERR_ARG for k < 0 or a
+ * NULL count. */
+int sell_debug_fail_alloc(int64_t k);
+int sell_debug_live_allocs(int64_t *count);
+
 /* ------------------------------------------------------------------------------------ */
 /* Sparse matrix (Sec. 3.1, 5.1)                                                        */
 

@@ -96,6 +96,8 @@ _SIGNATURES = {
     "sell_cg": ([_P, _P, _P, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_cg_mixed": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_probe_bandwidth": ([_I, _P, _P, _I64, _P], _I),
+    "sell_debug_fail_alloc": ([_I64], _I),
+    "sell_debug_live_allocs": ([ct.POINTER(_I64)], _I),
     "sell_probe_gather": ([_P, _I64, _I32, _P, _I64, _P, _P], _I),
     "sell_kpm_dos": ([_P, _I64, _I32, _I32, _D, _D, _P, _I64, _P, _P], _I),
     "sell_grad_values": ([_P, _P, _P, _D, _I, _P, _P], _I),
@@ -652,6 +654,18 @@ def sell_batch_cg(A64, Alo, B, X, tol=1e-10, maxit=100000, inner_tol=0.1, inner_
                             int(maxit), float(inner_tol), int(inner_maxit), SELL_BATCH_GRAPH if graph else 0, st,
                             _stream(stream)), "sell_batch_cg")
     return [{k: getattr(e, k) for k, _ in sell_cg_stats._fields_} for e in st]
+
+
+def sell_debug_fail_alloc(k):
+    """Test hook: the k-th next allocation of the library fails as out of memory (0 clears)."""
+    _ok(lib().sell_debug_fail_alloc(int(k)), "sell_debug_fail_alloc")
+
+
+def sell_debug_live_allocs():
+    """Test hook: device and pinned host allocations the library currently holds."""
+    n = _I64()
+    _ok(lib().sell_debug_live_allocs(ct.byref(n)), "sell_debug_live_allocs")
+    return n.value
 
 
 def sell_probe_bandwidth(kind, dst, src, nbytes, stream=None):

@@ -92,14 +92,14 @@ void batch_free(sell_batch *B) {
     for (int i = 0; i < kSlots; ++i) {
         if (B->ev[i]) (void)hipEventSynchronize(B->ev[i]);
         if (B->ev[i]) (void)hipEventDestroy(B->ev[i]);
-        if (B->d_slot[i]) (void)hipFree(B->d_slot[i]);
-        if (B->h_slot[i]) (void)hipHostFree(B->h_slot[i]);
+        if (B->d_slot[i]) (void)lib_free(B->d_slot[i]);
+        if (B->h_slot[i]) (void)lib_host_free(B->h_slot[i]);
     }
-    if (B->partials) (void)hipFree(B->partials);
-    if (B->d_row_off) (void)hipFree(B->d_row_off);
-    if (B->d_vblk) (void)hipFree(B->d_vblk);
-    if (B->d_widths) (void)hipFree(B->d_widths);
-    if (B->d_dotoff) (void)hipFree(B->d_dotoff);
+    if (B->partials) (void)lib_free(B->partials);
+    if (B->d_row_off) (void)lib_free(B->d_row_off);
+    if (B->d_vblk) (void)lib_free(B->d_vblk);
+    if (B->d_widths) (void)lib_free(B->d_widths);
+    if (B->d_dotoff) (void)lib_free(B->d_dotoff);
 }
 
 // True when the matrices have widths of their own that differ from the operands' width b.
@@ -184,10 +184,10 @@ int ensure_partials(sell_batch *B, int32_t G, int32_t G0) {
     const size_t need = size_t(3) * kMaxSliceCols * size_t(std::max<int64_t>(std::max(G, G0), B->K));
     if (need <= B->partials_cap) return SELL_OK;
     // grows outside any steady state (the first call of a shape)
-    if (B->partials) HIPCHK(hipFree(B->partials));
+    if (B->partials) HIPCHK(lib_free(B->partials));
     B->partials = nullptr;
     B->partials_cap = 0;
-    HIPCHK(hipMalloc(&B->partials, need * sizeof(double)));
+    HIPCHK(lib_malloc(&B->partials, need * sizeof(double)));
     B->partials_cap = need;
     return SELL_OK;
 }
@@ -500,8 +500,8 @@ int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
     };
     hipError_t e;
     for (int i = 0; i < kSlots; ++i) {
-        if ((e = hipMalloc(&B->d_slot[i], B->table_bytes)) != hipSuccess) return fail(e);
-        if ((e = hipHostMalloc(&B->h_slot[i], B->table_bytes, hipHostMallocDefault)) != hipSuccess) return fail(e);
+        if ((e = lib_malloc(&B->d_slot[i], B->table_bytes)) != hipSuccess) return fail(e);
+        if ((e = lib_host_malloc(&B->h_slot[i], B->table_bytes, hipHostMallocDefault)) != hipSuccess) return fail(e);
         if ((e = hipEventCreateWithFlags(&B->ev[i], hipEventDisableTiming)) != hipSuccess) return fail(e);
     }
     // vector-kernel workgroups for the batched solvers: 2 * kCgMaxGrid in total, split by the
@@ -518,8 +518,8 @@ int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
         }
         apportion(w, cap, Gv, vblk);
         B->vgrid = vblk[size_t(count)];
-        if ((e = hipMalloc(&B->d_row_off, sizeof(int64_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
-        if ((e = hipMalloc(&B->d_vblk, sizeof(int32_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
+        if ((e = lib_malloc(&B->d_row_off, sizeof(int64_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
+        if ((e = lib_malloc(&B->d_vblk, sizeof(int32_t) * (size_t(count) + 1))) != hipSuccess) return fail(e);
         if ((e = hipMemcpy(B->d_row_off, B->row_off.data(), sizeof(int64_t) * (size_t(count) + 1),
                            hipMemcpyHostToDevice)) != hipSuccess)
             return fail(e);
@@ -557,64 +557,79 @@ int sell_batch_set_widths(sell_batch *B, const int32_t *widths) {
             if (widths[m] < 1 || widths[m] > kMaxSliceCols) return SELL_ERR_ARG;
     // earlier launches may still read the device copies of the widths and offsets
     HIPCHK(hipDeviceSynchronize());
-    std::vector<int64_t> dotoff, off_ord;
-    std::vector<int32_t> w_ord;
-    try {
-        B->blk_cache_w.clear();
-        if (!widths) {
-            B->widths.clear();
-            B->porder.clear();
-            B->cost_w.clear();
-            B->xoff.clear();
-            B->yoff.clear();
-            B->x_elems = B->y_elems = B->sum_w = 0;
-            B->wmax = 0;
-            return SELL_OK;
-        }
-        const size_t K = size_t(B->K);
-        B->widths.assign(widths, widths + K);
-        B->xoff.assign(K + 1, 0);
-        B->yoff.assign(K + 1, 0);
-        dotoff.assign(K, 0);
+    if (!widths) {
+        B->widths.clear();
+        B->porder.clear();
+        B->cost_w.clear();
+        B->xoff.clear();
+        B->yoff.clear();
+        B->x_elems = B->y_elems = B->sum_w = 0;
         B->wmax = 0;
-        B->sum_w = 0;
+        B->blk_cache_w.clear();
+        return SELL_OK;
+    }
+    // everything is computed aside and published at the end, so that a failure leaves the batch
+    // as it was (or, after a failed copy to the device, without widths)
+    if (!B->d_widths) HIPCHK(lib_malloc(&B->d_widths, sizeof(int32_t) * size_t(B->K)));
+    if (!B->d_dotoff) HIPCHK(lib_malloc(&B->d_dotoff, sizeof(int64_t) * size_t(B->K)));
+    const size_t K = size_t(B->K);
+    std::vector<int32_t> wv, porder, w_ord;
+    std::vector<int64_t> xoff, yoff, dotoff, off_ord;
+    std::vector<double> cost;
+    int64_t sum_w = 0;
+    int32_t wmax = 0;
+    try {
+        wv.assign(widths, widths + K);
+        xoff.assign(K + 1, 0);
+        yoff.assign(K + 1, 0);
+        dotoff.assign(K, 0);
+        cost.assign(K, 0.0);
         // cost at the matrix's own width: its stored entries, the rows of X they gather (weighted
         // 0.7: mostly served by the caches; the factor reproduces the measured ratio of width-32
         // to width-1 batched products on 7-point Laplacians, 13x), and the rows of X and Y
         const double vb = B->vdt == SELL_F64 ? 8.0 : B->vdt == SELL_F32 ? 4.0 : 2.0;
         const double eb = B->vdt == SELL_F64 ? 8.0 : 4.0;
-        B->cost_w.assign(K, 0.0);
         for (size_t m = 0; m < K; ++m) {
             const HostSell &h = B->mats[m]->h;
             const int64_t w = widths[m];
-            B->xoff[m + 1] = B->xoff[m] + h.ncols * w;
-            B->yoff[m + 1] = B->yoff[m] + h.nrows * w;
-            dotoff[m] = B->sum_w;
-            B->sum_w += w;
-            B->wmax = std::max<int32_t>(B->wmax, int32_t(w));
-            B->cost_w[m] = double(h.stored) * (vb + 4.0 + 0.7 * double(w) * eb) + double(h.nrows + h.ncols) * double(w) * eb;
+            xoff[m + 1] = xoff[m] + h.ncols * w;
+            yoff[m + 1] = yoff[m] + h.nrows * w;
+            dotoff[m] = sum_w;
+            sum_w += w;
+            wmax = std::max<int32_t>(wmax, int32_t(w));
+            cost[m] = double(h.stored) * (vb + 4.0 + 0.7 * double(w) * eb) + double(h.nrows + h.ncols) * double(w) * eb;
         }
-        B->x_elems = B->xoff[K];
-        B->y_elems = B->yoff[K];
         // the launch table lists the matrices by width (stable), so that the contiguous ranges
         // of workgroups that the XCDs receive hold matrices of one width where possible
-        B->porder.resize(K);
-        for (size_t m = 0; m < K; ++m) B->porder[m] = int32_t(m);
-        std::stable_sort(B->porder.begin(), B->porder.end(),
-                         [&](int32_t a, int32_t c) { return widths[a] < widths[c]; });
+        porder.resize(K);
+        for (size_t m = 0; m < K; ++m) porder[m] = int32_t(m);
+        std::stable_sort(porder.begin(), porder.end(), [&](int32_t x, int32_t y) { return widths[x] < widths[y]; });
         w_ord.resize(K);
         off_ord.resize(K);
         for (size_t p = 0; p < K; ++p) {
-            w_ord[p] = widths[B->porder[p]];
-            off_ord[p] = dotoff[size_t(B->porder[p])];
+            w_ord[p] = widths[porder[p]];
+            off_ord[p] = dotoff[size_t(porder[p])];
         }
     } catch (const std::bad_alloc &) {
         return SELL_ERR_OOM;
     }
-    if (!B->d_widths) HIPCHK(hipMalloc(&B->d_widths, sizeof(int32_t) * size_t(B->K)));
-    if (!B->d_dotoff) HIPCHK(hipMalloc(&B->d_dotoff, sizeof(int64_t) * size_t(B->K)));
-    HIPCHK(hipMemcpy(B->d_widths, w_ord.data(), sizeof(int32_t) * size_t(B->K), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(B->d_dotoff, off_ord.data(), sizeof(int64_t) * size_t(B->K), hipMemcpyHostToDevice));
+    if (hipMemcpy(B->d_widths, w_ord.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(B->d_dotoff, off_ord.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice) != hipSuccess) {
+        B->widths.clear();  // the device copies may be stale: the batch has no widths now
+        B->porder.clear();
+        B->blk_cache_w.clear();
+        return SELL_ERR_HIP;
+    }
+    B->widths.swap(wv);
+    B->porder.swap(porder);
+    B->xoff.swap(xoff);
+    B->yoff.swap(yoff);
+    B->cost_w.swap(cost);
+    B->x_elems = B->xoff[K];
+    B->y_elems = B->yoff[K];
+    B->sum_w = sum_w;
+    B->wmax = wmax;
+    B->blk_cache_w.clear();
     return SELL_OK;
 }
 

@@ -62,12 +62,12 @@ constexpr int kCheckEvery = 8;
 struct DevBuffers {
     std::vector<void *> ptrs;
     ~DevBuffers() {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : ptrs) (void)lib_free(p);
     }
     int alloc(void **p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 16;
-        HIPCHK(hipMalloc(p, bytes));
+        HIPCHK(lib_malloc(p, bytes));
         ptrs.push_back(*p);
         return SELL_OK;
     }

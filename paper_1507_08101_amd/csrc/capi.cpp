@@ -28,25 +28,27 @@ template <class T>
 int dev_upload(T **dst, const T *src, size_t n, hipStream_t s) {
     *dst = nullptr;
     if (n == 0) return SELL_OK;
-    HIPCHK(hipMalloc(reinterpret_cast<void **>(dst), n * sizeof(T)));
+    HIPCHK(lib_malloc(reinterpret_cast<void **>(dst), n * sizeof(T)));
     HIPCHK(hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
     return SELL_OK;
 }
 
+// Frees every device array the matrix holds: also those of a construction that failed half way
+// (on_device is only set once an upload is complete).
 void free_device(sell_mat *A) {
-    if (!A->on_device) return;
+    if (A->device < 0) return;  // never touched a device (host-only matrix)
     int cur = 0;
     (void)hipGetDevice(&cur);
-    if (A->device >= 0 && A->device != cur) (void)hipSetDevice(A->device);
-    hipFree(A->d_col);
-    hipFree(A->d_val);
-    hipFree(A->d_cl);
-    hipFree(A->d_cs);
-    hipFree(A->d_perm);
-    hipFree(A->d_tiles);
-    hipFree(A->d_rowslot);
-    hipFree(A->d_rowptr);
-    hipFree(A->d_tpos);
+    if (A->device != cur) (void)hipSetDevice(A->device);
+    lib_free(A->d_col);
+    lib_free(A->d_val);
+    lib_free(A->d_cl);
+    lib_free(A->d_cs);
+    lib_free(A->d_perm);
+    lib_free(A->d_tiles);
+    lib_free(A->d_rowslot);
+    lib_free(A->d_rowptr);
+    lib_free(A->d_tpos);
     A->d_tpos = nullptr;
     A->d_col = nullptr;
     A->d_val = nullptr;
@@ -56,7 +58,7 @@ void free_device(sell_mat *A) {
     A->d_tiles = nullptr;
     A->d_rowslot = nullptr;
     A->d_rowptr = nullptr;
-    if (A->device >= 0 && A->device != cur) (void)hipSetDevice(cur);
+    if (A->device != cur) (void)hipSetDevice(cur);
 }
 
 int upload(sell_mat *A, hipStream_t s) {
@@ -65,7 +67,7 @@ int upload(sell_mat *A, hipStream_t s) {
     int rc;
     if ((rc = dev_upload(&A->d_col, h.col.data(), h.col.size(), s))) return rc;
     if (h.stored > 0) {
-        HIPCHK(hipMalloc(&A->d_val, h.val.size()));
+        HIPCHK(lib_malloc(&A->d_val, h.val.size()));
         HIPCHK(hipMemcpyAsync(A->d_val, h.val.data(), h.val.size(), hipMemcpyHostToDevice, s));
     }
     if ((rc = dev_upload(&A->d_cl, h.cl.data(), h.cl.size(), s))) return rc;
@@ -102,9 +104,9 @@ int get_workspace(hipStream_t s, Workspace **ws) {
     }
     Workspace w;
     const size_t np = size_t(kMaxTiles) * 3 * kMaxSliceCols;
-    HIPCHK(hipMalloc(&w.partials, np * sizeof(double)));
-    if (hipMalloc(&w.scratch, kScratchBytes) != hipSuccess) {
-        hipFree(w.partials);
+    HIPCHK(lib_malloc(&w.partials, np * sizeof(double)));
+    if (lib_malloc(&w.scratch, kScratchBytes) != hipSuccess) {
+        lib_free(w.partials);
         return SELL_ERR_OOM;
     }
     auto res = g_ws.emplace(key, w);
@@ -118,8 +120,8 @@ void drop_workspace(hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find(std::make_pair(dev, s));
     if (it == g_ws.end()) return;
-    (void)hipFree(it->second.partials);
-    (void)hipFree(it->second.scratch);
+    (void)lib_free(it->second.partials);
+    (void)lib_free(it->second.scratch);
     g_ws.erase(it);
 }
 
@@ -487,11 +489,21 @@ int ensure_update_maps(sell_mat *A, hipStream_t s) {
         const int64_t row = h.has_perm ? h.perm[slot] : (slot < h.nrows ? slot : -1);
         if (row >= 0) rowslot[row] = int32_t(slot);
     }
-    int rc = dev_upload(&A->d_rowptr, h.rowptr.data(), h.rowptr.size(), s);
-    if (rc) return rc;
-    rc = dev_upload(&A->d_rowslot, rowslot.data(), rowslot.size(), s);
-    if (rc) return rc;
-    HIPCHK(hipStreamSynchronize(s));
+    // both maps are built before either is published: d_rowptr marks them as present, so a
+    // failure half way must not leave it set
+    int64_t *rp = nullptr;
+    int32_t *rs = nullptr;
+    int rc = dev_upload(&rp, h.rowptr.data(), h.rowptr.size(), s);
+    if (!rc) rc = dev_upload(&rs, rowslot.data(), rowslot.size(), s);
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = SELL_ERR_HIP;
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        (void)lib_free(rp);
+        (void)lib_free(rs);
+        return rc;
+    }
+    A->d_rowptr = rp;
+    A->d_rowslot = rs;
     return SELL_OK;
 }
 }  // namespace sellcs
@@ -537,11 +549,11 @@ int sell_update_values(sell_mat *A, const double *val, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (A->h.nnz == 0) return SELL_OK;
     double *d = nullptr;
-    HIPCHK(hipMalloc(&d, size_t(A->h.nnz) * sizeof(double)));
+    HIPCHK(lib_malloc(&d, size_t(A->h.nnz) * sizeof(double)));
     hipError_t e = hipMemcpyAsync(d, val, size_t(A->h.nnz) * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) rc = sell_update_values_device(A, d, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    hipFree(d);
+    lib_free(d);
     if (e != hipSuccess) return hip_err(e);
     return rc;
 }
@@ -578,10 +590,10 @@ int sell_bv_create(sell_bv **X, int64_t nrows, int32_t ncols, sell_dtype dt, sel
         v->ld = lay == SELL_ROW_MAJOR ? ncols : std::max<int64_t>(nrows, 1);
         const size_t bytes = size_t(nrows) * size_t(ncols) * dtype_bytes(dt);
         if (bytes > 0) {
-            hipError_t e = hipMalloc(&v->ptr, bytes);
+            hipError_t e = lib_malloc(&v->ptr, bytes);
             if (e == hipSuccess) e = hipMemset(v->ptr, 0, bytes);
             if (e != hipSuccess) {
-                hipFree(v->ptr);
+                lib_free(v->ptr);
                 delete v;
                 return hip_err(e);
             }
@@ -594,7 +606,7 @@ int sell_bv_create(sell_bv **X, int64_t nrows, int32_t ncols, sell_dtype dt, sel
 
 int sell_bv_destroy(sell_bv *X) {
     if (!X) return SELL_OK;
-    if (X->owned && X->ptr) hipFree(X->ptr);
+    if (X->owned && X->ptr) lib_free(X->ptr);
     delete X;
     return SELL_OK;
 }
@@ -707,7 +719,7 @@ int ensure_transpose(const sell_mat *A, hipStream_t s) {
     if (rc == SELL_OK && hipStreamSynchronize(s) != hipSuccess) rc = SELL_ERR_HIP;
     if (rc) {
         sell_destroy(T);
-        hipFree(M->d_tpos);
+        lib_free(M->d_tpos);
         M->d_tpos = nullptr;
         return rc;
     }
@@ -784,8 +796,8 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
     const int32_t nt = A->ntiles;
     const size_t per_step = size_t(3) * b * size_t(nt > 0 ? nt : 1);
     double *dots = nullptr, *parts = nullptr;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&dots), size_t(M) * 3 * b * sizeof(double), s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void **>(&parts), size_t(M) * per_step * sizeof(double), s);
+    hipError_t e = lib_malloc_async(reinterpret_cast<void **>(&dots), size_t(M) * 3 * b * sizeof(double), s);
+    if (e == hipSuccess) e = lib_malloc_async(reinterpret_cast<void **>(&parts), size_t(M) * per_step * sizeof(double), s);
     if (e != hipSuccess) rc = hip_err(e);
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
     // v1 = (A v0 - c v0) / s, with <v1,v1>, <v0,v1>, <v0,v0>
@@ -813,11 +825,11 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
         rc = launch_fill(dots, SELL_F64, M, 3 * b, 3 * b, 1, 0.0, s);
     if (rc == SELL_OK) rc = launch_kpm_moments(dots, M, b, mu, s);
     if (parts) {
-        e = hipFreeAsync(parts, s);
+        e = lib_free_async(parts, s);
         if (rc == SELL_OK && e != hipSuccess) rc = hip_err(e);
     }
     if (dots) {
-        e = hipFreeAsync(dots, s);
+        e = lib_free_async(dots, s);
         if (rc == SELL_OK && e != hipSuccess) rc = hip_err(e);
     }
     if (step_ms) {

@@ -53,11 +53,11 @@ struct Temps {
     std::vector<void *> ptrs;
     explicit Temps(hipStream_t st) : s(st) {}
     ~Temps() {
-        for (void *p : ptrs) (void)hipFreeAsync(p, s);
+        for (void *p : ptrs) (void)lib_free_async(p, s);
     }
     int alloc(void **p, size_t bytes) {
         *p = nullptr;
-        HIPCHK(hipMallocAsync(p, bytes ? bytes : 16, s));
+        HIPCHK(lib_malloc_async(p, bytes ? bytes : 16, s));
         ptrs.push_back(*p);
         return SELL_OK;
     }

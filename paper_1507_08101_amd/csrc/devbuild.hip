@@ -115,11 +115,11 @@ __global__ void __launch_bounds__(kT) fill_kernel(const int64_t *rowptr, const i
 struct DevTemp {
     std::vector<void *> p;
     ~DevTemp() {
-        for (void *q : p) (void)hipFree(q);
+        for (void *q : p) (void)lib_free(q);
     }
     hipError_t alloc(void **q, size_t bytes) {
         *q = nullptr;
-        hipError_t e = hipMalloc(q, bytes ? bytes : 16);
+        hipError_t e = lib_malloc(q, bytes ? bytes : 16);
         if (e == hipSuccess) p.push_back(*q);
         return e;
     }
@@ -172,7 +172,7 @@ int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *
         DCHK(T.alloc(reinterpret_cast<void **>(&keys), sizeof(uint64_t) * size_t(nrows)));
         DCHK(T.alloc(reinterpret_cast<void **>(&keys_out), sizeof(uint64_t) * size_t(nrows)));
         DCHK(T.alloc(reinterpret_cast<void **>(&rows), sizeof(int32_t) * size_t(nrows)));
-        DCHK(hipMalloc(reinterpret_cast<void **>(&slot_row), sizeof(int32_t) * size_t(nslots)));
+        DCHK(lib_malloc(reinterpret_cast<void **>(&slot_row), sizeof(int32_t) * size_t(nslots)));
         M->d_perm = slot_row;  // owned by the matrix from here on (freed with it, or dropped below)
     }
     if (nrows > 0) {
@@ -201,14 +201,14 @@ int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *
     if (hflags[0] || hflags[1]) return SELL_ERR_ARG;
     const bool has_perm = sort && hflags[2];
     if (sort && !has_perm) {  // the sort kept every row in place: no permutation
-        DCHK(hipFree(slot_row));
+        DCHK(lib_free(slot_row));
         M->d_perm = nullptr;
         slot_row = nullptr;
     }
 
     // chunk lengths and starts
-    DCHK(hipMalloc(reinterpret_cast<void **>(&M->d_cl), sizeof(int32_t) * size_t(std::max<int64_t>(nch, 1))));
-    DCHK(hipMalloc(reinterpret_cast<void **>(&M->d_cs), sizeof(int64_t) * (size_t(nch) + 1)));
+    DCHK(lib_malloc(reinterpret_cast<void **>(&M->d_cl), sizeof(int32_t) * size_t(std::max<int64_t>(nch, 1))));
+    DCHK(lib_malloc(reinterpret_cast<void **>(&M->d_cs), sizeof(int64_t) * (size_t(nch) + 1)));
     DCHK(T.alloc(reinterpret_cast<void **>(&csz), sizeof(int64_t) * (size_t(nch) + 1)));
     hipLaunchKernelGGL(chunk_len_kernel, dim3(grid_for(nch + 1)), dim3(kT), 0, s, len, slot_row, nrows, nch, C,
                        M->d_cl, csz);
@@ -229,8 +229,8 @@ int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *
 
     // the fill
     const int vb = dtype_bytes(vdt);
-    DCHK(hipMalloc(reinterpret_cast<void **>(&M->d_col), sizeof(int32_t) * size_t(std::max<int64_t>(stored, 1))));
-    DCHK(hipMalloc(&M->d_val, size_t(vb) * size_t(std::max<int64_t>(stored, 1))));
+    DCHK(lib_malloc(reinterpret_cast<void **>(&M->d_col), sizeof(int32_t) * size_t(std::max<int64_t>(stored, 1))));
+    DCHK(lib_malloc(&M->d_val, size_t(vb) * size_t(std::max<int64_t>(stored, 1))));
     if (nslots > 0) {
         if (vdt == SELL_F64)
             hipLaunchKernelGGL(fill_kernel<double>, dim3(grid_for(nslots)), dim3(kT), 0, s, rowptr, col, val, len,
@@ -261,7 +261,7 @@ int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *
     h.vdt = vdt;
     h.has_perm = has_perm;
     make_tiles(h.cl, C, default_tile_count(nch), h.tiles);
-    DCHK(hipMalloc(reinterpret_cast<void **>(&M->d_tiles), sizeof(int32_t) * h.tiles.size()));
+    DCHK(lib_malloc(reinterpret_cast<void **>(&M->d_tiles), sizeof(int32_t) * h.tiles.size()));
     DCHK(hipMemcpyAsync(M->d_tiles, h.tiles.data(), sizeof(int32_t) * h.tiles.size(), hipMemcpyHostToDevice, s));
     DCHK(hipStreamSynchronize(s));
     M->ntiles = int32_t(h.tiles.size()) - 1;

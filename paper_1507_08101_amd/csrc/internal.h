@@ -255,6 +255,23 @@ int launch_axpby(int vec_dt, int64_t n, int32_t b, int64_t ld, double alpha, con
 // dst[pos[p]] = convert(src[p]) for p < n, dst of storage type vdt
 int launch_scatter_values(const double *src, const int64_t *pos, int64_t n, int vdt, void *dst, hipStream_t s);
 
+// Device and pinned host allocations of the library (alloc.cpp): hipMalloc and friends with a
+// count of live allocations and a test hook that makes the k-th next allocation fail.
+hipError_t lib_malloc(void **p, size_t bytes);
+hipError_t lib_malloc_async(void **p, size_t bytes, hipStream_t s);
+hipError_t lib_host_malloc(void **p, size_t bytes, unsigned flags);
+hipError_t lib_free(void *p);
+hipError_t lib_free_async(void *p, hipStream_t s);
+hipError_t lib_host_free(void *p);
+template <class T>
+hipError_t lib_malloc(T **p, size_t bytes) {
+    return lib_malloc(reinterpret_cast<void **>(p), bytes);
+}
+template <class T>
+hipError_t lib_malloc_async(T **p, size_t bytes, hipStream_t s) {
+    return lib_malloc_async(reinterpret_cast<void **>(p), bytes, s);
+}
+
 // Argument helpers of the entry points (capi.cpp).
 int check_device(const sell_mat *A);     // on the device and the current one
 int validate_bv(const sell_bv *v);

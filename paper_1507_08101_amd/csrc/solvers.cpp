@@ -40,12 +40,12 @@ constexpr int kCheckEvery = 8;
 struct Buffers {
     std::vector<void *> ptrs;
     ~Buffers() {
-        for (void *p : ptrs) hipFree(p);
+        for (void *p : ptrs) lib_free(p);
     }
     int alloc(void **p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 16;
-        HIPCHK(hipMalloc(p, bytes));
+        HIPCHK(lib_malloc(p, bytes));
         ptrs.push_back(*p);
         return SELL_OK;
     }

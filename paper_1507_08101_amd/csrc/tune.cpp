@@ -152,14 +152,14 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
     const size_t es = vt == SELL_F64 ? 8 : 4;
     void *px = nullptr, *py = nullptr;
     double *pdot = nullptr;
-    HIPCHK(hipMalloc(&px, std::max<size_t>(16, size_t(ncols) * b * es)));
+    HIPCHK(lib_malloc(&px, std::max<size_t>(16, size_t(ncols) * b * es)));
     auto cleanup = [&]() {
-        if (px) (void)hipFree(px);
-        if (py) (void)hipFree(py);
-        if (pdot) (void)hipFree(pdot);
+        if (px) (void)lib_free(px);
+        if (py) (void)lib_free(py);
+        if (pdot) (void)lib_free(pdot);
     };
-    if (hipMalloc(&py, std::max<size_t>(16, size_t(nrows) * b * es)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&pdot), 3 * kMaxSliceCols * sizeof(double)) != hipSuccess) {
+    if (lib_malloc(&py, std::max<size_t>(16, size_t(nrows) * b * es)) != hipSuccess ||
+        lib_malloc(reinterpret_cast<void **>(&pdot), 3 * kMaxSliceCols * sizeof(double)) != hipSuccess) {
         cleanup();
         return SELL_ERR_OOM;
     }
