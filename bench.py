@@ -175,7 +175,7 @@ def batch_row(sc, torch, synth, model, nmat=64, b=8, tol=1e-10):
     for A, Mk in zip(mats, M["f64"]):
         alg_bytes += model.bytes_min(A.nnz, A.nrows, A.ncols, b, 8, 8, read_y=False, nchunks=Mk.info["nchunks"])
     us, us_min = time_launches(torch, lambda: sc.sell_batch_spmmv_aug(B64, Xd, Yd, flags=sc.DOT_XY, dot=dots),
-                               reps=20)
+                               reps=10, inner=5)
     out["batched_product_f64"] = {"us": round(us, 1), "GB/s": round(alg_bytes / (us * 1e-6) / 1e9, 1),
                                   "GFLOP/s": round(2.0 * nnz_tot * b / (us * 1e-6) / 1e9, 1),
                                   "bytes": int(alg_bytes)}
@@ -198,7 +198,7 @@ def batch_row(sc, torch, synth, model, nmat=64, b=8, tol=1e-10):
     Yp = torch.empty(ny, dtype=torch.float64, device="cuda")
     dp = torch.zeros(nd, dtype=torch.float64, device="cuda")
     usw, _ = time_launches(torch, lambda: sc.sell_batch_spmmv_aug_packed(B64, Xp, Yp, flags=sc.DOT_XY, dot=dp),
-                           reps=10)
+                           reps=4, inner=5)
     B64.set_widths(None)
     xo = np.cumsum([0] + [A.ncols * wlist[k] for k, A in enumerate(mats)])
     yo = np.cumsum([0] + [A.nrows * wlist[k] for k, A in enumerate(mats)])
@@ -266,18 +266,21 @@ def batch_row(sc, torch, synth, model, nmat=64, b=8, tol=1e-10):
     return out
 
 
-def time_launches(torch, fn, reps=20, warm=3):
-    """Mean and best duration (us) of fn() with HIP events on the current stream."""
+def time_launches(torch, fn, reps=20, warm=3, inner=1):
+    """Mean and best duration (us) of fn() with HIP events on the current stream. With inner > 1
+    each event pair spans inner back-to-back calls (throughput: one call's host overhead and the
+    idle start after a synchronisation are not counted)."""
     for _ in range(warm):
         fn()
     ts = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        fn()
+        for _ in range(inner):
+            fn()
         e1.record()
         e1.synchronize()
-        ts.append(e0.elapsed_time(e1) * 1e3)
+        ts.append(e0.elapsed_time(e1) * 1e3 / inner)
     return float(np.mean(ts)), float(np.min(ts))
 
 
@@ -294,7 +297,7 @@ def other_rows(sc, torch, model, A, Mh, b, s):
     for dt, vb in (("bf16", 2), ("f32", 4)):
         Ml = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=dt)
         mean, best = time_launches(torch, lambda: sc.sell_spmmv_aug(Ml, X32, Y32, flags=flags, alpha=2.0 / s,
-                                                                     beta=-1.0, dot=dot))
+                                                                     beta=-1.0, dot=dot), reps=10, inner=5)
         by = model.bytes_min(A.nnz, n, n, b, vb, 4, read_y=True, nchunks=info["nchunks"])
         out[f"aug_{dt}_values_f32_vectors"] = {"us": round(mean, 2), "GB/s": round(by / (mean * 1e-6) / 1e9, 1),
                                                "GFLOP/s": round(model.flops(A.nnz, b) / (mean * 1e-6) / 1e9, 1),
@@ -312,7 +315,8 @@ def other_rows(sc, torch, model, A, Mh, b, s):
     out["plain_spmv_b1_us"] = round(spmv_us, 2)
     by = model.bytes_min(A.nnz, n, n, b, 8, 8, nchunks=info["nchunks"])
     for det in (False, True):
-        mean, best = time_launches(torch, lambda: sc.sell_spmmv_T(Mh, X64, Y64, deterministic=det))
+        mean, best = time_launches(torch, lambda: sc.sell_spmmv_T(Mh, X64, Y64, deterministic=det), reps=4,
+                                   inner=5)
         out["transpose_" + ("deterministic" if det else "atomic")] = {
             "us": round(mean, 2), "GB/s": round(by / (mean * 1e-6) / 1e9, 1)}
     upd, _ = time_launches(torch, lambda: Mh.update_values(newv))
@@ -326,7 +330,7 @@ def other_rows(sc, torch, model, A, Mh, b, s):
     alpha, gamma = 2.0 / s, 0.1
     fl = sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_YY | sc.DOT_XY
     fused, _ = time_launches(torch, lambda: sc.sell_spmmv_aug(Mh, X64, Yf, flags=fl, alpha=alpha, gamma=gamma,
-                                                               beta=-1.0, dot=dotf))
+                                                               beta=-1.0, dot=dotf), reps=10, inner=5)
 
     def unfused():
         sc.sell_spmmv(Mh, X64, T)
@@ -334,7 +338,7 @@ def other_rows(sc, torch, model, A, Mh, b, s):
         torch.linalg.vecdot(Yf, Yf, dim=0)
         torch.linalg.vecdot(X64, Yf, dim=0)
 
-    unf, _ = time_launches(torch, unfused)
+    unf, _ = time_launches(torch, unfused, reps=10, inner=5)
     # the same step one vector at a time, unfused: the paper's KPM comparison (block vectors
     # together with the augmented product against single-vector steps with separate passes)
     x1u = X64[:, :1].contiguous()
@@ -347,7 +351,7 @@ def other_rows(sc, torch, model, A, Mh, b, s):
         torch.linalg.vecdot(y1u, y1u, dim=0)
         torch.linalg.vecdot(x1u, y1u, dim=0)
 
-    unf1, _ = time_launches(torch, unfused_b1)
+    unf1, _ = time_launches(torch, unfused_b1, reps=10, inner=5)
     out["fusion_kpm_step_b8"] = {"fused_us": round(fused, 2), "unfused_us": round(unf, 2),
                                  "speedup": round(unf / fused, 2), "unfused_b1_us": round(unf1, 2),
                                  "block_and_fusion_speedup": round(b * unf1 / fused, 2)}
@@ -475,7 +479,7 @@ def tsm_row(sc, torch, n=1 << 22, m=8, k=8):
             ("tsmm", lambda: sc.sell_tsmm(V, X, W, beta=0.5), n * (m + 2 * k) * 8),
             ("tsmm_inplace", lambda: sc.sell_tsmm_inplace(V, Xs, beta=0.5), 2 * n * m * 8)]
     for name, fn, by in rows:
-        us, _ = time_launches(torch, fn, reps=10)
+        us, _ = time_launches(torch, fn, reps=10, inner=5)
         out[name] = {"us": round(us, 1), "GB/s": round(by / (us * 1e-6) / 1e9, 1)}
     return out
 
@@ -507,7 +511,7 @@ def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
             for b in widths:
                 X = torch.rand((A.ncols, b), dtype=vt, device="cuda")
                 Y = torch.empty((A.nrows, b), dtype=vt, device="cuda")
-                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, X, Y), reps=10)
+                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, X, Y), reps=4, inner=5)
                 bmin = model.bytes_min(A.nnz, A.nrows, A.ncols, b, vb, xs, nchunks=info["nchunks"],
                                        has_perm=sg > 1)
                 bsell = model.bytes_sell(info["stored"], A.nrows, A.ncols, b, vb, xs, nchunks=info["nchunks"],
@@ -522,13 +526,13 @@ def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
                 lay = {"row_major_templated_us": row["b8"]["us"]}
                 Xc = torch.rand((b, A.ncols), dtype=torch.float64, device="cuda").T
                 Yc = torch.empty((b, A.nrows), dtype=torch.float64, device="cuda").T
-                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, Xc, Yc), reps=10)
+                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, Xc, Yc), reps=4, inner=5)
                 lay["col_major_us"] = round(us, 1)
                 lay["col_major_GB/s"] = round(bmin / (us * 1e-6) / 1e9, 1)
                 del Xc, Yc
                 Xp = torch.rand((A.ncols, b + 1), dtype=torch.float64, device="cuda")[:, :b]
                 Yp = torch.empty((A.nrows, b + 1), dtype=torch.float64, device="cuda")[:, :b]
-                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, Xp, Yp), reps=10)
+                us, _ = time_launches(torch, lambda: sc.sell_spmmv(M, Xp, Yp), reps=4, inner=5)
                 lay["row_major_ld9_runtime_width_us"] = round(us, 1)
                 lay["row_major_ld9_runtime_width_GB/s"] = round(bmin / (us * 1e-6) / 1e9, 1)
                 del Xp, Yp
@@ -549,8 +553,7 @@ def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
         for name, cnt in (("half_nnz", A.nnz // 2), ("nnz", A.nnz)):
             ix = idx[:cnt]
             # five back-to-back launches per timed call (a single call's host overhead would count)
-            us, _ = time_launches(torch, lambda: [sc.sell_probe_gather(x, ix, sink) for _ in range(5)], reps=4)
-            us /= 5
+            us, _ = time_launches(torch, lambda: sc.sell_probe_gather(x, ix, sink), reps=4, inner=5)
             probe[f"b{b}_{name}"] = {"gathers": cnt, "us": round(us, 1), "Ggathers/s": round(cnt / us / 1e3, 2)}
         del x
     out["gather_probe_f64"] = probe
