@@ -25,6 +25,13 @@ measures):
                        half of each row's columns in a +-5000 band around the
                        diagonal (reflected at the borders), half uniform;
                        values N(0, 1).
+* ``ring_*``           a matrix given entry by entry by formulas, for sizes past
+                       2^31 stored entries: row i has 30 + i mod 5 entries, entry
+                       j at column (i + offset_j) mod n, with small dyadic values;
+                       block vectors by formula as well. Its columns keep the
+                       offsets' order (unique within a row, not sorted). The
+                       formulas work on numpy arrays and torch tensors alike, so
+                       the same matrix can be made on the host and on a GPU.
 """
 from __future__ import annotations
 
@@ -281,3 +288,97 @@ def random_sparse(nrows: int, ncols: int, density: float, seed: int, int_values:
 def laplacian3d_batch(count: int = 64, lo: int = 20, hi: int = 100, seed: int = SEED_MATRIX):
     """Grid edges for a batch of 3D Laplacians, edge ~ U{lo..hi}, one per matrix."""
     return [int(e) for e in randint(substream(seed, 31), count, lo, hi)]
+
+
+# --------------------------------------------------------------------------------------
+# formula ("ring") matrices: sizes past 2^31 stored entries without random streams
+
+
+RING_MAX_LEN = 34
+
+
+def ring_offsets(n: int) -> np.ndarray:
+    """The 34 column offsets of the ring matrix of order n, distinct modulo n (n >= 2^19):
+    short ones (neighbours, rows of a 64-wide grid), and fractions of n up to n/2 (far gathers)."""
+    near = [1, 2, 3, 5, 64, 65, 4096, 4097]
+    far = [n // 64, n // 64 + 1, n // 16, n // 16 + 3, n // 8, n // 5, n // 3, n // 3 + 7, n // 2 - 1]
+    offs = [0, *[s * o for o in near + far for s in (1, -1)]][:RING_MAX_LEN]
+    out = np.array(offs, dtype=np.int64)
+    if len(out) != RING_MAX_LEN or len(set((out % n).tolist())) != RING_MAX_LEN:
+        raise ValueError(f"ring offsets not distinct modulo n = {n}")
+    return out
+
+
+def ring_length(i):
+    """Entries of row i (numpy array or torch tensor of int64 rows): 30 + i mod 5."""
+    return 30 + i % 5
+
+
+def ring_nnz(n: int) -> int:
+    """Closed form of sum_{i < n} (30 + i mod 5)."""
+    r = n % 5
+    return 30 * n + 10 * (n // 5) + r * (r - 1) // 2
+
+
+def ring_col(i, j, offs, n: int):
+    """Column of entry j of row i: (i + offs[j]) mod n (offs indexable by j: a numpy array for
+    numpy j, a tensor on j's device for torch j)."""
+    return (i + offs[j]) % n
+
+
+def ring_val(i, j, variant: int = 0):
+    """Value of entry j of row i: +-m / 4 with m in 1..7 (exact in BF16, FP32 and FP64).
+    variant 1 gives a second set of values on the same pattern."""
+    a, c = (5, 3) if variant == 0 else (3, 5)
+    mag = (a * i + c * j) % 7 + 1
+    sign = 1 - 2 * ((i + j + variant) % 2)
+    return (mag * sign) * 0.25
+
+
+def ring_x(k, t):
+    """Block-vector entry (row k, column t): q / 8 with q in -8..8."""
+    return ((5 * k + 3 * t) % 17 - 8) * 0.125
+
+
+def ring_y(k, t):
+    """Second block-vector entry (row k, column t): r / 16 with r in -6..6."""
+    return ((3 * k + 7 * t) % 13 - 6) * 0.0625
+
+
+def ring_csr(n: int, variant: int = 0) -> CSR:
+    """The ring matrix of order n on the host (for sizes the host can hold)."""
+    offs = ring_offsets(n)
+    rows = np.arange(n, dtype=np.int64)
+    lens = ring_length(rows)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=rowptr[1:])
+    ie = np.repeat(rows, lens)
+    je = np.arange(int(rowptr[-1]), dtype=np.int64) - np.repeat(rowptr[:-1], lens)
+    return CSR(n, n, rowptr, ring_col(ie, je, offs, n).astype(np.int32), ring_val(ie, je, variant),
+               f"ring_{n}")
+
+
+def ring_csr_torch(n: int, device, variant: int = 0, chunk_rows: int = 1 << 22, values_only: bool = False):
+    """The ring matrix of order n as torch tensors on a device (rowptr int64, col int32, val
+    float64), made in row chunks to bound the temporaries. values_only: val alone (col None)."""
+    import torch
+
+    offs = torch.from_numpy(ring_offsets(n)).to(device)
+    lens = ring_length(torch.arange(n, dtype=torch.int64, device=device))
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(lens, 0, out=rowptr[1:])
+    nnz = int(rowptr[-1])
+    col = None if values_only else torch.empty(nnz, dtype=torch.int32, device=device)
+    val = torch.empty(nnz, dtype=torch.float64, device=device)
+    for r0 in range(0, n, chunk_rows):
+        r1 = min(n, r0 + chunk_rows)
+        rows = torch.arange(r0, r1, dtype=torch.int64, device=device)
+        ln = lens[r0:r1]
+        p0, p1 = int(rowptr[r0]), int(rowptr[r1])
+        ie = torch.repeat_interleave(rows, ln)
+        je = torch.arange(p0, p1, dtype=torch.int64, device=device) - torch.repeat_interleave(rowptr[r0:r1], ln)
+        if col is not None:
+            col[p0:p1] = ring_col(ie, je, offs, n).to(torch.int32)
+        val[p0:p1] = ring_val(ie, je, variant)
+        del ie, je, rows
+    return rowptr, col, val
