@@ -587,9 +587,53 @@ def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
         if el >= target_s or calls >= 200:
             break
     gf = calls * 2 * A.nnz * b / el / 1e9
-    return ({"value": gf, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
-             "sample": f"{calls} augmented products (one KPM step each, b={b}) on the full "
-                       f"{A.name} matrix, {el:.1f} s"}, (X, Y, first))
+    cores = oracle.num_threads()
+    # CSR byte model of one call: each nonzero's value and column once, the row pointers,
+    # x read, y read and written
+    csr_bytes = A.nnz * 12 + 8 * (A.nrows + 1) + 3 * A.nrows * b * 8
+    out = {"value": gf, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{calls} augmented products (one KPM step each, b={b}) on the full "
+                     f"{A.name} matrix, {el:.1f} s",
+           "gbs_csr_model": round(calls * csr_bytes / el / 1e9, 2), "cpu": host_cpu_model()}
+    # the same on one core (a shorter sample), and the host's STREAM triad on all cores
+    oracle.set_num_threads(1)
+    try:
+        c1, t1 = 0, time.perf_counter()
+        while True:
+            oracle.spmmv_aug(A, X, Y=Y, flags=flags, alpha=2.0 / s, beta=-1.0, gamma=0.0)
+            c1 += 1
+            e1 = time.perf_counter() - t1
+            if e1 >= target_s / 4 or c1 >= 50:
+                break
+    finally:
+        oracle.set_num_threads(cores)
+    out["one_core"] = {"value": round(c1 * 2 * A.nnz * b / e1 / 1e9, 3), "unit": "GFLOP/s",
+                       "sample": f"{c1} products, {e1:.1f} s"}
+    out["host_triad_gbs"] = round(host_triad_gbs(oracle), 1)
+    return out, (X, Y, first)
+
+
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_triad_gbs(oracle, n=1 << 27, reps=5):
+    """Best STREAM triad rate (3 x 8 bytes per element, 1 GiB arrays) on the oracle's threads."""
+    a, b, c = np.zeros(n), np.ones(n), np.full(n, 2.0)
+    oracle.triad(a, b, c, 3.0)  # first touch
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.triad(a, b, c, 3.0)
+        best = min(best, time.perf_counter() - t0)
+    return 3 * 8 * n / best / 1e9
 
 
 def parity_row(sc, torch, A, Mh, b, s, ref):

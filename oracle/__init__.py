@@ -45,6 +45,9 @@ def lib():
         L.orc_cg.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, _P]
         L.orc_chebyshev.argtypes = [_I64, _P, _P, _P, _P, _I64, _D, _D, _P, _P]
         L.orc_num_threads.restype = ct.c_int
+        L.orc_set_num_threads.argtypes = [ct.c_int]
+        L.orc_set_num_threads.restype = None
+        L.orc_triad.argtypes = [_I64, _P, _P, _P, _D]
         L.orc_cheb_apply.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P]
         L.orc_cheb_grad.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _D, _D, _P, _P, _P]
         L.orc_pattern_outer.argtypes = [_I64, _P, _P, _I64, _P, _P, _P]
@@ -71,6 +74,18 @@ def _check(rc, what):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's later parallel loops."""
+    lib().orc_set_num_threads(int(n))
+
+
+def triad(a, b, c, s):
+    """STREAM triad a = b + s c in place on float64 arrays (host bandwidth probe)."""
+    assert a.dtype == b.dtype == c.dtype == np.float64 and a.shape == b.shape == c.shape
+    assert a.flags.c_contiguous and b.flags.c_contiguous and c.flags.c_contiguous
+    _check(lib().orc_triad(a.size, _p(a), _p(b), _p(c), float(s)), "triad")
 
 
 def spmmv(A, X):

@@ -25,6 +25,24 @@ int orc_num_threads(void) {
 #endif
 }
 
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Host memory bandwidth probe for reporting beside the baseline (McCalpin's STREAM triad):
+ * a = b + s c over n doubles, in the same static split of the loop as the oracle's products. */
+int orc_triad(int64_t n, double *a, const double *b, const double *c, double s) {
+    if (n < 0 || (n > 0 && (!a || !b || !c))) return -1;
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) a[i] = b[i] + s * c[i];
+    return 0;
+}
+
 /* ---------------------------------------------------------------------------------
  * Sparse matrix times block vector (Sec. 5.1, 5.2): Y = A X, one row at a time, the
  * row's entries summed in stored order starting from +0.

@@ -127,6 +127,13 @@ int orc_tsmm_inplace(int64_t n, int64_t m, double alpha, double *V, const double
 /* Threads the oracle's parallel loops use (OpenMP), for reporting. */
 int orc_num_threads(void);
 
+/* Sets the threads of the oracle's later parallel loops (n >= 1; other values are ignored). */
+void orc_set_num_threads(int n);
+
+/* STREAM triad a = b + s c over n doubles (host bandwidth probe for the baseline's report,
+ * not part of the product). Returns 0, or -1 for a negative n or a missing array. */
+int orc_triad(int64_t n, double *a, const double *b, const double *c, double s);
+
 #ifdef __cplusplus
 }
 #endif

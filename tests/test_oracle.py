@@ -520,3 +520,21 @@ def test_cheb_filter_diagonal_closed_form_and_degenerate_cases(orc):
     e = np.zeros(8)
     e[7] = 1.0
     assert np.abs(orc.cheb_filter(A, X, e, s, c) - orc.cheb_apply(A, X, 7, s, c)).max() <= 1e-14
+
+
+def test_oracle_triad_and_threads(orc):
+    """The host bandwidth probe computes a = b + s c exactly (one rounding per element), and
+    the thread setting takes effect and can be restored."""
+    n = 100_003
+    b = synth.uniform(synth.SEED_X, n, -1.0, 1.0)
+    c = synth.uniform(synth.SEED_Y, n, -1.0, 1.0)
+    a = np.zeros(n)
+    orc.triad(a, b, c, 0.75)
+    assert np.array_equal(a, b + 0.75 * c)  # numpy rounds s*c, then the sum: the same two steps
+    before = orc.num_threads()
+    orc.set_num_threads(1)
+    assert orc.num_threads() == 1
+    orc.set_num_threads(before)
+    assert orc.num_threads() == before
+    orc.set_num_threads(0)  # ignored
+    assert orc.num_threads() == before
