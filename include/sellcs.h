@@ -153,6 +153,8 @@ typedef struct {
     int32_t ntiles;        /* work partitions of one product launch              */
     int32_t has_perm;      /* 0 when the row order is unchanged (sigma = 1)      */
     int64_t matrix_bytes;  /* bytes of all device arrays of the matrix           */
+    int32_t batch;         /* index batch length of the products (5, 7 or 8; see
+                              sell_set_batch)                                     */
 } sell_info_t;
 
 int sell_info(const sell_mat *A, sell_info_t *out);
@@ -387,6 +389,16 @@ int sell_set_waves(sell_mat *A, int32_t waves);
  * Results per row are the same; dots may differ in the last bits. */
 int sell_set_slice(sell_mat *A, int32_t slice);
 
+/* Index batch length of the single-matrix products of widths 1, 2, 4, 8, 16 and 32 (the
+ * run-time-width kernel, the transposed product and batched launches keep 8). A lane loads
+ * the column indices and values of `batch` consecutive entries of its row, then all their x
+ * rows, then sums them; a chunk of L entries (Sec. 5.1: all rows of a chunk are padded to the
+ * chunk's length) takes ceil(L / batch) such rounds, the last one re-reading its final entry
+ * for the slots past L. batch in {5, 7, 8}: rows of 5 or 7 entries (2D and 3D stencils) then
+ * waste no loads. 0 restores the construction's choice, which picks the length from the chunk
+ * lengths (5, 7 or 8) and is reported by sell_info. Results are the same bit for bit. */
+int sell_set_batch(sell_mat *A, int32_t batch);
+
 typedef struct {
     int32_t C;             /* chosen chunk height                                      */
     int64_t sigma;         /* chosen sorting window                                    */
@@ -397,6 +409,7 @@ typedef struct {
     int32_t trials;        /* configurations timed; 0 when answered from the cache     */
     int32_t slice;         /* chosen slice width for the block (0 = whole block)       */
     int32_t waves;         /* chosen grid in waves of resident workgroups (0 = one)    */
+    int32_t batch;         /* chosen index batch length (0 = the construction's choice) */
 } sell_tune_result;
 
 #define SELL_TUNE_NO_CACHE 0x1u /* time the candidates even if the shape class is cached */
@@ -404,8 +417,9 @@ typedef struct {
 /* Times candidate formats of the CSR matrix (same arguments as sell_build) for products
  * with block width b (1..64) on the current device: C in {16, 32, 64} with sigma in
  * {1, 8 C, 256 C}, then columns per lane {1, 2, 4} and workgroups per CU {limit, 1, 2} for the
- * best pair, then grids of 2, 4 or 8 waves (sell_set_waves), then slices of 8, 16 or 32 columns
- * that divide b (the b packing, sell_set_slice);
+ * best pair, then grids of 2, 4 or 8 waves (sell_set_waves), then index batches of 5, 7 and 8
+ * entries (sell_set_batch), then slices of 8, 16 or 32 columns that divide b (the b packing,
+ * sell_set_slice);
  * a candidate replaces the best so far only when more than 3 % faster (the default,
  * C = 32, sigma = 1, is timed first). The trial product is the one a CG iteration issues (fused
  * <x, y>; plain for a rectangular matrix). Results are cached per process for the matrix's

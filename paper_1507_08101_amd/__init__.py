@@ -51,13 +51,13 @@ class sell_info_t(ct.Structure):
                 ("stored", ct.c_int64), ("nchunks", ct.c_int64), ("sigma", ct.c_int64),
                 ("C", ct.c_int32), ("vdtype", ct.c_int32), ("on_device", ct.c_int32),
                 ("device", ct.c_int32), ("ntiles", ct.c_int32), ("has_perm", ct.c_int32),
-                ("matrix_bytes", ct.c_int64)]
+                ("matrix_bytes", ct.c_int64), ("batch", ct.c_int32)]
 
 
 class sell_tune_result(ct.Structure):
     _fields_ = [("C", ct.c_int32), ("sigma", ct.c_int64), ("vpt", ct.c_int32), ("blocks_per_cu", ct.c_int32),
                 ("us", ct.c_double), ("default_us", ct.c_double), ("trials", ct.c_int32), ("slice", ct.c_int32),
-                ("waves", ct.c_int32)]
+                ("waves", ct.c_int32), ("batch", ct.c_int32)]
 
 
 class sell_cg_stats(ct.Structure):
@@ -110,6 +110,7 @@ _SIGNATURES = {
     "sell_set_launch": ([_P, _I32, _I32], _I),
     "sell_set_slice": ([_P, _I32], _I),
     "sell_set_waves": ([_P, _I32], _I),
+    "sell_set_batch": ([_P, _I32], _I),
     "sell_autotune": ([_I64, _I64, _P, _P, _P, _I, _I32, ct.c_uint32, ct.POINTER(sell_tune_result), _P], _I),
     "sell_batch_create": ([_PP, _I32, _PP], _I),
     "sell_batch_destroy": ([_P], _I),
@@ -306,6 +307,11 @@ class SellMatrix:
         """Process wider blocks in launches over column slices of this width (0 = whole block)."""
         _ok(lib().sell_set_slice(self.handle, int(slice_width)), "sell_set_slice")
 
+    def set_batch(self, batch=0):
+        """Index batch length of the products (5, 7 or 8; 0 = the construction's choice)."""
+        _ok(lib().sell_set_batch(self.handle, int(batch)), "sell_set_batch")
+        self.info = sell_info(self.handle)
+
     @classmethod
     def from_device_csr(cls, nrows, ncols, rowptr, col, val, C=32, sigma=1, dtype="f64", stream=None):
         """Build on the GPU from CSR arrays that are device tensors."""
@@ -320,6 +326,7 @@ class SellMatrix:
         M.set_launch(t["vpt"], t["blocks_per_cu"])
         M.set_slice(t["slice"])
         M.set_waves(t["waves"])
+        M.set_batch(t["batch"])
         M.tune = t
         return M
 

@@ -96,6 +96,28 @@ void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
     tiles[ntiles] = int32_t(nch);
 }
 
+// The products issue a chunk's index loads and gathers in batches of U, every batch whole (a
+// partial last batch re-reads its last entry: branches around the loads would split the batch
+// and serialise its latency). Per chunk of length L that is ceil(L / U) rounds of U loads, and
+// a round costs about kRound loads more in latency. kRound = 13 is what the 128^3 Anderson
+// product shows (7 entries per row: batches of 7 take 133.6 us against 140.4 us for 8, a ratio
+// of (8 + 13) / (7 + 13)). Batches of 5 and 7 exist for the 5- and 7-entry rows of 2D and 3D
+// stencils; other lengths keep 8.
+int32_t choose_batch_len(const std::vector<int32_t> &cl) {
+    constexpr double kRound = 13.0;
+    int32_t best = 8;
+    double best_cost = 0.0;
+    for (int32_t u : {8, 7, 5}) {
+        double cost = 0.0;
+        for (int32_t l : cl) cost += double((l + u - 1) / u) * (u + kRound);
+        if (u == 8 || cost < best_cost) {
+            best = u;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
                     const int32_t *col, const double *val, int32_t C, int64_t sigma, int vdt) {
     if (nrows < 0 || ncols < 0 || nrows >= (int64_t(1) << 31) || ncols >= (int64_t(1) << 31))
@@ -218,6 +240,7 @@ int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *ro
     h.rowptr.assign(rowptr, rowptr + nrows + 1);
     const int32_t nt = default_tile_count(nch);
     make_tiles(h.cl, C, nt, h.tiles);
+    h.batch = choose_batch_len(h.cl);
     return SELL_OK;
 }
 

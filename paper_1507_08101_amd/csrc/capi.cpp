@@ -183,6 +183,7 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.vpt_hint = A->vpt_hint;
     a.bpc_hint = A->bpc_hint;
     a.waves_hint = A->waves_hint;
+    a.batch_hint = A->batch_hint > 0 ? A->batch_hint : A->h.batch;
 }
 
 // Split b columns into launches: slices of width `hint` when it divides b (a width chosen for
@@ -400,6 +401,7 @@ int sell_info(const sell_mat *A, sell_info_t *o) {
     o->matrix_bytes = A->on_device ? A->matrix_bytes
                                    : int64_t(A->h.col.size() * 4 + A->h.val.size() + A->h.cl.size() * 4 +
                                              A->h.cs.size() * 8 + A->h.perm.size() * 4);
+    o->batch = A->batch_hint > 0 ? A->batch_hint : A->h.batch;
     return SELL_OK;
 }
 

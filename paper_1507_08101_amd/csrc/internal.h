@@ -54,12 +54,17 @@ struct HostSell {
     raw_vector<uint8_t> val;      // stored values in storage type
     std::vector<int32_t> tiles;   // ntiles + 1 chunk boundaries
     std::vector<int64_t> rowptr;  // CSR row pointers of the input (for export and updates)
+    int32_t batch = 8;            // index batch length suited to the chunk lengths (5, 7 or 8)
 };
 
 // Work partitions: contiguous chunk ranges of roughly equal cost.
 int32_t default_tile_count(int64_t nch);
 void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
                 std::vector<int32_t> &tiles);
+
+// Index batch length (5, 7 or 8) for the product kernels, from the chunk lengths: a chunk of
+// L entries costs ceil(L / U) batch rounds of U loads each plus a fixed cost per round.
+int32_t choose_batch_len(const std::vector<int32_t> &cl);
 
 // Validates CSR input and builds the host SELL arrays. Returns SELL_OK or an error.
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
@@ -100,6 +105,7 @@ struct sell_mat {
     int32_t bpc_hint = 0;
     int32_t slice_hint = 0;         // process wider blocks in slices of this width (0: whole)
     int32_t waves_hint = 0;         // product grid in waves of the resident workgroups (0, 1: one)
+    int32_t batch_hint = 0;         // index batch length set by the caller (5, 7, 8; 0: h.batch)
 };
 
 struct sell_bv {
@@ -132,6 +138,7 @@ struct ProdArgs {
     int32_t vpt_hint;      // columns per lane requested for the matrix (0: default)
     int32_t bpc_hint;      // workgroups per compute unit requested (0: occupancy limit)
     int32_t waves_hint;    // product grid in waves of resident workgroups (0, 1: one wave)
+    int32_t batch_hint;    // index batch length of the single-matrix kernels (5, 7; else 8)
     int32_t runtime_width; // batched launch of mixed widths: 1 = this matrix's rows do not
                            // allow vector accesses, use the run-time-width body
     int64_t nrows;

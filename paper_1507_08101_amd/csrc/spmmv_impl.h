@@ -139,14 +139,14 @@ constexpr int batch_len() {
 // B == 0: run-time width nb <= 64, one column per lane, VL = next power of two >= nb,
 //         any strides.
 // The product over the tiles of workgroup `tile` (one of a.nblocks) of one matrix.
-template <int VK, int B, int VPT, bool AUG>
+template <int VK, int B, int VPT, bool AUG, int UB = 0>
 __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, const int vl_log2) {
     using V = typename KTypes<VK>::V;
     using X = typename KTypes<VK>::X;
     using Acc = typename KTypes<VK>::Acc;
     constexpr bool DYN = (B == 0);
     constexpr bool VEC = !DYN;
-    constexpr int U = batch_len<X, VPT>();
+    constexpr int U = UB > 0 ? UB : batch_len<X, VPT>();
     const int nb = DYN ? a.nb : B;
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
@@ -343,7 +343,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     }
 }
 
-template <int VK, int B, int VPT, bool AUG>
+template <int VK, int B, int VPT, bool AUG, int UB = 0>
 __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
     int vls = vl_log2;
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         vls = 0;
         while ((1 << vls) < a.nb) ++vls;
     }
-    prod_body<VK, B, VPT, AUG>(a, tile, vls);
+    prod_body<VK, B, VPT, AUG, UB>(a, tile, vls);
 }
 
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
@@ -470,18 +470,32 @@ __global__ void __launch_bounds__(kBlock) transpose_kernel(ProdArgs a, int vl_lo
     }
 }
 
-template <int VK, int B, int VPT, bool AUG>
-inline int go_prod(ProdArgs &a, hipStream_t s) {
+template <int VK, int B, int VPT, bool AUG, int UB = 0>
+inline int go_prod_u(ProdArgs &a, hipStream_t s) {
     int vl_log2 = 0;
     if (B == 0) {
         while ((1 << vl_log2) < a.nb) ++vl_log2;
     }
-    auto k = prod_kernel<VK, B, VPT, AUG>;
+    auto k = prod_kernel<VK, B, VPT, AUG, UB>;
     a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles, a.bpc_hint);
     // several waves: workgroups that finish early take the next ones (uneven tiles)
     if (a.waves_hint > 1) a.nblocks = int32_t(std::min<int64_t>(int64_t(a.nblocks) * a.waves_hint, a.ntiles));
     hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
+// The fixed-width kernels of 8-entry index batches come with batches of 5 and 7 as well: a
+// batch is issued whole, so a chunk of L entries costs ceil(L / U) rounds of U loads, and
+// 7- or 5-entry batches waste no loads on rows of 7 or 5 entries (3D and 2D stencils). The
+// matrix's batch_hint (chosen from its chunk lengths, or set by the caller) picks one.
+template <int VK, int B, int VPT, bool AUG>
+inline int go_prod(ProdArgs &a, hipStream_t s) {
+    using X = typename KTypes<VK>::X;
+    if constexpr (B > 0 && batch_len<X, VPT>() == 8) {
+        if (a.batch_hint == 7) return go_prod_u<VK, B, VPT, AUG, 7>(a, s);
+        if (a.batch_hint == 5) return go_prod_u<VK, B, VPT, AUG, 5>(a, s);
+    }
+    return go_prod_u<VK, B, VPT, AUG>(a, s);
 }
 
 template <int VK, int B, int VPT>

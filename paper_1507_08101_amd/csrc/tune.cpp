@@ -67,6 +67,7 @@ struct Trial {
     double us;
     int32_t slice = 0;
     int32_t waves = 0;
+    int32_t batch = 0;
 };
 
 // Average time of one product on A (after warm-up launches).
@@ -114,6 +115,13 @@ int sell_set_waves(sell_mat *A, int32_t waves) {
     if (!A) return SELL_ERR_ARG;
     if (!(waves == 0 || waves == 1 || waves == 2 || waves == 4 || waves == 8 || waves == 16)) return SELL_ERR_ARG;
     A->waves_hint = waves;
+    return SELL_OK;
+}
+
+int sell_set_batch(sell_mat *A, int32_t batch) {
+    if (!A) return SELL_ERR_ARG;
+    if (!(batch == 0 || batch == 5 || batch == 7 || batch == 8)) return SELL_ERR_ARG;
+    A->batch_hint = batch;
     return SELL_OK;
 }
 
@@ -241,21 +249,42 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
                     if (t.us < kMargin * best.us) best = t;
                 }
             }
+            // index batch lengths other than the construction's choice
+            for (int32_t bl : {5, 7, 8}) {
+                if (rc || bl == A->h.batch) continue;
+                A->batch_hint = bl;
+                A->waves_hint = best.waves;
+                Trial t;
+                rc = run(best.C, best.sigma, best.vpt, best.bpc, A, &t);
+                A->batch_hint = 0;
+                A->waves_hint = 0;
+                t.waves = best.waves;
+                t.batch = bl;
+                if (!rc) {
+                    trials.back().waves = best.waves;
+                    trials.back().batch = bl;
+                    if (t.us < kMargin * best.us) best = t;
+                }
+            }
             // stage 3: the block in slices of 8, 16 or 32 columns (the b packing), timed as the
             // whole sliced call with the best launch shape
             for (int32_t sl : {8, 16, 32}) {
                 if (rc || sl >= b || b % sl != 0) continue;
                 A->slice_hint = sl;
                 A->waves_hint = best.waves;
+                A->batch_hint = best.batch;
                 Trial t;
                 rc = run(best.C, best.sigma, best.vpt, best.bpc, A, &t);
                 A->slice_hint = 0;
                 A->waves_hint = 0;
+                A->batch_hint = 0;
                 t.slice = sl;
                 t.waves = best.waves;
+                t.batch = best.batch;
                 if (!rc) {
                     trials.back().slice = sl;
                     trials.back().waves = best.waves;
+                    trials.back().batch = best.batch;
                     if (t.us < kMargin * best.us) best = t;
                 }
             }
@@ -271,6 +300,7 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
     res.blocks_per_cu = best.bpc;
     res.slice = best.slice;
     res.waves = best.waves;
+    res.batch = best.batch;
     res.us = best.us;
     res.default_us = deflt.us;
     res.trials = int32_t(trials.size());

@@ -177,3 +177,29 @@ def test_byte_model_matches_paper_figures():
         assert int(100 * red) == case["reduction_percent"]
     ch = json.load(open(os.path.join(GOLDEN, "chunk_height.json")))
     assert model.min_chunk_height(ch["simd_bytes"], ch["element_bytes"]) == ch["C_min"]
+
+
+@pytest.mark.parametrize("name,make,C,sigma,batch", [
+    ("anderson3d_24", lambda: synth.anderson3d(24), 32, 1, 7),      # 7 entries per row
+    ("laplacian3d_20", lambda: synth.laplacian3d(20), 32, 1, 7),    # 7, 4..6 at the faces
+    ("laplacian2d_64", lambda: synth.laplacian2d(64), 32, 1, 5),    # 5, 3..4 at the edges
+    ("laplacian2d_64_C64", lambda: synth.laplacian2d(64), 64, 4096, 5),
+    ("irregular_20000", lambda: synth.irregular(20000, band=2000, max_len=300, seed=5), 32, 1, 8),
+    ("empty_rows", lambda: synth.CSR(10, 10, np.zeros(11, np.int64), np.zeros(0, np.int32), np.zeros(0), "z"),
+     4, 1, 8),
+])
+def test_batch_length_choice(sc, name, make, C, sigma, batch):
+    """The construction picks the index batch length from the chunk lengths: 7 for 7-entry rows,
+    5 for 5-entry rows, 8 otherwise; sell_set_batch overrides it and 0 restores the choice."""
+    M = _host(sc, make(), C, sigma)
+    assert M.info["batch"] == batch, name
+    for b in (5, 7, 8):
+        M.set_batch(b)
+        assert M.info["batch"] == b
+    M.set_batch(0)
+    assert M.info["batch"] == batch
+    for bad in (-1, 1, 4, 6, 9, 16):
+        with pytest.raises(sc.SellError):
+            M.set_batch(bad)
+    assert M.info["batch"] == batch
+    M.close()

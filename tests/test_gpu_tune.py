@@ -127,12 +127,70 @@ def test_autotune_reports_slice(sc):
     A = synth.irregular(30000, band=3000, max_len=400, seed=69)
     t = sc.sell_autotune(A, 32, "f64", cache=False)
     assert t["slice"] in (0, 8, 16) and t["waves"] in (0, 2, 4, 8) and t["us"] <= t["default_us"]
+    assert t["batch"] in (0, 5, 7, 8)
     M = sc.SellMatrix.from_csr_tuned(A, 32, "f64", cache=True)
-    assert M.tune["slice"] == t["slice"] and M.tune["waves"] == t["waves"]
+    assert M.tune["slice"] == t["slice"] and M.tune["waves"] == t["waves"] and M.tune["batch"] == t["batch"]
+    if t["batch"]:
+        assert M.info["batch"] == t["batch"]
     import torch
 
     X = synth.block_vector(A.ncols, 32, 70)
     Y = torch.zeros((A.nrows, 32), dtype=torch.float64, device="cuda:0")
     sc.sell_spmmv(M, dev(X), Y)
     assert colwise_relerr(host(Y), oracle.spmmv(A, X), abs_product(A, X)) <= 1e-12
+    M.close()
+
+
+def _batch_cases():
+    return [
+        ("random_ragged", lambda: synth.random_sparse(3001, 3001, 0.003, 71, empty_rows=40, long_row=700), 32, 128),
+        ("anderson3d_16", lambda: synth.anderson3d(16), 32, 1),
+        ("laplacian2d_45", lambda: synth.laplacian2d(45), 32, 1),
+    ]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("case", range(3))
+def test_batch_lengths_bit_identical(sc, dt, case):
+    """Index batches of 5, 7 and 8 entries give every output bit for bit (each row is summed
+    in stored order either way) for the fixed widths and columns per lane, and the FP64 result
+    matches the oracle; the augmented product with dots and the chain as well."""
+    import torch
+
+    name, make, C, sigma = _batch_cases()[case]
+    A = make()
+    M = sc.SellMatrix.from_csr(A, C=C, sigma=sigma, dtype=dt)
+    vt = torch.float64 if dt == "f64" else torch.float32
+    for b, vpts in ((1, (1,)), (2, (1, 2)), (4, (4,)), (8, (1, 2, 4)), (16, (4,)), (32, (4,))):
+        X = dev(synth.block_vector(A.ncols, b, 72), vt)
+        for vpt in vpts:
+            M.set_launch(vpt, 0)
+            ref = None
+            for bl in (8, 7, 5, 0):
+                M.set_batch(bl)
+                Y = torch.zeros((A.nrows, b), dtype=vt, device="cuda:0")
+                sc.sell_spmmv(M, X, Y)
+                got = host(Y)
+                if ref is None:
+                    ref = got
+                    if dt == "f64":
+                        Xh = host(X)
+                        assert colwise_relerr(got, oracle.spmmv(A, Xh), abs_product(A, Xh)) <= 1e-12, (name, b)
+                assert np.array_equal(got, ref), (name, dt, b, vpt, bl)
+    M.set_launch(0, 0)
+    b = 8
+    X = dev(synth.block_vector(A.ncols, b, 73), vt)
+    Y0 = dev(synth.block_vector(A.nrows, b, 74), vt)
+    Z0 = dev(synth.block_vector(A.nrows, b, 75), vt)
+    fl = sc.SCALE | sc.AXPBY | sc.DOT_YY | sc.DOT_XY | sc.CHAIN | (sc.SHIFT | sc.DOT_XX if A.nrows == A.ncols else 0)
+    ref = None
+    for bl in (8, 7, 5):
+        M.set_batch(bl)
+        Y, Z = Y0.clone(), Z0.clone()
+        dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+        sc.sell_spmmv_aug(M, X, Y, Z, flags=fl, alpha=0.5, beta=-1.0, gamma=0.25, delta=0.5, eta=2.0, dot=dot)
+        got = (host(Y), host(Z), host(dot))
+        if ref is None:
+            ref = got
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref)), (name, dt, bl)
     M.close()
