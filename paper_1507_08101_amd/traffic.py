@@ -6,7 +6,7 @@ known size (``bench.py --copy-probe-mib N``), whose readings calibrate the count
 counted KiB). The result is written as JSON; ``bench.py`` reports it while the kernel sources
 still have the hash recorded in it.
 
-    python -m paper_1507_08101_amd.traffic --kernel 'prod_kernel<0, 8, 4, true>' \\
+    python -m paper_1507_08101_amd.traffic --kernel 'prod_kernel<0, 8, 4, true, 7>' \\
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-mib 1024 \\
         --steps 200 --algorithmic-bytes B --hash H --out profiles/traffic_....json
 """
