@@ -389,8 +389,10 @@ int sell_set_waves(sell_mat *A, int32_t waves);
  * Results per row are the same; dots may differ in the last bits. */
 int sell_set_slice(sell_mat *A, int32_t slice);
 
-/* Index batch length of the single-matrix products of widths 1, 2, 4, 8, 16 and 32 (the
- * run-time-width kernel, the transposed product and batched launches keep 8). A lane loads
+/* Index batch length of the products of widths 1, 2, 4, 8, 16 and 32. A batched launch
+ * (sell_batch_spmmv_aug, sell_batch_cg) uses the length its matrices share, and 8 when they
+ * differ (the length is taken when the batch is created); the run-time-width kernel, the
+ * packed mixed-width launch and the atomic transposed product keep 8. A lane loads
  * the column indices and values of `batch` consecutive entries of its row, then all their x
  * rows, then sums them; a chunk of L entries (Sec. 5.1: all rows of a chunk are padded to the
  * chunk's length) takes ceil(L / batch) such rounds, the last one re-reading its final entry

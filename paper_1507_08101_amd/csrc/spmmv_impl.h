@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
 // active != null and active[m] == 0 is skipped (its dot partials are zeroed). With the
 // run-time-width kernel (B == 0) and vl_log2 < 0 every matrix gets the lanes per row of its
 // own width (table[m].nb), so matrices of different block widths share the launch.
-template <int VK, int B, int VPT, bool AUG>
+template <int VK, int B, int VPT, bool AUG, int UB = 0>
 __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__restrict__ table,
                                                             const int32_t *__restrict__ blk_start, int K,
                                                             const int32_t *__restrict__ active, int vl_log2) {
@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__re
         vls = 0;
         while ((1 << vls) < a.nb) ++vls;
     }
-    prod_body<VK, B, VPT, AUG>(a, tile, vls);
+    prod_body<VK, B, VPT, AUG, UB>(a, tile, vls);
 }
 
 // A batch whose matrices have block widths of their own, in one launch: every workgroup runs
@@ -537,28 +537,41 @@ int dispatch_prod(ProdArgs &a, hipStream_t s, bool fixed_ok) {
     return go_prod<VK, 0, 1, AUG>(a, s);
 }
 
-template <int VK, int B, int VPT, bool AUG>
-inline const void *bk() {
-    return reinterpret_cast<const void *>(prod_batch_kernel<VK, B, VPT, AUG>);
+template <int VK, int B, int VPT, bool AUG, int UB = 0>
+inline const void *bk_u() {
+    return reinterpret_cast<const void *>(prod_batch_kernel<VK, B, VPT, AUG, UB>);
 }
 
-// The batched kernel for (width, columns per lane); fixed_ok as in dispatch_prod.
+// The batched kernel of index batch length ub (5 or 7 where the width's default is 8, as
+// for the single-matrix kernels; else the default)
+template <int VK, int B, int VPT, bool AUG>
+inline const void *bk(int ub) {
+    using X = typename KTypes<VK>::X;
+    if constexpr (B > 0 && batch_len<X, VPT>() == 8) {
+        if (ub == 7) return bk_u<VK, B, VPT, AUG, 7>();
+        if (ub == 5) return bk_u<VK, B, VPT, AUG, 5>();
+    }
+    return bk_u<VK, B, VPT, AUG>();
+}
+
+// The batched kernel for (width, columns per lane, index batch length); fixed_ok as in
+// dispatch_prod.
 template <int VK, bool AUG>
-const void *batch_kernel_for(int b, int vpt, bool fixed_ok) {
+const void *batch_kernel_for(int b, int vpt, bool fixed_ok, int ub) {
     if (fixed_ok) {
         switch (b) {
-            case 1: return bk<VK, 1, 1, AUG>();
-            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>() : bk<VK, 2, 1, AUG>();
-            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>() : vpt == 2 ? bk<VK, 4, 2, AUG>() : bk<VK, 4, 1, AUG>();
-            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>() : vpt == 2 ? bk<VK, 8, 2, AUG>() : bk<VK, 8, 1, AUG>();
+            case 1: return bk<VK, 1, 1, AUG>(ub);
+            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>(ub) : bk<VK, 2, 1, AUG>(ub);
+            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>(ub) : vpt == 2 ? bk<VK, 4, 2, AUG>(ub) : bk<VK, 4, 1, AUG>(ub);
+            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>(ub) : vpt == 2 ? bk<VK, 8, 2, AUG>(ub) : bk<VK, 8, 1, AUG>(ub);
             case 16:
-                return vpt >= 4 ? bk<VK, 16, 4, AUG>() : vpt == 2 ? bk<VK, 16, 2, AUG>() : bk<VK, 16, 1, AUG>();
+                return vpt >= 4 ? bk<VK, 16, 4, AUG>(ub) : vpt == 2 ? bk<VK, 16, 2, AUG>(ub) : bk<VK, 16, 1, AUG>(ub);
             case 32:
-                return vpt >= 4 ? bk<VK, 32, 4, AUG>() : vpt == 2 ? bk<VK, 32, 2, AUG>() : bk<VK, 32, 1, AUG>();
+                return vpt >= 4 ? bk<VK, 32, 4, AUG>(ub) : vpt == 2 ? bk<VK, 32, 2, AUG>(ub) : bk<VK, 32, 1, AUG>(ub);
             default: break;
         }
     }
-    return bk<VK, 0, 1, AUG>();
+    return bk<VK, 0, 1, AUG>(ub);
 }
 
 template <int VK, bool AUG>

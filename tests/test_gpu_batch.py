@@ -406,3 +406,41 @@ def test_batch_widths_state_and_errors(sc):
     Bt.close()
     for M in Ms:
         M.close()
+
+
+@pytest.mark.parametrize("dt", ["f64", "bf16"])
+def test_batch_index_batch_lengths_bit_identical(sc, dt):
+    """A batched launch takes the index batch length its matrices share (set before the batch
+    is created; 8 when they differ): every length gives the same outputs and dots bit for bit."""
+    import torch
+
+    mats = [synth.laplacian3d(12), synth.laplacian3d(9), synth.anderson3d(10),
+            synth.random_sparse(900, 900, 0.01, 76, empty_rows=9, long_row=300)]
+    vt = torch.float64 if dt == "f64" else torch.float32
+    b = 8
+    Xd = dev(_stack([synth.block_vector(A.ncols, b, 77 + k) for k, A in enumerate(mats)], b), vt)
+    Y0 = _stack([synth.block_vector(A.nrows, b, 78 + k) for k, A in enumerate(mats)], b)
+    fl = sc.SCALE | sc.SHIFT | sc.AXPBY | sc.DOT_YY | sc.DOT_XY | sc.DOT_XX
+    ref = None
+    for lens in ((8, 8, 8, 8), (7, 7, 7, 7), (5, 5, 5, 5), (7, 5, 8, 7), (0, 0, 0, 0)):
+        Ms = [sc.SellMatrix.from_csr(A, C=32, sigma=64, dtype=dt) for A in mats]
+        for M, ln in zip(Ms, lens):
+            M.set_batch(ln)
+        Bt = sc.SellBatch(Ms)
+        Yd = dev(Y0, vt)
+        dot = torch.zeros(3 * b * len(mats), dtype=torch.float64, device="cuda:0")
+        sc.sell_batch_spmmv_aug(Bt, Xd, Yd, flags=fl, alpha=0.5, gamma=0.25, beta=-1.0, dot=dot)
+        got = (host(Yd), host(dot))
+        if ref is None:
+            ref = got
+            # the first matrix alone (single-matrix kernel) gives its rows of the batch
+            n0 = mats[0].nrows
+            Y1 = dev(Y0[:n0], vt)
+            d1 = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+            sc.sell_spmmv_aug(Ms[0], Xd[:mats[0].ncols].contiguous(), Y1, flags=fl, alpha=0.5, gamma=0.25,
+                              beta=-1.0, dot=d1)
+            assert np.array_equal(host(Y1), got[0][:n0])
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), lens
+        Bt.close()
+        for M in Ms:
+            M.close()
