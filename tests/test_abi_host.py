@@ -198,7 +198,7 @@ def test_batch_length_choice(sc, name, make, C, sigma, batch):
         assert M.info["batch"] == b
     M.set_batch(0)
     assert M.info["batch"] == batch
-    for bad in (-1, 1, 4, 6, 9, 16):
+    for bad in (-1, 1, 4, 6, 9, 16, 32):
         with pytest.raises(sc.SellError):
             M.set_batch(bad)
     assert M.info["batch"] == batch
