@@ -155,6 +155,8 @@ typedef struct {
     int64_t matrix_bytes;  /* bytes of all device arrays of the matrix           */
     int32_t batch;         /* index batch length of the products (5, 7 or 8; see
                               sell_set_batch)                                     */
+    int32_t batch_wide;    /* the same for the kernels that gather 32 bytes per
+                              lane (FP64, 4 columns per lane: b >= 4)             */
 } sell_info_t;
 
 int sell_info(const sell_mat *A, sell_info_t *out);
@@ -398,7 +400,10 @@ int sell_set_slice(sell_mat *A, int32_t slice);
  * chunk's length) takes ceil(L / batch) such rounds, the last one re-reading its final entry
  * for the slots past L. batch in {5, 7, 8}: rows of 5 or 7 entries (2D and 3D stencils) then
  * waste no loads. 0 restores the construction's choice, which picks the length from the chunk
- * lengths (5, 7 or 8) and is reported by sell_info. Results are the same bit for bit. */
+ * lengths: 5, 7 or 8, and 5 or 7 for the kernels whose lane gathers 32 bytes per entry (FP64
+ * values and vectors at b >= 4), where 8-entry batches leave two waves per SIMD instead of
+ * three. sell_info reports both (batch, batch_wide); a length set here applies to every
+ * kernel. Results are the same bit for bit. */
 int sell_set_batch(sell_mat *A, int32_t batch);
 
 typedef struct {

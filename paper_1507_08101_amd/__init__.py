@@ -51,7 +51,7 @@ class sell_info_t(ct.Structure):
                 ("stored", ct.c_int64), ("nchunks", ct.c_int64), ("sigma", ct.c_int64),
                 ("C", ct.c_int32), ("vdtype", ct.c_int32), ("on_device", ct.c_int32),
                 ("device", ct.c_int32), ("ntiles", ct.c_int32), ("has_perm", ct.c_int32),
-                ("matrix_bytes", ct.c_int64), ("batch", ct.c_int32)]
+                ("matrix_bytes", ct.c_int64), ("batch", ct.c_int32), ("batch_wide", ct.c_int32)]
 
 
 class sell_tune_result(ct.Structure):

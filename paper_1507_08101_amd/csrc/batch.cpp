@@ -23,9 +23,9 @@
 using namespace sellcs;
 
 namespace sellcs {
-const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok, int ub);
-const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok, int ub);
-const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok, int ub);
+const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw);
+const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw);
+const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw);
 const void *batch_mixed_kernel_f64(bool aug);
 const void *batch_mixed_kernel_f32(bool aug);
 const void *batch_mixed_kernel_bf16(bool aug);
@@ -74,6 +74,7 @@ struct sell_batch {
     int32_t vgrid = 0;
     int32_t vpt_hint = 0, bpc_hint = 0;  // launch parameters shared by all matrices (else 0)
     int32_t batch_len = 8;               // index batch length shared by all matrices (else 8)
+    int32_t batch_len_wide = 8;          // the same for the kernels gathering 32 bytes per lane
     std::map<int32_t, std::vector<int32_t>> blk_cache;  // workgroup offsets per resident grid size
     // block widths of the matrices for packed operands (empty: not set)
     std::vector<int32_t> widths;
@@ -271,10 +272,10 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     if (chain) bv_strides(Z, zrs, zcs);
     bool fixed_ok = fixed_width(b) && vec_ok(X->ptr, xrs, xcs, esize, align) && vec_ok(Y->ptr, yrs, ycs, esize, align);
     if (chain) fixed_ok = fixed_ok && vec_ok(Z->ptr, zrs, zcs, esize, align);
-    const int ub = B->batch_len;
-    const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok, ub)
-                       : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok, ub)
-                                         : batch_kernel_bf16(b, vpt, aug, fixed_ok, ub);
+    const int ub = B->batch_len, ubw = B->batch_len_wide;
+    const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok, ub, ubw)
+                       : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok, ub, ubw)
+                                         : batch_kernel_bf16(b, vpt, aug, fixed_ok, ub, ubw);
     // workgroups per matrix: waves of the resident grid split so that the busiest workgroup
     // has as little work as possible
     const int32_t G0 = product_grid(B, kern);
@@ -491,9 +492,13 @@ int sell_batch_create(sell_mat *const *mats, int32_t count, sell_batch **out) {
         }
         // one kernel serves every matrix of a launch: their common index batch length, else 8
         auto blen = [](const sell_mat *M) { return M->batch_hint > 0 ? M->batch_hint : M->h.batch; };
+        auto blenw = [](const sell_mat *M) { return M->batch_hint > 0 ? M->batch_hint : M->h.batch_wide; };
         B->batch_len = blen(mats[0]);
-        for (int32_t m = 1; m < count; ++m)
+        B->batch_len_wide = blenw(mats[0]);
+        for (int32_t m = 1; m < count; ++m) {
             if (blen(mats[m]) != B->batch_len) B->batch_len = 8;
+            if (blenw(mats[m]) != B->batch_len_wide) B->batch_len_wide = 8;
+        }
         B->cols = B->col_off[size_t(count)];
         B->table_bytes = sizeof(ProdArgs) * size_t(count) + sizeof(int32_t) * (size_t(count) + 1);
     } catch (const std::bad_alloc &) {

@@ -102,15 +102,19 @@ void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
 // a round costs about kRound loads more in latency. kRound = 13 is what the 128^3 Anderson
 // product shows (7 entries per row: batches of 7 take 133.6 us against 140.4 us for 8, a ratio
 // of (8 + 13) / (7 + 13)). Batches of 5 and 7 exist for the 5- and 7-entry rows of 2D and 3D
-// stencils; other lengths keep 8.
-int32_t choose_batch_len(const std::vector<int32_t> &cl) {
+// stencils; other lengths keep 8. The kernels whose lane gathers 32 bytes per entry (FP64
+// values and vectors, 4 columns per lane) hold 180 VGPRs with 8-entry batches, two waves per
+// SIMD, and 162 or 147 with 7 or 5, three waves: there only 7 and 5 compete (the 4 M-row
+// irregular matrix at b = 8, sigma = 1024: 1,435 and 1,335 us against 1,534 us for 8).
+int32_t choose_batch_len(const std::vector<int32_t> &cl, bool wide) {
     constexpr double kRound = 13.0;
-    int32_t best = 8;
+    int32_t best = 0;
     double best_cost = 0.0;
     for (int32_t u : {8, 7, 5}) {
+        if (wide && u == 8) continue;
         double cost = 0.0;
         for (int32_t l : cl) cost += double((l + u - 1) / u) * (u + kRound);
-        if (u == 8 || cost < best_cost) {
+        if (best == 0 || cost < best_cost) {
             best = u;
             best_cost = cost;
         }
@@ -241,6 +245,7 @@ int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *ro
     const int32_t nt = default_tile_count(nch);
     make_tiles(h.cl, C, nt, h.tiles);
     h.batch = choose_batch_len(h.cl);
+    h.batch_wide = choose_batch_len(h.cl, true);
     return SELL_OK;
 }
 

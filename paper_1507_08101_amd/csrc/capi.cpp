@@ -184,6 +184,7 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.bpc_hint = A->bpc_hint;
     a.waves_hint = A->waves_hint;
     a.batch_hint = A->batch_hint > 0 ? A->batch_hint : A->h.batch;
+    a.batch_hint_wide = A->batch_hint > 0 ? A->batch_hint : A->h.batch_wide;
 }
 
 // Split b columns into launches: slices of width `hint` when it divides b (a width chosen for
@@ -402,6 +403,7 @@ int sell_info(const sell_mat *A, sell_info_t *o) {
                                    : int64_t(A->h.col.size() * 4 + A->h.val.size() + A->h.cl.size() * 4 +
                                              A->h.cs.size() * 8 + A->h.perm.size() * 4);
     o->batch = A->batch_hint > 0 ? A->batch_hint : A->h.batch;
+    o->batch_wide = A->batch_hint > 0 ? A->batch_hint : A->h.batch_wide;
     return SELL_OK;
 }
 

@@ -262,6 +262,7 @@ int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *
     h.has_perm = has_perm;
     make_tiles(h.cl, C, default_tile_count(nch), h.tiles);
     h.batch = choose_batch_len(h.cl);
+    h.batch_wide = choose_batch_len(h.cl, true);
     DCHK(lib_malloc(reinterpret_cast<void **>(&M->d_tiles), sizeof(int32_t) * h.tiles.size()));
     DCHK(hipMemcpyAsync(M->d_tiles, h.tiles.data(), sizeof(int32_t) * h.tiles.size(), hipMemcpyHostToDevice, s));
     DCHK(hipStreamSynchronize(s));

@@ -55,6 +55,7 @@ struct HostSell {
     std::vector<int32_t> tiles;   // ntiles + 1 chunk boundaries
     std::vector<int64_t> rowptr;  // CSR row pointers of the input (for export and updates)
     int32_t batch = 8;            // index batch length suited to the chunk lengths (5, 7 or 8)
+    int32_t batch_wide = 7;       // the same for the kernels gathering 32 bytes per lane (5 or 7)
 };
 
 // Work partitions: contiguous chunk ranges of roughly equal cost.
@@ -63,8 +64,10 @@ void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
                 std::vector<int32_t> &tiles);
 
 // Index batch length (5, 7 or 8) for the product kernels, from the chunk lengths: a chunk of
-// L entries costs ceil(L / U) batch rounds of U loads each plus a fixed cost per round.
-int32_t choose_batch_len(const std::vector<int32_t> &cl);
+// L entries costs ceil(L / U) batch rounds of U loads each plus a fixed cost per round. wide:
+// for the kernels whose lane gathers 32 bytes per entry, where 8-entry batches leave room for
+// two waves per SIMD instead of three: 5 or 7 only.
+int32_t choose_batch_len(const std::vector<int32_t> &cl, bool wide = false);
 
 // Validates CSR input and builds the host SELL arrays. Returns SELL_OK or an error.
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
@@ -105,7 +108,8 @@ struct sell_mat {
     int32_t bpc_hint = 0;
     int32_t slice_hint = 0;         // process wider blocks in slices of this width (0: whole)
     int32_t waves_hint = 0;         // product grid in waves of the resident workgroups (0, 1: one)
-    int32_t batch_hint = 0;         // index batch length set by the caller (5, 7, 8; 0: h.batch)
+    int32_t batch_hint = 0;         // index batch length set by the caller (5, 7, 8; 0: h.batch
+                                    // and h.batch_wide)
 };
 
 struct sell_bv {
@@ -138,7 +142,8 @@ struct ProdArgs {
     int32_t vpt_hint;      // columns per lane requested for the matrix (0: default)
     int32_t bpc_hint;      // workgroups per compute unit requested (0: occupancy limit)
     int32_t waves_hint;    // product grid in waves of resident workgroups (0, 1: one wave)
-    int32_t batch_hint;    // index batch length of the single-matrix kernels (5, 7; else 8)
+    int32_t batch_hint;    // index batch length of the kernels (5, 7; else 8)
+    int32_t batch_hint_wide; // the same for the kernels gathering 32 bytes per lane
     int32_t runtime_width; // batched launch of mixed widths: 1 = this matrix's rows do not
                            // allow vector accesses, use the run-time-width body
     int64_t nrows;

@@ -492,8 +492,9 @@ template <int VK, int B, int VPT, bool AUG>
 inline int go_prod(ProdArgs &a, hipStream_t s) {
     using X = typename KTypes<VK>::X;
     if constexpr (B > 0 && batch_len<X, VPT>() == 8) {
-        if (a.batch_hint == 7) return go_prod_u<VK, B, VPT, AUG, 7>(a, s);
-        if (a.batch_hint == 5) return go_prod_u<VK, B, VPT, AUG, 5>(a, s);
+        const int hint = VPT * sizeof(X) >= 32 ? a.batch_hint_wide : a.batch_hint;
+        if (hint == 7) return go_prod_u<VK, B, VPT, AUG, 7>(a, s);
+        if (hint == 5) return go_prod_u<VK, B, VPT, AUG, 5>(a, s);
     }
     return go_prod_u<VK, B, VPT, AUG>(a, s);
 }
@@ -542,12 +543,14 @@ inline const void *bk_u() {
     return reinterpret_cast<const void *>(prod_batch_kernel<VK, B, VPT, AUG, UB>);
 }
 
-// The batched kernel of index batch length ub (5 or 7 where the width's default is 8, as
-// for the single-matrix kernels; else the default)
+// The batched kernel of index batch length ub (ubw for the kernels gathering 32 bytes per
+// lane; 5 or 7 where the width's default is 8, as for the single-matrix kernels; else the
+// default)
 template <int VK, int B, int VPT, bool AUG>
-inline const void *bk(int ub) {
+inline const void *bk(int ub0, int ubw) {
     using X = typename KTypes<VK>::X;
     if constexpr (B > 0 && batch_len<X, VPT>() == 8) {
+        const int ub = VPT * sizeof(X) >= 32 ? ubw : ub0;
         if (ub == 7) return bk_u<VK, B, VPT, AUG, 7>();
         if (ub == 5) return bk_u<VK, B, VPT, AUG, 5>();
     }
@@ -557,21 +560,21 @@ inline const void *bk(int ub) {
 // The batched kernel for (width, columns per lane, index batch length); fixed_ok as in
 // dispatch_prod.
 template <int VK, bool AUG>
-const void *batch_kernel_for(int b, int vpt, bool fixed_ok, int ub) {
+const void *batch_kernel_for(int b, int vpt, bool fixed_ok, int ub, int ubw) {
     if (fixed_ok) {
         switch (b) {
-            case 1: return bk<VK, 1, 1, AUG>(ub);
-            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>(ub) : bk<VK, 2, 1, AUG>(ub);
-            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>(ub) : vpt == 2 ? bk<VK, 4, 2, AUG>(ub) : bk<VK, 4, 1, AUG>(ub);
-            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>(ub) : vpt == 2 ? bk<VK, 8, 2, AUG>(ub) : bk<VK, 8, 1, AUG>(ub);
+            case 1: return bk<VK, 1, 1, AUG>(ub, ubw);
+            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>(ub, ubw) : bk<VK, 2, 1, AUG>(ub, ubw);
+            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 4, 2, AUG>(ub, ubw) : bk<VK, 4, 1, AUG>(ub, ubw);
+            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 8, 2, AUG>(ub, ubw) : bk<VK, 8, 1, AUG>(ub, ubw);
             case 16:
-                return vpt >= 4 ? bk<VK, 16, 4, AUG>(ub) : vpt == 2 ? bk<VK, 16, 2, AUG>(ub) : bk<VK, 16, 1, AUG>(ub);
+                return vpt >= 4 ? bk<VK, 16, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 16, 2, AUG>(ub, ubw) : bk<VK, 16, 1, AUG>(ub, ubw);
             case 32:
-                return vpt >= 4 ? bk<VK, 32, 4, AUG>(ub) : vpt == 2 ? bk<VK, 32, 2, AUG>(ub) : bk<VK, 32, 1, AUG>(ub);
+                return vpt >= 4 ? bk<VK, 32, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 32, 2, AUG>(ub, ubw) : bk<VK, 32, 1, AUG>(ub, ubw);
             default: break;
         }
     }
-    return bk<VK, 0, 1, AUG>(ub);
+    return bk<VK, 0, 1, AUG>(ub, ubw);
 }
 
 template <int VK, bool AUG>

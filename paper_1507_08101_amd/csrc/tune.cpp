@@ -249,9 +249,9 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
                     if (t.us < kMargin * best.us) best = t;
                 }
             }
-            // index batch lengths other than the construction's choice
+            // index batch lengths set for every kernel (against the construction's choice)
             for (int32_t bl : {5, 7, 8}) {
-                if (rc || bl == A->h.batch) continue;
+                if (rc) break;
                 A->batch_hint = bl;
                 A->waves_hint = best.waves;
                 Trial t;

@@ -179,25 +179,26 @@ def test_byte_model_matches_paper_figures():
     assert model.min_chunk_height(ch["simd_bytes"], ch["element_bytes"]) == ch["C_min"]
 
 
-@pytest.mark.parametrize("name,make,C,sigma,batch", [
-    ("anderson3d_24", lambda: synth.anderson3d(24), 32, 1, 7),      # 7 entries per row
-    ("laplacian3d_20", lambda: synth.laplacian3d(20), 32, 1, 7),    # 7, 4..6 at the faces
-    ("laplacian2d_64", lambda: synth.laplacian2d(64), 32, 1, 5),    # 5, 3..4 at the edges
-    ("laplacian2d_64_C64", lambda: synth.laplacian2d(64), 64, 4096, 5),
-    ("irregular_20000", lambda: synth.irregular(20000, band=2000, max_len=300, seed=5), 32, 1, 8),
+@pytest.mark.parametrize("name,make,C,sigma,batch,wide", [
+    ("anderson3d_24", lambda: synth.anderson3d(24), 32, 1, 7, 7),      # 7 entries per row
+    ("laplacian3d_20", lambda: synth.laplacian3d(20), 32, 1, 7, 7),    # 7, 4..6 at the faces
+    ("laplacian2d_64", lambda: synth.laplacian2d(64), 32, 1, 5, 5),    # 5, 3..4 at the edges
+    ("laplacian2d_64_C64", lambda: synth.laplacian2d(64), 64, 4096, 5, 5),
+    ("irregular_20000", lambda: synth.irregular(20000, band=2000, max_len=300, seed=5), 32, 1, 8, 7),
     ("empty_rows", lambda: synth.CSR(10, 10, np.zeros(11, np.int64), np.zeros(0, np.int32), np.zeros(0), "z"),
-     4, 1, 8),
+     4, 1, 8, 7),
 ])
-def test_batch_length_choice(sc, name, make, C, sigma, batch):
+def test_batch_length_choice(sc, name, make, C, sigma, batch, wide):
     """The construction picks the index batch length from the chunk lengths: 7 for 7-entry rows,
-    5 for 5-entry rows, 8 otherwise; sell_set_batch overrides it and 0 restores the choice."""
+    5 for 5-entry rows, 8 otherwise (5 or 7 only for the kernels gathering 32 bytes per lane);
+    sell_set_batch sets one length for every kernel and 0 restores the choice."""
     M = _host(sc, make(), C, sigma)
-    assert M.info["batch"] == batch, name
+    assert (M.info["batch"], M.info["batch_wide"]) == (batch, wide), name
     for b in (5, 7, 8):
         M.set_batch(b)
-        assert M.info["batch"] == b
+        assert M.info["batch"] == b and M.info["batch_wide"] == b
     M.set_batch(0)
-    assert M.info["batch"] == batch
+    assert (M.info["batch"], M.info["batch_wide"]) == (batch, wide)
     for bad in (-1, 1, 4, 6, 9, 16, 32):
         with pytest.raises(sc.SellError):
             M.set_batch(bad)
