@@ -705,6 +705,8 @@ def main():
     s = (6.0 + W_DISORDER / 2) / 0.99  # Gershgorin bound with 1 % margin
     t0 = time.perf_counter()
     Mh = sc.SellMatrix.from_csr(A, C=args.C, sigma=args.sigma, dtype="f64")
+    # index batch length of the timed kernel (FP64 at b >= 4 gathers 32 bytes per lane)
+    kern_batch = Mh.info["batch_wide"] if args.b >= 4 else Mh.info["batch"]
     build_s = time.perf_counter() - t0
     info = Mh.info
     log(f"[bench] SELL-{args.C}-{args.sigma} build+upload {build_s:.2f} s, stored {info['stored']}")
@@ -806,7 +808,8 @@ def main():
         "kpm_dos": head.get("dos"),
         "roofline": {"bound": "hbm", "achieved": round(head["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(frac, 4), "traffic": traffic,
-                     "kernel": f"prod_kernel (FP64 values and vectors, b={args.b}, augmented, fused dots)",
+                     "kernel": f"prod_kernel (FP64 values and vectors, b={args.b}, augmented, fused dots, "
+                               f"{kern_batch}-entry index batches)",
                      "bytes_per_launch": int(head["bytes_per_launch"]),
                      "launch_avg_us": round(head["launch_avg_us"], 2)},
         "cpu_baseline": cpu,
