@@ -104,6 +104,7 @@ __device__ __forceinline__ void load_row(const SELL_GLOBAL X *p, int64_t cs, X (
     }
 }
 
+// Row stores are nontemporal: the product never reads its outputs again in the same launch.
 template <class X, int VPT, bool VEC>
 __device__ __forceinline__ void store_row(SELL_GLOBAL X *p, int64_t cs, const X (&o)[VPT]) {
     constexpr int bytes = VPT * int(sizeof(X));
@@ -112,12 +113,12 @@ __device__ __forceinline__ void store_row(SELL_GLOBAL X *p, int64_t cs, const X 
         for (int q = 0; q < bytes / 16; ++q) {
             u32x4 v;
             __builtin_memcpy(&v, reinterpret_cast<const char *>(o) + 16 * q, 16);
-            reinterpret_cast<SELL_GLOBAL u32x4 *>(p)[q] = v;
+            __builtin_nontemporal_store(v, reinterpret_cast<SELL_GLOBAL u32x4 *>(p) + q);
         }
     } else if constexpr (VEC && bytes == 8) {
         u32x2 v;
         __builtin_memcpy(&v, o, 8);
-        *reinterpret_cast<SELL_GLOBAL u32x2 *>(p) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<SELL_GLOBAL u32x2 *>(p));
     } else {
 #pragma unroll
         for (int t = 0; t < VPT; ++t) p[t * cs] = o[t];
