@@ -19,19 +19,20 @@ from . import build as _build
 
 SHIFT, VSHIFT, SCALE, AXPBY, DOT_YY, DOT_XY, DOT_XX, CHAIN = (1, 2, 4, 8, 16, 32, 64, 128)
 
-_lib = None
+_libs = {}
 _P = ct.c_void_p
 _I64 = ct.c_int64
 _D = ct.c_double
 
 
-def lib():
-    """Load (building on first use if absent) the oracle shared library."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_build.LIB):
+def lib(fma: bool = False):
+    """Load (building on first use if absent) the oracle shared library; fma: the build whose
+    multiply-adds are contracted into FMAs (for the rounding-noise envelope only)."""
+    path = _build.LIB_FMA if fma else _build.LIB
+    if path not in _libs:
+        if not os.path.exists(path):
             _build.build()
-        L = ct.CDLL(_build.LIB)
+        L = ct.CDLL(path)
         L.orc_spmmv.argtypes = [_I64, _P, _P, _P, _I64, _P, _I64, _P, _I64]
         L.orc_spmmv_aug.argtypes = [_I64, _I64, _P, _P, _P, _I64, _P, _I64, _P, _I64, _P, _I64,
                                     ct.c_uint, _D, _D, _D, _P, _D, _D, _P]
@@ -55,8 +56,8 @@ def lib():
         L.orc_tsmttsm.argtypes = [_I64, _I64, _I64, _D, _P, _P, _D, _P, ct.c_int]
         L.orc_tsmm.argtypes = [_I64, _I64, _I64, _D, _P, _P, _D, _P]
         L.orc_tsmm_inplace.argtypes = [_I64, _I64, _D, _P, _P, _D]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _p(a):
@@ -88,14 +89,15 @@ def triad(a, b, c, s):
     _check(lib().orc_triad(a.size, _p(a), _p(b), _p(c), float(s)), "triad")
 
 
-def spmmv(A, X):
-    """Y = A X for a row-major block vector X (ncols x b) or a vector (ncols,)."""
+def spmmv(A, X, fma=False):
+    """Y = A X for a row-major block vector X (ncols x b) or a vector (ncols,); fma: the
+    FMA-contracted build."""
     X = _f64(X)
     vec = X.ndim == 1
     X2 = X.reshape(-1, 1) if vec else X
     b = X2.shape[1]
     Y = np.empty((A.nrows, b))
-    _check(lib().orc_spmmv(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), b, _p(Y), b), "spmmv")
+    _check(lib(fma).orc_spmmv(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), b, _p(X2), b, _p(Y), b), "spmmv")
     return Y[:, 0] if vec else Y
 
 
@@ -180,12 +182,13 @@ def cg(A, bvec, x0=None, tol=1e-10, maxit=100000):
     return x, it.value
 
 
-def chebyshev(A, x, M, s, c=0.0):
-    """Direct KPM moments mu[0..M] = <x, T_m(A~) x> with A~ = (A - cI)/s, and v_M."""
+def chebyshev(A, x, M, s, c=0.0, fma=False):
+    """Direct KPM moments mu[0..M] = <x, T_m(A~) x> with A~ = (A - cI)/s, and v_M; fma: the
+    FMA-contracted build."""
     x = _f64(x)
     mu = np.empty(M + 1)
     v = np.empty(A.nrows)
-    _check(lib().orc_chebyshev(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(x), M, s, c, _p(mu),
+    _check(lib(fma).orc_chebyshev(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(x), M, s, c, _p(mu),
                                _p(v)), "chebyshev")
     return mu, v
 

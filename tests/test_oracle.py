@@ -538,3 +538,19 @@ def test_oracle_triad_and_threads(orc):
     assert orc.num_threads() == before
     orc.set_num_threads(0)  # ignored
     assert orc.num_threads() == before
+
+
+def test_oracle_fma_build_contracts(orc):
+    """The two oracle builds differ exactly where contraction must change the bits: the row
+    [1, a] times [c, x] with a = x = 1 + 2^-30 and c = -(1 + 2^-29). Without FMA, a x rounds to
+    1 + 2^-29 and the sum is 0; with FMA, the sum is the exact 2^-60."""
+    a = 1.0 + 2.0 ** -30
+    A = synth.CSR(1, 2, np.array([0, 2], np.int64), np.array([0, 1], np.int32), np.array([1.0, a]), "fma_pin")
+    X = np.array([-(1.0 + 2.0 ** -29), a])
+    assert orc.spmmv(A, X)[0] == 0.0
+    assert orc.spmmv(A, X, fma=True)[0] == 2.0 ** -60
+    # and on ordinary data both builds agree to rounding
+    B = synth.anderson3d(8)
+    x = synth.block_vector(B.nrows, 1, synth.SEED_X)[:, 0]
+    y0, y1 = orc.spmmv(B, x), orc.spmmv(B, x, fma=True)
+    assert np.max(np.abs(y0 - y1)) <= 1e-14 * np.max(np.abs(y0))
