@@ -273,6 +273,9 @@ class SellMatrix:
     def __init__(self, handle):
         self.handle = handle
         self.info = sell_info(handle)
+        # bumped by every value update: lets a saved computation tell whether the values it
+        # used are still the ones on the device
+        self.values_version = 0
 
     @classmethod
     def from_csr(cls, A, C=32, sigma=1, dtype="f64", stream=None, host_only=False):
@@ -340,6 +343,7 @@ class SellMatrix:
         if not self.info["on_device"]:
             stream = 0  # host-only matrix: no stream involved
         sell_update_values(self.handle, val, stream)
+        self.values_version += 1
 
     def close(self):
         if self.handle:

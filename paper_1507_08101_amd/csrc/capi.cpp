@@ -679,6 +679,12 @@ int ensure_transpose(const sell_mat *A, hipStream_t s) {
     std::vector<int64_t> rp(size_t(h.nrows) + 1);
     std::vector<int32_t> col(static_cast<size_t>(h.nnz));
     std::vector<double> val(static_cast<size_t>(h.nnz));
+    // the export reads the device values with blocking copies on the null stream, which do not
+    // wait for work on a non-blocking stream: a value update still queued on s must land first
+    if (A->on_device) {
+        const hipError_t se = hipStreamSynchronize(s);
+        if (se != hipSuccess) return hip_err(se);
+    }
     int rc = sell_export_csr(A, rp.data(), col.data(), val.data());
     if (rc) return rc;
     // CSR of A^T by a counting sort over columns (rows stay ascending inside each column);

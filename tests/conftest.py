@@ -18,3 +18,14 @@ def orc():
 
     oracle.lib()
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter):
+    gu = sys.modules.get("gpu_util")
+    if gu is None:
+        return
+    st = gu.RELERR_STATS
+    if st["columns"]:
+        terminalreporter.write_line(
+            f"normwise relative error: {st['columns']} columns checked against ||y_ref||, "
+            f"{st['scale_denominator']} of them divided by the cancellation scale (||y_ref|| tiny)")

@@ -74,6 +74,70 @@ def test_transpose_follows_value_updates(sc):
     M.close()
 
 
+def test_first_transpose_after_update_on_side_stream(sc):
+    """A value update queued on a non-blocking side stream, then the first deterministic
+    transposed product on that stream: the copy of A^T it builds must hold the new values."""
+    import torch
+
+    A = synth.random_sparse(2000, 1500, 0.01, 128)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=64)
+    X = synth.block_vector(A.nrows, 3, 129)
+    newv = synth.uniform(130, A.nnz, -2, 2)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        nv = dev(newv)
+        Xd = dev(X)
+        side.synchronize()
+        # a long kernel queued first keeps the stream busy while the update waits behind it
+        big = torch.randn(4096, 4096, dtype=torch.float64, device="cuda:0")
+        for _ in range(4):
+            big = big @ big * 1e-3
+        M.update_values(nv)  # on the current stream: side
+        Y = torch.zeros((A.ncols, 3), dtype=torch.float64, device="cuda:0")
+        sc.sell_spmmv_T(M, Xd, Y, deterministic=True)
+    side.synchronize()
+    A2 = synth.CSR(A.nrows, A.ncols, A.rowptr, A.col, newv)
+    assert _relnorm(host(Y), oracle.spmmv_T(A2, X)) <= 1e-14
+    M.close()
+
+
+@pytest.mark.parametrize("fn", ["spmm", "chebyshev"])
+def test_autograd_two_forwards_one_handle(sc, fn):
+    """Two forwards with different theta on one matrix handle before either backward: each
+    backward must give the gradients of the matrix its own forward used."""
+    import torch
+
+    from paper_1507_08101_amd.autograd import chebyshev, spmm
+
+    A = synth.anderson3d(6)
+    s = (6 + 16.5 / 2) / 0.99
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    X = synth.block_vector(A.nrows, 2, 131)
+    th1 = A.val.copy()
+    th2 = A.val * synth.uniform(132, A.nnz, 0.5, 1.0)
+    run = (lambda t, x: spmm(t, x, M)) if fn == "spmm" else (lambda t, x: chebyshev(t, x, M, 7, s, 0.0, 3))
+    grads = []
+    outs = []
+    for th in (th1, th2):
+        t = torch.tensor(th, device="cuda:0", requires_grad=True)
+        x = torch.tensor(X, device="cuda:0", requires_grad=True)
+        outs.append((t, x, run(t, x)))
+    for t, x, y in reversed(outs):  # backward of the second forward first, then the first
+        (y * y).sum().backward()
+        grads.append((host(t.grad), host(x.grad)))
+    grads.reverse()
+    for (th, (gt, gx)) in zip((th1, th2), grads):
+        Ak = synth.CSR(A.nrows, A.ncols, A.rowptr, A.col, th)
+        if fn == "spmm":
+            Y = oracle.spmmv(Ak, X)
+            rx, rt = oracle.spmmv_T(Ak, 2 * Y), oracle.pattern_outer(Ak, 2 * Y, X)
+        else:
+            Y = oracle.cheb_apply(Ak, X, 7, s, 0.0)
+            rx, rt = oracle.cheb_grad(Ak, X, 7, s, 0.0, 2 * Y)
+        assert _relnorm(gx, rx) <= 1e-12 and _relnorm(gt, rt) <= 1e-12
+    M.close()
+
+
 def _anderson_case(L, b, seed):
     A = synth.anderson3d(L)
     s = (6 + 16.5 / 2) / 0.99

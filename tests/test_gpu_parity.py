@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import abs_product, colwise_relerr, dev, host, to_oracle_flags
+from gpu_util import abs_product, assert_lowprec_product, colwise_relerr, dev, host, to_oracle_flags
 
 pytestmark = pytest.mark.gpu
 
@@ -293,8 +293,11 @@ def test_low_precision_integer_laplacian_bit_exact(sc, dt):
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-@pytest.mark.parametrize("b", [1, 8])
+@pytest.mark.parametrize("b", [1, 2, 3, 4, 8, 16, 32])
 def test_low_precision_error_bound(sc, dt, b):
+    """O7: every block width the single-matrix kernels instantiate (and a generic one, 3), on the
+    irregular matrix with sigma = 1024 and the C = 32 slices, against the exact product of the
+    rounded inputs within the deterministic FP32 bound."""
     import torch
 
     A = MATS["irregular_5000"]
@@ -303,13 +306,7 @@ def test_low_precision_error_bound(sc, dt, b):
     Yd = torch.zeros((A.nrows, b), dtype=torch.float32, device="cuda:0")
     sc.sell_spmmv(M, dev(X32, torch.float32), Yd)
     got = host(Yd)
-    Ar = synth.CSR(A.nrows, A.ncols, A.rowptr, A.col,
-                   oracle.round_f32(A.val) if dt == "f32" else oracle.round_bf16(A.val), "rounded")
-    exact = oracle.spmmv(Ar, X32)  # exact product of the rounded inputs, up to FP64 rounding
-    k = A.row_lengths().reshape(-1, 1) + 1
-    u = 2.0 ** -24
-    gam = k * u / (1 - k * u)
-    assert np.all(np.abs(got - exact) <= gam * abs_product(Ar, X32) + 1e-30)
+    assert_lowprec_product(got, A, X32, dt, what=(dt, b))
     # error against the unrounded FP64 product, reported rather than pinned
     err = colwise_relerr(got, oracle.spmmv(A, X32))
     print(f"{dt} b={b}: rel err vs unrounded FP64 product {err:.2e}")

@@ -6,7 +6,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import abs_product, colwise_relerr, dev, host
+from gpu_util import (abs_product, assert_lowprec_product, colwise_relerr, dev, gamma_bound, host,
+                      rounded_matrix, to_oracle_flags)
 
 pytestmark = pytest.mark.gpu
 
@@ -173,9 +174,11 @@ def test_batch_lengths_bit_identical(sc, dt, case):
                 got = host(Y)
                 if ref is None:
                     ref = got
+                    Xh = host(X)
                     if dt == "f64":
-                        Xh = host(X)
                         assert colwise_relerr(got, oracle.spmmv(A, Xh), abs_product(A, Xh)) <= 1e-12, (name, b)
+                    else:
+                        assert_lowprec_product(got, A, Xh, dt, what=(name, dt, b, vpt))
                 assert np.array_equal(got, ref), (name, dt, b, vpt, bl)
     M.set_launch(0, 0)
     b = 8
@@ -192,5 +195,39 @@ def test_batch_lengths_bit_identical(sc, dt, case):
         got = (host(Y), host(Z), host(dot))
         if ref is None:
             ref = got
+            _check_aug_against_oracle(A, dt, fl, host(X), host(Y0), host(Z0), got)
         assert all(np.array_equal(g, r) for g, r in zip(got, ref)), (name, dt, bl)
     M.close()
+
+
+def _check_aug_against_oracle(A, dt, fl, X, Y0, Z0, got):
+    """The augmented product of the test above (alpha 0.5, beta -1, gamma 0.25, delta 0.5, eta 2)
+    against the oracle: FP64 within the normwise 1e-12; FP32/BF16 values with FP32 vectors
+    against the exact augmented product of the rounded inputs, per element, within
+    gamma_{k+4}(2^-24) (|alpha|(|A~||x| + |gamma||x|) + |beta||y0|) for y (k products, shift,
+    scale and axpby, the alpha of the shift counted once more) and |eta| times that plus
+    gamma_2 (|delta||z0| + |eta||y|) for the chain; the dots are FP64 sums of the stored y."""
+    kw = dict(alpha=0.5, beta=-1.0, gamma=0.25, delta=0.5, eta=2.0)
+    oflags = to_oracle_flags(fl)
+    Ar = rounded_matrix(A, dt)
+    ry, rz, rd = oracle.spmmv_aug(Ar, X, Y=Y0, Z=Z0, flags=oflags, **kw)
+    gy, gz, gd = got
+    shift = 0.25 if oflags & oracle.SHIFT else 0.0
+    scale = 0.5 * (abs_product(Ar, X) + shift * np.abs(X)) + np.abs(Y0)
+    if dt == "f64":
+        assert colwise_relerr(gy, ry, scale) <= 1e-12
+        assert colwise_relerr(gz, rz, 0.5 * np.abs(Z0) + 2.0 * np.abs(ry) + 2.0 * scale) <= 1e-12
+    else:
+        k = A.row_lengths().reshape(-1, 1)
+        by = gamma_bound(k + 4, 2.0 ** -24) * scale
+        assert np.all(np.abs(gy - ry) <= by), float(np.max(np.abs(gy - ry) / by))
+        bz = 2.0 * by + gamma_bound(2, 2.0 ** -24) * (0.5 * np.abs(Z0) + 2.0 * np.abs(gy))
+        assert np.all(np.abs(gz - rz) <= bz), float(np.max(np.abs(gz - rz) / bz))
+    b = X.shape[1]
+    pairs = [(gy, gy), (X[:A.nrows], gy), (X[:A.nrows], X[:A.nrows])]
+    for g, bit in enumerate((oracle.DOT_YY, oracle.DOT_XY, oracle.DOT_XX)):
+        if not oflags & bit:
+            continue
+        u, v = pairs[g]
+        ref = np.array([oracle.dot(u[:, j], v[:, j]) for j in range(b)])
+        assert np.all(np.abs(gd[g * b:(g + 1) * b] - ref) <= 1e-12 * np.sum(np.abs(u * v), axis=0)), g

@@ -105,3 +105,40 @@ def test_stochastic_block_moments_of_the_chain():
     sigma_f = 2 * np.linalg.norm(oracle.jackson(2 * M + 1)) / np.sqrt(n * b)
     assert np.all(np.abs(rho - ref) * w <= 4 * sigma_f), (rho, ref, sigma_f)
     assert np.all(np.abs(rho - ref) * w > 0)  # a real estimate, not the exact moments
+
+
+def test_recurrence_bounds_hold_between_oracle_builds():
+    """The forward-error bounds that judge the GPU's 200-step KPM against the oracle
+    (kpm_bounds) must hold between any two correct FP64 runs: the oracle's no-FMA and FMA builds
+    (v_M within 2 D_M, direct moments within twice the direct bound) and, on the oracle's own
+    vectors, the doubling-identity moments against the direct ones (within the sum of both
+    bounds). The bounds must also be non-trivial: well below the size of the quantities."""
+    from kpm_bounds import moment_bounds, recurrence_bounds
+
+    A = synth.anderson3d(8)
+    s = (6 + 16.5 / 2) / 0.99
+    M = 60
+    x = synth.block_vector(A.nrows, 1, 9)[:, 0]
+    nx = float(np.linalg.norm(x))
+    D = recurrence_bounds(A, nx, 2 * M, s, 0.0)
+    direct, dbl = moment_bounds(D, nx, A.nrows)
+    assert D[2 * M] < 1e-9 * nx and np.all(np.diff(D) >= 0)
+    mu0, v0 = oracle.chebyshev(A, x, M, s, 0.0)
+    mu1, v1 = oracle.chebyshev(A, x, M, s, 0.0, fma=True)
+    assert np.linalg.norm(v1 - v0) <= 2 * D[M]
+    m0, _ = oracle.chebyshev(A, x, 2 * M, s, 0.0)
+    m1, _ = oracle.chebyshev(A, x, 2 * M, s, 0.0, fma=True)
+    assert np.all(np.abs(m1 - m0) <= 2 * direct)
+    vs = [x] + [oracle.chebyshev(A, x, m, s, 0.0)[1] for m in range(1, M + 1)]
+    dbl_mu = np.zeros(2 * M + 1)
+    dbl_mu[0], dbl_mu[1] = x @ x, x @ vs[1]
+    for m in range(1, M + 1):
+        dbl_mu[2 * m] = 2 * (vs[m] @ vs[m]) - dbl_mu[0]
+        if 2 * m + 1 <= 2 * M:
+            dbl_mu[2 * m + 1] = 2 * (vs[m + 1] @ vs[m]) - dbl_mu[1]
+    assert np.all(np.abs(dbl_mu - m0) <= direct + dbl)
+    # a dropped term is caught: the recurrence without the - v_{m-1} is far outside the bound
+    wrong = [x, vs[1]]
+    for m in range(1, M):
+        wrong.append(2 * oracle.spmmv(A, wrong[m].reshape(-1, 1))[:, 0] / s)
+    assert np.linalg.norm(wrong[M] - v0) > 1e3 * D[M]
