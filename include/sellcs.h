@@ -238,6 +238,20 @@ typedef struct {
 int sell_spmmv_aug(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z,
                    const sell_spmv_opts *opts, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): sell_spmmv_aug with the same arguments, kernels and
+ * results, bit for bit, but no allocation. sell_spmmv_aug keeps its dot partials in a workspace
+ * that it allocates on its first call on each stream; this variant keeps them, with the
+ * kernels' lane scratch, in a fixed array of 6,324,224 bytes per device (3 dots x 64 columns x
+ * 4,096 workgroups of FP64 partials, plus 32 KiB), which each device holds until the process
+ * ends. The first call on a device looks up the array's address (hipGetSymbolAddress); later
+ * calls only launch kernels. Every call on a device shares the array: calls that overlap on one
+ * device (other streams, other threads) race on it and must be ordered by the caller. Returns
+ * SELL_ERR_UNSUPPORTED if a launch could need more partials than the array holds (a matrix with
+ * more than 4,096 work tiles; the library never builds one), else the errors of sell_spmmv_aug. */
+int sell_spmmv_aug_noalloc(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z,
+                           const sell_spmv_opts *opts, void *stream);
+
 /* Y = A^T X. X: nrows x b, Y: ncols x b, row-major. deterministic = 0 scatters with
  * floating-point atomics (results may differ in the last bits from run to run);
  * deterministic = 1 runs the forward kernel on a SELL-C-sigma copy of A^T, which the

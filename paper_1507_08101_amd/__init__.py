@@ -91,6 +91,7 @@ _SIGNATURES = {
     "sell_bv_copy": ([_P, _P, _P], _I),
     "sell_spmmv": ([_P, _P, _P, _P], _I),
     "sell_spmmv_aug": ([_P, _P, _P, _P, ct.POINTER(sell_spmv_opts), _P], _I),
+    "sell_spmmv_aug_noalloc": ([_P, _P, _P, _P, ct.POINTER(sell_spmv_opts), _P], _I),
     "sell_spmmv_T": ([_P, _P, _P, _I, _P], _I),
     "sell_kpm": ([_P, _P, _P, _I64, _D, _D, _P, ct.POINTER(_I), _P, _P], _I),
     "sell_cg": ([_P, _P, _P, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
@@ -488,6 +489,18 @@ def sell_spmmv_aug(A, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0.0, gam
     o, keep = make_opts(flags, alpha, beta, gamma, gamma_v, delta, eta, dot)
     _ok(lib().sell_spmmv_aug(_mat(A), x.handle, y.handle, z.handle if z else None, ct.byref(o), _stream(stream)),
         "sell_spmmv_aug")
+    del keep
+
+
+def sell_spmmv_aug_noalloc(A, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=0.0, gamma_v=None, delta=0.0,
+                           eta=1.0, dot=None, stream=None):
+    """sell_spmmv_aug without any device allocation: the dot partials live in the library's
+    fixed per-device array (calls that overlap on one device race on it)."""
+    x, y = _bv(X), _bv(Y)
+    z = _bv(Z) if Z is not None else None
+    o, keep = make_opts(flags, alpha, beta, gamma, gamma_v, delta, eta, dot)
+    _ok(lib().sell_spmmv_aug_noalloc(_mat(A), x.handle, y.handle, z.handle if z else None, ct.byref(o),
+                                     _stream(stream)), "sell_spmmv_aug_noalloc")
     del keep
 
 

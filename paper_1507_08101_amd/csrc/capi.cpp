@@ -217,14 +217,16 @@ int validate_bv(const sell_bv *v) {
 
 // y = alpha (A x - gamma x) + beta y, dots, chain; no argument checks (callers check).
 int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o,
-             bool aug, hipStream_t s, double *partials_out, int32_t *nblocks_out) {
+             bool aug, hipStream_t s, double *partials_out, int32_t *nblocks_out, const Workspace *ws_in) {
     if (nblocks_out) *nblocks_out = 0;
     const int b = X->ncols;
     const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
-    Workspace *ws = nullptr;
-    {
-        int rc = get_workspace(s, &ws);
+    const Workspace *ws = ws_in;
+    if (!ws) {
+        Workspace *w = nullptr;
+        int rc = get_workspace(s, &w);
         if (rc) return rc;
+        ws = w;
     }
     if (A->h.nrows == 0 || A->h.tiles.size() < 2) {
         // empty matrix: y is empty; dots of empty columns are zero
@@ -648,6 +650,18 @@ int sell_spmmv(const sell_mat *A, const sell_bv *X, sell_bv *Y, void *stream) {
 
 int sell_spmmv_aug(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts *opts,
                    void *stream) {
+    sell_spmv_opts o;
+    int rc = check_aug_call(A, X, Y, Z, opts, &o);
+    if (rc) return rc;
+    const bool plain = (o.flags == 0);
+    return aug_impl(A, X, Y, Z, o, !plain, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace sellcs {
+int check_aug_call(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts *opts,
+                   sell_spmv_opts *out) {
     int rc = check_product_operands(A, X, Y);
     if (rc) return rc;
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
@@ -666,13 +680,10 @@ int sell_spmmv_aug(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, 
         if (Z->nrows != Y->nrows || Z->ncols != Y->ncols) return SELL_ERR_SHAPE;
         if (Z->ptr == Y->ptr && A->h.nrows > 0) return SELL_ERR_ARG;
     }
-    const bool plain = (o.flags == 0);
-    return aug_impl(A, X, Y, Z, o, !plain, static_cast<hipStream_t>(stream));
+    *out = o;
+    return SELL_OK;
 }
 
-}  // extern "C"
-
-namespace sellcs {
 int ensure_transpose(const sell_mat *A, hipStream_t s) {
     if (A->transpose) return SELL_OK;
     const HostSell &h = A->h;

@@ -244,8 +244,15 @@ int launch_batch_dot_finish_packed(const double *partials, const int32_t *blk, c
 // a finishing kernel). Else the tile partials of the (single, b <= 64) slice are left in
 // partials_out (3 * b * ntiles doubles) for the caller to reduce, and o.dot is not used.
 // *nblocks_out (may be null) receives the number of partials per quantity (workgroups).
+// ws_in: the reduction partials and lane scratch to use; nullptr takes the stream's workspace
+// (allocated on the first call on a stream).
+struct Workspace;
 int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts &o, bool aug,
-             hipStream_t s, double *partials_out = nullptr, int32_t *nblocks_out = nullptr);
+             hipStream_t s, double *partials_out = nullptr, int32_t *nblocks_out = nullptr,
+             const Workspace *ws_in = nullptr);
+// Checks the operands of sell_spmmv_aug and fills *o from opts (the defaults when null).
+int check_aug_call(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const sell_spmv_opts *opts,
+                   sell_spmv_opts *o);
 // Workgroups of one product launch: as many as the device holds at once (occupancy of the
 // kernel times the compute units), at most the number of fine tiles.
 // blocks_per_cu > 0 lowers the workgroups per compute unit to at most that many.
