@@ -545,6 +545,20 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *B, sell_bv *X
  * by kinds 2 and 4 (may be NULL). Asynchronous. */
 int sell_probe_bandwidth(int kind, void *dst, const void *src, int64_t bytes, void *stream);
 
+/* Streaming probe of a given read:write mix and launch shape, for the achievable-bandwidth
+ * figure against which the products are judged (the roofline reading of Sec. 4.1: a kernel
+ * bound by memory traffic is measured against what the memory sustains for that traffic).
+ * reads R in 0..4 streams of bytes each, laid out one after another in src (R * bytes);
+ * writes W in {0, 1}: with W = 1, dst (bytes) receives element by element the sum of the R
+ * read streams (16-byte float4 elements; R = 0 writes a constant); with W = 0 the sums are
+ * reduced to one 16-byte partial per workgroup in dst (grid * 16 bytes). unroll in {1, 2, 4, 8}:
+ * elements per stream and thread in flight (R * unroll loads); nontemporal != 0 uses
+ * nontemporal loads and stores; grid: workgroups of 256 threads, 1..2^20, grid-stride.
+ * Moves (R + W) * bytes. bytes a positive multiple of 16, buffers 16-byte aligned.
+ * Asynchronous. Errors: SELL_ERR_ARG for any other argument. */
+int sell_probe_stream(int reads, int writes, int unroll, int nontemporal, int grid, void *dst, const void *src,
+                      int64_t bytes, void *stream);
+
 /* Random-gather probe: for i < count, reads row idx[i] of x (nrows rows of row_bytes bytes,
  * row_bytes in {8, 16, 32, 64}; x 8-byte aligned for 8, else 16-byte aligned), 8 gathers in
  * flight per thread. It gives the achievable rate of the scattered row gathers that a product

@@ -97,6 +97,7 @@ _SIGNATURES = {
     "sell_cg": ([_P, _P, _P, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_cg_mixed": ([_P, _P, _P, _P, _D, _I64, _D, _I64, ct.POINTER(sell_cg_stats), _P], _I),
     "sell_probe_bandwidth": ([_I, _P, _P, _I64, _P], _I),
+    "sell_probe_stream": ([_I, _I, _I, _I, _I, _P, _P, _I64, _P], _I),
     "sell_debug_fail_alloc": ([_I64], _I),
     "sell_debug_live_allocs": ([ct.POINTER(_I64)], _I),
     "sell_probe_gather": ([_P, _I64, _I32, _P, _I64, _P, _P], _I),
@@ -696,6 +697,14 @@ def sell_probe_bandwidth(kind, dst, src, nbytes, stream=None):
     _ok(lib().sell_probe_bandwidth(int(kind), ct.c_void_p(dst.data_ptr()),
                                    ct.c_void_p(src.data_ptr()) if src is not None else None, int(nbytes),
                                    _stream(stream)), "sell_probe_bandwidth")
+
+
+def sell_probe_stream(reads, writes, unroll, nontemporal, grid, dst, src, nbytes, stream=None):
+    """Streaming probe: ``reads`` streams of ``nbytes`` each, back to back in ``src``, summed into
+    ``dst`` (``writes`` = 1) or reduced to one partial per workgroup in ``dst`` (``writes`` = 0)."""
+    _ok(lib().sell_probe_stream(int(reads), int(writes), int(unroll), int(nontemporal), int(grid),
+                                ct.c_void_p(dst.data_ptr()), ct.c_void_p(src.data_ptr()) if src is not None else None,
+                                int(nbytes), _stream(stream)), "sell_probe_stream")
 
 
 def sell_probe_gather(x, idx, out, stream=None):

@@ -878,4 +878,15 @@ int sell_probe_bandwidth(int kind, void *dst, const void *src, int64_t bytes, vo
     return launch_probe(kind, dst, src, bytes, static_cast<hipStream_t>(stream));
 }
 
+int sell_probe_stream(int reads, int writes, int unroll, int nontemporal, int grid, void *dst, const void *src,
+                      int64_t bytes, void *stream) {
+    if (reads < 0 || reads > 4 || writes < 0 || writes > 1 || reads + writes < 1) return SELL_ERR_ARG;
+    if (unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8) return SELL_ERR_ARG;
+    if (grid < 1 || grid > (1 << 20) || bytes <= 0 || bytes % 16 != 0 || !dst) return SELL_ERR_ARG;
+    if (reads > 0 && !src) return SELL_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15u) return SELL_ERR_ARG;
+    return launch_probe_stream(reads, writes, unroll, nontemporal, grid, dst, src, bytes,
+                               static_cast<hipStream_t>(stream));
+}
+
 }  // extern "C"

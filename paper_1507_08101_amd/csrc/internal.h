@@ -170,6 +170,8 @@ int launch_fill(void *p, int dt, int64_t nrows, int32_t ncols, int64_t rs, int64
 int launch_copy(const sell_bv *dst, const sell_bv *src, hipStream_t s);
 int launch_update_values(const sell_mat *A, const double *val_dev, hipStream_t s);
 int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s);
+int launch_probe_stream(int reads, int writes, int unroll, int nontemporal, int grid, void *dst, const void *src,
+                        int64_t bytes, hipStream_t s);
 int launch_kpm_moments(const double *dots, int64_t M, int32_t b, double *mu, hipStream_t s);
 // dot[g * dot_b + j] = sum_t partials[(g * nb + j) * nparts + t] for the groups g requested
 // in flags (yy, xy, xx), fixed summation order; batch > 1 handles consecutive partial

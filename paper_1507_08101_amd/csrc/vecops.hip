@@ -349,6 +349,101 @@ __global__ void __launch_bounds__(256) probe_write_plain(f4 *__restrict__ d, int
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = v;
 }
 
+// Streams of R reads and W (0 or 1) writes over 16-byte elements: element i of the write
+// stream is the sum of element i of the R read streams (stream r at src + r n); with W = 0 the
+// sums are reduced to one 16-byte partial per workgroup in sink. U elements per stream and
+// thread in flight per iteration (R U loads), grid-stride over the arrays.
+template <bool NT>
+__device__ __forceinline__ f4 probe_ld(const f4 *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <bool NT>
+__device__ __forceinline__ void probe_st(f4 v, f4 *p) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <int R, int W, int U, bool NT>
+__global__ void __launch_bounds__(256) probe_stream_kernel(f4 *__restrict__ d, const f4 *__restrict__ s, int64_t n,
+                                                           f4 *__restrict__ sink) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const f4 one = {1.f, 2.f, 3.f, 4.f};
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        f4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = R == 0 ? one : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] += probe_ld<NT>(s + r * n + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if constexpr (W == 1) probe_st<NT>(v[u], d + i + u * stride);
+            else acc += v[u];
+        }
+    }
+    for (; i < n; i += stride) {
+        f4 v = R == 0 ? one : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < R; ++r) v += probe_ld<NT>(s + r * n + i);
+        if constexpr (W == 1) probe_st<NT>(v, d + i);
+        else acc += v;
+    }
+    if constexpr (W == 0) {
+        __shared__ f4 part[256];
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (int(threadIdx.x) < h) part[threadIdx.x] += part[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) sink[blockIdx.x] = part[0];
+    }
+}
+
+template <int R, int W, int U>
+void launch_stream_u(bool nt, unsigned g, f4 *d, const f4 *sp, int64_t n, hipStream_t s) {
+    if (nt) hipLaunchKernelGGL((probe_stream_kernel<R, W, U, true>), dim3(g), dim3(256), 0, s, d, sp, n, d);
+    else hipLaunchKernelGGL((probe_stream_kernel<R, W, U, false>), dim3(g), dim3(256), 0, s, d, sp, n, d);
+}
+
+template <int R, int W>
+void launch_stream_rw(int unroll, bool nt, unsigned g, f4 *d, const f4 *sp, int64_t n, hipStream_t s) {
+    switch (unroll) {
+        case 1: launch_stream_u<R, W, 1>(nt, g, d, sp, n, s); break;
+        case 2: launch_stream_u<R, W, 2>(nt, g, d, sp, n, s); break;
+        case 4: launch_stream_u<R, W, 4>(nt, g, d, sp, n, s); break;
+        default: launch_stream_u<R, W, 8>(nt, g, d, sp, n, s); break;
+    }
+}
+
+int launch_probe_stream(int reads, int writes, int unroll, int nontemporal, int grid, void *dst, const void *src,
+                        int64_t bytes, hipStream_t s) {
+    const int64_t n = bytes / 16;
+    f4 *d = static_cast<f4 *>(dst);
+    const f4 *sp = static_cast<const f4 *>(src);
+    const unsigned g = unsigned(grid);
+    const bool nt = nontemporal != 0;
+    const int key = reads * 2 + writes;
+    switch (key) {
+        case 1: launch_stream_rw<0, 1>(unroll, nt, g, d, sp, n, s); break;
+        case 2: launch_stream_rw<1, 0>(unroll, nt, g, d, sp, n, s); break;
+        case 3: launch_stream_rw<1, 1>(unroll, nt, g, d, sp, n, s); break;
+        case 4: launch_stream_rw<2, 0>(unroll, nt, g, d, sp, n, s); break;
+        case 5: launch_stream_rw<2, 1>(unroll, nt, g, d, sp, n, s); break;
+        case 6: launch_stream_rw<3, 0>(unroll, nt, g, d, sp, n, s); break;
+        case 7: launch_stream_rw<3, 1>(unroll, nt, g, d, sp, n, s); break;
+        case 8: launch_stream_rw<4, 0>(unroll, nt, g, d, sp, n, s); break;
+        case 9: launch_stream_rw<4, 1>(unroll, nt, g, d, sp, n, s); break;
+        default: return SELL_ERR_ARG;
+    }
+    return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+}
+
 int launch_probe(int kind, void *dst, const void *src, int64_t bytes, hipStream_t s) {
     const int64_t n = bytes / 16;
     const unsigned g = 256 * 16;
