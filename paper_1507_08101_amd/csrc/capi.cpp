@@ -50,6 +50,16 @@ void free_device(sell_mat *A) {
     lib_free(A->d_rowptr);
     lib_free(A->d_tpos);
     A->d_tpos = nullptr;
+    lib_free(A->d_stage_np);
+    lib_free(A->d_stage_pages);
+    lib_free(A->d_stage_own);
+    lib_free(A->d_lcol);
+    lib_free(A->d_plan_slot);
+    lib_free(A->d_plan_miss);
+    A->d_stage_np = A->d_stage_pages = A->d_stage_own = nullptr;
+    A->d_lcol = nullptr;
+    A->d_plan_slot = nullptr;
+    A->d_plan_miss = nullptr;
     A->d_col = nullptr;
     A->d_val = nullptr;
     A->d_cl = nullptr;
@@ -173,6 +183,7 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.cshift = -1;
     if ((A->h.C & (A->h.C - 1)) == 0) a.cshift = __builtin_ctz(unsigned(A->h.C));
     a.nrows = A->h.nrows;
+    a.ncols_x = A->h.ncols;
     a.alpha = 1.0;
     a.eta = 1.0;
     static const int xcd_map = [] {
@@ -180,6 +191,16 @@ void base_args(ProdArgs &a, const sell_mat *A) {
         return e ? std::atoi(e) : 1;
     }();
     a.xcd_map = xcd_map;
+    a.tile_stride = A->tile_stride_hint;
+    a.stage = 0;  // set by the product call when the stage arrays and plan fit the launch
+    a.st_ntiles = A->stage_ntiles;
+    a.st_chunks = A->stage_chunks;
+    a.unit_chunks = A->tile_stride_hint > 0 ? A->unit_chunks_hint : 0;
+    a.nch = A->h.nch;
+    a.st_np = A->d_stage_np;
+    a.st_pages = A->d_stage_pages;
+    a.st_own = A->d_stage_own;
+    a.lcol = A->d_lcol;
     a.vpt_hint = A->vpt_hint;
     a.bpc_hint = A->bpc_hint;
     a.waves_hint = A->waves_hint;
@@ -221,6 +242,36 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
     if (nblocks_out) *nblocks_out = 0;
     const int b = X->ncols;
     const bool dots = aug && (o.flags & SELL_SPMV_DOTS);
+    // x through LDS: stage tiles of one pass of the kernel (kBlock * columns per lane / b rows)
+    // for the fixed widths whose rows are at least 16 bytes, one workgroup per compute unit and
+    // a precomputed slot plan. A caller that brings its own workspace may not allocate: it runs
+    // staged only when the arrays and the plan already fit the launch.
+    bool staged = false;
+    int32_t st_nblk = 0, st_stride = 0;
+    const int xbytes_row = b * (A->h.vdt == SELL_F64 ? 8 : 4);
+    if (A->stage_hint && A->h.nrows > 0 && (b == 2 || b == 4 || b == 8 || b == 16 || b == 32) && xbytes_row >= 16 &&
+        (partials_out || slices(b, A->slice_hint).size() == 1)) {
+        const int vpt = choose_vpt(vec_kind(A->h.vdt), b, A->vpt_hint);
+        const int32_t chunks = std::max<int32_t>(1, int32_t(kBlock * vpt / b) / A->h.C);
+        const int32_t ns = std::min<int32_t>(kStageMaxPages, kStageBytes / (kStagePage * xbytes_row));
+        int ncu = 0, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        int rc = SELL_OK;
+        if (!A->d_lcol || A->stage_chunks != chunks) rc = ws_in ? SELL_ERR_STATE : ensure_stage(A, chunks, s);
+        if (rc == SELL_OK) {
+            const int64_t units = A->stage_ntiles;
+            st_nblk = int32_t(std::min<int64_t>(ncu, units));
+            st_stride = A->tile_stride_hint;
+            if (st_stride > 0 && (units % st_stride || st_nblk % st_stride)) st_stride = 0;
+            if (!(A->d_plan_slot && A->plan_nblk == st_nblk && A->plan_stride == st_stride && A->plan_ns == ns))
+                rc = ws_in ? SELL_ERR_STATE : ensure_stage_plan(A, st_nblk, st_stride, ns, s);
+        }
+        if (rc == SELL_OK)
+            staged = true;
+        else if (!ws_in)
+            return rc;
+    }
     const Workspace *ws = ws_in;
     if (!ws) {
         Workspace *w = nullptr;
@@ -253,6 +304,13 @@ int aug_impl(const sell_mat *A, const sell_bv *X, sell_bv *Y, sell_bv *Z, const 
         a.X = elem_ptr(X, 0, sl.first);
         a.Y = elem_ptr(Y, 0, sl.first);
         a.scratch = ws->scratch;
+        a.stage = staged ? 1 : 0;
+        if (staged) {
+            a.tile_stride = st_stride;
+            a.st_nblocks = st_nblk;
+            a.st_slot = A->d_plan_slot;
+            a.st_miss = A->d_plan_miss;
+        }
         if (aug && (o.flags & SELL_SPMV_CHAIN)) {
             bv_strides(Z, a.zrs, a.zcs);
             a.Z = elem_ptr(Z, 0, sl.first);

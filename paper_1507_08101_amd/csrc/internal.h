@@ -15,6 +15,12 @@ namespace sellcs {
 constexpr int kMaxSliceCols = 64;   // widest column slice one product launch handles
 constexpr int kMaxTiles = 4096;     // upper bound on work partitions per launch
 constexpr int kBlock = 512;         // threads per block of the product kernels
+// Gathering x through LDS: x rows in pages of kStagePage rows; a tile is staged when it
+// references at most kStageMaxPages pages; the page cache of a workgroup holds kStageBytes.
+constexpr int kStagePageShift = 6;
+constexpr int kStagePage = 1 << kStagePageShift;
+constexpr int kStageMaxPages = 64;
+constexpr int kStageBytes = 144 * 1024;
 
 inline int dtype_bytes(int dt) { return dt == SELL_F64 ? 8 : dt == SELL_F32 ? 4 : 2; }
 
@@ -103,6 +109,21 @@ struct sell_mat {
     int64_t *d_rowptr = nullptr;  // CSR row pointers, built on first device value update
     sell_mat *transpose = nullptr;  // SELL copy of A^T for the deterministic transpose
     int64_t *d_tpos = nullptr;      // position in the SELL arrays of A^T of each CSR entry of A
+    // LDS staging of x (built on first use, stage.hip): per tile the page count (0: not
+    // staged), the sorted page list, the list position of the tile's own first row page (-1:
+    // not all own rows listed); per stored entry the tile-local column index
+    int32_t *d_stage_np = nullptr;
+    int32_t *d_stage_pages = nullptr;
+    int32_t *d_stage_own = nullptr;
+    uint16_t *d_lcol = nullptr;
+    int8_t *d_plan_slot = nullptr;  // staged launch plan: slot of each page of each stage tile,
+    uint64_t *d_plan_miss = nullptr;  // and the pages each tile loads, for (plan_nblk
+    int32_t plan_nblk = -1, plan_stride = -1, plan_ns = -1;  // workgroups, stride, slots)
+    int32_t stage_chunks = 0;       // chunks per stage tile of the arrays above
+    int32_t stage_ntiles = 0;       // number of stage tiles
+    int32_t stage_hint = 0;         // 1: products gather x through LDS where the tile allows
+    int32_t tile_stride_hint = 0;   // > 0: workgroups take every tile_stride-th tile
+    int32_t unit_chunks_hint = 0;   // > 0: with a stride, unstaged units of this many chunks
     int64_t matrix_bytes = 0;
     int32_t vpt_hint = 0;           // launch parameters chosen for this matrix (0: defaults)
     int32_t bpc_hint = 0;
@@ -144,9 +165,22 @@ struct ProdArgs {
     int32_t waves_hint;    // product grid in waves of resident workgroups (0, 1: one wave)
     int32_t batch_hint;    // index batch length of the kernels (5, 7; else 8)
     int32_t batch_hint_wide; // the same for the kernels gathering 32 bytes per lane
+    int32_t tile_stride;   // > 0: workgroup g takes every tile_stride-th tile (stage tile
+                           // when staged) of its column
+    int32_t stage;         // 1: gather x through the LDS page cache (the stage arrays below)
+    int32_t st_ntiles;     // stage tiles: st_chunks consecutive chunks each (the last may be short)
+    int32_t st_chunks;
+    int32_t unit_chunks;   // > 0 (with tile_stride): unstaged work units of this many chunks
+    int64_t nch;           // chunks of the matrix
+    const int32_t *st_np, *st_pages, *st_own;
+    const uint16_t *lcol;
+    const int8_t *st_slot;     // the launch plan (ensure_stage_plan) for st_nblocks workgroups
+    const uint64_t *st_miss;
+    int32_t st_nblocks;
     int32_t runtime_width; // batched launch of mixed widths: 1 = this matrix's rows do not
                            // allow vector accesses, use the run-time-width body
     int64_t nrows;
+    int64_t ncols_x;       // rows of X (columns of the matrix)
     int32_t nb;            // columns in this slice
     const void *X; int64_t xrs, xcs;   // element (i, j) at X[i * xrs + j * xcs]
     void *Y; int64_t yrs, ycs;
@@ -266,6 +300,12 @@ int choose_vpt(int vk, int b, int hint = 0);
 // Lazily built device maps (row -> slot, CSR row pointers) and the SELL copy of A^T.
 int ensure_update_maps(sell_mat *A, hipStream_t s);
 int ensure_transpose(const sell_mat *A, hipStream_t s);
+// Page lists and tile-local column indices for the LDS-staged product (stage.hip), over stage
+// tiles of `chunks` consecutive chunks; rebuilt when a different tile size is asked for.
+int ensure_stage(const sell_mat *A, int32_t chunks, hipStream_t s);
+// The slot plan of a staged launch with nblk workgroups, unit stride (0: contiguous) and ns
+// cache slots (stage.hip); rebuilt when any of them changes.
+int ensure_stage_plan(const sell_mat *A, int32_t nblk, int32_t stride, int32_t ns, hipStream_t s);
 
 // Value-gradient kernels (grad.hip).
 int launch_grad_accum(const sell_mat *A, const void *G, int64_t ldg, const void *X, int64_t ldx, int vec_dt,

@@ -27,6 +27,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -140,7 +141,7 @@ constexpr int batch_len() {
 // B == 0: run-time width nb <= 64, one column per lane, VL = next power of two >= nb,
 //         any strides.
 // The product over the tiles of workgroup `tile` (one of a.nblocks) of one matrix.
-template <int VK, int B, int VPT, bool AUG, int UB = 0>
+template <int VK, int B, int VPT, bool AUG, int UB = 0, bool STG = false>
 __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, const int vl_log2) {
     using V = typename KTypes<VK>::V;
     using X = typename KTypes<VK>::X;
@@ -159,9 +160,44 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     const SELL_GLOBAL int64_t *__restrict__ csp = to_global(a.cs);
     const SELL_GLOBAL int32_t *__restrict__ tiles = to_global(a.tiles);
     const int64_t nrows = a.nrows;
-    const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
-    const int64_t s_begin = int64_t(tiles[t0]) * C;
-    const int64_t s_end = int64_t(tiles[t1]) * C;
+    // The tiles of this workgroup: the contiguous range [t0, t1) as one range of slots (as
+    // single tiles when x is staged), or with a tile stride S the tiles Y + S k, k in [k0, k1),
+    // of column Y = tile % S one after another (on a matrix whose far neighbours lie S tiles
+    // away, such as the next plane of a 3D grid, each tile then gathers much of what the
+    // previous one gathered)
+    // With x staged the work units are the stage tiles (a.st_ntiles of a.st_chunks chunks),
+    // taken one at a time.
+    const int S = a.tile_stride;
+    const int64_t uch = STG ? int64_t(a.st_chunks) : int64_t(a.unit_chunks);  // > 0: chunk-group units
+    const int64_t nunits = uch > 0 ? (a.nch + uch - 1) / uch : int64_t(a.ntiles);
+    int64_t r_first, r_count, r_step, r_len;  // range i: units [r_first + i r_step, + r_len)
+    if (S > 0) {
+        const int64_t Q = nunits / S, nseg = a.nblocks / S, q = tile / S;
+        const int64_t k0 = q * Q / nseg, k1 = (q + 1) * Q / nseg;
+        r_first = (tile % S) + S * k0;
+        r_count = k1 - k0;
+        r_step = S;
+        r_len = 1;
+    } else {
+        const int64_t t0 = int64_t(tile) * nunits / a.nblocks, t1 = int64_t(tile + 1) * nunits / a.nblocks;
+        r_first = t0;
+        r_count = STG ? t1 - t0 : 1;
+        r_step = 1;
+        r_len = STG ? 1 : t1 - t0;
+    }
+    // slots of units [u, u + len)
+    auto unit_slots = [&](int64_t u, int64_t len, int64_t &sb, int64_t &se) {
+        if (uch > 0) {
+            const int64_t nch = a.nch;
+            const int64_t c0 = u * uch, c1 = (u + len) * uch;
+            sb = (c0 < nch ? c0 : nch) * C;
+            se = (c1 < nch ? c1 : nch) * C;
+        } else {
+            sb = int64_t(tiles[u]) * C;
+            se = int64_t(tiles[u + len]) * C;
+        }
+    };
+    int64_t s_begin = 0, s_end = 0;
     const int tid = threadIdx.x;
     const int vg = tid & (VL - 1);
     const int rows_per_pass = kBlock >> vls;
@@ -191,7 +227,45 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
 #pragma unroll
     for (int t = 0; t < VPT; ++t) dyy[t] = dxy[t] = dxx[t] = 0.0;
 
-    if (s_begin >= s_end && !want_dots) return;
+    // ---- LDS page cache of x (STG): NS slots of kStagePage rows of RB bytes. The slot of every
+    // page of every unit and the pages a unit loads come from a plan made for this launch
+    // shape (a.st_slot, a.st_miss). Wave 0 copies the next unit's missing pages into their
+    // slots by asynchronous global-to-LDS loads, and its page -> slot table into the other half
+    // of slot_tab, while the workgroup works on the current unit; the barrier that ends a unit
+    // (after wave 0 has waited for its copies) makes them visible.
+    constexpr int RB = (B > 0 ? B : 1) * int(sizeof(X));
+    constexpr int NS_ = kStageBytes / (kStagePage * RB);
+    constexpr int NS = STG ? (NS_ < kStageMaxPages ? NS_ : kStageMaxPages) : 1;
+    constexpr int PGB = kStagePage * RB;  // bytes per page
+    __shared__ __attribute__((aligned(16))) unsigned char cache[STG ? NS * PGB : 16];
+    __shared__ int32_t slot_tab[STG ? 2 : 1][STG ? kStageMaxPages : 1];  // slot of a unit's i-th page
+    const int lane = tid & 63;
+    // Wave 0: start loading unit ub's missing pages (npb pages listed) and its slot table into
+    // slot_tab[half]. The caller waits for the copies (s_waitcnt) and then synchronises the
+    // workgroup before either is read.
+    auto load_unit = [&](int64_t ub, int npb, int half_) {
+        const SELL_GLOBAL int8_t *sp = to_global(a.st_slot) + ub * kStageMaxPages;
+        const SELL_GLOBAL int32_t *pl = to_global(a.st_pages) + ub * kStageMaxPages;
+        if (lane < npb) slot_tab[half_][lane] = sp[lane];
+        const SELL_GLOBAL unsigned char *xb = reinterpret_cast<const SELL_GLOBAL unsigned char *>(Xp);
+        const int64_t xbytes = a.ncols_x * RB;
+        uint64_t todo = to_global(a.st_miss)[ub];
+        while (todo) {
+            const int k = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int64_t goff = int64_t(pl[k]) * PGB;
+            const int sl = sp[k];
+#pragma unroll
+            for (int q = 0; q < (PGB + 1023) / 1024; ++q) {
+                const int o = q * 1024 + lane * 16;
+                if (o < PGB && goff + o + 16 <= xbytes)
+                    __builtin_amdgcn_global_load_lds(xb + goff + o,
+                                                     (__attribute__((address_space(3))) void *)(cache + sl * PGB + q * 1024),
+                                                     16, 0, 0);
+            }
+        }
+    };
+
     double gam[VPT];
 #pragma unroll
     for (int t = 0; t < VPT; ++t) gam[t] = (a.has_gamma_v && col_ok) ? a.gamma_v[jb + t] : a.gamma_s;
@@ -200,8 +274,8 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     // is clamped into the tile, and without a permutation the row load re-reads the chunk
     // length) and nothing is computed from them until the next pass, so their latency
     // overlaps the current pass.
-    auto load_meta = [&](int64_t ss, int &clv, int64_t &csv, int &pv) {
-        const int64_t sc = ss < s_end ? ss : s_end - 1;
+    auto load_meta = [&](int64_t ss, int64_t se_, int &clv, int64_t &csv, int &pv) {
+        const int64_t sc = ss < se_ ? ss : se_ - 1;
         const int64_t c = cshift >= 0 ? (sc >> cshift) : int64_t(uint32_t(sc) / uint32_t(C));
         const SELL_GLOBAL int32_t *pp = perm ? perm + sc : clp + c;
         clv = clp[c];
@@ -209,20 +283,76 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
         pv = *pp;
     };
 
-    int64_t s = s_begin + (tid >> vls);
+    // The workgroup's passes over all of its units, one after another: the metadata of the next
+    // pass (in this unit or at the start of the next) is loaded one pass ahead.
+    // STG: a unit's pages are resident and listed in slot_tab[half] when its first pass starts;
+    // the first unit is staged here, each next one during the unit before it when both fit.
+    int half = 0;
+    auto unit_np = [&](int64_t u) {
+        const int n = a.st_np[u];
+        return (n > 0 && n <= NS) ? n : 0;
+    };
+    int64_t rr = 0;
+    if (r_count > 0) unit_slots(r_first, r_len, s_begin, s_end);
+    if constexpr (STG) {
+        if (r_count > 0) {
+            const int n0 = unit_np(r_first);
+            if (n0 > 0) {
+                if (tid < 64) {
+                    load_unit(r_first, n0, 0);
+                    __builtin_amdgcn_s_waitcnt(0);
+                }
+                __syncthreads();
+            }
+        }
+    }
+    int64_t pb = s_begin;  // first slot of the current pass
     int cl_n = 0, pv_n = 0;
     int64_t cs_n = 0;
-    if (s_begin < s_end) load_meta(s, cl_n, cs_n, pv_n);
+    if (r_count > 0 && s_begin < s_end) load_meta(pb + (tid >> vls), s_end, cl_n, cs_n, pv_n);
     // Settle the first pass's metadata here, so that at the loop head only the previous
     // pass's stores are outstanding and the metadata loads of the following pass are not
     // held up behind them.
     __builtin_amdgcn_s_waitcnt(0);
-    for (; s < s_end; s += rows_per_pass) {
+    bool staged = false, ahead = false;
+    int own_pos = -1, np_next = 0;
+    int64_t tb = 0, own_p0 = 0;
+    while (rr < r_count) {
+        const int64_t ta = r_first + rr * r_step;
+        if (pb == s_begin) {
+            // first pass of unit ta
+            if constexpr (STG) {
+                const int npa = unit_np(ta);
+                staged = npa > 0;
+                own_pos = staged ? a.st_own[ta] : -1;
+                ahead = false;
+                np_next = 0;
+                if (rr + 1 < r_count) {
+                    tb = ta + r_step;
+                    np_next = unit_np(tb);
+                    // the next unit's pages load during this one when both fit the cache together
+                    ahead = np_next > 0 && npa + np_next <= NS;
+                    if (ahead && tid < 64) load_unit(tb, np_next, half ^ 1);
+                }
+            }
+            // list position of the page of the unit's first row (own rows read x from the cache)
+            own_p0 = s_begin >> kStagePageShift;
+        }
+        // the following pass: in this unit, or the first pass of the next one
+        int64_t nrr = rr, nsb = s_begin, nse = s_end, npb = pb + rows_per_pass;
+        if (npb >= s_end) {
+            nrr = rr + 1;
+            if (nrr < r_count) {
+                unit_slots(r_first + nrr * r_step, r_len, nsb, nse);
+                npb = nsb;
+            }
+        }
+        const int64_t s = pb + (tid >> vls);
         const int64_t c = cshift >= 0 ? (s >> cshift) : int64_t(uint32_t(s) / uint32_t(C));
-        const int len = cl_n;
+        const int len = s < s_end ? cl_n : 0;
         const int64_t base = cs_n + (s - c * C);
-        const int64_t row = s < nrows ? (perm ? int64_t(pv_n) : s) : -1;
-        load_meta(s + rows_per_pass, cl_n, cs_n, pv_n);  // one pass ahead
+        const int64_t row = s < s_end && s < nrows ? (perm ? int64_t(pv_n) : s) : -1;
+        if (nrr < r_count && nsb < nse) load_meta(npb + (tid >> vls), nse, cl_n, cs_n, pv_n);  // one pass ahead
         const bool live = row >= 0 && col_ok;
         // Lanes without an output row (slots past the last row, or unused columns of the
         // generic kernel) read row 0 / column 0 and store into the scratch area, so no load
@@ -235,7 +365,13 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
 #pragma unroll
         for (int t = 0; t < VPT; ++t) xin[t] = yin[t] = zin[t] = X(0);
         if (AUG) {
-            if (need_x) load_row<X, VPT, VEC>(Xp + rowc * xrs + int64_t(jl) * xcs, xcs, xin);
+            if (STG && staged && own_pos >= 0 && need_x) {
+                const int pos = own_pos + int((rowc >> kStagePageShift) - own_p0);
+                const int sl = live ? slot_tab[half][pos] : slot_tab[half][own_pos];
+                const X *src = reinterpret_cast<const X *>(cache + ((sl << kStagePageShift) | int(rowc & (kStagePage - 1))) * RB) + jb;
+#pragma unroll
+                for (int t = 0; t < VPT; ++t) xin[t] = src[t];
+            } else if (need_x) load_row<X, VPT, VEC>(Xp + rowc * xrs + int64_t(jl) * xcs, xcs, xin);
             if (read_y) load_row<X, VPT, VEC>(Yp + rowc * yrs + int64_t(jl) * ycs, ycs, yin);
             if (read_z) load_row<X, VPT, VEC>(Zp + rowc * zrs + int64_t(jl) * zcs, zcs, zin);
         }
@@ -247,21 +383,45 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
             for (int k0 = 0; k0 < len; k0 += U) {
                 int ci[U];
                 V vv[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    // clamp to the row's last entry so every load is in bounds and unconditional
-                    const int k = min(k0 + u, len - 1);
-                    const int64_t at = base + int64_t(k) * C;
-                    const int cc = __builtin_nontemporal_load(col + at);
-                    const V v = __builtin_nontemporal_load(val + at);
-                    ci[u] = (k0 + u < len) ? cc : -1;
-                    vv[u] = v;
-                }
                 X xg[U][VPT];
+                if (STG && staged) {
+                    // tile-local indices (page position, row in page), gathered from the cache
+                    const SELL_GLOBAL uint16_t *__restrict__ lcol = to_global(a.lcol);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int cu = ci[u] >= 0 ? ci[u] : 0;  // padding / tail: harmless in-bounds gather
-                    load_row<X, VPT, VEC>(Xp + int64_t(cu) * xrs + int64_t(jb) * xcs, xcs, xg[u]);
+                    for (int u = 0; u < U; ++u) {
+                        const int k = min(k0 + u, len - 1);
+                        const int64_t at = base + int64_t(k) * C;
+                        const int lc = __builtin_nontemporal_load(lcol + at);
+                        const V v = __builtin_nontemporal_load(val + at);
+                        ci[u] = (k0 + u < len && lc != 0xFFFF) ? lc : -1;
+                        vv[u] = v;
+                    }
+                    int sl[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) sl[u] = slot_tab[half][(ci[u] >= 0 ? ci[u] : 0) >> kStagePageShift];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int lr = (sl[u] << kStagePageShift) | ((ci[u] >= 0 ? ci[u] : 0) & (kStagePage - 1));
+                        const X *src = reinterpret_cast<const X *>(cache + lr * RB) + jb;
+#pragma unroll
+                        for (int t = 0; t < VPT; ++t) xg[u][t] = src[t];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        // clamp to the row's last entry so every load is in bounds and unconditional
+                        const int k = min(k0 + u, len - 1);
+                        const int64_t at = base + int64_t(k) * C;
+                        const int cc = __builtin_nontemporal_load(col + at);
+                        const V v = __builtin_nontemporal_load(val + at);
+                        ci[u] = (k0 + u < len) ? cc : -1;
+                        vv[u] = v;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int cu = ci[u] >= 0 ? ci[u] : 0;  // padding / tail: harmless in-bounds gather
+                        load_row<X, VPT, VEC>(Xp + int64_t(cu) * xrs + int64_t(jb) * xcs, xcs, xg[u]);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -309,13 +469,37 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
                 store_row<X, VPT, VEC>(zdst, live ? zcs : 1, zout);
             }
         }
-    }
+        if (nrr != rr) {
+            // last pass of unit ta
+            if constexpr (STG) {
+                if (ahead) {
+                    // wave 0's copies of the next unit's pages must land before anyone reads them
+                    if (tid < 64) __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    half ^= 1;
+                } else if (np_next > 0) {
+                    // the next unit's pages did not fit beside this unit's: load them now
+                    __syncthreads();
+                    if (tid < 64) {
+                        load_unit(tb, np_next, half ^ 1);
+                        __builtin_amdgcn_s_waitcnt(0);
+                    }
+                    __syncthreads();
+                    half ^= 1;
+                }
+            }
+            s_begin = nsb;
+            s_end = nse;
+        }
+        rr = nrr;
+        pb = npb;
+    }  // passes
 
     if (!want_dots) return;
 
     // ---- dot partials of this tile (deterministic: butterfly in the wave, waves in order)
     __shared__ double red[kBlock / 64][3 * kMaxSliceCols];
-    const int lane = tid & 63, w = tid >> 6;
+    const int w = tid >> 6;
 #pragma unroll
     for (int t = 0; t < VPT; ++t) {
         for (int m = 32; m >= VL; m >>= 1) {
@@ -344,7 +528,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     }
 }
 
-template <int VK, int B, int VPT, bool AUG, int UB = 0>
+template <int VK, int B, int VPT, bool AUG, int UB = 0, bool STG = false>
 __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
     int vls = vl_log2;
@@ -352,7 +536,7 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         vls = 0;
         while ((1 << vls) < a.nb) ++vls;
     }
-    prod_body<VK, B, VPT, AUG, UB>(a, tile, vls);
+    prod_body<VK, B, VPT, AUG, UB, STG>(a, tile, vls);
 }
 
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
@@ -477,10 +661,28 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
     if (B == 0) {
         while ((1 << vl_log2) < a.nb) ++vl_log2;
     }
-    auto k = prod_kernel<VK, B, VPT, AUG, UB>;
+    using X = typename KTypes<VK>::X;
+    // x through the LDS page cache: fixed widths over contiguous, 16-byte aligned rows
+    if (a.stage && !(B > 0 && B * sizeof(X) >= 16 && a.xrs == B && a.xcs == 1 && a.lcol && a.st_slot &&
+                     (reinterpret_cast<uintptr_t>(a.X) & 15u) == 0))
+        a.stage = 0;
+    auto k = a.stage ? prod_kernel<VK, B, VPT, AUG, UB, (B > 0)> : prod_kernel<VK, B, VPT, AUG, UB>;
+    if (a.stage) {
+        a.nblocks = a.st_nblocks;  // the launch the plan was made for (stride checked there)
+        hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
+        return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
+    }
     a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles, a.bpc_hint);
     // several waves: workgroups that finish early take the next ones (uneven tiles)
     if (a.waves_hint > 1) a.nblocks = int32_t(std::min<int64_t>(int64_t(a.nblocks) * a.waves_hint, a.ntiles));
+    // a tile stride needs whole columns of tiles and of workgroups
+    {
+        const int64_t units = a.stage ? int64_t(a.st_ntiles)
+                                      : a.unit_chunks > 0 ? (a.nch + a.unit_chunks - 1) / a.unit_chunks
+                                                          : int64_t(a.ntiles);
+        if (a.tile_stride > 0 && (units % a.tile_stride || a.nblocks % a.tile_stride || a.nblocks > units))
+            a.tile_stride = 0;
+    }
     hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }
