@@ -618,12 +618,28 @@ def cpu_baseline(oracle, synth, A, b, s, target_s=15.0):
             break
     gf = calls * 2 * A.nnz * b / el / 1e9
     cores = oracle.num_threads()
+    # the oracle's plain product alone (its parallel part), to state how much of the augmented
+    # call is the serial epilogue (shift, scale, axpby, Neumaier dots) and the wrapper's copy of y
+    cp, tp = 0, time.perf_counter()
+    while True:
+        oracle.spmmv(A, X)
+        cp += 1
+        ep = time.perf_counter() - tp
+        if ep >= target_s / 3 or cp >= 100:
+            break
     # CSR byte model of one call: each nonzero's value and column once, the row pointers,
     # x read, y read and written
     csr_bytes = A.nnz * 12 + 8 * (A.nrows + 1) + 3 * A.nrows * b * 8
+    t_aug, t_plain = el / calls, ep / cp
     out = {"value": gf, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
            "sample": f"{calls} augmented products (one KPM step each, b={b}) on the full "
                      f"{A.name} matrix, {el:.1f} s",
+           "what": "the oracle as it stands, not tuned: an OpenMP CSR product followed by a serial "
+                   "epilogue (shift, scale, axpby, Neumaier-compensated dots) and a copy of y in its "
+                   "Python wrapper; a large GPU/CPU ratio says nothing about the kernel",
+           "plain_product": {"value": round(cp * 2 * A.nnz * b / ep / 1e9, 3), "unit": "GFLOP/s",
+                             "sample": f"{cp} plain products (oracle.spmmv, same threads), {ep:.1f} s"},
+           "serial_share": round(max(0.0, (t_aug - t_plain) / t_aug), 3),
            "gbs_csr_model": round(calls * csr_bytes / el / 1e9, 2), "cpu": host_cpu_model()}
     # the same on one core (a shorter sample), and the host's STREAM triad on all cores
     oracle.set_num_threads(1)

@@ -512,8 +512,9 @@ def sell_spmmv_aug_noalloc(A, X, Y, Z=None, flags=0, alpha=1.0, beta=0.0, gamma=
     del keep
 
 
-def sell_spmmv_T(A, X, Y, deterministic=False, stream=None):
-    """Y = A^T X."""
+def sell_spmmv_T(A, X, Y, deterministic=True, stream=None):
+    """Y = A^T X. deterministic (the default): the forward kernel on a SELL copy of A^T, built
+    by the first such call; False: scatter with floating-point atomics (no copy, slower)."""
     x, y = _bv(X), _bv(Y)
     _ok(lib().sell_spmmv_T(_mat(A), x.handle, y.handle, 1 if deterministic else 0, _stream(stream)),
         "sell_spmmv_T")

@@ -15,9 +15,12 @@
 //     VL lanes with contiguous addresses. Consecutive row slots of a chunk go to
 //     consecutive lane groups, so the column-major chunk entries (value and index of
 //     entry k of consecutive rows are adjacent) stream coalesced.
-//   * The chunk loop is unrolled by 4 with all index/value loads issued before the
-//     gathers, to keep enough loads in flight for HBM. Padding entries (column -1) are
-//     skipped: no gather, no arithmetic.
+//   * The chunk loop takes batches of U entries (8, or 7 and 5 for rows of that length),
+//     issuing all index/value loads of a batch before its gathers, to keep enough loads in
+//     flight for HBM. Padding entries (column -1) are skipped: no gather, no arithmetic.
+//   * Optionally (STG) x is gathered from a cache of x pages in LDS, filled by asynchronous
+//     global-to-LDS copies of the next work unit's pages during the current one, with
+//     16-bit unit-local column indices (stage.hip builds them and the slot plan).
 //   * Dots are reduced without floating-point atomics: butterfly shuffles inside the
 //     wave, LDS across the waves of the workgroup, one partial per tile written with a
 //     plain store; a separate small kernel (or the caller's next kernel) sums the partials
@@ -128,13 +131,10 @@ __device__ __forceinline__ void store_row(SELL_GLOBAL X *p, int64_t cs, const X 
 
 // Entries gathered per batch: all index/value loads of a batch are issued before its
 // gathers, and all gathers before the FMAs, so a row of up to U entries costs one round of
-// index loads and one round of gathers. The gathered values take U * VPT * sizeof(X) / 4
-// VGPRs (up to 64); an 8-wave workgroup still runs one per CU below 256 VGPRs.
-template <class X, int VPT>
-constexpr int batch_len() {
-    constexpr int regs = VPT * int(sizeof(X)) / 4;  // VGPRs per gathered row piece
-    return regs <= 8 ? 8 : 4;
-}
+// index loads and one round of gathers. The default is 8; the fixed-width kernels also come
+// with 7 and 5 (rows of 7 and 5 entries). The gathered values take U * VPT * sizeof(X) / 4
+// VGPRs (at most 64 with 4 FP64 columns per lane).
+constexpr int kBatchDefault = 8;
 
 // B > 0: compile-time slice width with VPT columns per lane (VL = B / VPT lanes per row);
 //        the block vectors are row-major with rows aligned for vector accesses (VEC).
@@ -148,7 +148,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     using Acc = typename KTypes<VK>::Acc;
     constexpr bool DYN = (B == 0);
     constexpr bool VEC = !DYN;
-    constexpr int U = UB > 0 ? UB : batch_len<X, VPT>();
+    constexpr int U = UB > 0 ? UB : kBatchDefault;
     const int nb = DYN ? a.nb : B;
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
@@ -694,7 +694,7 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
 template <int VK, int B, int VPT, bool AUG>
 inline int go_prod(ProdArgs &a, hipStream_t s) {
     using X = typename KTypes<VK>::X;
-    if constexpr (B > 0 && batch_len<X, VPT>() == 8) {
+    if constexpr (B > 0) {
         const int hint = VPT * sizeof(X) >= 32 ? a.batch_hint_wide : a.batch_hint;
         if (hint == 7) return go_prod_u<VK, B, VPT, AUG, 7>(a, s);
         if (hint == 5) return go_prod_u<VK, B, VPT, AUG, 5>(a, s);
@@ -752,7 +752,7 @@ inline const void *bk_u() {
 template <int VK, int B, int VPT, bool AUG>
 inline const void *bk(int ub0, int ubw) {
     using X = typename KTypes<VK>::X;
-    if constexpr (B > 0 && batch_len<X, VPT>() == 8) {
+    if constexpr (B > 0) {
         const int ub = VPT * sizeof(X) >= 32 ? ubw : ub0;
         if (ub == 7) return bk_u<VK, B, VPT, AUG, 7>();
         if (ub == 5) return bk_u<VK, B, VPT, AUG, 5>();
