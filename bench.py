@@ -165,6 +165,33 @@ def cg_compare(sc, torch, synth, edge, nrhs=8, tol=1e-10):
     return out
 
 
+def cg_reference_row(sc, torch, synth, oracle, edge=50, tol=1e-10):
+    """Iteration counts of the GPU's CG drivers beside the oracle's on one right-hand side of a
+    3D Laplacian: FP64 CG, and the textbook refinement around a float inner CG on BF16 values
+    that restarts at every refinement after a 1e-4 reduction (the GPU's mixed driver instead
+    keeps its search direction across reliable updates)."""
+    A = synth.laplacian3d(edge)
+    b = synth.block_vector(A.nrows, 1, synth.SEED_Y)
+    out = {"matrix": f"3D 7-point Dirichlet Laplacian {edge}^3", "n": A.nrows, "nrhs": 1}
+    t0 = time.perf_counter()
+    _, it64 = oracle.cg(A, b[:, 0], tol=tol)
+    _, outer, inner, rr = oracle.cg_refine(A, b[:, 0], val_low=oracle.round_bf16(A.val), tol=tol, inner_rtol=1e-4)
+    out["oracle"] = {"fp64_cg_iterations": it64, "refine_bf16_outer": outer, "refine_bf16_inner_total": inner,
+                     "refine_relres": rr, "inner_rtol": 1e-4, "seconds": round(time.perf_counter() - t0, 2)}
+    A64 = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype="f64")
+    Alo = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype="bf16")
+    Bd = torch.from_numpy(b).cuda()
+    Xd = torch.zeros_like(Bd)
+    st64 = sc.sell_cg(A64, Bd, Xd, tol=tol)
+    Xd = torch.zeros_like(Bd)
+    stm = sc.sell_cg_mixed(A64, Alo, Bd, Xd, tol=tol)
+    out["gpu"] = {"fp64_cg_iterations": st64["iterations"], "mixed_bf16_iterations": stm["iterations"],
+                  "mixed_bf16_refinements": stm["refinements"], "mixed_relres": stm["relres"]}
+    A64.close()
+    Alo.close()
+    return out
+
+
 def batch_row(sc, torch, synth, model, nmat=64, b=8, tol=1e-10):
     """Batched workload: nmat 3D Laplacians with edges ~ U{20..100}, b right-hand sides each.
     Formats and launch shapes from the autotuner; one batched product launch (FP64) against
@@ -839,6 +866,11 @@ def main():
         log(f"[bench] cpu baseline: {cpu}")
         parity = parity_row(sc, torch, A, Mh, args.b, s, ref)
         log(f"[bench] parity against the oracle: {parity}")
+        if not args.no_cg:
+            cg_ref = cg_reference_row(sc, torch, synth, oracle)
+            log(f"[bench] CG iteration counts beside the oracle's: {cg_ref}")
+            if cg is not None and "error" not in cg:
+                cg["reference_iterations"] = cg_ref
 
     src_hash = kernel_source_hash()
     traffic = load_traffic(f"traffic_anderson{args.L}_b{args.b}.json", src_hash)

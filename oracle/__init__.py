@@ -44,6 +44,7 @@ def lib(fma: bool = False):
         L.orc_round_bf16.argtypes = [_I64, _P, _P]
         L.orc_round_f32.argtypes = [_I64, _P, _P]
         L.orc_cg.argtypes = [_I64, _P, _P, _P, _P, _P, _D, _I64, _P]
+        L.orc_cg_refine.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _D, _D, _I64, _I64, ct.c_int, _P, _P, _P]
         L.orc_chebyshev.argtypes = [_I64, _P, _P, _P, _P, _I64, _D, _D, _P, _P]
         L.orc_num_threads.restype = ct.c_int
         L.orc_set_num_threads.argtypes = [ct.c_int]
@@ -180,6 +181,20 @@ def cg(A, bvec, x0=None, tol=1e-10, maxit=100000):
     _check(lib().orc_cg(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(bvec), _p(x), tol, maxit,
                         ct.byref(it)), "cg")
     return x, it.value
+
+
+def cg_refine(A, bvec, val_low=None, x0=None, tol=1e-10, inner_rtol=1e-4, inner_maxit=100000, maxouter=1000,
+              single=True):
+    """Iterative refinement with an inner CG in float (single) or double on the values val_low
+    (default: A's values); returns (x, outer refinements, inner iterations, final relres)."""
+    bvec = _f64(bvec)
+    vl = A.val if val_low is None else _f64(val_low)
+    x = np.zeros(A.nrows) if x0 is None else _f64(x0).copy()
+    o, i, rr = ct.c_int64(0), ct.c_int64(0), ct.c_double(0.0)
+    _check(lib().orc_cg_refine(A.nrows, _p(A.rowptr), _p(A.col), _p(A.val), _p(vl), _p(bvec), _p(x), tol,
+                               inner_rtol, inner_maxit, maxouter, 1 if single else 0, ct.byref(o), ct.byref(i),
+                               ct.byref(rr)), "cg_refine")
+    return x, o.value, i.value, rr.value
 
 
 def chebyshev(A, x, M, s, c=0.0, fma=False):

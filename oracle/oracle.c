@@ -298,6 +298,137 @@ int orc_cg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *v
 }
 
 /* ---------------------------------------------------------------------------------
+ * Iterative refinement with a low-precision inner CG: the reference for the iteration counts
+ * of the refined solver (CG is only named by the paper; refinement is the textbook scheme).
+ *   r = b - A x                          (FP64 values, FP64 arithmetic)
+ *   while ||r|| > tol ||b|| and fewer than maxouter refinements:
+ *       d = 0; CG on A_low d = r from d = 0 until its recursive residual has dropped to
+ *           inner_rtol ||r|| or after inner_maxit steps; A_low holds val_low (the values in
+ *           the inner storage precision, given as doubles); with single != 0 the vectors and
+ *           the products are float (each product term and sum rounded to float), the dots and
+ *           the scalars double; with single == 0 everything is double
+ *       x = x + d;  r = b - A x          (FP64)
+ * *outer gets the refinements, *inner the CG steps over all of them, *relres the final
+ * ||b - A x|| / ||b||.
+ */
+static void orc_spmv_f32(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                         const float *x, float *y) {
+    for (int64_t i = 0; i < n; ++i) {
+        float acc = 0.0f;
+        for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const float prod = (float)val[p] * x[col[p]];
+            acc = acc + prod;
+        }
+        y[i] = acc;
+    }
+}
+
+static double orc_dot_f32(int64_t n, const float *a, const float *b) {
+    double s = 0.0, c = 0.0; /* Neumaier, as orc_dot */
+    for (int64_t i = 0; i < n; ++i) {
+        const double t = (double)a[i] * (double)b[i];
+        const double u = s + t;
+        if (fabs(s) >= fabs(t))
+            c += (s - u) + t;
+        else
+            c += (t - u) + s;
+        s = u;
+    }
+    return s + c;
+}
+
+int orc_cg_refine(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                  const double *val_low, const double *bvec, double *x, double tol, double inner_rtol,
+                  int64_t inner_maxit, int64_t maxouter, int single, int64_t *outer, int64_t *inner,
+                  double *relres) {
+    if (n < 0 || inner_maxit < 0 || maxouter < 0) return -1;
+    const size_t nn = (size_t)(n > 0 ? n : 1);
+    double *r = (double *)malloc(sizeof(double) * nn), *t = (double *)malloc(sizeof(double) * nn);
+    double *dd = (double *)malloc(sizeof(double) * nn), *pd = (double *)malloc(sizeof(double) * nn);
+    double *qd = (double *)malloc(sizeof(double) * nn), *rd = (double *)malloc(sizeof(double) * nn);
+    float *df = (float *)malloc(sizeof(float) * nn), *pf = (float *)malloc(sizeof(float) * nn);
+    float *qf = (float *)malloc(sizeof(float) * nn), *rf = (float *)malloc(sizeof(float) * nn);
+    int rc = 0;
+    if (!r || !t || !dd || !pd || !qd || !rd || !df || !pf || !qf || !rf) {
+        rc = -1;
+        goto done;
+    }
+    const double bnorm = sqrt(orc_dot(n, bvec, 1, bvec, 1));
+    int64_t nout = 0, nin = 0;
+    orc_spmmv(n, rowptr, col, val, 1, x, 1, t, 1);
+    for (int64_t i = 0; i < n; ++i) r[i] = bvec[i] - t[i];
+    double rnorm = sqrt(orc_dot(n, r, 1, r, 1));
+    while (rnorm > tol * bnorm && nout < maxouter) {
+        const double stop = inner_rtol * rnorm;
+        int64_t it = 0;
+        if (single) {
+            for (int64_t i = 0; i < n; ++i) {
+                df[i] = 0.0f;
+                rf[i] = (float)r[i];
+                pf[i] = rf[i];
+            }
+            double rr = orc_dot_f32(n, rf, rf);
+            while (it < inner_maxit && sqrt(rr) > stop) {
+                orc_spmv_f32(n, rowptr, col, val_low, pf, qf);
+                const double alpha = rr / orc_dot_f32(n, pf, qf);
+                for (int64_t i = 0; i < n; ++i) {
+                    df[i] = (float)((double)df[i] + alpha * (double)pf[i]);
+                    rf[i] = (float)((double)rf[i] - alpha * (double)qf[i]);
+                }
+                const double rr_new = orc_dot_f32(n, rf, rf);
+                const double beta = rr_new / rr;
+                for (int64_t i = 0; i < n; ++i) pf[i] = (float)((double)rf[i] + beta * (double)pf[i]);
+                rr = rr_new;
+                ++it;
+            }
+            for (int64_t i = 0; i < n; ++i) x[i] = x[i] + (double)df[i];
+        } else {
+            for (int64_t i = 0; i < n; ++i) {
+                dd[i] = 0.0;
+                rd[i] = r[i];
+                pd[i] = rd[i];
+            }
+            double rr = orc_dot(n, rd, 1, rd, 1);
+            while (it < inner_maxit && sqrt(rr) > stop) {
+                orc_spmmv(n, rowptr, col, val_low, 1, pd, 1, qd, 1);
+                const double alpha = rr / orc_dot(n, pd, 1, qd, 1);
+                for (int64_t i = 0; i < n; ++i) {
+                    dd[i] = dd[i] + alpha * pd[i];
+                    rd[i] = rd[i] - alpha * qd[i];
+                }
+                const double rr_new = orc_dot(n, rd, 1, rd, 1);
+                const double beta = rr_new / rr;
+                for (int64_t i = 0; i < n; ++i) pd[i] = rd[i] + beta * pd[i];
+                rr = rr_new;
+                ++it;
+            }
+            for (int64_t i = 0; i < n; ++i) x[i] = x[i] + dd[i];
+        }
+        nin += it;
+        ++nout;
+        orc_spmmv(n, rowptr, col, val, 1, x, 1, t, 1);
+        for (int64_t i = 0; i < n; ++i) r[i] = bvec[i] - t[i];
+        rnorm = sqrt(orc_dot(n, r, 1, r, 1));
+        if (it == 0) break; /* no progress possible (inner_rtol >= 1 or inner_maxit == 0) */
+    }
+    if (outer) *outer = nout;
+    if (inner) *inner = nin;
+    if (relres) *relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
+done:
+    free(r);
+    free(t);
+    free(dd);
+    free(pd);
+    free(qd);
+    free(rd);
+    free(df);
+    free(pf);
+    free(qf);
+    free(rf);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------------------
  * Chebyshev recurrence of the kernel polynomial method, direct moments.
  */
 int orc_chebyshev(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,

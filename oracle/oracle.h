@@ -85,6 +85,17 @@ int orc_round_f32(int64_t n, const double *in, double *out);
 int orc_cg(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
            const double *bvec, double *x, double tol, int64_t maxit, int64_t *iters);
 
+/* Iterative refinement around a CG in a lower inner precision (float vectors and products
+ * when single != 0; double dots and scalars), values val_low for the inner products, FP64
+ * residuals b - A x outside; restarts the inner CG from d = 0 at every refinement and stops
+ * it when its residual has dropped to inner_rtol of the current true residual (or after
+ * inner_maxit steps). *outer: refinements, *inner: total inner steps, *relres: final
+ * ||b - A x|| / ||b||. */
+int orc_cg_refine(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                  const double *val_low, const double *bvec, double *x, double tol, double inner_rtol,
+                  int64_t inner_maxit, int64_t maxouter, int single, int64_t *outer, int64_t *inner,
+                  double *relres);
+
 /* Chebyshev recurrence of the kernel polynomial method for A~ = (A - c I) / s:
  *   v0 = x, v1 = A~ v0, v_{m+1} = 2 A~ v_m - v_{m-1};
  * mu[m] = <v0, v_m> for m = 0..M (the textbook moments, no doubling trick);

@@ -351,6 +351,44 @@ def test_cg_manufactured_solution(orc):
     assert 10 < it < A.nrows
 
 
+def test_cg_refine_reduces_to_plain_cg(orc):
+    """With a double inner solve on the unrounded values, an inner tolerance equal to the outer
+    one and one refinement from x = 0, the refinement is plain CG: r = b - A 0 = b exactly, so
+    it takes the same steps and returns the same x bit for bit."""
+    A = synth.laplacian3d(11)
+    b = synth.block_vector(A.nrows, 1, 93)[:, 0]
+    x, it = orc.cg(A, b, tol=1e-9)
+    x2, outer, inner, _ = orc.cg_refine(A, b, single=False, tol=1e-9, inner_rtol=1e-9, maxouter=1)
+    assert outer == 1 and inner == it and np.array_equal(x2, x)
+
+
+@pytest.mark.parametrize("vdt", ["f32", "bf16"])
+def test_cg_refine_manufactured_solution(orc, vdt):
+    """A float inner solve alone stalls near its unit roundoff (about 1e-7 relative); the FP64
+    residual of each refinement restores the digits, so b - A x reaches 1e-10 after about
+    log(1e-10) / log(inner_rtol) refinements, and x approaches x* within ||r|| / lambda_min.
+    The 3D Laplacian's 6 / -1 are exact in both storage types."""
+    A = synth.laplacian3d(12)
+    xs = synth.block_vector(A.nrows, 1, 94)[:, 0]
+    b = A.dense() @ xs
+    low = orc.round_f32(A.val) if vdt == "f32" else orc.round_bf16(A.val)
+    assert np.array_equal(low, A.val)
+    x, outer, inner, rr = orc.cg_refine(A, b, val_low=low, tol=1e-10, inner_rtol=1e-4)
+    res = np.linalg.norm(b - A.dense() @ x) / np.linalg.norm(b)
+    assert res <= 1e-10 and abs(res - rr) <= 1e-3 * rr
+    assert 3 <= outer <= 4  # three decades of 1e-4 reach 1e-10 (one more if a float solve falls short)
+    lmin = 6 - 6 * math.cos(math.pi / 13)
+    assert np.linalg.norm(x - xs) <= 1.05e-10 * np.linalg.norm(b) / lmin
+    # without refinement the float solve cannot get there
+    _, _, _, rr1 = orc.cg_refine(A, b, val_low=low, tol=1e-10, inner_rtol=1e-12, maxouter=1, inner_maxit=2000)
+    assert rr1 > 1e-9
+    # and with a perturbed inner matrix (a dropped term) refinement still converges, but slower
+    bad = low.copy()
+    bad[::7] *= 0.9
+    _, outer2, _, rr2 = orc.cg_refine(A, b, val_low=bad, tol=1e-10, inner_rtol=1e-4)
+    assert rr2 <= 1e-10 and outer2 > outer
+
+
 def test_chebyshev_diagonal_closed_form(orc):
     d = synth.uniform(91, 300, -0.99, 0.99)
     n = d.size
