@@ -541,7 +541,7 @@ def tsm_row(sc, torch, n=1 << 22, m=8, k=8):
     return out
 
 
-def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
+def irregular_row(sc, torch, synth, model, n=4_000_000, C=32, probes=None):
     """The irregular matrix (lognormal row lengths, mean 15, half banded / half uniform
     columns): plain products y = A X for every sorting window, value type and block width,
     with algorithmic (true nonzeros) and SELL (stored entries, padding included) GB/s.
@@ -599,22 +599,40 @@ def irregular_row(sc, torch, synth, model, n=4_000_000, C=32):
             log(f"[bench] irregular {dt} sigma={sg}: {row}")
     out["products"] = res
     # achievable rate of scattered row gathers (the library's gather probe): as many uniform
-    # random rows as the matrix has uniform columns (half its nonzeros), and as many as nonzeros
+    # random rows as the matrix has uniform columns (half its nonzeros), and as many as nonzeros,
+    # for rows of 8 to 256 bytes (b FP64 or FP32 values per row)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(synth.SEED_X)
     idx = torch.randint(0, A.ncols, (A.nnz,), dtype=torch.int32, device="cuda", generator=gen)
     sink = torch.zeros(1, dtype=torch.float64, device="cuda")
     probe = {}
-    for b in (1, 8):
-        x = torch.rand((A.ncols, b), dtype=torch.float64, device="cuda")
+    gather_us = {}
+    for rb in (8, 16, 32, 64, 128, 256):
+        x = torch.rand((A.ncols, rb // 8), dtype=torch.float64, device="cuda")
         for name, cnt in (("half_nnz", A.nnz // 2), ("nnz", A.nnz)):
             ix = idx[:cnt]
             # five back-to-back launches per timed call (a single call's host overhead would count)
             us, _ = time_launches(torch, lambda: sc.sell_probe_gather(x, ix, sink), reps=4, inner=5)
-            probe[f"b{b}_{name}"] = {"gathers": cnt, "us": round(us, 1), "Ggathers/s": round(cnt / us / 1e3, 2)}
+            probe[f"row{rb}B_{name}"] = {"gathers": cnt, "us": round(us, 1), "Ggathers/s": round(cnt / us / 1e3, 2)}
+            if name == "half_nnz":
+                gather_us[rb] = us
         del x
-    out["gather_probe_f64"] = probe
+    out["gather_probe"] = probe
     log(f"[bench] gather probe: {probe}")
+    # floor of each product: the uniform half's gathers at the probe's rate (rows of b x-element
+    # bytes, at least 8), the banded half taken as free (L2 hits), plus the matrix stream at
+    # the read probe's rate and y at the write probe's rate; ratio = measured / floor
+    if probes:
+        rd, wr = probes["read"]["GB/s"] * 1e3, probes["write"]["GB/s"] * 1e3  # bytes per us
+        for dt, vb in (("f64", 8), ("f32", 4), ("bf16", 2)):
+            xs = 8 if dt == "f64" else 4
+            for key, row in res[dt].items():
+                stored = row["stored_over_nnz"] * A.nnz
+                for b in widths:
+                    rb = max(8, b * xs)
+                    t = gather_us[rb] + (stored * (vb + 4) + 4 * A.nrows) / rd + A.nrows * b * xs / wr
+                    row[f"b{b}"]["floor_us"] = round(t, 1)
+                    row[f"b{b}"]["over_floor"] = round(row[f"b{b}"]["us"] / t, 2)
     # the autotuner on this matrix at b = 32, FP64: (C, sigma), launch shape and slice width
     t0 = time.perf_counter()
     tune = sc.sell_autotune(A, 32, "f64", cache=False)
@@ -856,7 +874,7 @@ def main():
         batch = batch_row(sc, torch, synth, model, nmat=args.batch_count)
     irregular = None
     if not args.no_irregular:
-        irregular = irregular_row(sc, torch, synth, model)
+        irregular = irregular_row(sc, torch, synth, model, probes=probes)
     cpu = None
     parity = None
     if not args.no_cpu:

@@ -394,10 +394,11 @@ int sell_tsmm_inplace(sell_bv *V, const double *X, int64_t ldx, double alpha, do
 int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu);
 
 /* Grid of the product launches of A in waves of resident workgroups: waves in {0, 1, 2, 4, 8,
- * 16} (0 and 1: one wave, the default). Several waves let workgroups that finish early take the
- * next ones, which balances matrices whose tiles differ in speed (scattered gathers); the grid
- * never exceeds the matrix's fine tiles. Results per row are the same; dots may differ in the
- * last bits. */
+ * 16}; 0 restores the construction's choice: 4 waves when the chunk lengths spread widely
+ * (coefficient of variation above 1/2), else one. Several waves let workgroups that finish early
+ * take the next ones, which balances matrices whose tiles differ in speed (scattered gathers);
+ * the grid never exceeds the matrix's fine tiles. Results per row are the same; dots may differ
+ * in the last bits. */
 int sell_set_waves(sell_mat *A, int32_t waves);
 
 /* Processes blocks wider than `slice` columns (slice in {1, 2, 4, 8, 16, 32}; 0 = the whole
@@ -585,8 +586,9 @@ int sell_probe_stream(int reads, int writes, int unroll, int nontemporal, int gr
                       int64_t bytes, void *stream);
 
 /* Random-gather probe: for i < count, reads row idx[i] of x (nrows rows of row_bytes bytes,
- * row_bytes in {8, 16, 32, 64}; x 8-byte aligned for 8, else 16-byte aligned), 8 gathers in
- * flight per thread. It gives the achievable rate of the scattered row gathers that a product
+ * row_bytes in {8, 16, 32, 64, 128, 256}; x 8-byte aligned for 8, else 16-byte aligned), 8
+ * gathers in flight per thread; rows of 64, 128 and 256 bytes are split over 2, 4 and 8 lanes
+ * (32 bytes each, as the product kernels split a row of x). It gives the achievable rate of the scattered row gathers that a product
  * with scattered column indices performs (a row of X per nonzero; Sec. 5.2 notes that SpMMV
  * gathers whole rows of a row-major block vector).
  * idx: device int32[count] (may be NULL when count is 0); entries outside [0, nrows) read

@@ -122,6 +122,24 @@ int32_t choose_batch_len(const std::vector<int32_t> &cl, bool wide) {
     return best;
 }
 
+// Default grid of the product launches in waves of resident workgroups: 4 when the chunk
+// lengths spread widely (coefficient of variation above 1/2: scattered long rows, whose tiles
+// run at different speeds however their entries are balanced), else 1. Measured on the 4 M-row
+// irregular matrix: one wave 875 us, several 695 us (b = 1, sigma = 1024); on stencils more
+// waves only cost (the 100^3 Laplacian, FP32 values, b = 8: 39.4 us in one wave, 53.5 in 4).
+int32_t choose_waves(const std::vector<int32_t> &cl) {
+    if (cl.size() < 2) return 1;
+    double s = 0.0, s2 = 0.0;
+    for (int32_t l : cl) {
+        s += l;
+        s2 += double(l) * l;
+    }
+    const double n = double(cl.size()), mean = s / n;
+    if (mean <= 0.0) return 1;
+    const double var = std::max(0.0, s2 / n - mean * mean);
+    return std::sqrt(var) > 0.5 * mean ? 4 : 1;
+}
+
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
                     const int32_t *col, const double *val, int32_t C, int64_t sigma, int vdt) {
     if (nrows < 0 || ncols < 0 || nrows >= (int64_t(1) << 31) || ncols >= (int64_t(1) << 31))
@@ -246,6 +264,7 @@ int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *ro
     make_tiles(h.cl, C, nt, h.tiles);
     h.batch = choose_batch_len(h.cl);
     h.batch_wide = choose_batch_len(h.cl, true);
+    h.waves = choose_waves(h.cl);
     return SELL_OK;
 }
 

@@ -203,7 +203,7 @@ void base_args(ProdArgs &a, const sell_mat *A) {
     a.lcol = A->d_lcol;
     a.vpt_hint = A->vpt_hint;
     a.bpc_hint = A->bpc_hint;
-    a.waves_hint = A->waves_hint;
+    a.waves_hint = A->waves_hint > 0 ? A->waves_hint : A->h.waves;
     a.batch_hint = A->batch_hint > 0 ? A->batch_hint : A->h.batch;
     a.batch_hint_wide = A->batch_hint > 0 ? A->batch_hint : A->h.batch_wide;
 }

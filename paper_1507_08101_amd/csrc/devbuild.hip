@@ -263,6 +263,7 @@ int build_device_sell(sell_mat *M, int64_t nrows, int64_t ncols, const int64_t *
     make_tiles(h.cl, C, default_tile_count(nch), h.tiles);
     h.batch = choose_batch_len(h.cl);
     h.batch_wide = choose_batch_len(h.cl, true);
+    h.waves = choose_waves(h.cl);
     DCHK(lib_malloc(reinterpret_cast<void **>(&M->d_tiles), sizeof(int32_t) * h.tiles.size()));
     DCHK(hipMemcpyAsync(M->d_tiles, h.tiles.data(), sizeof(int32_t) * h.tiles.size(), hipMemcpyHostToDevice, s));
     DCHK(hipStreamSynchronize(s));

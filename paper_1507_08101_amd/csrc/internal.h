@@ -62,6 +62,7 @@ struct HostSell {
     std::vector<int64_t> rowptr;  // CSR row pointers of the input (for export and updates)
     int32_t batch = 8;            // index batch length suited to the chunk lengths (5, 7 or 8)
     int32_t batch_wide = 7;       // the same for the kernels gathering 32 bytes per lane (5 or 7)
+    int32_t waves = 1;            // default product grid in waves of resident workgroups (1 or 4)
 };
 
 // Work partitions: contiguous chunk ranges of roughly equal cost.
@@ -74,6 +75,8 @@ void make_tiles(const std::vector<int32_t> &cl, int32_t C, int32_t ntiles,
 // for the kernels whose lane gathers 32 bytes per entry, where 8-entry batches leave room for
 // two waves per SIMD instead of three: 5 or 7 only.
 int32_t choose_batch_len(const std::vector<int32_t> &cl, bool wide = false);
+// Default product grid in waves of resident workgroups from the spread of the chunk lengths.
+int32_t choose_waves(const std::vector<int32_t> &cl);
 
 // Validates CSR input and builds the host SELL arrays. Returns SELL_OK or an error.
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,

@@ -12,23 +12,28 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int kGT = 256;     // threads per workgroup
 constexpr int kGU = 8;       // gathers in flight per thread
 
-template <int W>  // doubles per row: 1, 2, 4 or 8
-__device__ __forceinline__ double load_row(const double *__restrict__ x, int64_t r) {
-    if (W == 1) return x[r];
-    const d2 *p = reinterpret_cast<const d2 *>(x + r * W);
+// The part of row r that lane `part` of its group of L lanes loads: W / L doubles (rows of W
+// doubles: 1, 2, 4, 8, 16 or 32).
+template <int W, int L>
+__device__ __forceinline__ double load_row(const double *__restrict__ x, int64_t r, int part) {
+    constexpr int PW = W / L;
+    if (PW == 1) return x[r * W + part];
+    const d2 *p = reinterpret_cast<const d2 *>(x + r * W + part * PW);
     d2 acc = p[0];
 #pragma unroll
-    for (int t = 1; t < W / 2; ++t) acc += p[t];
+    for (int t = 1; t < PW / 2; ++t) acc += p[t];
     return acc.x + acc.y;
 }
 
-// Every thread takes kGU indices at a time (coalesced index loads), then issues the kGU row
+// Every group of L lanes (one lane for rows up to 32 bytes, 32 bytes per lane for longer rows,
+// as the product kernels split a row of x) takes kGU indices at a time, then issues the kGU row
 // gathers together; an index outside [0, nrows) is replaced by 0.
-template <int W>
+template <int W, int L>
 __global__ void __launch_bounds__(kGT) gather_kernel(const double *__restrict__ x, int64_t nrows,
                                                      const int32_t *__restrict__ idx, int64_t count, double *out) {
-    const int64_t stride = int64_t(gridDim.x) * kGT;
-    int64_t i = int64_t(blockIdx.x) * kGT + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * (kGT / L);
+    const int part = int(threadIdx.x) % L;
+    int64_t i = int64_t(blockIdx.x) * (kGT / L) + threadIdx.x / L;
     double acc = 0.0;
     for (; i + (kGU - 1) * stride < count; i += kGU * stride) {
         int64_t r[kGU];
@@ -39,13 +44,13 @@ __global__ void __launch_bounds__(kGT) gather_kernel(const double *__restrict__ 
         }
         double g[kGU];
 #pragma unroll
-        for (int u = 0; u < kGU; ++u) g[u] = load_row<W>(x, r[u]);
+        for (int u = 0; u < kGU; ++u) g[u] = load_row<W, L>(x, r[u], part);
 #pragma unroll
         for (int u = 0; u < kGU; ++u) acc += g[u];
     }
     for (; i < count; i += stride) {
         const int32_t v = idx[i];
-        acc += load_row<W>(x, (v >= 0 && v < nrows) ? v : 0);
+        acc += load_row<W, L>(x, (v >= 0 && v < nrows) ? v : 0, part);
     }
     if (acc == 1.2345e-300) out[0] = acc;  // keeps the loads alive; practically never taken
 }
@@ -59,7 +64,8 @@ using namespace sellcs;
 extern "C" int sell_probe_gather(const void *x, int64_t nrows, int32_t row_bytes, const int32_t *idx, int64_t count,
                                  void *out, void *stream) {
     if (!x || !out || nrows < 1 || count < 0 || (count > 0 && !idx)) return SELL_ERR_ARG;
-    if (row_bytes != 8 && row_bytes != 16 && row_bytes != 32 && row_bytes != 64) return SELL_ERR_ARG;
+    if (row_bytes != 8 && row_bytes != 16 && row_bytes != 32 && row_bytes != 64 && row_bytes != 128 && row_bytes != 256)
+        return SELL_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(x) & uintptr_t(row_bytes == 8 ? 7 : 15)) return SELL_ERR_ARG;
     if (reinterpret_cast<uintptr_t>(out) & 7u) return SELL_ERR_ARG;
     if (count == 0) return SELL_OK;
@@ -68,10 +74,12 @@ extern "C" int sell_probe_gather(const void *x, int64_t nrows, int32_t row_bytes
     double *o = static_cast<double *>(out);
     const unsigned g = 256 * 16;
     switch (row_bytes) {
-        case 8: hipLaunchKernelGGL(gather_kernel<1>, dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
-        case 16: hipLaunchKernelGGL(gather_kernel<2>, dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
-        case 32: hipLaunchKernelGGL(gather_kernel<4>, dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
-        default: hipLaunchKernelGGL(gather_kernel<8>, dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
+        case 8: hipLaunchKernelGGL((gather_kernel<1, 1>), dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
+        case 16: hipLaunchKernelGGL((gather_kernel<2, 1>), dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
+        case 32: hipLaunchKernelGGL((gather_kernel<4, 1>), dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
+        case 64: hipLaunchKernelGGL((gather_kernel<8, 2>), dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
+        case 128: hipLaunchKernelGGL((gather_kernel<16, 4>), dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
+        default: hipLaunchKernelGGL((gather_kernel<32, 8>), dim3(g), dim3(kGT), 0, s, xp, nrows, idx, count, o); break;
     }
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }

@@ -246,8 +246,9 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
                     if (!rc && t.us < kMargin * best.us) best = t;
                 }
             // grids of several waves of resident workgroups (uneven tiles balance dynamically)
-            for (int32_t wv : {2, 4, 8}) {
+            for (int32_t wv : {1, 2, 4, 8}) {
                 if (rc) break;
+                if (wv == std::max(A->h.waves, 1)) continue;  // the default grid, timed above
                 A->waves_hint = wv;
                 Trial t;
                 rc = run(best.C, best.sigma, best.vpt, best.bpc, A, &t);

@@ -71,7 +71,7 @@ def test_stream_probe_rejects(sc):
         sc.sell_probe_stream(1, 1, 1, 0, 8, a, None, 1024)  # reads without a source
 
 
-@pytest.mark.parametrize("b", [1, 2, 4, 8])
+@pytest.mark.parametrize("b", [1, 2, 4, 8, 16, 32])
 def test_gather_probe_runs(sc, b):
     import torch
 
