@@ -46,11 +46,11 @@ __global__ void __launch_bounds__(kVT) cg_alpha_kernel(const double *prod_partia
     }
 }
 
-// x += alpha p ; r -= alpha q ; per-workgroup partials of <r, r>.
+// r -= alpha q ; per-workgroup partials of <r, r>. (x is advanced by the direction kernel,
+// which reads p anyway: one pass over x, p, r and q fewer per iteration.)
 template <class T>
-__global__ void __launch_bounds__(kVT) cg_xr_kernel(T *X, T *R, const T *P, const T *Q, int64_t n, int b,
-                                                    int bpad, int64_t ld, const double *alpha_v,
-                                                    double *partials) {
+__global__ void __launch_bounds__(kVT) cg_r_kernel(T *R, const T *Q, int64_t n, int b, int bpad, int64_t ld,
+                                                   const double *alpha_v, double *partials) {
     const int tid = threadIdx.x;
     const int j = tid & (bpad - 1);
     const int rows_per = kVT / bpad;
@@ -59,9 +59,7 @@ __global__ void __launch_bounds__(kVT) cg_xr_kernel(T *X, T *R, const T *P, cons
         const double alpha = alpha_v[j];
         for (int64_t i = int64_t(blockIdx.x) * rows_per + tid / bpad; i < n; i += int64_t(gridDim.x) * rows_per) {
             const int64_t e = i * ld + j;
-            const T x = T(double(X[e]) + alpha * double(P[e]));
             const T r = T(double(R[e]) - alpha * double(Q[e]));
-            X[e] = x;
             R[e] = r;
             acc += double(r) * double(r);
         }
@@ -82,16 +80,18 @@ __global__ void __launch_bounds__(kVT) cg_beta_kernel(const double *partials, in
     }
 }
 
-// p = r + beta p
+// x += alpha p (the iteration's step along the old direction), then p = r + beta p
 template <class T>
-__global__ void __launch_bounds__(kVT) cg_p_kernel(T *P, const T *R, int64_t n, int b, int64_t ld,
-                                                   const double *beta) {
+__global__ void __launch_bounds__(kVT) cg_p_kernel(T *P, T *X, const T *R, int64_t n, int b, int64_t ld,
+                                                   const double *alpha, const double *beta) {
     const int64_t N = n * b;
     for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
         const int64_t i = e / b;
         const int j = int(e - i * b);
         const int64_t k = i * ld + j;
-        P[k] = T(double(R[k]) + beta[j] * double(P[k]));
+        const double p = double(P[k]);
+        X[k] = T(double(X[k]) + alpha[j] * p);
+        P[k] = T(double(R[k]) + beta[j] * p);
     }
 }
 
@@ -214,10 +214,11 @@ __global__ void __launch_bounds__(kVT) bcg_alpha_kernel(const double *pparts, co
     }
 }
 
-// d += alpha p ; r -= alpha q on the rows of active systems; partials of <r, r>.
+// r -= alpha q on the rows of active systems; partials of <r, r> (d is advanced by the
+// direction kernel).
 template <class T>
-__global__ void __launch_bounds__(kVT) bcg_xr_kernel(T *D, T *R, const T *P, const T *Q, int b, int bpad,
-                                                     BatchSeg sg, BatchCg sc, double *partials) {
+__global__ void __launch_bounds__(kVT) bcg_r_kernel(T *R, const T *Q, int b, int bpad, BatchSeg sg, BatchCg sc,
+                                                    double *partials) {
     const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
     const int j = threadIdx.x & (bpad - 1);
     double acc = 0.0;
@@ -225,9 +226,7 @@ __global__ void __launch_bounds__(kVT) bcg_xr_kernel(T *D, T *R, const T *P, con
         const double alpha = sc.alpha[m * b + j];
         seg_rows(sg, m, bpad, [&](int64_t i) {
             const int64_t e = i * b + j;
-            const T d = T(double(D[e]) + alpha * double(P[e]));
             const T r = T(double(R[e]) - alpha * double(Q[e]));
-            D[e] = d;
             R[e] = r;
             acc += double(r) * double(r);
         });
@@ -240,6 +239,9 @@ __global__ void __launch_bounds__(kVT) bcg_xr_kernel(T *D, T *R, const T *P, con
 __global__ void __launch_bounds__(kVT) bcg_beta_kernel(const double *partials, int G, BatchSeg sg, int b,
                                                        BatchCg sc) {
     const int m = blockIdx.x;
+    // sys_step[m]: the system took this iteration's step (the direction kernel advances its d
+    // even when the step retired its last column)
+    if (threadIdx.x == 0) sc.sys_step[m] = sc.sys_active[m];
     if (!sc.sys_active[m]) return;
     const int v0 = sg.vblk[m], nv = sg.vblk[m + 1] - v0;
     int any = 0;
@@ -262,16 +264,21 @@ __global__ void __launch_bounds__(kVT) bcg_beta_kernel(const double *partials, i
     }
 }
 
-// p = r + beta p on the rows of active systems
+// d += alpha p on the rows of the systems that took this iteration's step, then p = r + beta p
+// on the rows of the systems still active
 template <class T>
-__global__ void __launch_bounds__(kVT) bcg_p_kernel(T *P, const T *R, int b, int bpad, BatchSeg sg, BatchCg sc) {
+__global__ void __launch_bounds__(kVT) bcg_p_kernel(T *P, T *D, const T *R, int b, int bpad, BatchSeg sg,
+                                                    BatchCg sc) {
     const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
     const int j = threadIdx.x & (bpad - 1);
-    if (j >= b || !sc.sys_active[m]) return;
-    const double beta = sc.beta[m * b + j];
+    if (j >= b || !sc.sys_step[m]) return;
+    const double alpha = sc.alpha[m * b + j], beta = sc.beta[m * b + j];
+    const bool dir = sc.sys_active[m] != 0;
     seg_rows(sg, m, bpad, [&](int64_t i) {
         const int64_t e = i * b + j;
-        P[e] = T(double(R[e]) + beta * double(P[e]));
+        const double p = double(P[e]);
+        D[e] = T(double(D[e]) + alpha * p);
+        if (dir) P[e] = T(double(R[e]) + beta * p);
     });
 }
 
@@ -397,31 +404,30 @@ int cg_launch_alpha(const double *prod_partials, int ntiles, int b, const CgDev 
     return ok();
 }
 
-int cg_launch_xr(int dt, void *X, void *R, const void *P, const void *Q, int64_t n, int b, int64_t ld,
-                 const CgDev &sc, double *partials, hipStream_t s) {
+int cg_launch_r(int dt, void *R, const void *Q, int64_t n, int b, int64_t ld, const CgDev &sc, double *partials,
+                hipStream_t s) {
     const int bpad = pow2_at_least(b);
     const unsigned g = cg_reduce_grid(n, b);
     if (dt == SELL_F64)
-        hipLaunchKernelGGL(cg_xr_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(X),
-                           static_cast<double *>(R), static_cast<const double *>(P),
+        hipLaunchKernelGGL(cg_r_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(R),
                            static_cast<const double *>(Q), n, b, bpad, ld, sc.alpha, partials);
     else
-        hipLaunchKernelGGL(cg_xr_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(X),
-                           static_cast<float *>(R), static_cast<const float *>(P), static_cast<const float *>(Q),
-                           n, b, bpad, ld, sc.alpha, partials);
+        hipLaunchKernelGGL(cg_r_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(R),
+                           static_cast<const float *>(Q), n, b, bpad, ld, sc.alpha, partials);
     if (ok() != SELL_OK) return SELL_ERR_HIP;
     hipLaunchKernelGGL(cg_beta_kernel, dim3(b), dim3(kVT), 0, s, partials, int(g), sc);
     return ok();
 }
 
-int cg_launch_p(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const double *beta, hipStream_t s) {
+int cg_launch_p(int dt, void *P, void *X, const void *R, int64_t n, int b, int64_t ld, const CgDev &sc,
+                hipStream_t s) {
     const unsigned g = vgrid(n * b, 4096);
     if (dt == SELL_F64)
         hipLaunchKernelGGL(cg_p_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(P),
-                           static_cast<const double *>(R), n, b, ld, beta);
+                           static_cast<double *>(X), static_cast<const double *>(R), n, b, ld, sc.alpha, sc.beta);
     else
         hipLaunchKernelGGL(cg_p_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(P),
-                           static_cast<const float *>(R), n, b, ld, beta);
+                           static_cast<float *>(X), static_cast<const float *>(R), n, b, ld, sc.alpha, sc.beta);
     return ok();
 }
 
@@ -480,28 +486,29 @@ int bcg_launch_alpha(const double *pparts, const int32_t *pblk, int K, int b, co
     return ok();
 }
 
-int bcg_launch_xr(int dt, void *D, void *R, const void *P, const void *Q, int b, const BatchSeg &sg,
-                  const BatchCg &sc, double *partials, hipStream_t s) {
+int bcg_launch_r(int dt, void *R, const void *Q, int b, const BatchSeg &sg, const BatchCg &sc, double *partials,
+                 hipStream_t s) {
     const int bpad = pow2_at_least(b);
     if (dt == SELL_F64)
-        hipLaunchKernelGGL(bcg_xr_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(D), tp<double>(R),
-                           ctp<double>(P), ctp<double>(Q), b, bpad, sg, sc, partials);
+        hipLaunchKernelGGL(bcg_r_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), ctp<double>(Q), b, bpad,
+                           sg, sc, partials);
     else
-        hipLaunchKernelGGL(bcg_xr_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(D), tp<float>(R),
-                           ctp<float>(P), ctp<float>(Q), b, bpad, sg, sc, partials);
+        hipLaunchKernelGGL(bcg_r_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(R), ctp<float>(Q), b, bpad,
+                           sg, sc, partials);
     if (ok() != SELL_OK) return SELL_ERR_HIP;
     hipLaunchKernelGGL(bcg_beta_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, sc);
     return ok();
 }
 
-int bcg_launch_p(int dt, void *P, const void *R, int b, const BatchSeg &sg, const BatchCg &sc, hipStream_t s) {
+int bcg_launch_p(int dt, void *P, void *D, const void *R, int b, const BatchSeg &sg, const BatchCg &sc,
+                 hipStream_t s) {
     const int bpad = pow2_at_least(b);
     if (dt == SELL_F64)
-        hipLaunchKernelGGL(bcg_p_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), ctp<double>(R), b, bpad,
-                           sg, sc);
+        hipLaunchKernelGGL(bcg_p_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), tp<double>(D),
+                           ctp<double>(R), b, bpad, sg, sc);
     else
-        hipLaunchKernelGGL(bcg_p_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(P), ctp<float>(R), b, bpad,
-                           sg, sc);
+        hipLaunchKernelGGL(bcg_p_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(P), tp<float>(D), ctp<float>(R),
+                           b, bpad, sg, sc);
     return ok();
 }
 

@@ -4,8 +4,8 @@
 // vectors, Sec. 5.2, with per-column scalars as in its vaxpy/vaxpby operations). An
 // iteration is three launches with no host synchronisation:
 //   q = A p            augmented product with the fused dot <p, q>
-//   x += a p, r -= a q fused update with <r, r> and the per-column scalars (device FP64)
-//   p = r + b p
+//   r -= a q           update with <r, r> and the per-column scalars (device FP64)
+//   x += a p, p = r + b p   the step along the old direction and the new direction in one pass
 // The host reads the per-column "active" flags every few iterations.
 //
 // sell_cg:        FP64 throughout; convergence is confirmed on the true residual b - A x.
@@ -123,8 +123,8 @@ int cg_iterate(const sell_mat *A, int dt, sell_bv &X, sell_bv &R, sell_bv &P, se
         int32_t nblk = 0;
         if ((rc = aug_impl(A, &P, &Q, nullptr, o, true, s, S.prod_parts, &nblk))) return rc;
         if ((rc = cg_launch_alpha(S.prod_parts, nblk, b, S.dev(), s))) return rc;
-        if ((rc = cg_launch_xr(dt, X.ptr, R.ptr, P.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
-        if ((rc = cg_launch_p(dt, P.ptr, R.ptr, n, b, b, S.beta, s))) return rc;
+        if ((rc = cg_launch_r(dt, R.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
+        if ((rc = cg_launch_p(dt, P.ptr, X.ptr, R.ptr, n, b, b, S.dev(), s))) return rc;
         ++*its;
         if (*its % kCheckEvery == 0 && (rc = any_active(S, b, s, &any))) return rc;
     }
@@ -317,8 +317,8 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
         int32_t nblk = 0;
         if ((rc = aug_impl(Alo, &P, &Q, nullptr, o, true, s, S.prod_parts, &nblk))) return rc;
         if ((rc = cg_launch_alpha(S.prod_parts, nblk, b, S.dev(), s))) return rc;
-        if ((rc = cg_launch_xr(SELL_F32, D.ptr, R.ptr, P.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
-        if ((rc = cg_launch_p(SELL_F32, P.ptr, R.ptr, n, b, b, S.beta, s))) return rc;
+        if ((rc = cg_launch_r(SELL_F32, R.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
+        if ((rc = cg_launch_p(SELL_F32, P.ptr, D.ptr, R.ptr, n, b, b, S.dev(), s))) return rc;
         ++st.iterations;
         ++since;
         if (st.iterations % kCheckEvery == 0 || st.iterations == maxit) {
