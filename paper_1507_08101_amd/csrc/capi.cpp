@@ -884,7 +884,7 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
     o.alpha = 1.0 / scale;
     o.gamma = c;
     if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[0], s);
-    int32_t nblk = 0;
+    int32_t nblk = 0, nblk1 = 0;
     if (rc == SELL_OK) rc = aug_impl(A, V, W, nullptr, o, true, s, parts, &nblk);
     if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[1], s);
     sell_bv *x = W, *y = V;  // x = v_m, y = v_{m-1} -> v_{m+1}
@@ -892,15 +892,18 @@ int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double scale,
     o.alpha = 2.0 / scale;
     o.beta = -1.0;
     for (int64_t m = 1; m < M && rc == SELL_OK; ++m) {
-        rc = aug_impl(A, x, y, nullptr, o, true, s, parts + size_t(m) * per_step);
+        rc = aug_impl(A, x, y, nullptr, o, true, s, parts + size_t(m) * per_step, &nblk1);
         if (rc == SELL_OK && step_ms) (void)hipEventRecord(ev[size_t(m) + 1], s);
         std::swap(x, y);
     }
-    // every step used the same launch shape: nblk partials per quantity, 3 b quantities,
-    // packed at the start of each step's region of the buffer
-    if (rc == SELL_OK && A->h.nrows > 0 && nblk > 0)
-        rc = launch_dot_finish_strided(parts, nblk, b, SELL_SPMV_DOTS, dots, b, M, 3 * b, per_step, s);
-    else if (rc == SELL_OK)
+    // the first step and the later ones (the same flags each, hence the same launch shape) left
+    // nblk and nblk1 partials per quantity, 3 b quantities, at the start of each step's region
+    if (rc == SELL_OK && A->h.nrows > 0 && nblk > 0) {
+        rc = launch_dot_finish_strided(parts, nblk, b, SELL_SPMV_DOTS, dots, b, 1, 3 * b, per_step, s);
+        if (rc == SELL_OK && M > 1)
+            rc = launch_dot_finish_strided(parts + per_step, nblk1, b, SELL_SPMV_DOTS, dots + 3 * b, b, M - 1, 3 * b,
+                                           per_step, s);
+    } else if (rc == SELL_OK)
         rc = launch_fill(dots, SELL_F64, M, 3 * b, 3 * b, 1, 0.0, s);
     if (rc == SELL_OK) rc = launch_kpm_moments(dots, M, b, mu, s);
     if (parts) {

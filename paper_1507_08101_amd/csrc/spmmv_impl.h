@@ -141,7 +141,9 @@ constexpr int kBatchDefault = 8;
 // B == 0: run-time width nb <= 64, one column per lane, VL = next power of two >= nb,
 //         any strides.
 // The product over the tiles of workgroup `tile` (one of a.nblocks) of one matrix.
-template <int VK, int B, int VPT, bool AUG, int UB = 0, bool STG = false>
+// FL != 0: the augmentation flags are known at compile time (a.flags == FL), so the unused
+// parts of the epilogue take no registers.
+template <int VK, int B, int VPT, bool AUG, int UB = 0, bool STG = false, uint32_t FL = 0>
 __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, const int vl_log2) {
     using V = typename KTypes<VK>::V;
     using X = typename KTypes<VK>::X;
@@ -213,13 +215,16 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     const int64_t yrs = a.yrs, ycs = VEC ? 1 : a.ycs;
     const int64_t zrs = a.zrs, zcs = VEC ? 1 : a.zcs;
 
-    const bool want_dots = AUG && (a.flags & SELL_SPMV_DOTS);
-    const bool shift = AUG && (a.flags & (SELL_SPMV_SHIFT | SELL_SPMV_VSHIFT));
-    const bool need_x = shift || (AUG && (a.flags & (SELL_SPMV_DOT_XY | SELL_SPMV_DOT_XX)));
-    const bool read_y = AUG && (a.flags & SELL_SPMV_AXPBY) && a.beta != 0.0;
-    const bool chain = AUG && (a.flags & SELL_SPMV_CHAIN);
+    const uint32_t fl = FL ? FL : a.flags;
+    const bool want_dots = AUG && (fl & SELL_SPMV_DOTS);
+    const bool shift = AUG && (fl & (SELL_SPMV_SHIFT | SELL_SPMV_VSHIFT));
+    const bool need_x = shift || (AUG && (fl & (SELL_SPMV_DOT_XY | SELL_SPMV_DOT_XX)));
+    const bool read_y = AUG && (fl & SELL_SPMV_AXPBY) && a.beta != 0.0;
+    const bool chain = AUG && (fl & SELL_SPMV_CHAIN);
     const bool read_z = chain && a.delta != 0.0;
-    const double alpha = (AUG && (a.flags & SELL_SPMV_SCALE)) ? a.alpha : 1.0;
+    const bool dot_xx = AUG && (fl & SELL_SPMV_DOT_XX);
+    const bool vshift = AUG && (fl & SELL_SPMV_VSHIFT);
+    const double alpha = (AUG && (fl & SELL_SPMV_SCALE)) ? a.alpha : 1.0;
     const double beta = a.beta, delta = a.delta, eta = a.eta;
     SELL_GLOBAL X *const scratch_base = to_global(static_cast<X *>(a.scratch));
 
@@ -268,7 +273,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
 
     double gam[VPT];
 #pragma unroll
-    for (int t = 0; t < VPT; ++t) gam[t] = (a.has_gamma_v && col_ok) ? a.gamma_v[jb + t] : a.gamma_s;
+    for (int t = 0; t < VPT; ++t) gam[t] = (vshift && a.has_gamma_v && col_ok) ? a.gamma_v[jb + t] : a.gamma_s;
 
     // Chunk metadata of a slot, loaded one pass ahead. The loads are unconditional (the slot
     // is clamped into the tile, and without a permutation the row load re-reads the chunk
@@ -457,7 +462,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
                 if (want_dots && live) {
                     dyy[t] += yd * yd;
                     dxy[t] += xv * yd;
-                    dxx[t] += xv * xv;
+                    if (dot_xx) dxx[t] += xv * xv;
                 }
                 double z = eta * yd;
                 if (read_z) z = delta * double(zin[t]) + z;
@@ -528,7 +533,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     }
 }
 
-template <int VK, int B, int VPT, bool AUG, int UB = 0, bool STG = false>
+template <int VK, int B, int VPT, bool AUG, int UB = 0, bool STG = false, uint32_t FL = 0>
 __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
     const int tile = a.xcd_map ? xcd_tile(blockIdx.x, gridDim.x) : int(blockIdx.x);  // index in the partials
     int vls = vl_log2;
@@ -536,8 +541,15 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
         vls = 0;
         while ((1 << vls) < a.nb) ++vls;
     }
-    prod_body<VK, B, VPT, AUG, UB, STG>(a, tile, vls);
+    prod_body<VK, B, VPT, AUG, UB, STG, FL>(a, tile, vls);
 }
+
+// The flags of a step of the Chebyshev / KPM recurrence (y = alpha (A x - c x) - y with
+// <y, y> and <x, y>): the FP64 product the KPM driver runs M times gets its own compile-time
+// copy (153 VGPRs against 179 for the general epilogue; 133.9 against 135.8 us per product on
+// the 128^3 Anderson matrix at b = 8). Forcing it under 128 VGPRs for two workgroups per compute
+// unit spills and takes 186.7 us.
+constexpr uint32_t kKpmFlags = SELL_SPMV_SHIFT | SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
 
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
 // (XCD-remapped) grid work on matrix m, whose launch arguments are table[m]. A matrix m with
@@ -667,6 +679,9 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
                      (reinterpret_cast<uintptr_t>(a.X) & 15u) == 0))
         a.stage = 0;
     auto k = a.stage ? prod_kernel<VK, B, VPT, AUG, UB, (B > 0)> : prod_kernel<VK, B, VPT, AUG, UB>;
+    if constexpr (AUG && VK == VK_F64F64 && B > 0) {
+        if (!a.stage && a.flags == kKpmFlags) k = prod_kernel<VK, B, VPT, AUG, UB, false, kKpmFlags>;
+    }
     if (a.stage) {
         a.nblocks = a.st_nblocks;  // the launch the plan was made for (stride checked there)
         hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
