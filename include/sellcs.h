@@ -433,18 +433,16 @@ int sell_set_batch(sell_mat *A, int32_t batch);
  * pages than the cache holds (at most 64) gather from global memory as before. Applies to the
  * single-matrix products at the fixed widths 1, 2, 4, 8, 16 and 32 with row-major x whose rows
  * are contiguous and 16-byte aligned; other calls ignore it.
- * tile_stride > 0: workgroup g takes the units g % S + S k of its share of k (S = tile_stride)
- * one after another instead of a contiguous range, where S divides the number of units and of
- * workgroups (else ignored): for a matrix whose far neighbours lie S units away (the next plane
- * of a 3D grid) consecutive units of a workgroup then share most of their pages. A unit is a
- * stage tile when x is staged (one pass of the kernel: 512 * columns per lane / b rows), else a
- * work tile of the construction, or unit_rows rows (rounded down to whole chunks) when
- * unit_rows > 0.
+ * tile_stride > 0 (staged launches): workgroup g takes the stage tiles g % S + S k of its share
+ * of k (S = tile_stride) one after another instead of a contiguous range, where S divides the
+ * number of stage tiles and of workgroups (else ignored): for a matrix whose far neighbours lie
+ * S stage tiles away (the next plane of a 3D grid) consecutive tiles of a workgroup then share
+ * most of their pages. A stage tile is one pass of the kernel (512 * columns per lane / b rows).
  * 0, 0 restores the defaults. y and z are the same bit for bit (every row sums the same entries
  * in the same order); the dots, summed over the rows in another grouping when a workgroup takes
  * its tiles one at a time, may differ in the last bits. Errors: SELL_ERR_ARG for stage outside
- * {0, 1}, a negative stride or unit_rows. */
-int sell_set_stage(sell_mat *A, int32_t stage, int32_t tile_stride, int32_t unit_rows);
+ * {0, 1} or a negative stride. */
+int sell_set_stage(sell_mat *A, int32_t stage, int32_t tile_stride);
 
 typedef struct {
     int32_t C;             /* chosen chunk height                                      */

@@ -113,7 +113,7 @@ _SIGNATURES = {
     "sell_set_slice": ([_P, _I32], _I),
     "sell_set_waves": ([_P, _I32], _I),
     "sell_set_batch": ([_P, _I32], _I),
-    "sell_set_stage": ([_P, _I32, _I32, _I32], _I),
+    "sell_set_stage": ([_P, _I32, _I32], _I),
     "sell_autotune": ([_I64, _I64, _P, _P, _P, _I, _I32, ct.c_uint32, ct.POINTER(sell_tune_result), _P], _I),
     "sell_batch_create": ([_PP, _I32, _PP], _I),
     "sell_batch_destroy": ([_P], _I),
@@ -313,11 +313,10 @@ class SellMatrix:
         """Process wider blocks in launches over column slices of this width (0 = whole block)."""
         _ok(lib().sell_set_slice(self.handle, int(slice_width)), "sell_set_slice")
 
-    def set_stage(self, stage=0, tile_stride=0, unit_rows=0):
+    def set_stage(self, stage=0, tile_stride=0):
         """Gather x through the LDS page cache (1) or from global memory (0); tile_stride > 0
-        makes each workgroup take every tile_stride-th unit (unstaged: of unit_rows rows when
-        given, else the construction's tiles)."""
-        _ok(lib().sell_set_stage(self.handle, int(stage), int(tile_stride), int(unit_rows)), "sell_set_stage")
+        makes each workgroup of a staged launch take every tile_stride-th stage tile."""
+        _ok(lib().sell_set_stage(self.handle, int(stage), int(tile_stride)), "sell_set_stage")
 
     def set_batch(self, batch=0):
         """Index batch length of the products (5, 7 or 8; 0 = the construction's choice)."""

@@ -307,7 +307,6 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
         a.nb = b;
         a.nblocks = blk[size_t(m) + 1] - blk[size_t(m)];
         a.tile_stride = 0;
-        a.unit_chunks = 0;
         a.stage = 0;
         a.xrs = xrs;
         a.xcs = xcs;
@@ -413,7 +412,6 @@ int batch_aug_packed_impl(sell_batch *B, const void *X, void *Y, void *Z, const 
         a.nb = w;
         a.nblocks = blk[size_t(p) + 1] - blk[size_t(p)];
         a.tile_stride = 0;
-        a.unit_chunks = 0;
         a.stage = 0;
         a.X = xb + B->xoff[size_t(m)] * esize;
         a.Y = yb + B->yoff[size_t(m)] * esize;

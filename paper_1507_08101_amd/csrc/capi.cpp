@@ -191,11 +191,10 @@ void base_args(ProdArgs &a, const sell_mat *A) {
         return e ? std::atoi(e) : 1;
     }();
     a.xcd_map = xcd_map;
-    a.tile_stride = A->tile_stride_hint;
-    a.stage = 0;  // set by the product call when the stage arrays and plan fit the launch
+    a.tile_stride = 0;  // staged launches only: set with the plan
+    a.stage = 0;        // set by the product call when the stage arrays and plan fit the launch
     a.st_ntiles = A->stage_ntiles;
     a.st_chunks = A->stage_chunks;
-    a.unit_chunks = A->tile_stride_hint > 0 ? A->unit_chunks_hint : 0;
     a.nch = A->h.nch;
     a.st_np = A->d_stage_np;
     a.st_pages = A->d_stage_pages;

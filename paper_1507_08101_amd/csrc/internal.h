@@ -126,7 +126,6 @@ struct sell_mat {
     int32_t stage_ntiles = 0;       // number of stage tiles
     int32_t stage_hint = 0;         // 1: products gather x through LDS where the tile allows
     int32_t tile_stride_hint = 0;   // > 0: workgroups take every tile_stride-th tile
-    int32_t unit_chunks_hint = 0;   // > 0: with a stride, unstaged units of this many chunks
     int64_t matrix_bytes = 0;
     int32_t vpt_hint = 0;           // launch parameters chosen for this matrix (0: defaults)
     int32_t bpc_hint = 0;
@@ -168,12 +167,11 @@ struct ProdArgs {
     int32_t waves_hint;    // product grid in waves of resident workgroups (0, 1: one wave)
     int32_t batch_hint;    // index batch length of the kernels (5, 7; else 8)
     int32_t batch_hint_wide; // the same for the kernels gathering 32 bytes per lane
-    int32_t tile_stride;   // > 0: workgroup g takes every tile_stride-th tile (stage tile
-                           // when staged) of its column
+    int32_t tile_stride;   // > 0 (staged launches): workgroup g takes every tile_stride-th
+                           // stage tile of its column
     int32_t stage;         // 1: gather x through the LDS page cache (the stage arrays below)
     int32_t st_ntiles;     // stage tiles: st_chunks consecutive chunks each (the last may be short)
     int32_t st_chunks;
-    int32_t unit_chunks;   // > 0 (with tile_stride): unstaged work units of this many chunks
     int64_t nch;           // chunks of the matrix
     const int32_t *st_np, *st_pages, *st_own;
     const uint16_t *lcol;

@@ -162,42 +162,34 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     const SELL_GLOBAL int64_t *__restrict__ csp = to_global(a.cs);
     const SELL_GLOBAL int32_t *__restrict__ tiles = to_global(a.tiles);
     const int64_t nrows = a.nrows;
-    // The tiles of this workgroup: the contiguous range [t0, t1) as one range of slots (as
-    // single tiles when x is staged), or with a tile stride S the tiles Y + S k, k in [k0, k1),
-    // of column Y = tile % S one after another (on a matrix whose far neighbours lie S tiles
-    // away, such as the next plane of a 3D grid, each tile then gathers much of what the
-    // previous one gathered)
-    // With x staged the work units are the stage tiles (a.st_ntiles of a.st_chunks chunks),
-    // taken one at a time.
-    const int S = a.tile_stride;
-    const int64_t uch = STG ? int64_t(a.st_chunks) : int64_t(a.unit_chunks);  // > 0: chunk-group units
-    const int64_t nunits = uch > 0 ? (a.nch + uch - 1) / uch : int64_t(a.ntiles);
-    int64_t r_first, r_count, r_step, r_len;  // range i: units [r_first + i r_step, + r_len)
+    // STG: the work units are the stage tiles (a.st_ntiles of a.st_chunks chunks), taken one at
+    // a time: the contiguous range of units [t0, t1) of this workgroup, or with a unit stride S
+    // the units Y + S k, k in [k0, k1), of column Y = tile % S one after another (on a matrix
+    // whose far neighbours lie S units away, such as the next plane of a 3D grid, each unit
+    // then needs much of what the previous one loaded). Otherwise the workgroup's tiles form one
+    // contiguous range of slots.
+    const int S = STG ? a.tile_stride : 0;
+    const int64_t uch = STG ? int64_t(a.st_chunks) : 0;
+    const int64_t nunits = STG ? (a.nch + uch - 1) / uch : int64_t(a.ntiles);
+    int64_t r_first, r_count, r_step;  // unit i: r_first + i r_step (STG)
     if (S > 0) {
         const int64_t Q = nunits / S, nseg = a.nblocks / S, q = tile / S;
         const int64_t k0 = q * Q / nseg, k1 = (q + 1) * Q / nseg;
         r_first = (tile % S) + S * k0;
         r_count = k1 - k0;
         r_step = S;
-        r_len = 1;
     } else {
         const int64_t t0 = int64_t(tile) * nunits / a.nblocks, t1 = int64_t(tile + 1) * nunits / a.nblocks;
         r_first = t0;
-        r_count = STG ? t1 - t0 : 1;
+        r_count = t1 - t0;
         r_step = 1;
-        r_len = STG ? 1 : t1 - t0;
     }
-    // slots of units [u, u + len)
-    auto unit_slots = [&](int64_t u, int64_t len, int64_t &sb, int64_t &se) {
-        if (uch > 0) {
-            const int64_t nch = a.nch;
-            const int64_t c0 = u * uch, c1 = (u + len) * uch;
-            sb = (c0 < nch ? c0 : nch) * C;
-            se = (c1 < nch ? c1 : nch) * C;
-        } else {
-            sb = int64_t(tiles[u]) * C;
-            se = int64_t(tiles[u + len]) * C;
-        }
+    // slots of unit u (STG)
+    auto unit_slots = [&](int64_t u, int64_t &sb, int64_t &se) {
+        const int64_t nch = a.nch;
+        const int64_t c0 = u * uch, c1 = (u + 1) * uch;
+        sb = (c0 < nch ? c0 : nch) * C;
+        se = (c1 < nch ? c1 : nch) * C;
     };
     int64_t s_begin = 0, s_end = 0;
     const int tid = threadIdx.x;
@@ -288,76 +280,12 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
         pv = *pp;
     };
 
-    // The workgroup's passes over all of its units, one after another: the metadata of the next
-    // pass (in this unit or at the start of the next) is loaded one pass ahead.
-    // STG: a unit's pages are resident and listed in slot_tab[half] when its first pass starts;
-    // the first unit is staged here, each next one during the unit before it when both fit.
-    int half = 0;
-    auto unit_np = [&](int64_t u) {
-        const int n = a.st_np[u];
-        return (n > 0 && n <= NS) ? n : 0;
-    };
-    int64_t rr = 0;
-    if (r_count > 0) unit_slots(r_first, r_len, s_begin, s_end);
-    if constexpr (STG) {
-        if (r_count > 0) {
-            const int n0 = unit_np(r_first);
-            if (n0 > 0) {
-                if (tid < 64) {
-                    load_unit(r_first, n0, 0);
-                    __builtin_amdgcn_s_waitcnt(0);
-                }
-                __syncthreads();
-            }
-        }
-    }
-    int64_t pb = s_begin;  // first slot of the current pass
-    int cl_n = 0, pv_n = 0;
-    int64_t cs_n = 0;
-    if (r_count > 0 && s_begin < s_end) load_meta(pb + (tid >> vls), s_end, cl_n, cs_n, pv_n);
-    // Settle the first pass's metadata here, so that at the loop head only the previous
-    // pass's stores are outstanding and the metadata loads of the following pass are not
-    // held up behind them.
-    __builtin_amdgcn_s_waitcnt(0);
-    bool staged = false, ahead = false;
-    int own_pos = -1, np_next = 0;
-    int64_t tb = 0, own_p0 = 0;
-    while (rr < r_count) {
-        const int64_t ta = r_first + rr * r_step;
-        if (pb == s_begin) {
-            // first pass of unit ta
-            if constexpr (STG) {
-                const int npa = unit_np(ta);
-                staged = npa > 0;
-                own_pos = staged ? a.st_own[ta] : -1;
-                ahead = false;
-                np_next = 0;
-                if (rr + 1 < r_count) {
-                    tb = ta + r_step;
-                    np_next = unit_np(tb);
-                    // the next unit's pages load during this one when both fit the cache together
-                    ahead = np_next > 0 && npa + np_next <= NS;
-                    if (ahead && tid < 64) load_unit(tb, np_next, half ^ 1);
-                }
-            }
-            // list position of the page of the unit's first row (own rows read x from the cache)
-            own_p0 = s_begin >> kStagePageShift;
-        }
-        // the following pass: in this unit, or the first pass of the next one
-        int64_t nrr = rr, nsb = s_begin, nse = s_end, npb = pb + rows_per_pass;
-        if (npb >= s_end) {
-            nrr = rr + 1;
-            if (nrr < r_count) {
-                unit_slots(r_first + nrr * r_step, r_len, nsb, nse);
-                npb = nsb;
-            }
-        }
-        const int64_t s = pb + (tid >> vls);
-        const int64_t c = cshift >= 0 ? (s >> cshift) : int64_t(uint32_t(s) / uint32_t(C));
-        const int len = s < s_end ? cl_n : 0;
-        const int64_t base = cs_n + (s - c * C);
-        const int64_t row = s < s_end && s < nrows ? (perm ? int64_t(pv_n) : s) : -1;
-        if (nrr < r_count && nsb < nse) load_meta(npb + (tid >> vls), nse, cl_n, cs_n, pv_n);  // one pass ahead
+    // One pass: the lanes' slot s (row `row`, -1 for none) with len entries at base; with x
+    // staged (staged), gathers read the LDS cache through slot_tab[half], and the own rows'
+    // x from their pages (own_pos: list position of the page of the unit's first row,
+    // own_p0 that page).
+    auto pass_body = [&](const int64_t s, const int len, const int64_t base, const int64_t row, const bool staged,
+                         const int own_pos, const int64_t own_p0, const int half) {
         const bool live = row >= 0 && col_ok;
         // Lanes without an output row (slots past the last row, or unused columns of the
         // generic kernel) read row 0 / column 0 and store into the scratch area, so no load
@@ -474,31 +402,126 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
                 store_row<X, VPT, VEC>(zdst, live ? zcs : 1, zout);
             }
         }
-        if (nrr != rr) {
-            // last pass of unit ta
-            if constexpr (STG) {
-                if (ahead) {
-                    // wave 0's copies of the next unit's pages must land before anyone reads them
-                    if (tid < 64) __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
-                    half ^= 1;
-                } else if (np_next > 0) {
-                    // the next unit's pages did not fit beside this unit's: load them now
-                    __syncthreads();
+    };
+
+    if constexpr (!STG) {
+        const int64_t t0 = int64_t(tile) * a.ntiles / a.nblocks, t1 = int64_t(tile + 1) * a.ntiles / a.nblocks;
+        s_begin = int64_t(tiles[t0]) * C;
+        s_end = int64_t(tiles[t1]) * C;
+        int64_t s = s_begin + (tid >> vls);
+        int cl_n = 0, pv_n = 0;
+        int64_t cs_n = 0;
+        if (s_begin < s_end) load_meta(s, s_end, cl_n, cs_n, pv_n);
+        // Settle the first pass's metadata here, so that at the loop head only the previous
+        // pass's stores are outstanding and the metadata loads of the following pass are not
+        // held up behind them.
+        __builtin_amdgcn_s_waitcnt(0);
+        for (; s < s_end; s += rows_per_pass) {
+            const int64_t c = cshift >= 0 ? (s >> cshift) : int64_t(uint32_t(s) / uint32_t(C));
+            const int len = cl_n;
+            const int64_t base = cs_n + (s - c * C);
+            const int64_t row = s < nrows ? (perm ? int64_t(pv_n) : s) : -1;
+            load_meta(s + rows_per_pass, s_end, cl_n, cs_n, pv_n);  // one pass ahead
+            pass_body(s, len, base, row, false, -1, 0, 0);
+        }
+    } else {
+        // The workgroup's passes over all of its units, one after another: the metadata of the next
+        // pass (in this unit or at the start of the next) is loaded one pass ahead.
+        // STG: a unit's pages are resident and listed in slot_tab[half] when its first pass starts;
+        // the first unit is staged here, each next one during the unit before it when both fit.
+        int half = 0;
+        auto unit_np = [&](int64_t u) {
+            const int n = a.st_np[u];
+            return (n > 0 && n <= NS) ? n : 0;
+        };
+        int64_t rr = 0;
+        if (r_count > 0) unit_slots(r_first, s_begin, s_end);
+        if constexpr (STG) {
+            if (r_count > 0) {
+                const int n0 = unit_np(r_first);
+                if (n0 > 0) {
                     if (tid < 64) {
-                        load_unit(tb, np_next, half ^ 1);
+                        load_unit(r_first, n0, 0);
                         __builtin_amdgcn_s_waitcnt(0);
                     }
                     __syncthreads();
-                    half ^= 1;
                 }
             }
-            s_begin = nsb;
-            s_end = nse;
         }
-        rr = nrr;
-        pb = npb;
-    }  // passes
+        int64_t pb = s_begin;  // first slot of the current pass
+        int cl_n = 0, pv_n = 0;
+        int64_t cs_n = 0;
+        if (r_count > 0 && s_begin < s_end) load_meta(pb + (tid >> vls), s_end, cl_n, cs_n, pv_n);
+        // Settle the first pass's metadata here, so that at the loop head only the previous
+        // pass's stores are outstanding and the metadata loads of the following pass are not
+        // held up behind them.
+        __builtin_amdgcn_s_waitcnt(0);
+        bool staged = false, ahead = false;
+        int own_pos = -1, np_next = 0;
+        int64_t tb = 0, own_p0 = 0;
+        while (rr < r_count) {
+            const int64_t ta = r_first + rr * r_step;
+            if (pb == s_begin) {
+                // first pass of unit ta
+                if constexpr (STG) {
+                    const int npa = unit_np(ta);
+                    staged = npa > 0;
+                    own_pos = staged ? a.st_own[ta] : -1;
+                    ahead = false;
+                    np_next = 0;
+                    if (rr + 1 < r_count) {
+                        tb = ta + r_step;
+                        np_next = unit_np(tb);
+                        // the next unit's pages load during this one when both fit the cache together
+                        ahead = np_next > 0 && npa + np_next <= NS;
+                        if (ahead && tid < 64) load_unit(tb, np_next, half ^ 1);
+                    }
+                }
+                // list position of the page of the unit's first row (own rows read x from the cache)
+                own_p0 = s_begin >> kStagePageShift;
+            }
+            // the following pass: in this unit, or the first pass of the next one
+            int64_t nrr = rr, nsb = s_begin, nse = s_end, npb = pb + rows_per_pass;
+            if (npb >= s_end) {
+                nrr = rr + 1;
+                if (nrr < r_count) {
+                    unit_slots(r_first + nrr * r_step, nsb, nse);
+                    npb = nsb;
+                }
+            }
+            const int64_t s = pb + (tid >> vls);
+            const int64_t c = cshift >= 0 ? (s >> cshift) : int64_t(uint32_t(s) / uint32_t(C));
+            const int len = s < s_end ? cl_n : 0;
+            const int64_t base = cs_n + (s - c * C);
+            const int64_t row = s < s_end && s < nrows ? (perm ? int64_t(pv_n) : s) : -1;
+            if (nrr < r_count && nsb < nse) load_meta(npb + (tid >> vls), nse, cl_n, cs_n, pv_n);  // one pass ahead
+            pass_body(s, len, base, row, staged, own_pos, own_p0, half);
+            if (nrr != rr) {
+                // last pass of unit ta
+                if constexpr (STG) {
+                    if (ahead) {
+                        // wave 0's copies of the next unit's pages must land before anyone reads them
+                        if (tid < 64) __builtin_amdgcn_s_waitcnt(0);
+                        __syncthreads();
+                        half ^= 1;
+                    } else if (np_next > 0) {
+                        // the next unit's pages did not fit beside this unit's: load them now
+                        __syncthreads();
+                        if (tid < 64) {
+                            load_unit(tb, np_next, half ^ 1);
+                            __builtin_amdgcn_s_waitcnt(0);
+                        }
+                        __syncthreads();
+                        half ^= 1;
+                    }
+                }
+                s_begin = nsb;
+                s_end = nse;
+            }
+            rr = nrr;
+            pb = npb;
+        }  // passes
+    }
 
     if (!want_dots) return;
 
@@ -546,9 +569,10 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
 
 // The flags of a step of the Chebyshev / KPM recurrence (y = alpha (A x - c x) - y with
 // <y, y> and <x, y>): the FP64 product the KPM driver runs M times gets its own compile-time
-// copy (153 VGPRs against 179 for the general epilogue; 133.9 against 135.8 us per product on
-// the 128^3 Anderson matrix at b = 8). Forcing it under 128 VGPRs for two workgroups per compute
-// unit spills and takes 186.7 us.
+// copy (130 VGPRs against 160 for the general epilogue; 133.9 against 135.8 us per product on
+// the 128^3 Anderson matrix at b = 8). Forcing it to 128 VGPRs for two workgroups per compute
+// unit (amdgpu_waves_per_eu(4)) spills a register and is slower (142.5 against 138.0 us per
+// call with its dot finish).
 constexpr uint32_t kKpmFlags = SELL_SPMV_SHIFT | SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
 
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
@@ -680,7 +704,8 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
         a.stage = 0;
     auto k = a.stage ? prod_kernel<VK, B, VPT, AUG, UB, (B > 0)> : prod_kernel<VK, B, VPT, AUG, UB>;
     if constexpr (AUG && VK == VK_F64F64 && B > 0) {
-        if (!a.stage && a.flags == kKpmFlags) k = prod_kernel<VK, B, VPT, AUG, UB, false, kKpmFlags>;
+        if (!a.stage && a.flags == kKpmFlags)
+            k = prod_kernel<VK, B, VPT, AUG, UB, false, kKpmFlags>;
     }
     if (a.stage) {
         a.nblocks = a.st_nblocks;  // the launch the plan was made for (stride checked there)
@@ -691,13 +716,7 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
     // several waves: workgroups that finish early take the next ones (uneven tiles)
     if (a.waves_hint > 1) a.nblocks = int32_t(std::min<int64_t>(int64_t(a.nblocks) * a.waves_hint, a.ntiles));
     // a tile stride needs whole columns of tiles and of workgroups
-    {
-        const int64_t units = a.stage ? int64_t(a.st_ntiles)
-                                      : a.unit_chunks > 0 ? (a.nch + a.unit_chunks - 1) / a.unit_chunks
-                                                          : int64_t(a.ntiles);
-        if (a.tile_stride > 0 && (units % a.tile_stride || a.nblocks % a.tile_stride || a.nblocks > units))
-            a.tile_stride = 0;
-    }
+    a.tile_stride = 0;  // a unit stride applies to staged launches only
     hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
     return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
 }

@@ -125,12 +125,11 @@ int sell_set_batch(sell_mat *A, int32_t batch) {
     return SELL_OK;
 }
 
-int sell_set_stage(sell_mat *A, int32_t stage, int32_t tile_stride, int32_t unit_rows) {
+int sell_set_stage(sell_mat *A, int32_t stage, int32_t tile_stride) {
     if (!A) return SELL_ERR_ARG;
-    if (stage < 0 || stage > 1 || tile_stride < 0 || unit_rows < 0) return SELL_ERR_ARG;
+    if (stage < 0 || stage > 1 || tile_stride < 0) return SELL_ERR_ARG;
     A->stage_hint = stage;
     A->tile_stride_hint = tile_stride;
-    A->unit_chunks_hint = unit_rows > 0 ? std::max<int32_t>(1, unit_rows / A->h.C) : 0;
     return SELL_OK;
 }
 

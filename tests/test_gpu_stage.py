@@ -68,10 +68,10 @@ def test_staged_equals_unstaged(sc, name, dt):
         for flags in (None, sc.SCALE | sc.AXPBY | sc.DOT_YY | sc.CHAIN | (sc.SHIFT | sc.DOT_XY | sc.DOT_XX if square else 0)):
             M.set_stage(0, 0)
             ref = _run(sc, M, X, Y0, Z0, flags, vt)
-            for stage, stride, unit in ((1, 0, 0), (1, 2, 0), (1, 3, 0), (0, 2, 0), (0, 2, 64), (0, 3, 96)):
-                M.set_stage(stage, stride, unit)
+            for stage, stride in ((1, 0), (1, 2), (1, 3), (0, 2)):
+                M.set_stage(stage, stride)
                 got = _run(sc, M, X, Y0, Z0, flags, vt)
-                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (name, dt, b, flags, stage, stride, unit)
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (name, dt, b, flags, stage, stride)
                 if flags is not None:
                     y, x = ref[0], host(X)[:A.nrows] if square else None
                     sums = [np.sum(np.abs(y * y), axis=0)]
@@ -79,7 +79,7 @@ def test_staged_equals_unstaged(sc, name, dt):
                         sums += [np.sum(np.abs(x * y), axis=0), np.sum(x * x, axis=0)]
                     for g, sm in enumerate(sums):
                         seg = slice(g * b, (g + 1) * b)
-                        assert np.all(np.abs(got[2][seg] - ref[2][seg]) <= 1e-12 * sm), (name, dt, b, stage, stride, unit, g)
+                        assert np.all(np.abs(got[2][seg] - ref[2][seg]) <= 1e-12 * sm), (name, dt, b, stage, stride, g)
             if dt == "f64" and flags is None:
                 Xh = host(X)
                 assert colwise_relerr(got[0], oracle.spmmv(A, Xh), abs_product(A, Xh)) <= 1e-12
@@ -99,8 +99,8 @@ def test_staged_kpm_full_size(sc):
     V0 = synth.block_vector(A.nrows, b, synth.SEED_X)
     M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
     out = []
-    for stage, stride, unit in ((0, 0, 0), (1, 0, 0), (1, 64, 0), (0, 64, 256)):
-        M.set_stage(stage, stride, unit)
+    for stage, stride in ((0, 0), (1, 0), (1, 64), (0, 64)):
+        M.set_stage(stage, stride)
         V = dev(V0)
         W = torch.zeros_like(V)
         mu = torch.zeros((2 * Mst + 1) * b, dtype=torch.float64, device="cuda:0")
@@ -117,7 +117,7 @@ def test_staged_kpm_full_size(sc):
 def test_stage_setter_rejects(sc):
     A = synth.laplacian2d(10)
     M = sc.SellMatrix.from_csr(A)
-    for bad in ((2, 0, 0), (-1, 0, 0), (1, -3, 0), (0, 1, -1)):
+    for bad in ((2, 0), (-1, 0), (1, -3)):
         with pytest.raises(sc.SellError):
             M.set_stage(*bad)
     M.close()
