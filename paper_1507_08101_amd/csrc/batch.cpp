@@ -123,6 +123,7 @@ BatchSeg batch_seg(const sell_batch *B) {
     sg.vblk = B->d_vblk;
     sg.K = B->K;
     sg.G = B->vgrid;
+    sg.rows = B->rows;
     return sg;
 }
 

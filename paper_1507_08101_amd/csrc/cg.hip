@@ -4,6 +4,10 @@
 // Column sums are deterministic: butterfly shuffles inside a wave, LDS across waves, one
 // partial per workgroup (plain stores), then a one-workgroup-per-column kernel adds the
 // partials in workgroup order and performs the per-column scalar updates.
+#include <algorithm>
+#include <initializer_list>
+#include <type_traits>
+
 #include "devutil.h"
 #include "internal.h"
 
@@ -21,6 +25,66 @@ __device__ void colsum_store(double v, int bpad, int b, double *partials) {
     if (lane < bpad) red[w][lane] = v;
     __syncthreads();
     if (tid < b) {
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kVT / 64; ++ww) s += red[ww][tid];
+        partials[size_t(tid) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------- 16-byte column groups
+// The iteration's two vector passes in the common case: b a multiple of the 16-byte group
+// (4 floats or 2 doubles) with a power-of-two number of groups per row (TPR <= 16), rows 16-byte
+// aligned. Each thread owns one group of every row it visits and keeps kVU rows in flight, so a
+// wave moves 1 KiB per load instruction. Every element is computed as in the per-element
+// kernels (cg_r_kernel, cg_p_kernel and their batched forms), which serve the other shapes; only
+// the order in which the column sums are accumulated differs.
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int V = 4;
+};
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int V = 2;
+};
+
+// rows in flight per thread (8, or 1024 / 4096 workgroups instead of 2048 for the batched
+// kernels, changed the batched CG times by less than 2 %)
+constexpr int kVU = 4;
+
+template <bool NT, class VT>
+__device__ __forceinline__ VT ld16(const VT *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+template <bool NT, class VT>
+__device__ __forceinline__ void st16(VT v, VT *p) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+// Per-workgroup column sums when thread t holds the sums of columns (t % TPR) * V + v.
+template <int V, int TPR>
+__device__ void colsum_store_vec(const double (&acc)[V], double *partials) {
+    __shared__ double red[kVT / 64][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        double x = acc[v];
+#pragma unroll
+        for (int m = 32; m >= TPR; m >>= 1) x += __shfl_xor(x, m, 64);
+        if (lane < TPR) red[w][lane * V + v] = x;
+    }
+    __syncthreads();
+    if (tid < TPR * V) {
         double s = 0.0;
 #pragma unroll
         for (int ww = 0; ww < kVT / 64; ++ww) s += red[ww][tid];
@@ -92,6 +156,90 @@ __global__ void __launch_bounds__(kVT) cg_p_kernel(T *P, T *X, const T *R, int64
         const double p = double(P[k]);
         X[k] = T(double(X[k]) + alpha[j] * p);
         P[k] = T(double(R[k]) + beta[j] * p);
+    }
+}
+
+// cg_r_kernel on 16-byte column groups (row pitch ldv groups)
+template <class T, int TPR, int U = kVU, bool NT = false>
+__global__ void __launch_bounds__(kVT) cg_r_vec_kernel(T *R, const T *Q, int64_t n, int64_t ldv, const double *alpha_v,
+                                                       double *partials) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::V, rows_per = kVT / TPR;
+    const int g = threadIdx.x % TPR;
+    double al[V], acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        al[v] = alpha_v[g * V + v];
+        acc[v] = 0.0;
+    }
+    VT *Rv = reinterpret_cast<VT *>(R);
+    const VT *Qv = reinterpret_cast<const VT *>(Q);
+    const int64_t st = int64_t(gridDim.x) * rows_per;
+    for (int64_t i = int64_t(blockIdx.x) * rows_per + threadIdx.x / TPR; i < n; i += U * st) {
+        VT rv[U] = {}, qv[U] = {};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < n) {
+                rv[u] = ld16<NT>(Rv + (i + u * st) * ldv + g);
+                qv[u] = ld16<NT>(Qv + (i + u * st) * ldv + g);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < n) {
+                VT o;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const T r = T(double(rv[u][v]) - al[v] * double(qv[u][v]));
+                    o[v] = r;
+                    acc[v] += double(r) * double(r);
+                }
+                st16<NT>(o, Rv + (i + u * st) * ldv + g);
+            }
+    }
+    colsum_store_vec<V, TPR>(acc, partials);
+}
+
+// cg_p_kernel on 16-byte column groups
+template <class T, int TPR, int U = kVU, bool NT = false>
+__global__ void __launch_bounds__(kVT) cg_p_vec_kernel(T *P, T *X, const T *R, int64_t n, int64_t ldv,
+                                                       const double *alpha, const double *beta) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::V, rows_per = kVT / TPR;
+    const int g = threadIdx.x % TPR;
+    double al[V], be[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        al[v] = alpha[g * V + v];
+        be[v] = beta[g * V + v];
+    }
+    VT *Pv = reinterpret_cast<VT *>(P);
+    VT *Xv = reinterpret_cast<VT *>(X);
+    const VT *Rv = reinterpret_cast<const VT *>(R);
+    const int64_t st = int64_t(gridDim.x) * rows_per;
+    for (int64_t i = int64_t(blockIdx.x) * rows_per + threadIdx.x / TPR; i < n; i += U * st) {
+        VT pv[U] = {}, xv[U] = {}, rv[U] = {};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < n) {
+                const int64_t k = (i + u * st) * ldv + g;
+                pv[u] = ld16<NT>(Pv + k);
+                xv[u] = ld16<NT>(Xv + k);
+                rv[u] = ld16<NT>(Rv + k);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < n) {
+                VT xo, po;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const double p = double(pv[u][v]);
+                    xo[v] = T(double(xv[u][v]) + al[v] * p);
+                    po[v] = T(double(rv[u][v]) + be[v] * p);
+                }
+                const int64_t k = (i + u * st) * ldv + g;
+                st16<NT>(xo, Xv + k);
+                st16<NT>(po, Pv + k);
+            }
     }
 }
 
@@ -282,6 +430,96 @@ __global__ void __launch_bounds__(kVT) bcg_p_kernel(T *P, T *D, const T *R, int 
     });
 }
 
+// bcg_r_kernel on 16-byte column groups (b = TPR * V, rows contiguous)
+template <class T, int TPR, int U = kVU, bool NT = false>
+__global__ void __launch_bounds__(kVT) bcg_r_vec_kernel(T *R, const T *Q, BatchSeg sg, BatchCg sc, double *partials) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::V, b = TPR * V, rows_per = kVT / TPR;
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int g = threadIdx.x % TPR;
+    double acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+    if (sc.sys_active[m]) {
+        double al[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) al[v] = sc.alpha[m * b + g * V + v];
+        VT *Rv = reinterpret_cast<VT *>(R);
+        const VT *Qv = reinterpret_cast<const VT *>(Q);
+        const int lb = int(blockIdx.x) - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
+        const int64_t r1 = sg.row_off[m + 1], st = int64_t(nbl) * rows_per;
+        for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / TPR; i < r1; i += U * st) {
+            VT rv[U] = {}, qv[U] = {};
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i + u * st < r1) {
+                    rv[u] = ld16<NT>(Rv + (i + u * st) * TPR + g);
+                    qv[u] = ld16<NT>(Qv + (i + u * st) * TPR + g);
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i + u * st < r1) {
+                    VT o;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const T r = T(double(rv[u][v]) - al[v] * double(qv[u][v]));
+                        o[v] = r;
+                        acc[v] += double(r) * double(r);
+                    }
+                    st16<NT>(o, Rv + (i + u * st) * TPR + g);
+                }
+        }
+    }
+    colsum_store_vec<V, TPR>(acc, partials);
+}
+
+// bcg_p_kernel on 16-byte column groups
+template <class T, int TPR, int U = kVU, bool NT = false>
+__global__ void __launch_bounds__(kVT) bcg_p_vec_kernel(T *P, T *D, const T *R, BatchSeg sg, BatchCg sc) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::V, b = TPR * V, rows_per = kVT / TPR;
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    if (!sc.sys_step[m]) return;
+    const int g = threadIdx.x % TPR;
+    double al[V], be[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        al[v] = sc.alpha[m * b + g * V + v];
+        be[v] = sc.beta[m * b + g * V + v];
+    }
+    const bool dir = sc.sys_active[m] != 0;
+    VT *Pv = reinterpret_cast<VT *>(P);
+    VT *Dv = reinterpret_cast<VT *>(D);
+    const VT *Rv = reinterpret_cast<const VT *>(R);
+    const int lb = int(blockIdx.x) - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
+    const int64_t r1 = sg.row_off[m + 1], st = int64_t(nbl) * rows_per;
+    for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / TPR; i < r1; i += U * st) {
+        VT pv[U] = {}, dv[U] = {}, rv[U] = {};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < r1) {
+                const int64_t k = (i + u * st) * TPR + g;
+                pv[u] = ld16<NT>(Pv + k);
+                dv[u] = ld16<NT>(Dv + k);
+                if (dir) rv[u] = ld16<NT>(Rv + k);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < r1) {
+                VT dn, pn;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const double p = double(pv[u][v]);
+                    dn[v] = T(double(dv[u][v]) + al[v] * p);
+                    pn[v] = T(double(rv[u][v]) + be[v] * p);
+                }
+                const int64_t k = (i + u * st) * TPR + g;
+                st16<NT>(dn, Dv + k);
+                if (dir) st16<NT>(pn, Pv + k);
+            }
+    }
+}
+
 // Per-workgroup partials of <U_j, V_j> on the rows of the systems with mask[m] != 0
 // (all systems when mask is null).
 template <class T>
@@ -404,11 +642,80 @@ int cg_launch_alpha(const double *prod_partials, int ntiles, int b, const CgDev 
     return ok();
 }
 
+// Threads per row of the 16-byte-group kernels for b columns of T, row pitch ld, and the given
+// pointers; 0 when those kernels do not apply.
+template <class T>
+static int group_tpr(int b, int64_t ld, std::initializer_list<const void *> ptrs) {
+    constexpr int V = Vec16<T>::V;
+    if (b < V || b % V || ld % V) return 0;
+    const int tpr = b / V;
+    if (tpr > 16 || (tpr & (tpr - 1))) return 0;
+    for (const void *p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) & 15u) return 0;
+    return tpr;
+}
+
+// Calls f(std::integral_constant<int, TPR>) for tpr in {1, 2, 4, 8, 16}.
+template <class F>
+static void with_tpr(int tpr, F &&f) {
+    switch (tpr) {
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 2: f(std::integral_constant<int, 2>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 8: f(std::integral_constant<int, 8>()); break;
+        default: f(std::integral_constant<int, 16>()); break;
+    }
+}
+
+// Vectors of at least this many bytes are streamed past the caches (nontemporal loads and
+// stores): with the iteration's four or five of them far larger than the 256 MB infinity cache
+// nothing is reused from it, and the nontemporal path streams faster (batched FP64 CG of 64
+// Laplacians, 710 MB vectors: 1.30 against 1.35 s). Smaller vectors stay cached: a 100^3 FP64
+// CG with 64 MB vectors runs 72 ms nontemporal against 68 ms.
+constexpr int64_t kNtBytes = int64_t(128) << 20;
+
+// Calls f(std::bool_constant<nontemporal>) for vectors of n_elems elements of T.
+template <class T, class F>
+static void with_nt(int64_t n_elems, F &&f) {
+    if (n_elems * int64_t(sizeof(T)) >= kNtBytes)
+        f(std::true_type());
+    else
+        f(std::false_type());
+}
+
+static unsigned group_grid(int64_t n, int tpr, unsigned cap) {
+    const int64_t rows_per = kVT / tpr;
+    int64_t g = (n + rows_per * kVU - 1) / (rows_per * kVU);
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>(g, cap)));
+}
+
+template <class T>
+static bool launch_r_groups(T *R, const T *Q, int64_t n, int b, int64_t ld, const CgDev &sc, double *partials,
+                            unsigned *grid, hipStream_t s) {
+    const int tpr = group_tpr<T>(b, ld, {R, Q});
+    if (!tpr) return false;
+    const unsigned g = group_grid(n, tpr, kCgMaxGrid);
+    with_tpr(tpr, [&](auto c) {
+        constexpr int TPR = decltype(c)::value;
+        with_nt<T>(n * ld, [&](auto nt) {
+            hipLaunchKernelGGL((cg_r_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(g), dim3(kVT), 0, s, R, Q, n,
+                               ld / Vec16<T>::V, sc.alpha, partials);
+        });
+    });
+    *grid = g;
+    return true;
+}
+
 int cg_launch_r(int dt, void *R, const void *Q, int64_t n, int b, int64_t ld, const CgDev &sc, double *partials,
                 hipStream_t s) {
     const int bpad = pow2_at_least(b);
-    const unsigned g = cg_reduce_grid(n, b);
-    if (dt == SELL_F64)
+    unsigned g = cg_reduce_grid(n, b);
+    if (n > 0 && (dt == SELL_F64 ? launch_r_groups(static_cast<double *>(R), static_cast<const double *>(Q), n, b, ld,
+                                                   sc, partials, &g, s)
+                                 : launch_r_groups(static_cast<float *>(R), static_cast<const float *>(Q), n, b, ld,
+                                                   sc, partials, &g, s))) {
+        // launched on 16-byte groups
+    } else if (dt == SELL_F64)
         hipLaunchKernelGGL(cg_r_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(R),
                            static_cast<const double *>(Q), n, b, bpad, ld, sc.alpha, partials);
     else
@@ -419,8 +726,28 @@ int cg_launch_r(int dt, void *R, const void *Q, int64_t n, int b, int64_t ld, co
     return ok();
 }
 
+template <class T>
+static bool launch_p_groups(T *P, T *X, const T *R, int64_t n, int b, int64_t ld, const CgDev &sc, hipStream_t s) {
+    const int tpr = group_tpr<T>(b, ld, {P, X, R});
+    if (!tpr) return false;
+    const unsigned g = group_grid(n, tpr, 2 * kCgMaxGrid);
+    with_tpr(tpr, [&](auto c) {
+        constexpr int TPR = decltype(c)::value;
+        with_nt<T>(n * ld, [&](auto nt) {
+            hipLaunchKernelGGL((cg_p_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(g), dim3(kVT), 0, s, P, X, R, n,
+                               ld / Vec16<T>::V, sc.alpha, sc.beta);
+        });
+    });
+    return true;
+}
+
 int cg_launch_p(int dt, void *P, void *X, const void *R, int64_t n, int b, int64_t ld, const CgDev &sc,
                 hipStream_t s) {
+    if (n > 0 && (dt == SELL_F64 ? launch_p_groups(static_cast<double *>(P), static_cast<double *>(X),
+                                                   static_cast<const double *>(R), n, b, ld, sc, s)
+                                 : launch_p_groups(static_cast<float *>(P), static_cast<float *>(X),
+                                                   static_cast<const float *>(R), n, b, ld, sc, s)))
+        return ok();
     const unsigned g = vgrid(n * b, 4096);
     if (dt == SELL_F64)
         hipLaunchKernelGGL(cg_p_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(P),
@@ -486,10 +813,42 @@ int bcg_launch_alpha(const double *pparts, const int32_t *pblk, int K, int b, co
     return ok();
 }
 
+template <class T>
+static bool blaunch_r_groups(T *R, const T *Q, int b, const BatchSeg &sg, const BatchCg &sc, double *partials,
+                             hipStream_t s) {
+    const int tpr = group_tpr<T>(b, b, {R, Q});
+    if (!tpr) return false;
+    with_tpr(tpr, [&](auto c) {
+        constexpr int TPR = decltype(c)::value;
+        with_nt<T>(sg.rows * b, [&](auto nt) {
+            hipLaunchKernelGGL((bcg_r_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s, R, Q,
+                               sg, sc, partials);
+        });
+    });
+    return true;
+}
+
+template <class T>
+static bool blaunch_p_groups(T *P, T *D, const T *R, int b, const BatchSeg &sg, const BatchCg &sc, hipStream_t s) {
+    const int tpr = group_tpr<T>(b, b, {P, D, R});
+    if (!tpr) return false;
+    with_tpr(tpr, [&](auto c) {
+        constexpr int TPR = decltype(c)::value;
+        with_nt<T>(sg.rows * b, [&](auto nt) {
+            hipLaunchKernelGGL((bcg_p_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s, P, D,
+                               R, sg, sc);
+        });
+    });
+    return true;
+}
+
 int bcg_launch_r(int dt, void *R, const void *Q, int b, const BatchSeg &sg, const BatchCg &sc, double *partials,
                  hipStream_t s) {
     const int bpad = pow2_at_least(b);
-    if (dt == SELL_F64)
+    if (dt == SELL_F64 ? blaunch_r_groups(tp<double>(R), ctp<double>(Q), b, sg, sc, partials, s)
+                       : blaunch_r_groups(tp<float>(R), ctp<float>(Q), b, sg, sc, partials, s)) {
+        // launched on 16-byte groups
+    } else if (dt == SELL_F64)
         hipLaunchKernelGGL(bcg_r_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), ctp<double>(Q), b, bpad,
                            sg, sc, partials);
     else
@@ -502,6 +861,9 @@ int bcg_launch_r(int dt, void *R, const void *Q, int b, const BatchSeg &sg, cons
 
 int bcg_launch_p(int dt, void *P, void *D, const void *R, int b, const BatchSeg &sg, const BatchCg &sc,
                  hipStream_t s) {
+    if (dt == SELL_F64 ? blaunch_p_groups(tp<double>(P), tp<double>(D), ctp<double>(R), b, sg, sc, s)
+                       : blaunch_p_groups(tp<float>(P), tp<float>(D), ctp<float>(R), b, sg, sc, s))
+        return ok();
     const int bpad = pow2_at_least(b);
     if (dt == SELL_F64)
         hipLaunchKernelGGL(bcg_p_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), tp<double>(D),

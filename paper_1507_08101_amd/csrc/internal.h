@@ -251,6 +251,7 @@ struct BatchSeg {
     const int64_t *row_off;  // K + 1 row offsets (device)
     const int32_t *vblk;     // K + 1 workgroup offsets of the vector kernels (device)
     int32_t K, G;            // systems; workgroups of a vector launch (vblk[K])
+    int64_t rows;            // rows of the whole batch (row_off[K])
 };
 struct BatchCg {
     double *rho, *alpha, *beta, *thresh2;  // K * b each, index m * b + j

@@ -127,7 +127,7 @@ def test_slices_do_not_change_rows(sc, b, slices):
 def test_autotune_reports_slice(sc):
     A = synth.irregular(30000, band=3000, max_len=400, seed=69)
     t = sc.sell_autotune(A, 32, "f64", cache=False)
-    assert t["slice"] in (0, 8, 16) and t["waves"] in (0, 2, 4, 8) and t["us"] <= t["default_us"]
+    assert t["slice"] in (0, 8, 16) and t["waves"] in (0, 1, 2, 4, 8) and t["us"] <= t["default_us"]
     assert t["batch"] in (0, 5, 7, 8)
     M = sc.SellMatrix.from_csr_tuned(A, 32, "f64", cache=True)
     assert M.tune["slice"] == t["slice"] and M.tune["waves"] == t["waves"] and M.tune["batch"] == t["batch"]
