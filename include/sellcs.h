@@ -394,10 +394,11 @@ int sell_tsmm_inplace(sell_bv *V, const double *X, int64_t ldx, double alpha, do
 int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu);
 
 /* Grid of the product launches of A in waves of resident workgroups: waves in {0, 1, 2, 4, 8,
- * 16}; 0 restores the construction's choice: 4 waves when the chunk lengths spread widely
+ * 16}; 0 restores the construction's choice: 16 waves when the chunk lengths spread widely
  * (coefficient of variation above 1/2), else one. Several waves let workgroups that finish early
- * take the next ones, which balances matrices whose tiles differ in speed (scattered gathers);
- * the grid never exceeds the matrix's fine tiles. Results per row are the same; dots may differ
+ * take the next ones, which balances matrices whose tiles differ in speed (scattered gathers),
+ * and keep the workgroups that run at the same time on neighbouring rows; the grid never
+ * exceeds the matrix's fine tiles (at most 4096). Results per row are the same; dots may differ
  * in the last bits. */
 int sell_set_waves(sell_mat *A, int32_t waves);
 

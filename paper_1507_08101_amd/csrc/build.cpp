@@ -122,11 +122,15 @@ int32_t choose_batch_len(const std::vector<int32_t> &cl, bool wide) {
     return best;
 }
 
-// Default grid of the product launches in waves of resident workgroups: 4 when the chunk
+// Default grid of the product launches in waves of resident workgroups: 16 when the chunk
 // lengths spread widely (coefficient of variation above 1/2: scattered long rows, whose tiles
-// run at different speeds however their entries are balanced), else 1. Measured on the 4 M-row
-// irregular matrix: one wave 875 us, several 695 us (b = 1, sigma = 1024); on stencils more
-// waves only cost (the 100^3 Laplacian, FP32 values, b = 8: 39.4 us in one wave, 53.5 in 4).
+// run at different speeds however their entries are balanced), else 1. Sixteen waves reach the
+// cap of one fine tile per workgroup on matrices of 4096 chunks or more, so the workgroups that
+// run at the same time on an XCD (dispatched in order) work on neighbouring rows and share the
+// x rows of their banded columns in its L2. Measured on the 4 M-row irregular matrix (sigma =
+// 1024): FP64 b = 8 1104 us with 4 waves, 969 with 8 or 16; BF16 values b = 8 915 / 765; FP64
+// b = 1 875 in one wave, 751 in 4, 692 in 16. On stencils more waves only cost (the 100^3
+// Laplacian, FP32 values, b = 8: 39.4 us in one wave, 53.5 in 4).
 int32_t choose_waves(const std::vector<int32_t> &cl) {
     if (cl.size() < 2) return 1;
     double s = 0.0, s2 = 0.0;
@@ -137,7 +141,7 @@ int32_t choose_waves(const std::vector<int32_t> &cl) {
     const double n = double(cl.size()), mean = s / n;
     if (mean <= 0.0) return 1;
     const double var = std::max(0.0, s2 / n - mean * mean);
-    return std::sqrt(var) > 0.5 * mean ? 4 : 1;
+    return std::sqrt(var) > 0.5 * mean ? 16 : 1;
 }
 
 int build_host_sell(HostSell &h, int64_t nrows, int64_t ncols, const int64_t *rowptr,
