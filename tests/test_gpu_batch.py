@@ -221,6 +221,34 @@ def test_batch_cg_converges(sc, mode, graph):
             obj.close()
 
 
+@pytest.mark.parametrize("mode", ["f64", "f32"])
+@pytest.mark.parametrize("b", [2, 8, 12, 16, 32])
+def test_batch_cg_every_vector_pass_width(sc, mode, b):
+    """The batched vector passes on 16-byte column groups (FP64 vectors: 1, 4, 8 and 16 groups
+    per row; FP32 vectors: 2, 4 and 8) and per element (6 FP64 groups or 3 FP32 groups at
+    b = 12; FP32 at b = 2, narrower than a group)."""
+    import torch
+
+    mats = _cg_systems()[:4]
+    M64 = [sc.SellMatrix.from_csr(A, C=32, sigma=1) for A in mats]
+    B64 = sc.SellBatch(M64)
+    Mlo = [sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype=mode) for A in mats] if mode != "f64" else []
+    Blo = sc.SellBatch(Mlo) if Mlo else None
+    Bs = [synth.block_vector(A.nrows, b, 1500 + 10 * k + b) for k, A in enumerate(mats)]
+    Xd = torch.zeros((B64.rows, b), dtype=torch.float64, device="cuda:0")
+    st = sc.sell_batch_cg(B64, Blo, dev(_stack(Bs, b)), Xd, tol=1e-10, maxit=4000)
+    X = host(Xd)
+    r0 = 0
+    for k, A in enumerate(mats):
+        assert st[k]["converged"] == 1, (k, st[k])
+        rel = _oracle_relres(A, Bs[k], X[r0:r0 + A.nrows])
+        assert np.all(rel <= 1.05e-10), (k, rel)
+        r0 += A.nrows
+    for obj in [B64, Blo] + M64 + Mlo:
+        if obj is not None:
+            obj.close()
+
+
 @pytest.mark.parametrize("mode", ["f64", "bf16"])
 def test_batch_cg_graph_equals_eager(sc, mode):
     import torch

@@ -50,6 +50,62 @@ def test_cg_fp64_reaches_tolerance(sc, b):
     M.close()
 
 
+# The iteration's two vector passes run on 16-byte column groups when b is a multiple of the
+# group (2 doubles, 4 floats) with a power-of-two number of groups per row up to 16, and per
+# element otherwise: every group count and both fallbacks (3 groups; 32 groups).
+@pytest.mark.parametrize("b", [2, 4, 6, 8, 16, 32, 64])
+def test_cg_fp64_every_vector_pass_width(sc, b):
+    A = synth.laplacian3d(9)
+    B = synth.block_vector(A.nrows, b, 40 + b)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    Xd = dev(np.zeros_like(B))
+    st = sc.sell_cg(M, dev(B), Xd, tol=TOL)
+    rr = _true_relres(A, B, host(Xd))
+    assert st["converged"] == 1 and rr.max() <= TOL * 1.001, (b, st, rr)
+    M.close()
+
+
+@pytest.mark.parametrize("b", [3, 4, 8, 12, 16, 32, 64])
+def test_cg_mixed_every_vector_pass_width(sc, b):
+    A = synth.laplacian3d(9)
+    B = synth.block_vector(A.nrows, b, 60 + b)
+    A64 = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    Alo = sc.SellMatrix.from_csr(A, C=32, sigma=1, dtype="bf16")
+    Xd = dev(np.zeros_like(B))
+    st = sc.sell_cg_mixed(A64, Alo, dev(B), Xd, tol=TOL)
+    rr = _true_relres(A, B, host(Xd))
+    assert st["converged"] == 1 and rr.max() <= TOL * 1.001, (b, st, rr)
+    A64.close()
+    Alo.close()
+
+
+def test_cg_fp64_unaligned_solution_takes_the_element_pass(sc):
+    """x 8 bytes past a 16-byte boundary sends the direction pass (which updates x) to the
+    per-element kernel, while the residual pass keeps the column groups: the two solves agree
+    to the tolerance and in their iteration counts (only the rounding of the dots differs)."""
+    import torch
+
+    A = synth.laplacian3d(12)
+    b = 8
+    B = synth.block_vector(A.nrows, b, 77)
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1)
+    out = []
+    for off in (0, 1):
+        buf = torch.zeros(A.nrows * b + 2, dtype=torch.float64, device="cuda:0")
+        Xd = buf[off:off + A.nrows * b].view(A.nrows, b)
+        assert (Xd.data_ptr() % 16 == 0) == (off == 0)
+        st = sc.sell_cg(M, dev(B), Xd, tol=TOL)
+        X = host(Xd)
+        rr = _true_relres(A, B, X)
+        assert st["converged"] == 1 and rr.max() <= TOL * 1.001, (off, st, rr)
+        out.append((X, st["iterations"]))
+    assert abs(out[0][1] - out[1][1]) <= 2
+    lmin = 6 - 6 * math.cos(math.pi / 13)
+    for j in range(b):
+        assert np.linalg.norm(out[0][0][:, j] - out[1][0][:, j]) <= 4 * TOL * np.linalg.norm(B[:, j]) / lmin
+    M.close()
+
+
 @pytest.mark.parametrize("lo", ["bf16", "f32"])
 def test_cg_mixed_reaches_tolerance(sc, lo):
     A = synth.laplacian3d(24)
