@@ -273,8 +273,10 @@ int sell_spmmv_T(const sell_mat *A, const sell_bv *X, sell_bv *Y, int determinis
  * W is a work block vector of the same shape. On return V and W hold v_M and v_{M-1}
  * (which one holds which is reported in *last_in_w, may be NULL). M >= 1.
  * step_ms: NULL for an asynchronous call; else a HOST array of M floats that receives the
- * duration of each augmented product, timed with HIP events recorded on "stream" around
- * each launch (the call then synchronises the stream before returning). */
+ * duration of each augmented product, timed with HIP events recorded on "stream" between
+ * consecutive launches (created with hipEventDisableSystemFence: timing only, no cache
+ * writeback and invalidation at each record; the call synchronises the stream before it
+ * reads them and returns). */
 int sell_kpm(const sell_mat *A, sell_bv *V, sell_bv *W, int64_t M, double s, double c,
              double *mu, int *last_in_w, float *step_ms, void *stream);
 
