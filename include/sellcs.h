@@ -25,6 +25,19 @@
  *   - Indices: local row and column indices are 32-bit (nrows, ncols < 2^31); offsets into
  *     the stored arrays are 64-bit, so a matrix may store more than 2^31 entries
  *     (Sec. 5.1 discusses 32-bit local indices).
+ *   - Environment overrides of launch shapes, read once per process, for tuning
+ *     experiments (every row is computed the same way under all of them; dot products may
+ *     differ in the last bits, from another split of the partial sums):
+ *       SELLCS_VPT=1|2|4           columns per lane of the fixed-width kernels (default up to 4)
+ *       SELLCS_BLOCKS_PER_CU=n     workgroups per compute unit of a resident grid (1..64;
+ *                                  default from the kernel's occupancy)
+ *       SELLCS_TILES=n             fine tiles of a matrix built afterwards (1..4096; default 4096)
+ *       SELLCS_BATCH_WAVES=n       grid of a batched product in waves of resident workgroups
+ *                                  (1..32; default 16)
+ *       SELLCS_XCD_MAP=0           plain workgroup-to-tile order instead of contiguous tile
+ *                                  ranges per XCD
+ *     The per-matrix setters (sell_set_launch, sell_set_waves, sell_set_batch, sell_set_slice)
+ *     take precedence where they apply.
  */
 #ifndef SELLCS_H
 #define SELLCS_H
