@@ -747,8 +747,8 @@ def parity_row(sc, torch, A, Mh, b, s, ref):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--L", type=int, default=128)
     ap.add_argument("--M", type=int, default=200)
     ap.add_argument("--b", type=int, default=8)
