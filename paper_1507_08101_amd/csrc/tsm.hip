@@ -29,7 +29,17 @@ __device__ __forceinline__ void neumaier_add(double &s, double &comp, double ter
 // row piece feeds 16 multiply-adds. The row groups' blocks are then added in group order
 // through LDS; output q = l * k + j lands in partials[q * G + g]. KAHAN: Neumaier-compensated
 // sums in both stages.
-template <bool KAHAN>
+// VEC (m and k multiples of 4, V and W rows 16-byte aligned): each thread loads its 4 + 4
+// values as 16-byte pieces with no bounds checks and keeps TV rows in flight; the rows are
+// visited in the same order, so the sums are the same bit for bit. V^T W with n = 4 M,
+// m = k = 8: 98.8 us against 118.9 for the per-element loads (1, 2, 4 or 8 rows in flight
+// within 3 %). The compensated sums keep the per-element loads: with 16-byte loads they ran
+// 156-163 us with 1 or 2 rows in flight against 157 us (within the noise between runs) and
+// 197 us with 8 rows (the Neumaier updates of more rows hold more registers).
+constexpr int kTV = 4;
+typedef double tsm_d2 __attribute__((ext_vector_type(2)));
+
+template <bool KAHAN, bool VEC, int TV = kTV>
 __global__ void __launch_bounds__(kTT) tsmttsm_partial_kernel(const double *__restrict__ V, int64_t ldv,
                                                               const double *__restrict__ W, int64_t ldw, int64_t n,
                                                               int m, int k, double *partials) {
@@ -43,7 +53,36 @@ __global__ void __launch_bounds__(kTT) tsmttsm_partial_kernel(const double *__re
     double acc[16], comp[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] = comp[e] = 0.0;
-    if (grp < groups) {
+    if (VEC && grp < groups) {
+        const int64_t st = groups;
+        for (int64_t i = r0 + grp; i < r1; i += TV * st) {
+            tsm_d2 v[TV][2], w[TV][2];
+#pragma unroll
+            for (int u = 0; u < TV; ++u)
+                if (i + u * st < r1) {
+                    const tsm_d2 *vp = reinterpret_cast<const tsm_d2 *>(V + (i + u * st) * ldv + l0);
+                    const tsm_d2 *wp = reinterpret_cast<const tsm_d2 *>(W + (i + u * st) * ldw + j0);
+                    v[u][0] = vp[0];
+                    v[u][1] = vp[1];
+                    w[u][0] = wp[0];
+                    w[u][1] = wp[1];
+                }
+#pragma unroll
+            for (int u = 0; u < TV; ++u)
+                if (i + u * st < r1) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const double va = v[u][a >> 1][a & 1], wc = w[u][c >> 1][c & 1];
+                            if (KAHAN)
+                                neumaier_add(acc[a * 4 + c], comp[a * 4 + c], va * wc);
+                            else
+                                acc[a * 4 + c] = fma(va, wc, acc[a * 4 + c]);
+                        }
+                }
+        }
+    } else if (grp < groups) {
 #pragma unroll 2
         for (int64_t i = r0 + grp; i < r1; i += groups) {
             double v[4], w[4];
@@ -174,12 +213,11 @@ int launch_tsmttsm(const double *V, int64_t ldv, const double *W, int64_t ldw, i
     if (G > 1024) G = 1024;
     if (G > max_partials / mk) G = max_partials / mk;
     if (G < 1) G = 1;
-    if (kahan)
-        hipLaunchKernelGGL(tsmttsm_partial_kernel<true>, dim3(unsigned(G)), dim3(kTT), 0, s, V, ldv, W, ldw, n, m, k,
-                           partials);
-    else
-        hipLaunchKernelGGL(tsmttsm_partial_kernel<false>, dim3(unsigned(G)), dim3(kTT), 0, s, V, ldv, W, ldw, n, m,
-                           k, partials);
+    const bool vec = m % 4 == 0 && k % 4 == 0 && ldv % 2 == 0 && ldw % 2 == 0 &&
+                     (reinterpret_cast<uintptr_t>(V) & 15u) == 0 && (reinterpret_cast<uintptr_t>(W) & 15u) == 0;
+    auto kern = kahan ? tsmttsm_partial_kernel<true, false>
+                      : (vec ? tsmttsm_partial_kernel<false, true> : tsmttsm_partial_kernel<false, false>);
+    hipLaunchKernelGGL(kern, dim3(unsigned(G)), dim3(kTT), 0, s, V, ldv, W, ldw, n, m, k, partials);
     if (hipGetLastError() != hipSuccess) return SELL_ERR_HIP;
     hipLaunchKernelGGL(tsmttsm_finish_kernel, dim3(mk), dim3(kTT), 0, s, partials, int(G), k, kahan, alpha, beta, X,
                        ldx);

@@ -51,6 +51,35 @@ def test_tsmttsm_kahan_accuracy_on_gpu(sc):
             assert abs(X[l, j] - exact) <= bound
 
 
+@pytest.mark.parametrize("m,k", [(8, 8), (4, 12), (16, 4)])
+@pytest.mark.parametrize("kahan", [False, True])
+def test_tsmttsm_aligned_path_equals_element_path(sc, m, k, kahan):
+    """m and k multiples of 4 with 16-byte aligned rows take the 16-byte-load kernel; the same
+    values in a buffer shifted by one double (rows 8 bytes off alignment) take the per-element
+    kernel. Both visit every thread's rows in the same order: equal bit for bit, and within the
+    oracle's bound."""
+    import torch
+
+    n = 123457
+    V = synth.block_vector(n, m, 170 + m)
+    W = synth.block_vector(n, k, 180 + k)
+    out = []
+    for off in (0, 1):
+        vb = torch.zeros(n * m + 2, dtype=torch.float64, device="cuda:0")
+        wb = torch.zeros(n * k + 2, dtype=torch.float64, device="cuda:0")
+        Vd = vb[off:off + n * m].view(n, m)
+        Wd = wb[off:off + n * k].view(n, k)
+        Vd.copy_(dev(V))
+        Wd.copy_(dev(W))
+        assert (Vd.data_ptr() % 16 == 0) == (off == 0)
+        Xd = torch.zeros((m, k), dtype=torch.float64, device="cuda:0")
+        sc.sell_tsmttsm(Vd, Wd, Xd, kahan=kahan)
+        out.append(host(Xd))
+    assert np.array_equal(out[0], out[1])
+    ref = oracle.tsmttsm(V, W, 1.0, 0.0, np.zeros((m, k)), kahan=kahan)
+    assert np.all(np.abs(out[0] - ref) <= 1e-12 * (np.abs(V).T @ np.abs(W)) + 1e-300)
+
+
 def test_tsmttsm_deterministic(sc):
     import torch
 
