@@ -403,7 +403,9 @@ int sell_tsmm_inplace(sell_bv *V, const double *X, int64_t ldx, double alpha, do
 
 /* Launch parameters of the product kernels for this matrix: columns per lane of the
  * fixed-width kernels (1, 2 or 4, at most the block width; 0 = default: 4 for b >= 4, else b)
- * and workgroups per compute unit (1..64, capped at the occupancy limit; 0 = the limit).
+ * and workgroups per compute unit (1..64, capped at the occupancy limit; 0 = the default:
+ * one where a lane gathers 32 bytes per entry (FP64 vectors, 4 columns per lane), else the
+ * occupancy limit).
  * Results do not depend on them (every row is computed the same way); dot products may
  * differ in the last bits (another split of the partial sums). */
 int sell_set_launch(sell_mat *A, int32_t vpt, int32_t blocks_per_cu);

@@ -712,7 +712,14 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
         return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HIP;
     }
-    a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles, a.bpc_hint);
+    // Lanes that gather 32 bytes per entry (FP64 rows, 4 columns per lane) run one workgroup per
+    // compute unit unless the caller chose (sell_set_launch): more waves of such gathers per CU
+    // slow the CU's vector memory path down (plain FP64 products at b = 8 / 16 / 32: 113 / 220 /
+    // 462 us with two workgroups per CU on the 128^3 Anderson matrix, 103 / 202 / 423 with one;
+    // FP32 vectors, 16 bytes per lane, stay faster with two).
+    int32_t bpc = a.bpc_hint;
+    if (bpc == 0 && VPT * int(sizeof(typename KTypes<VK>::X)) >= 32) bpc = 1;
+    a.nblocks = resident_grid(reinterpret_cast<const void *>(k), kBlock, a.ntiles, bpc);
     // several waves: workgroups that finish early take the next ones (uneven tiles)
     if (a.waves_hint > 1) a.nblocks = int32_t(std::min<int64_t>(int64_t(a.nblocks) * a.waves_hint, a.ntiles));
     // a tile stride needs whole columns of tiles and of workgroups
