@@ -155,6 +155,7 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
 
+    constexpr bool kDiagXin = VPT * int(sizeof(X)) >= 32;  // see the gathers below
     const int C = a.C;
     const int32_t cshift = a.cshift;
     const SELL_GLOBAL int32_t *__restrict__ perm = to_global(a.perm);
@@ -353,7 +354,18 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const int cu = ci[u] >= 0 ? ci[u] : 0;  // padding / tail: harmless in-bounds gather
-                        load_row<X, VPT, VEC>(Xp + int64_t(cu) * xrs + int64_t(jb) * xcs, xcs, xg[u]);
+                        if (AUG && kDiagXin && need_x && int64_t(cu) == rowc) {
+                            // the diagonal entry: the row's own x is in xin already (loaded for the
+                            // shift and the dots), so this lane's gather is masked off and the
+                            // CU's vector memory path carries 1/len less (128.4 against 132.8 us
+                            // for the KPM product on the 128^3 Anderson matrix at b = 8; with
+                            // 16-byte gathers the branch costs what it saves, so only lanes
+                            // that gather 32 bytes take it)
+#pragma unroll
+                            for (int t = 0; t < VPT; ++t) xg[u][t] = xin[t];
+                        } else {
+                            load_row<X, VPT, VEC>(Xp + int64_t(cu) * xrs + int64_t(jb) * xcs, xcs, xg[u]);
+                        }
                     }
                 }
 #pragma unroll
