@@ -155,7 +155,9 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
     const int VL = DYN ? (1 << vl_log2) : (B / VPT);
     const int vls = DYN ? vl_log2 : __builtin_ctz(B / VPT);
 
-    constexpr bool kDiagXin = VPT * int(sizeof(X)) >= 32;  // see the gathers below
+    // the diagonal entry from the row's own x (see the gathers below): kernels with compile-time
+    // flags whose lanes gather 32 bytes
+    constexpr bool kDiagXin = FL != 0 && VPT * int(sizeof(X)) >= 32;
     const int C = a.C;
     const int32_t cshift = a.cshift;
     const SELL_GLOBAL int32_t *__restrict__ perm = to_global(a.perm);
@@ -358,9 +360,11 @@ __device__ __forceinline__ void prod_body(const ProdArgs &a, const int tile, con
                             // the diagonal entry: the row's own x is in xin already (loaded for the
                             // shift and the dots), so this lane's gather is masked off and the
                             // CU's vector memory path carries 1/len less (128.4 against 132.8 us
-                            // for the KPM product on the 128^3 Anderson matrix at b = 8; with
-                            // 16-byte gathers the branch costs what it saves, so only lanes
-                            // that gather 32 bytes take it)
+                            // for the KPM product on the 128^3 Anderson matrix at b = 8). With
+                            // 16-byte gathers the branch costs what it saves, and in the kernels
+                            // with run-time flags it costs more (the 100^3 Laplacian with <x,y>
+                            // at b = 8: 64 -> 71 us; the 64-Laplacian batch 1336 -> 1405 us), so
+                            // only the compile-time-flag kernels that gather 32 bytes take it)
 #pragma unroll
                             for (int t = 0; t < VPT; ++t) xg[u][t] = xin[t];
                         } else {
