@@ -17,7 +17,14 @@
 //     entry k of consecutive rows are adjacent) stream coalesced.
 //   * The chunk loop takes batches of U entries (8, or 7 and 5 for rows of that length),
 //     issuing all index/value loads of a batch before its gathers, to keep enough loads in
-//     flight for HBM. Padding entries (column -1) are skipped: no gather, no arithmetic.
+//     flight. Batch slots past the chunk length are clamped to its last entry and skipped in
+//     the arithmetic; padding entries inside it (value 0 and the row's last real column) are
+//     gathered and multiplied like the others, which keeps the loop free of branches.
+//   * What bounds the kernel is the bytes its gathers carry through each CU's vector memory
+//     path (texture address and data units), more than HBM or where the gathers hit. So lanes
+//     that gather 32 bytes per entry run one workgroup per CU by default, and the KPM step's
+//     compile-time copy takes the diagonal entry from the row's own x (already loaded for the
+//     shift and the dots), with that lane masked off the gather.
 //   * Optionally (STG) x is gathered from a cache of x pages in LDS, filled by asynchronous
 //     global-to-LDS copies of the next work unit's pages during the current one, with
 //     16-bit unit-local column indices (stage.hip builds them and the slot plan).
