@@ -466,7 +466,7 @@ typedef struct {
     int32_t C;             /* chosen chunk height                                      */
     int64_t sigma;         /* chosen sorting window                                    */
     int32_t vpt;           /* chosen columns per lane (0 = default)                    */
-    int32_t blocks_per_cu; /* chosen workgroups per compute unit (0 = occupancy limit) */
+    int32_t blocks_per_cu; /* chosen workgroups per compute unit (0 = sell_set_launch default) */
     double us;             /* time of one product with the choice (microseconds)       */
     double default_us;     /* the same for C = 32, sigma = 1 and the default launch    */
     int32_t trials;        /* configurations timed; 0 when answered from the cache     */
