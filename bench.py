@@ -914,7 +914,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(frac, 4), "traffic": traffic,
                      "kernel": f"prod_kernel (FP64 values and vectors, b={args.b}, augmented, fused dots, "
-                               f"{kern_batch}-entry index batches, the KPM step's flags fixed at compile time)",
+                               f"{kern_batch}-entry index batches, the KPM step's flags fixed at compile time, "
+                               f"the diagonal entry from the row's own x)",
                      "bytes_per_launch": int(head["bytes_per_launch"]),
                      "launch_avg_us": round(head["launch_avg_us"], 2)},
         "cpu_baseline": cpu,
