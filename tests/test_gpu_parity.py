@@ -151,6 +151,24 @@ def test_aug_every_flag_combination_bit_exact_on_integers(sc, flags):
             assert np.all(got[2][seg] == -7.0), (flags, g)
 
 
+@pytest.mark.parametrize("name,sigma", [("random_ragged", 64), ("irregular_5000", 1024), ("anderson_12", 1)])
+@pytest.mark.parametrize("b", [4, 8, 16, 32])
+def test_kpm_step_flags_bit_exact_on_integers(sc, name, sigma, b):
+    """The KPM step's flag set (shift, scale, axpby, <y,y>, <x,y>) runs a compile-time copy of
+    the FP64 kernel that takes each row's diagonal entry from its own x row instead of gathering
+    it: bit-exact against the oracle on integer data for every width with 4 columns per lane, on
+    permuted rows (sigma > 1), empty and long rows, and rows without a stored diagonal."""
+    A0 = MATS[name]
+    A = synth.CSR(A0.nrows, A0.ncols, A0.rowptr, A0.col, np.rint(8 * A0.val), "int")
+    flags = sc.SHIFT | sc.SCALE | sc.AXPBY | sc.DOT_YY | sc.DOT_XY
+    kw = dict(alpha=0.5, beta=-2.0, gamma=0.25, gamma_v=None, delta=0.0, eta=1.0)
+    X, Y0, Z0, got, ref = _aug_case(sc, A, b, flags, C=32, sigma=sigma, integer=True, **kw)
+    assert np.array_equal(got[0], ref[0]), (name, b)
+    for g in (0, 1):
+        seg = slice(g * b, (g + 1) * b)
+        assert np.array_equal(got[2][seg], ref[2][seg]), (name, b, g)
+
+
 @pytest.mark.parametrize("b", [1, 2, 3, 8, 32, 33])
 @pytest.mark.parametrize("flags", [0x01 | 0x04 | 0x08 | 0x70, 0x02 | 0x08 | 0x80 | 0x10, 0xFF & ~0x01, 0x70])
 def test_aug_random_inputs(sc, b, flags):
