@@ -106,6 +106,28 @@ def test_irregular_4M_sampled_rows(sc, sigma, b, dt):
     M.close()
 
 
+def test_irregular_4M_whole_output_sigma1024_b8(sc):
+    """The irregular workload at full size in its fastest configuration (FP64, SELL-32-1024,
+    b = 8, the default 16-wave grid): every row of y against the oracle's CSR product, normwise
+    per column, and <y, y> within the dot bound."""
+    import torch
+
+    A = _irregular()
+    b = 8
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1024)
+    X = synth.block_vector(A.ncols, b, synth.SEED_X)
+    Yd = torch.zeros((A.nrows, b), dtype=torch.float64, device="cuda:0")
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv_aug(M, dev(X), Yd, flags=sc.DOT_YY, dot=dot)
+    Y = host(Yd)
+    M.close()
+    R = oracle.spmmv(A, X)
+    assert colwise_relerr(Y, R) <= 1e-12
+    d = host(dot)[:b]
+    ref = np.sum(R * R, axis=0)
+    assert np.all(np.abs(d - ref) <= 1e-12 * ref)
+
+
 def test_batch_64_laplacians_full(sc):
     """The batched workload at full size: 64 3D Dirichlet Laplacians with edges ~ U{20..100}
     (22.2 M rows), 8 right-hand sides each. The batched product (one launch) is checked row by
