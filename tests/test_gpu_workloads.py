@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import abs_product, colwise_relerr, dev, host
+from gpu_util import abs_product, assert_lowprec_product, colwise_relerr, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -126,6 +126,21 @@ def test_irregular_4M_whole_output_sigma1024_b8(sc):
     d = host(dot)[:b]
     ref = np.sum(R * R, axis=0)
     assert np.all(np.abs(d - ref) <= 1e-12 * ref)
+
+
+def test_irregular_4M_whole_output_bf16_sigma1024_b8(sc):
+    """The same at BF16 values with FP32 vectors: every element within the deterministic bound
+    of a k-term FP32 sum, gamma_k |A~||x|, against the exact product of the rounded inputs."""
+    import torch
+
+    A = _irregular()
+    b = 8
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=1024, dtype="bf16")
+    X32 = synth.block_vector(A.ncols, b, synth.SEED_X).astype(np.float32).astype(np.float64)
+    Yd = torch.zeros((A.nrows, b), dtype=torch.float32, device="cuda:0")
+    sc.sell_spmmv(M, dev(X32, torch.float32), Yd)
+    M.close()
+    assert_lowprec_product(host(Yd), A, X32, "bf16", what="irregular 4M bf16 b=8")
 
 
 def test_batch_64_laplacians_full(sc):
