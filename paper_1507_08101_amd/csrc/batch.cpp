@@ -23,9 +23,9 @@
 using namespace sellcs;
 
 namespace sellcs {
-const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw);
-const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw);
-const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw);
+const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw, uint32_t flags);
+const void *batch_kernel_f32(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw, uint32_t flags);
+const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw, uint32_t flags);
 const void *batch_mixed_kernel_f64(bool aug);
 const void *batch_mixed_kernel_f32(bool aug);
 const void *batch_mixed_kernel_bf16(bool aug);
@@ -274,9 +274,10 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     bool fixed_ok = fixed_width(b) && vec_ok(X->ptr, xrs, xcs, esize, align) && vec_ok(Y->ptr, yrs, ycs, esize, align);
     if (chain) fixed_ok = fixed_ok && vec_ok(Z->ptr, zrs, zcs, esize, align);
     const int ub = B->batch_len, ubw = B->batch_len_wide;
-    const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok, ub, ubw)
-                       : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok, ub, ubw)
-                                         : batch_kernel_bf16(b, vpt, aug, fixed_ok, ub, ubw);
+    const uint32_t kflags = aug ? o.flags : 0u;  // every matrix of the launch has these flags
+    const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok, ub, ubw, kflags)
+                       : vk == VK_F32F32 ? batch_kernel_f32(b, vpt, aug, fixed_ok, ub, ubw, kflags)
+                                         : batch_kernel_bf16(b, vpt, aug, fixed_ok, ub, ubw, kflags);
     // workgroups per matrix: waves of the resident grid split so that the busiest workgroup
     // has as little work as possible
     const int32_t G0 = product_grid(B, kern);

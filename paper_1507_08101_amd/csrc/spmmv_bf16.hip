@@ -9,9 +9,9 @@ int prod_bf16(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
 
 int transpose_bf16(ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_BF16F32>(a, s); }
 
-const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw) {
-    return aug ? batch_kernel_for<VK_BF16F32, true>(b, vpt, fixed_ok, ub, ubw)
-               : batch_kernel_for<VK_BF16F32, false>(b, vpt, fixed_ok, ub, ubw);
+const void *batch_kernel_bf16(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw, uint32_t flags) {
+    return aug ? batch_kernel_for<VK_BF16F32, true>(b, vpt, fixed_ok, ub, ubw, flags)
+               : batch_kernel_for<VK_BF16F32, false>(b, vpt, fixed_ok, ub, ubw, 0);
 }
 
 const void *batch_mixed_kernel_bf16(bool aug) {

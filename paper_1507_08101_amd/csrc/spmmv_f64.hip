@@ -9,9 +9,9 @@ int prod_f64(ProdArgs &a, bool aug, bool fixed_ok, hipStream_t s) {
 
 int transpose_f64(ProdArgs &a, hipStream_t s) { return dispatch_transpose<VK_F64F64>(a, s); }
 
-const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw) {
-    return aug ? batch_kernel_for<VK_F64F64, true>(b, vpt, fixed_ok, ub, ubw)
-               : batch_kernel_for<VK_F64F64, false>(b, vpt, fixed_ok, ub, ubw);
+const void *batch_kernel_f64(int b, int vpt, bool aug, bool fixed_ok, int ub, int ubw, uint32_t flags) {
+    return aug ? batch_kernel_for<VK_F64F64, true>(b, vpt, fixed_ok, ub, ubw, flags)
+               : batch_kernel_for<VK_F64F64, false>(b, vpt, fixed_ok, ub, ubw, 0);
 }
 
 const void *batch_mixed_kernel_f64(bool aug) {

@@ -598,12 +598,18 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
 // call with its dot finish).
 constexpr uint32_t kKpmFlags = SELL_SPMV_SHIFT | SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
 
+// The flags of a CG iteration's product (q = A p with <p, q>): the FP32-vector kernels (FP32 or
+// BF16 values, the mixed-precision solvers' inner iterations) get their own compile-time copy,
+// single-matrix and batched (100^3 Laplacian, BF16 values, b = 8: 36.0 -> 33.7 us). The FP64
+// kernel gains nothing from it (64.1 against 65.0 us) and keeps the run-time flags.
+constexpr uint32_t kCgFlags = SELL_SPMV_DOT_XY;
+
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
 // (XCD-remapped) grid work on matrix m, whose launch arguments are table[m]. A matrix m with
 // active != null and active[m] == 0 is skipped (its dot partials are zeroed). With the
 // run-time-width kernel (B == 0) and vl_log2 < 0 every matrix gets the lanes per row of its
 // own width (table[m].nb), so matrices of different block widths share the launch.
-template <int VK, int B, int VPT, bool AUG, int UB = 0>
+template <int VK, int B, int VPT, bool AUG, int UB = 0, uint32_t FL = 0>
 __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__restrict__ table,
                                                             const int32_t *__restrict__ blk_start, int K,
                                                             const int32_t *__restrict__ active, int vl_log2) {
@@ -628,7 +634,7 @@ __global__ void __launch_bounds__(kBlock) prod_batch_kernel(const ProdArgs *__re
         vls = 0;
         while ((1 << vls) < a.nb) ++vls;
     }
-    prod_body<VK, B, VPT, AUG, UB>(a, tile, vls);
+    prod_body<VK, B, VPT, AUG, UB, false, FL>(a, tile, vls);
 }
 
 // A batch whose matrices have block widths of their own, in one launch: every workgroup runs
@@ -730,6 +736,10 @@ inline int go_prod_u(ProdArgs &a, hipStream_t s) {
         if (!a.stage && a.flags == kKpmFlags)
             k = prod_kernel<VK, B, VPT, AUG, UB, false, kKpmFlags>;
     }
+    if constexpr (AUG && VK != VK_F64F64 && B > 0) {
+        if (!a.stage && a.flags == kCgFlags)
+            k = prod_kernel<VK, B, VPT, AUG, UB, false, kCgFlags>;
+    }
     if (a.stage) {
         a.nblocks = a.st_nblocks;  // the launch the plan was made for (stride checked there)
         hipLaunchKernelGGL(k, dim3(a.nblocks), dim3(kBlock), 0, s, a, vl_log2);
@@ -806,7 +816,10 @@ int dispatch_prod(ProdArgs &a, hipStream_t s, bool fixed_ok) {
 }
 
 template <int VK, int B, int VPT, bool AUG, int UB = 0>
-inline const void *bk_u() {
+inline const void *bk_u(bool cg) {
+    if constexpr (AUG && VK != VK_F64F64 && B > 0) {
+        if (cg) return reinterpret_cast<const void *>(prod_batch_kernel<VK, B, VPT, AUG, UB, kCgFlags>);
+    }
     return reinterpret_cast<const void *>(prod_batch_kernel<VK, B, VPT, AUG, UB>);
 }
 
@@ -814,34 +827,35 @@ inline const void *bk_u() {
 // lane; 5 or 7 where the width's default is 8, as for the single-matrix kernels; else the
 // default)
 template <int VK, int B, int VPT, bool AUG>
-inline const void *bk(int ub0, int ubw) {
+inline const void *bk(int ub0, int ubw, bool cg) {
     using X = typename KTypes<VK>::X;
     if constexpr (B > 0) {
         const int ub = VPT * sizeof(X) >= 32 ? ubw : ub0;
-        if (ub == 7) return bk_u<VK, B, VPT, AUG, 7>();
-        if (ub == 5) return bk_u<VK, B, VPT, AUG, 5>();
+        if (ub == 7) return bk_u<VK, B, VPT, AUG, 7>(cg);
+        if (ub == 5) return bk_u<VK, B, VPT, AUG, 5>(cg);
     }
-    return bk_u<VK, B, VPT, AUG>();
+    return bk_u<VK, B, VPT, AUG>(cg);
 }
 
 // The batched kernel for (width, columns per lane, index batch length); fixed_ok as in
 // dispatch_prod.
 template <int VK, bool AUG>
-const void *batch_kernel_for(int b, int vpt, bool fixed_ok, int ub, int ubw) {
+const void *batch_kernel_for(int b, int vpt, bool fixed_ok, int ub, int ubw, uint32_t flags) {
+    const bool cg = flags == kCgFlags;
     if (fixed_ok) {
         switch (b) {
-            case 1: return bk<VK, 1, 1, AUG>(ub, ubw);
-            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>(ub, ubw) : bk<VK, 2, 1, AUG>(ub, ubw);
-            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 4, 2, AUG>(ub, ubw) : bk<VK, 4, 1, AUG>(ub, ubw);
-            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 8, 2, AUG>(ub, ubw) : bk<VK, 8, 1, AUG>(ub, ubw);
+            case 1: return bk<VK, 1, 1, AUG>(ub, ubw, cg);
+            case 2: return vpt >= 2 ? bk<VK, 2, 2, AUG>(ub, ubw, cg) : bk<VK, 2, 1, AUG>(ub, ubw, cg);
+            case 4: return vpt >= 4 ? bk<VK, 4, 4, AUG>(ub, ubw, cg) : vpt == 2 ? bk<VK, 4, 2, AUG>(ub, ubw, cg) : bk<VK, 4, 1, AUG>(ub, ubw, cg);
+            case 8: return vpt >= 4 ? bk<VK, 8, 4, AUG>(ub, ubw, cg) : vpt == 2 ? bk<VK, 8, 2, AUG>(ub, ubw, cg) : bk<VK, 8, 1, AUG>(ub, ubw, cg);
             case 16:
-                return vpt >= 4 ? bk<VK, 16, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 16, 2, AUG>(ub, ubw) : bk<VK, 16, 1, AUG>(ub, ubw);
+                return vpt >= 4 ? bk<VK, 16, 4, AUG>(ub, ubw, cg) : vpt == 2 ? bk<VK, 16, 2, AUG>(ub, ubw, cg) : bk<VK, 16, 1, AUG>(ub, ubw, cg);
             case 32:
-                return vpt >= 4 ? bk<VK, 32, 4, AUG>(ub, ubw) : vpt == 2 ? bk<VK, 32, 2, AUG>(ub, ubw) : bk<VK, 32, 1, AUG>(ub, ubw);
+                return vpt >= 4 ? bk<VK, 32, 4, AUG>(ub, ubw, cg) : vpt == 2 ? bk<VK, 32, 2, AUG>(ub, ubw, cg) : bk<VK, 32, 1, AUG>(ub, ubw, cg);
             default: break;
         }
     }
-    return bk<VK, 0, 1, AUG>(ub, ubw);
+    return bk<VK, 0, 1, AUG>(ub, ubw, cg);
 }
 
 template <int VK, bool AUG>

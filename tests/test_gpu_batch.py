@@ -47,14 +47,15 @@ def _value_ref(A, dt):
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("b", [1, 3, 8, 32])
-@pytest.mark.parametrize("flags_name", ["plain", "shift_scale_axpby_dots", "vshift_chain_dots"])
+@pytest.mark.parametrize("flags_name", ["plain", "shift_scale_axpby_dots", "vshift_chain_dots", "cg_dot_xy"])
 def test_batch_product_vs_oracle_and_single(sc, dt, b, flags_name):
     import torch
 
     mats = _square_mats()
     flags = {"plain": 0,
              "shift_scale_axpby_dots": sc.SHIFT | sc.SCALE | sc.AXPBY | sc.DOTS,
-             "vshift_chain_dots": sc.VSHIFT | sc.SCALE | sc.AXPBY | sc.DOTS | sc.CHAIN}[flags_name]
+             "vshift_chain_dots": sc.VSHIFT | sc.SCALE | sc.AXPBY | sc.DOTS | sc.CHAIN,
+             "cg_dot_xy": sc.DOT_XY}[flags_name]
     kw = dict(alpha=0.5, beta=-1.25, gamma=0.1, delta=0.3, eta=-2.0,
               gamma_v=np.linspace(-1, 1, b) if flags & sc.VSHIFT else None)
     Ms = [sc.SellMatrix.from_csr(A, C=32 if k % 2 == 0 else 8, sigma=[1, 64, 7][k % 3], dtype=dt)
@@ -87,9 +88,10 @@ def test_batch_product_vs_oracle_and_single(sc, dt, b, flags_name):
         else:
             Yr, Zr, dr = oracle.spmmv(Ar, Xs[k]), None, None
         sl = slice(r0, r0 + A.nrows)
+        groups = [g for g, bit in enumerate((sc.DOT_YY, sc.DOT_XY, sc.DOT_XX)) if flags & bit]
         if A.nrows == 0:  # an empty matrix: no rows, its dots are zero
-            if flags & sc.DOTS:
-                assert np.all(dg[3 * b * k: 3 * b * (k + 1)] == 0.0)
+            for g in groups:
+                assert np.all(dg[3 * b * k + g * b: 3 * b * k + (g + 1) * b] == 0.0)
             continue
         scale = 0.5 * (abs_product(Ar, Xs[k]) + gmax * np.abs(Xs[k])) + 1.25 * np.abs(Ys[k]) if flags else \
             abs_product(Ar, Xs[k])
@@ -102,7 +104,9 @@ def test_batch_product_vs_oracle_and_single(sc, dt, b, flags_name):
             den = np.concatenate([np.sum(Yq * Yq + 2 * np.abs(Yq) * scale, axis=0),
                                   np.sum(np.abs(Xs[k]) * (np.abs(Yq) + scale), axis=0),
                                   np.sum(Xs[k] * Xs[k], axis=0)])
-            assert np.all(np.abs(got - dr) <= tol * den + 1e-300), (k, "dots")
+            for g in groups:
+                seg = slice(g * b, (g + 1) * b)
+                assert np.all(np.abs(got[seg] - dr[seg]) <= tol * den[seg] + 1e-300), (k, "dots", g)
         r0 += A.nrows
         # the single-matrix entry point computes every row the same way: identical y
         if flags & sc.CHAIN:

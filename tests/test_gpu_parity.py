@@ -3,6 +3,8 @@
 FP64 bar: per-column normwise relative error <= 1e-12; integer-valued inputs (exact in
 every order of summation) must agree bit for bit; dots within 1e-12 * sum |x_i y_i|.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -149,6 +151,31 @@ def test_aug_every_flag_combination_bit_exact_on_integers(sc, flags):
             assert np.array_equal(got[2][seg], ref[2][seg]), (flags, g)
         else:
             assert np.all(got[2][seg] == -7.0), (flags, g)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("b", [1, 2, 4, 8, 16, 32])
+def test_cg_product_flags_low_precision(sc, dt, b):
+    """A CG iteration's product (only <x, y>) runs a compile-time copy of the FP32-vector kernels:
+    its y is the plain product's bit for bit (no scale, shift or y input), and <x, y> matches an
+    exact sum of the GPU's own y within the dot bound."""
+    import torch
+
+    A = MATS["random_ragged"]
+    M = sc.SellMatrix.from_csr(A, C=32, sigma=64, dtype=dt)
+    X = dev(synth.block_vector(A.ncols, b, 90 + b), torch.float32)
+    Yp = torch.zeros((A.nrows, b), dtype=torch.float32, device="cuda:0")
+    Ya = torch.full((A.nrows, b), 5.0, dtype=torch.float32, device="cuda:0")
+    dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
+    sc.sell_spmmv(M, X, Yp)
+    sc.sell_spmmv_aug(M, X, Ya, flags=sc.DOT_XY, dot=dot)
+    yp, ya, x = host(Yp), host(Ya), host(X).astype(np.float64)
+    M.close()
+    assert np.array_equal(ya, yp), (dt, b)
+    d = host(dot)[b:2 * b]
+    for j in range(b):
+        terms = (x[:, j] * ya[:, j].astype(np.float64)).tolist()
+        assert abs(d[j] - math.fsum(terms)) <= 1e-12 * math.fsum(abs(t) for t in terms), (dt, b, j)
 
 
 @pytest.mark.parametrize("name,sigma", [("random_ragged", 64), ("irregular_5000", 1024), ("anderson_12", 1)])
