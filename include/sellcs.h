@@ -38,6 +38,15 @@
  *                                  ranges per XCD
  *     The per-matrix setters (sell_set_launch, sell_set_waves, sell_set_batch, sell_set_slice)
  *     take precedence where they apply.
+ *   - Diagnostics on stderr (the performance-warning and information lines of Sec. 4.1):
+ *       SELLCS_LOG=0|1|2           0 or unset: none; 1: a "[sellcs] PERFWARNING" line, once per
+ *                                  process and cause, when a product runs its slower
+ *                                  run-time-width kernel (a block width other than 1, 2, 4,
+ *                                  8, 16, 32, or block vectors that are not row-major with
+ *                                  aligned rows) or the atomic transpose; 2: also a
+ *                                  "[sellcs] INFO" line for each build (shape, stored
+ *                                  entries, chunks, tiles, batch length, grid) and each
+ *                                  autotuning result
  */
 #ifndef SELLCS_H
 #define SELLCS_H

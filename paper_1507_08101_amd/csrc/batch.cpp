@@ -19,6 +19,7 @@
 #include <utility>
 
 #include "internal.h"
+#include "log.h"
 
 using namespace sellcs;
 
@@ -273,6 +274,12 @@ int batch_aug_impl(sell_batch *B, const sell_bv *X, sell_bv *Y, sell_bv *Z, cons
     if (chain) bv_strides(Z, zrs, zcs);
     bool fixed_ok = fixed_width(b) && vec_ok(X->ptr, xrs, xcs, esize, align) && vec_ok(Y->ptr, yrs, ycs, esize, align);
     if (chain) fixed_ok = fixed_ok && vec_ok(Z->ptr, zrs, zcs, esize, align);
+    if (!fixed_ok)
+        log_warn_once(kWarnBatchGeneral,
+                      "batched product with block width %d and these block vectors (a width other than 1, 2, "
+                      "4, 8, 16, 32, or rows that are not row-major and %d-byte aligned): the run-time-width "
+                      "kernel runs",
+                      b, align);
     const int ub = B->batch_len, ubw = B->batch_len_wide;
     const uint32_t kflags = aug ? o.flags : 0u;  // every matrix of the launch has these flags
     const void *kern = vk == VK_F64F64   ? batch_kernel_f64(b, vpt, aug, fixed_ok, ub, ubw, kflags)

@@ -11,6 +11,7 @@
 
 #include "convert.h"
 #include "internal.h"
+#include "log.h"
 
 using namespace sellcs;
 
@@ -352,6 +353,19 @@ int check_product_operands(const sell_mat *A, const sell_bv *X, const sell_bv *Y
     return SELL_OK;
 }
 
+// SELLCS_LOG >= 2: what a build made
+void log_built(const sell_mat *M, const char *where) {
+    if (log_level() < 2) return;
+    const HostSell &h = M->h;
+    static const char *const kType[] = {"f64", "f32", "bf16"};
+    log_info("built SELL-%d-%lld %s: %lld x %lld, %lld nonzeros, %lld stored (%.4f per nonzero), %lld chunks, "
+             "%d tiles, %s values, index batch %d (%d for 32-byte lanes), grid of %d wave(s)",
+             int(h.C), (long long)h.sigma, where, (long long)h.nrows, (long long)h.ncols, (long long)h.nnz,
+             (long long)h.stored, h.nnz > 0 ? double(h.stored) / double(h.nnz) : 1.0, (long long)h.nch,
+             int(M->ntiles), h.vdt >= 0 && h.vdt <= 2 ? kType[h.vdt] : "?", int(h.batch), int(h.batch_wide),
+             int(h.waves));
+}
+
 int build_common(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowptr, const int32_t *col,
                  const double *val, int32_t C, int64_t sigma, sell_dtype vdt, bool device, hipStream_t s) {
     if (!A) return SELL_ERR_ARG;
@@ -379,6 +393,7 @@ int build_common(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t *rowp
             return rc;
         }
     }
+    log_built(M, device ? "from host CSR" : "in host memory only");
     *A = M;
     return SELL_OK;
 }
@@ -427,6 +442,7 @@ int sell_build_device(sell_mat **A, int64_t nrows, int64_t ncols, const int64_t 
         delete M;
         return rc;
     }
+    log_built(M, "on the device");
     *A = M;
     return SELL_OK;
 }
@@ -824,6 +840,9 @@ int sell_spmmv_T(const sell_mat *A, const sell_bv *X, sell_bv *Y, int determinis
         sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
         return aug_impl(A->transpose, X, Y, nullptr, o, false, s);
     }
+    log_warn_once(kWarnAtomicTranspose,
+                  "transposed product by atomic scatter (deterministic = 0): it is much slower than the "
+                  "deterministic transpose, which builds a SELL copy of the transpose once per matrix");
     int64_t yrs, ycs;
     bv_strides(Y, yrs, ycs);
     if ((rc = launch_fill(Y->ptr, Y->dt, Y->nrows, Y->ncols, yrs, ycs, 0.0, s))) return rc;

@@ -62,7 +62,7 @@ struct HostSell {
     std::vector<int64_t> rowptr;  // CSR row pointers of the input (for export and updates)
     int32_t batch = 8;            // index batch length suited to the chunk lengths (5, 7 or 8)
     int32_t batch_wide = 7;       // the same for the kernels gathering 32 bytes per lane (5 or 7)
-    int32_t waves = 1;            // default product grid in waves of resident workgroups (1 or 4)
+    int32_t waves = 1;            // default product grid in waves of resident workgroups (1 or 16)
 };
 
 // Work partitions: contiguous chunk ranges of roughly equal cost.

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "log.h"
 
 using namespace sellcs;
 
@@ -317,6 +318,11 @@ int sell_autotune(int64_t nrows, int64_t ncols, const int64_t *rowptr, const int
         std::lock_guard<std::mutex> lk(g_mu);
         g_cache[key] = res;
     }
+    log_info("autotune %lld x %lld, b = %d: C = %d, sigma = %lld, %d columns per lane, %d workgroup(s) per CU, "
+             "slice %d, %d wave(s), index batch %d: %.1f us against %.1f us for SELL-32-1 (%d trials)",
+             (long long)nrows, (long long)ncols, int(b), int(res.C), (long long)res.sigma, int(res.vpt),
+             int(res.blocks_per_cu), int(res.slice), int(res.waves), int(res.batch), res.us, res.default_us,
+             int(res.trials));
     *out = res;
     return SELL_OK;
 }

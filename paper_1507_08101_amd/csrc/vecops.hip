@@ -7,6 +7,7 @@
 #include "convert.h"
 #include "devutil.h"
 #include "internal.h"
+#include "log.h"
 
 namespace sellcs {
 
@@ -73,6 +74,18 @@ int launch_product(ProdArgs &a, int vk, bool aug, hipStream_t s) {
     bool fixed_ok = fixed_width(a.nb) && vec_ok(a.X, a.xrs, a.xcs, esize, align) &&
                     vec_ok(a.Y, a.yrs, a.ycs, esize, align);
     if (aug && (a.flags & SELL_SPMV_CHAIN)) fixed_ok = fixed_ok && vec_ok(a.Z, a.zrs, a.zcs, esize, align);
+    if (!fixed_ok) {
+        if (!fixed_width(a.nb))
+            log_warn_once(kWarnProductWidth,
+                          "block width %d has no fixed-width product kernel (1, 2, 4, 8, 16 and 32 have; "
+                          "sell_set_slice splits a block into such slices): the run-time-width kernel runs",
+                          a.nb);
+        else
+            log_warn_once(kWarnProductLayout,
+                          "block vectors that are not row-major with %d-byte aligned rows (column-major, "
+                          "strided or offset views): the run-time-width kernel runs",
+                          align);
+    }
     switch (vk) {
         case VK_F64F64: return prod_f64(a, aug, fixed_ok, s);
         case VK_F32F32: return prod_f32(a, aug, fixed_ok, s);

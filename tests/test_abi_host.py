@@ -204,3 +204,41 @@ def test_batch_length_choice(sc, name, make, C, sigma, batch, wide):
             M.set_batch(bad)
     assert M.info["batch"] == batch
     M.close()
+
+
+_LOG_SCRIPT = r"""
+import sys
+sys.path.insert(0, sys.argv[1])
+import paper_1507_08101_amd as sc, synth
+A = synth.laplacian2d(6)
+M = sc.SellMatrix.from_csr(A, C=4, sigma=8, host_only=True)
+info = M.info
+print(info["stored"], info["nchunks"], flush=True)
+M.close()
+"""
+
+
+@pytest.mark.parametrize("level", [None, "0", "1", "2"])
+def test_log_level_lines(sc, level):
+    """SELLCS_LOG: nothing at 0 (or unset) and 1 for a build, which has no performance warning;
+    at 2 one INFO line that states what the build made."""
+    import subprocess
+    import sys
+
+    env = dict(os.environ)
+    env.pop("SELLCS_LOG", None)
+    if level is not None:
+        env["SELLCS_LOG"] = level
+    r = subprocess.run([sys.executable, "-c", _LOG_SCRIPT, ROOT], env=env, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    stored, nch = (int(v) for v in r.stdout.split())
+    lines = [ln for ln in r.stderr.splitlines() if ln.startswith("[sellcs]")]
+    if level != "2":
+        assert lines == []
+        return
+    assert len(lines) == 1, lines
+    # laplacian2d(6): 36 rows, N^2 + 4N(N-1) = 156 nonzeros
+    assert lines[0].startswith(f"[sellcs] INFO built SELL-4-8 in host memory only: 36 x 36, 156 nonzeros, "
+                               f"{stored} stored ({stored / 156:.4f} per nonzero), {nch} chunks, "), lines[0]
+    assert "f64 values" in lines[0]
