@@ -2,14 +2,12 @@
 // advanced by the same kernel launches.
 //
 // Every system m (matrix A_m of the batch, right-hand sides B_m, one CG per column) keeps its
-// own FP64 scalars on the device. One iteration over the whole batch is five launches:
-//   Q = A P            batched product with the fused <p, A p> per system and column
-//   alpha              one workgroup per system
-//   R -= a Q           segmented vector kernel with the partials of <r, r>
-//   beta, rho, flags   one workgroup per system (a system whose columns have all converged
+// own FP64 scalars on the device. One iteration over the whole batch is four launches:
+//   Q = A P            batched product with the fused <p, q> and <q, q> per system and column
+//   alpha, beta        one workgroup per system (beta from <r', r'> = alpha^2 <q, q> - rho)
+//   R -= a Q, D += a P, P = R + b P   one segmented vector pass with the partials of <r, r>
+//   rho, flags         one workgroup per system (a system whose columns have all converged
 //                      drops out: the product and vector kernels skip it)
-//   D += a P, P = R + b P   segmented vector kernel: the step along the old direction (for
-//                      every system that took it) and the new direction, in one pass
 // Runs of kCheckEvery iterations are captured in a HIP graph and replayed (or launched
 // directly); the host looks at the scalars between runs. The launches of an iteration are
 // spread over the systems that still iterate only: whenever that set changes, the resident
@@ -185,8 +183,8 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     const int32_t Gv = 2 * kCgMaxGrid;  // vector-kernel workgroups of an iteration
     const size_t gmax = size_t(std::max(std::max(sg.G, Gv), K));
     const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * gmax;
-    // active, sys_active, mask, sys_step | iters (int64) | column mask | iteration workgroup offsets
-    const size_t ni = Kb + 3 * size_t(K) + 2 * size_t(K) + 2 + Kb + size_t(K) + 1;
+    // active, sys_active, mask | iters (int64) | column mask | iteration workgroup offsets
+    const size_t ni = Kb + 2 * size_t(K) + 2 * size_t(K) + 2 + Kb + size_t(K) + 1;
     if ((rc = DB.alloc(&pscal, nd * sizeof(double) + ni * sizeof(int32_t) + 16)))
         return rc;
     double *d = static_cast<double *>(pscal);
@@ -202,8 +200,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     sc.active = ip;
     sc.sys_active = ip + Kb;
     int32_t *mask_d = ip + Kb + K;
-    sc.sys_step = ip + Kb + 2 * size_t(K);
-    int64_t *iters_d = reinterpret_cast<int64_t *>(ip + Kb + 3 * size_t(K));
+    int64_t *iters_d = reinterpret_cast<int64_t *>(ip + Kb + 2 * size_t(K));
     // align the int64 counters
     iters_d = reinterpret_cast<int64_t *>((reinterpret_cast<uintptr_t>(iters_d) + 7) & ~uintptr_t(7));
     sc.iters = iters_d;
@@ -322,7 +319,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     };
 
     sell_spmv_opts po = SELL_SPMV_OPTS_INIT;
-    po.flags = SELL_SPMV_DOT_XY;
+    po.flags = SELL_SPMV_DOT_XY | SELL_SPMV_DOT_YY;
     auto iteration = [&]() -> int {
         int r;
         const int32_t *pblk = nullptr;
@@ -330,10 +327,9 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         if ((r = batch_aug_impl(Ain, &P, &Q, nullptr, po, true, sc.sys_active, appo_active.data(), false, s, &pblk,
                                 &pparts, true)))
             return r;
-        if ((r = bcg_launch_alpha(pparts, pblk, K, b, sc, s))) return r;
+        if ((r = bcg_launch_step(pparts, pblk, K, b, sc, s))) return r;
         if (sgi.G == 0) return SELL_OK;
-        if ((r = bcg_launch_r(idt, pr, pq, b, sgi, sc, vparts, s))) return r;
-        return bcg_launch_p(idt, pp, pd, pr, b, sgi, sc, s);
+        return bcg_launch_rp(idt, pr, pq, pp, pd, b, sgi, sc, vparts, s);
     };
 
     Graph graph;

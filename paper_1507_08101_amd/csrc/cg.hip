@@ -33,12 +33,12 @@ __device__ void colsum_store(double v, int bpad, int b, double *partials) {
 }
 
 // ---------------------------------------------------------------- 16-byte column groups
-// The iteration's two vector passes in the common case: b a multiple of the 16-byte group
+// The iteration's vector pass in the common case: b a multiple of the 16-byte group
 // (4 floats or 2 doubles) with a power-of-two number of groups per row (TPR <= 16), rows 16-byte
 // aligned. Each thread owns one group of every row it visits and keeps kVU rows in flight, so a
 // wave moves 1 KiB per load instruction. Every element is computed as in the per-element
-// kernels (cg_r_kernel, cg_p_kernel and their batched forms), which serve the other shapes; only
-// the order in which the column sums are accumulated differs.
+// kernels (cg_rp_kernel and its batched form), which serve the other shapes; only the order in
+// which the column sums are accumulated differs.
 template <class T>
 struct Vec16;
 template <>
@@ -99,31 +99,49 @@ __device__ double sum_partials(const double *p, int n) {
     return block_sum_256(s);
 }
 
-// alpha_j = rho_j / <p, A p>_j for active columns, from the product's tile partials
-// (quantity b + j). One workgroup per column.
-__global__ void __launch_bounds__(kVT) cg_alpha_kernel(const double *prod_partials, int ntiles, int b, CgDev sc) {
+// The scalars of iteration k for column j, from the product's tile partials of <q, q>
+// (quantity j) and <p, q> (quantity b + j), q = A p:
+//   alpha = rho / <p, q>,  beta = (alpha^2 <q, q> - rho) / rho.
+// With r' = r - alpha q, <r', r'> = rho - 2 alpha <r, q> + alpha^2 <q, q>, and <r, q> = <p, q>
+// because p - r is a multiple of the previous direction, which is A-conjugate to p; so the
+// numerator of beta is <r', r'> before r' exists, and the residual, the step and the new
+// direction are updated in one pass (the single-reduction form of Rupp et al., ACM TOMS 43(2),
+// 2016). rho itself stays the directly summed <r, r>, which also decides convergence. A
+// numerator that cancels to zero or below restarts the column from p = r' (beta = 0).
+__global__ void __launch_bounds__(kVT) cg_step_kernel(const double *prod_partials, int ntiles, int b, CgDev sc) {
     const int j = blockIdx.x;
+    const double qq = sum_partials(prod_partials + size_t(j) * ntiles, ntiles);
     const double pq = sum_partials(prod_partials + size_t(b + j) * ntiles, ntiles);
     if (threadIdx.x == 0) {
+        const double rho = sc.rho[j];
+        const bool act = sc.active[j] != 0;
+        const double al = (act && pq != 0.0) ? rho / pq : 0.0;
+        const double num = al * al * qq - rho;
         sc.pq[j] = pq;
-        sc.alpha[j] = (sc.active[j] && pq != 0.0) ? sc.rho[j] / pq : 0.0;
+        sc.alpha[j] = al;
+        sc.beta[j] = (act && rho != 0.0 && num > 0.0) ? num / rho : 0.0;
     }
 }
 
-// r -= alpha q ; per-workgroup partials of <r, r>. (x is advanced by the direction kernel,
-// which reads p anyway: one pass over x, p, r and q fewer per iteration.)
+// The iteration's vector pass: r' = r - alpha q, x += alpha p, p = r' + beta p, with the
+// per-workgroup partials of <r', r'>. (x, the solution or the correction, takes the step
+// along the direction before it is replaced.)
 template <class T>
-__global__ void __launch_bounds__(kVT) cg_r_kernel(T *R, const T *Q, int64_t n, int b, int bpad, int64_t ld,
-                                                   const double *alpha_v, double *partials) {
+__global__ void __launch_bounds__(kVT) cg_rp_kernel(T *R, const T *Q, T *P, T *X, int64_t n, int b, int bpad,
+                                                    int64_t ld, const double *alpha_v, const double *beta_v,
+                                                    double *partials) {
     const int tid = threadIdx.x;
     const int j = tid & (bpad - 1);
     const int rows_per = kVT / bpad;
     double acc = 0.0;
     if (j < b) {
-        const double alpha = alpha_v[j];
+        const double al = alpha_v[j], be = beta_v[j];
         for (int64_t i = int64_t(blockIdx.x) * rows_per + tid / bpad; i < n; i += int64_t(gridDim.x) * rows_per) {
             const int64_t e = i * ld + j;
-            const T r = T(double(R[e]) - alpha * double(Q[e]));
+            const double p = double(P[e]);
+            const T r = T(double(R[e]) - al * double(Q[e]));
+            X[e] = T(double(X[e]) + al * p);
+            P[e] = T(double(r) + be * p);
             R[e] = r;
             acc += double(r) * double(r);
         }
@@ -131,116 +149,68 @@ __global__ void __launch_bounds__(kVT) cg_r_kernel(T *R, const T *Q, int64_t n, 
     colsum_store(acc, bpad, b, partials);
 }
 
-// rho_new = <r, r>; beta = rho_new / rho; rho = rho_new; active &= rho_new > thresh2.
-__global__ void __launch_bounds__(kVT) cg_beta_kernel(const double *partials, int G, CgDev sc) {
+// rho = <r, r> from the vector pass's partials; active &= rho > thresh2.
+__global__ void __launch_bounds__(kVT) cg_rho_kernel(const double *partials, int G, CgDev sc) {
     const int j = blockIdx.x;
     const double rn = sum_partials(partials + size_t(j) * G, G);
     if (threadIdx.x == 0) {
-        const double rho = sc.rho[j];
         const bool act = sc.active[j] != 0;
-        sc.beta[j] = (act && rho != 0.0) ? rn / rho : 0.0;
         sc.rho[j] = rn;
         sc.active[j] = (act && rn > sc.thresh2[j]) ? 1 : 0;
     }
 }
 
-// x += alpha p (the iteration's step along the old direction), then p = r + beta p
-template <class T>
-__global__ void __launch_bounds__(kVT) cg_p_kernel(T *P, T *X, const T *R, int64_t n, int b, int64_t ld,
-                                                   const double *alpha, const double *beta) {
-    const int64_t N = n * b;
-    for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
-        const int64_t i = e / b;
-        const int j = int(e - i * b);
-        const int64_t k = i * ld + j;
-        const double p = double(P[k]);
-        X[k] = T(double(X[k]) + alpha[j] * p);
-        P[k] = T(double(R[k]) + beta[j] * p);
-    }
-}
-
-// cg_r_kernel on 16-byte column groups (row pitch ldv groups)
+// cg_rp_kernel on 16-byte column groups (row pitch ldv groups)
 template <class T, int TPR, int U = kVU, bool NT = false>
-__global__ void __launch_bounds__(kVT) cg_r_vec_kernel(T *R, const T *Q, int64_t n, int64_t ldv, const double *alpha_v,
-                                                       double *partials) {
+__global__ void __launch_bounds__(kVT) cg_rp_vec_kernel(T *R, const T *Q, T *P, T *X, int64_t n, int64_t ldv,
+                                                        const double *alpha_v, const double *beta_v,
+                                                        double *partials) {
     using VT = typename Vec16<T>::type;
     constexpr int V = Vec16<T>::V, rows_per = kVT / TPR;
     const int g = threadIdx.x % TPR;
-    double al[V], acc[V];
+    double al[V], be[V], acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         al[v] = alpha_v[g * V + v];
+        be[v] = beta_v[g * V + v];
         acc[v] = 0.0;
     }
     VT *Rv = reinterpret_cast<VT *>(R);
     const VT *Qv = reinterpret_cast<const VT *>(Q);
-    const int64_t st = int64_t(gridDim.x) * rows_per;
-    for (int64_t i = int64_t(blockIdx.x) * rows_per + threadIdx.x / TPR; i < n; i += U * st) {
-        VT rv[U] = {}, qv[U] = {};
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (i + u * st < n) {
-                rv[u] = ld16<NT>(Rv + (i + u * st) * ldv + g);
-                qv[u] = ld16<NT>(Qv + (i + u * st) * ldv + g);
-            }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (i + u * st < n) {
-                VT o;
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const T r = T(double(rv[u][v]) - al[v] * double(qv[u][v]));
-                    o[v] = r;
-                    acc[v] += double(r) * double(r);
-                }
-                st16<NT>(o, Rv + (i + u * st) * ldv + g);
-            }
-    }
-    colsum_store_vec<V, TPR>(acc, partials);
-}
-
-// cg_p_kernel on 16-byte column groups
-template <class T, int TPR, int U = kVU, bool NT = false>
-__global__ void __launch_bounds__(kVT) cg_p_vec_kernel(T *P, T *X, const T *R, int64_t n, int64_t ldv,
-                                                       const double *alpha, const double *beta) {
-    using VT = typename Vec16<T>::type;
-    constexpr int V = Vec16<T>::V, rows_per = kVT / TPR;
-    const int g = threadIdx.x % TPR;
-    double al[V], be[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        al[v] = alpha[g * V + v];
-        be[v] = beta[g * V + v];
-    }
     VT *Pv = reinterpret_cast<VT *>(P);
     VT *Xv = reinterpret_cast<VT *>(X);
-    const VT *Rv = reinterpret_cast<const VT *>(R);
     const int64_t st = int64_t(gridDim.x) * rows_per;
     for (int64_t i = int64_t(blockIdx.x) * rows_per + threadIdx.x / TPR; i < n; i += U * st) {
-        VT pv[U] = {}, xv[U] = {}, rv[U] = {};
+        VT rv[U] = {}, qv[U] = {}, pv[U] = {}, xv[U] = {};
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (i + u * st < n) {
                 const int64_t k = (i + u * st) * ldv + g;
+                rv[u] = ld16<NT>(Rv + k);
+                qv[u] = ld16<NT>(Qv + k);
                 pv[u] = ld16<NT>(Pv + k);
                 xv[u] = ld16<NT>(Xv + k);
-                rv[u] = ld16<NT>(Rv + k);
             }
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (i + u * st < n) {
-                VT xo, po;
+                VT ro, xo, po;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const double p = double(pv[u][v]);
+                    const T r = T(double(rv[u][v]) - al[v] * double(qv[u][v]));
+                    ro[v] = r;
                     xo[v] = T(double(xv[u][v]) + al[v] * p);
-                    po[v] = T(double(rv[u][v]) + be[v] * p);
+                    po[v] = T(double(r) + be[v] * p);
+                    acc[v] += double(r) * double(r);
                 }
                 const int64_t k = (i + u * st) * ldv + g;
+                st16<NT>(ro, Rv + k);
                 st16<NT>(xo, Xv + k);
                 st16<NT>(po, Pv + k);
             }
     }
+    colsum_store_vec<V, TPR>(acc, partials);
 }
 
 // per-workgroup partials of <U_j, V_j>
@@ -344,37 +314,46 @@ __device__ __forceinline__ void seg_rows(const BatchSeg &sg, int m, int bpad, F 
         f(i);
 }
 
-// alpha[m, j] = rho[m, j] / <p, A p>[m, j] from the batched product's partials (quantity
-// b + j of matrix m: pparts + 3 b pblk[m] + (b + j) npm, npm = pblk[m+1] - pblk[m]).
-// One workgroup per system.
-__global__ void __launch_bounds__(kVT) bcg_alpha_kernel(const double *pparts, const int32_t *pblk, int b,
-                                                        BatchCg sc) {
+// alpha[m, j] and beta[m, j] of every system that iterates, as cg_step_kernel computes them, from
+// the batched product's partials of matrix m (quantity t at pparts + 3 b pblk[m] + t npm,
+// npm = pblk[m+1] - pblk[m]; <q, q> is quantity j, <p, q> quantity b + j). One workgroup per system.
+__global__ void __launch_bounds__(kVT) bcg_step_kernel(const double *pparts, const int32_t *pblk, int b,
+                                                       BatchCg sc) {
     const int m = blockIdx.x;
     if (!sc.sys_active[m]) return;
     const int npm = pblk[m + 1] - pblk[m];
     const double *base = pparts + size_t(3) * b * pblk[m];
     for (int j = 0; j < b; ++j) {
+        const double qq = sum_partials(base + size_t(j) * npm, npm);
         const double pq = sum_partials(base + size_t(b + j) * npm, npm);
         if (threadIdx.x == 0) {
             const int q = m * b + j;
-            sc.alpha[q] = (sc.active[q] && pq != 0.0) ? sc.rho[q] / pq : 0.0;
+            const double rho = sc.rho[q];
+            const bool act = sc.active[q] != 0;
+            const double al = (act && pq != 0.0) ? rho / pq : 0.0;
+            const double num = al * al * qq - rho;
+            sc.alpha[q] = al;
+            sc.beta[q] = (act && rho != 0.0 && num > 0.0) ? num / rho : 0.0;
         }
     }
 }
 
-// r -= alpha q on the rows of active systems; partials of <r, r> (d is advanced by the
-// direction kernel).
+// The vector pass of cg_rp_kernel on the rows of the systems that iterate: r' = r - alpha q,
+// d += alpha p, p = r' + beta p, with the partials of <r', r'>.
 template <class T>
-__global__ void __launch_bounds__(kVT) bcg_r_kernel(T *R, const T *Q, int b, int bpad, BatchSeg sg, BatchCg sc,
-                                                    double *partials) {
+__global__ void __launch_bounds__(kVT) bcg_rp_kernel(T *R, const T *Q, T *P, T *D, int b, int bpad, BatchSeg sg,
+                                                     BatchCg sc, double *partials) {
     const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
     const int j = threadIdx.x & (bpad - 1);
     double acc = 0.0;
     if (j < b && sc.sys_active[m]) {
-        const double alpha = sc.alpha[m * b + j];
+        const double al = sc.alpha[m * b + j], be = sc.beta[m * b + j];
         seg_rows(sg, m, bpad, [&](int64_t i) {
             const int64_t e = i * b + j;
-            const T r = T(double(R[e]) - alpha * double(Q[e]));
+            const double p = double(P[e]);
+            const T r = T(double(R[e]) - al * double(Q[e]));
+            D[e] = T(double(D[e]) + al * p);
+            P[e] = T(double(r) + be * p);
             R[e] = r;
             acc += double(r) * double(r);
         });
@@ -382,14 +361,11 @@ __global__ void __launch_bounds__(kVT) bcg_r_kernel(T *R, const T *Q, int b, int
     colsum_store(acc, bpad, b, partials);
 }
 
-// rho_new = <r, r>; beta = rho_new / rho; rho = rho_new; active &= rho_new > thresh2;
-// the system stays active while one of its columns is; its iteration counter advances.
-__global__ void __launch_bounds__(kVT) bcg_beta_kernel(const double *partials, int G, BatchSeg sg, int b,
-                                                       BatchCg sc) {
+// rho = <r, r> from the vector pass's partials; active &= rho > thresh2; the system stays
+// active while one of its columns is; its iteration counter advances.
+__global__ void __launch_bounds__(kVT) bcg_rho_kernel(const double *partials, int G, BatchSeg sg, int b,
+                                                      BatchCg sc) {
     const int m = blockIdx.x;
-    // sys_step[m]: the system took this iteration's step (the direction kernel advances its d
-    // even when the step retired its last column)
-    if (threadIdx.x == 0) sc.sys_step[m] = sc.sys_active[m];
     if (!sc.sys_active[m]) return;
     const int v0 = sg.vblk[m], nv = sg.vblk[m + 1] - v0;
     int any = 0;
@@ -397,11 +373,8 @@ __global__ void __launch_bounds__(kVT) bcg_beta_kernel(const double *partials, i
         const double rn = sum_partials(partials + size_t(j) * G + v0, nv);
         if (threadIdx.x == 0) {
             const int q = m * b + j;
-            const double rho = sc.rho[q];
-            const bool act = sc.active[q] != 0;
-            sc.beta[q] = (act && rho != 0.0) ? rn / rho : 0.0;
+            const int still = (sc.active[q] && rn > sc.thresh2[q]) ? 1 : 0;
             sc.rho[q] = rn;
-            const int still = (act && rn > sc.thresh2[q]) ? 1 : 0;
             sc.active[q] = still;
             any |= still;
         }
@@ -412,27 +385,10 @@ __global__ void __launch_bounds__(kVT) bcg_beta_kernel(const double *partials, i
     }
 }
 
-// d += alpha p on the rows of the systems that took this iteration's step, then p = r + beta p
-// on the rows of the systems still active
-template <class T>
-__global__ void __launch_bounds__(kVT) bcg_p_kernel(T *P, T *D, const T *R, int b, int bpad, BatchSeg sg,
-                                                    BatchCg sc) {
-    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
-    const int j = threadIdx.x & (bpad - 1);
-    if (j >= b || !sc.sys_step[m]) return;
-    const double alpha = sc.alpha[m * b + j], beta = sc.beta[m * b + j];
-    const bool dir = sc.sys_active[m] != 0;
-    seg_rows(sg, m, bpad, [&](int64_t i) {
-        const int64_t e = i * b + j;
-        const double p = double(P[e]);
-        D[e] = T(double(D[e]) + alpha * p);
-        if (dir) P[e] = T(double(R[e]) + beta * p);
-    });
-}
-
-// bcg_r_kernel on 16-byte column groups (b = TPR * V, rows contiguous)
+// bcg_rp_kernel on 16-byte column groups (b = TPR * V, rows contiguous)
 template <class T, int TPR, int U = kVU, bool NT = false>
-__global__ void __launch_bounds__(kVT) bcg_r_vec_kernel(T *R, const T *Q, BatchSeg sg, BatchCg sc, double *partials) {
+__global__ void __launch_bounds__(kVT) bcg_rp_vec_kernel(T *R, const T *Q, T *P, T *D, BatchSeg sg, BatchCg sc,
+                                                         double *partials) {
     using VT = typename Vec16<T>::type;
     constexpr int V = Vec16<T>::V, b = TPR * V, rows_per = kVT / TPR;
     const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
@@ -441,83 +397,50 @@ __global__ void __launch_bounds__(kVT) bcg_r_vec_kernel(T *R, const T *Q, BatchS
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = 0.0;
     if (sc.sys_active[m]) {
-        double al[V];
+        double al[V], be[V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) al[v] = sc.alpha[m * b + g * V + v];
+        for (int v = 0; v < V; ++v) {
+            al[v] = sc.alpha[m * b + g * V + v];
+            be[v] = sc.beta[m * b + g * V + v];
+        }
         VT *Rv = reinterpret_cast<VT *>(R);
         const VT *Qv = reinterpret_cast<const VT *>(Q);
+        VT *Pv = reinterpret_cast<VT *>(P);
+        VT *Dv = reinterpret_cast<VT *>(D);
         const int lb = int(blockIdx.x) - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
         const int64_t r1 = sg.row_off[m + 1], st = int64_t(nbl) * rows_per;
         for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / TPR; i < r1; i += U * st) {
-            VT rv[U] = {}, qv[U] = {};
+            VT rv[U] = {}, qv[U] = {}, pv[U] = {}, dv[U] = {};
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (i + u * st < r1) {
-                    rv[u] = ld16<NT>(Rv + (i + u * st) * TPR + g);
-                    qv[u] = ld16<NT>(Qv + (i + u * st) * TPR + g);
+                    const int64_t k = (i + u * st) * TPR + g;
+                    rv[u] = ld16<NT>(Rv + k);
+                    qv[u] = ld16<NT>(Qv + k);
+                    pv[u] = ld16<NT>(Pv + k);
+                    dv[u] = ld16<NT>(Dv + k);
                 }
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (i + u * st < r1) {
-                    VT o;
+                    VT ro, dn, pn;
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
+                        const double p = double(pv[u][v]);
                         const T r = T(double(rv[u][v]) - al[v] * double(qv[u][v]));
-                        o[v] = r;
+                        ro[v] = r;
+                        dn[v] = T(double(dv[u][v]) + al[v] * p);
+                        pn[v] = T(double(r) + be[v] * p);
                         acc[v] += double(r) * double(r);
                     }
-                    st16<NT>(o, Rv + (i + u * st) * TPR + g);
+                    const int64_t k = (i + u * st) * TPR + g;
+                    st16<NT>(ro, Rv + k);
+                    st16<NT>(dn, Dv + k);
+                    st16<NT>(pn, Pv + k);
                 }
         }
     }
     colsum_store_vec<V, TPR>(acc, partials);
-}
-
-// bcg_p_kernel on 16-byte column groups
-template <class T, int TPR, int U = kVU, bool NT = false>
-__global__ void __launch_bounds__(kVT) bcg_p_vec_kernel(T *P, T *D, const T *R, BatchSeg sg, BatchCg sc) {
-    using VT = typename Vec16<T>::type;
-    constexpr int V = Vec16<T>::V, b = TPR * V, rows_per = kVT / TPR;
-    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
-    if (!sc.sys_step[m]) return;
-    const int g = threadIdx.x % TPR;
-    double al[V], be[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        al[v] = sc.alpha[m * b + g * V + v];
-        be[v] = sc.beta[m * b + g * V + v];
-    }
-    const bool dir = sc.sys_active[m] != 0;
-    VT *Pv = reinterpret_cast<VT *>(P);
-    VT *Dv = reinterpret_cast<VT *>(D);
-    const VT *Rv = reinterpret_cast<const VT *>(R);
-    const int lb = int(blockIdx.x) - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
-    const int64_t r1 = sg.row_off[m + 1], st = int64_t(nbl) * rows_per;
-    for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / TPR; i < r1; i += U * st) {
-        VT pv[U] = {}, dv[U] = {}, rv[U] = {};
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (i + u * st < r1) {
-                const int64_t k = (i + u * st) * TPR + g;
-                pv[u] = ld16<NT>(Pv + k);
-                dv[u] = ld16<NT>(Dv + k);
-                if (dir) rv[u] = ld16<NT>(Rv + k);
-            }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (i + u * st < r1) {
-                VT dn, pn;
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const double p = double(pv[u][v]);
-                    dn[v] = T(double(dv[u][v]) + al[v] * p);
-                    pn[v] = T(double(rv[u][v]) + be[v] * p);
-                }
-                const int64_t k = (i + u * st) * TPR + g;
-                st16<NT>(dn, Dv + k);
-                if (dir) st16<NT>(pn, Pv + k);
-            }
-    }
 }
 
 // Per-workgroup partials of <U_j, V_j> on the rows of the systems with mask[m] != 0
@@ -637,8 +560,8 @@ static int ok() { return hipGetLastError() == hipSuccess ? SELL_OK : SELL_ERR_HI
 
 unsigned cg_reduce_grid(int64_t n, int b) { return vgrid(n * pow2_at_least(b), kCgMaxGrid); }
 
-int cg_launch_alpha(const double *prod_partials, int ntiles, int b, const CgDev &sc, hipStream_t s) {
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(b), dim3(kVT), 0, s, prod_partials, ntiles, b, sc);
+int cg_launch_step(const double *prod_partials, int ntiles, int b, const CgDev &sc, hipStream_t s) {
+    hipLaunchKernelGGL(cg_step_kernel, dim3(b), dim3(kVT), 0, s, prod_partials, ntiles, b, sc);
     return ok();
 }
 
@@ -690,71 +613,42 @@ static unsigned group_grid(int64_t n, int tpr, unsigned cap) {
 }
 
 template <class T>
-static bool launch_r_groups(T *R, const T *Q, int64_t n, int b, int64_t ld, const CgDev &sc, double *partials,
-                            unsigned *grid, hipStream_t s) {
-    const int tpr = group_tpr<T>(b, ld, {R, Q});
+static bool launch_rp_groups(T *R, const T *Q, T *P, T *X, int64_t n, int b, int64_t ld, const CgDev &sc,
+                             double *partials, unsigned *grid, hipStream_t s) {
+    const int tpr = group_tpr<T>(b, ld, {R, Q, P, X});
     if (!tpr) return false;
     const unsigned g = group_grid(n, tpr, kCgMaxGrid);
     with_tpr(tpr, [&](auto c) {
         constexpr int TPR = decltype(c)::value;
         with_nt<T>(n * ld, [&](auto nt) {
-            hipLaunchKernelGGL((cg_r_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(g), dim3(kVT), 0, s, R, Q, n,
-                               ld / Vec16<T>::V, sc.alpha, partials);
+            hipLaunchKernelGGL((cg_rp_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(g), dim3(kVT), 0, s, R, Q, P,
+                               X, n, ld / Vec16<T>::V, sc.alpha, sc.beta, partials);
         });
     });
     *grid = g;
     return true;
 }
 
-int cg_launch_r(int dt, void *R, const void *Q, int64_t n, int b, int64_t ld, const CgDev &sc, double *partials,
-                hipStream_t s) {
-    const int bpad = pow2_at_least(b);
-    unsigned g = cg_reduce_grid(n, b);
-    if (n > 0 && (dt == SELL_F64 ? launch_r_groups(static_cast<double *>(R), static_cast<const double *>(Q), n, b, ld,
-                                                   sc, partials, &g, s)
-                                 : launch_r_groups(static_cast<float *>(R), static_cast<const float *>(Q), n, b, ld,
-                                                   sc, partials, &g, s))) {
-        // launched on 16-byte groups
-    } else if (dt == SELL_F64)
-        hipLaunchKernelGGL(cg_r_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(R),
-                           static_cast<const double *>(Q), n, b, bpad, ld, sc.alpha, partials);
-    else
-        hipLaunchKernelGGL(cg_r_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(R),
-                           static_cast<const float *>(Q), n, b, bpad, ld, sc.alpha, partials);
-    if (ok() != SELL_OK) return SELL_ERR_HIP;
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(b), dim3(kVT), 0, s, partials, int(g), sc);
-    return ok();
-}
-
 template <class T>
-static bool launch_p_groups(T *P, T *X, const T *R, int64_t n, int b, int64_t ld, const CgDev &sc, hipStream_t s) {
-    const int tpr = group_tpr<T>(b, ld, {P, X, R});
-    if (!tpr) return false;
-    const unsigned g = group_grid(n, tpr, 2 * kCgMaxGrid);
-    with_tpr(tpr, [&](auto c) {
-        constexpr int TPR = decltype(c)::value;
-        with_nt<T>(n * ld, [&](auto nt) {
-            hipLaunchKernelGGL((cg_p_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(g), dim3(kVT), 0, s, P, X, R, n,
-                               ld / Vec16<T>::V, sc.alpha, sc.beta);
-        });
-    });
-    return true;
+static void launch_rp(void *R, const void *Q, void *P, void *X, int64_t n, int b, int64_t ld, const CgDev &sc,
+                      double *partials, unsigned *grid, hipStream_t s) {
+    T *r = static_cast<T *>(R), *p = static_cast<T *>(P), *x = static_cast<T *>(X);
+    const T *q = static_cast<const T *>(Q);
+    if (n > 0 && launch_rp_groups(r, q, p, x, n, b, ld, sc, partials, grid, s)) return;
+    *grid = cg_reduce_grid(n, b);
+    hipLaunchKernelGGL(cg_rp_kernel<T>, dim3(*grid), dim3(kVT), 0, s, r, q, p, x, n, b, pow2_at_least(b), ld,
+                       sc.alpha, sc.beta, partials);
 }
 
-int cg_launch_p(int dt, void *P, void *X, const void *R, int64_t n, int b, int64_t ld, const CgDev &sc,
-                hipStream_t s) {
-    if (n > 0 && (dt == SELL_F64 ? launch_p_groups(static_cast<double *>(P), static_cast<double *>(X),
-                                                   static_cast<const double *>(R), n, b, ld, sc, s)
-                                 : launch_p_groups(static_cast<float *>(P), static_cast<float *>(X),
-                                                   static_cast<const float *>(R), n, b, ld, sc, s)))
-        return ok();
-    const unsigned g = vgrid(n * b, 4096);
+int cg_launch_rp(int dt, void *R, const void *Q, void *P, void *X, int64_t n, int b, int64_t ld, const CgDev &sc,
+                 double *partials, hipStream_t s) {
+    unsigned g = 0;
     if (dt == SELL_F64)
-        hipLaunchKernelGGL(cg_p_kernel<double>, dim3(g), dim3(kVT), 0, s, static_cast<double *>(P),
-                           static_cast<double *>(X), static_cast<const double *>(R), n, b, ld, sc.alpha, sc.beta);
+        launch_rp<double>(R, Q, P, X, n, b, ld, sc, partials, &g, s);
     else
-        hipLaunchKernelGGL(cg_p_kernel<float>, dim3(g), dim3(kVT), 0, s, static_cast<float *>(P),
-                           static_cast<float *>(X), static_cast<const float *>(R), n, b, ld, sc.alpha, sc.beta);
+        launch_rp<float>(R, Q, P, X, n, b, ld, sc, partials, &g, s);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(cg_rho_kernel, dim3(b), dim3(kVT), 0, s, partials, int(g), sc);
     return ok();
 }
 
@@ -808,69 +702,39 @@ template <class T>
 const T *ctp(const void *p) { return static_cast<const T *>(p); }
 }  // namespace
 
-int bcg_launch_alpha(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s) {
-    hipLaunchKernelGGL(bcg_alpha_kernel, dim3(K), dim3(kVT), 0, s, pparts, pblk, b, sc);
+int bcg_launch_step(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s) {
+    hipLaunchKernelGGL(bcg_step_kernel, dim3(K), dim3(kVT), 0, s, pparts, pblk, b, sc);
     return ok();
 }
 
 template <class T>
-static bool blaunch_r_groups(T *R, const T *Q, int b, const BatchSeg &sg, const BatchCg &sc, double *partials,
-                             hipStream_t s) {
-    const int tpr = group_tpr<T>(b, b, {R, Q});
-    if (!tpr) return false;
-    with_tpr(tpr, [&](auto c) {
-        constexpr int TPR = decltype(c)::value;
-        with_nt<T>(sg.rows * b, [&](auto nt) {
-            hipLaunchKernelGGL((bcg_r_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s, R, Q,
-                               sg, sc, partials);
+static void blaunch_rp(void *R, const void *Q, void *P, void *D, int b, const BatchSeg &sg, const BatchCg &sc,
+                       double *partials, hipStream_t s) {
+    T *r = tp<T>(R), *p = tp<T>(P), *d = tp<T>(D);
+    const T *q = ctp<T>(Q);
+    const int tpr = group_tpr<T>(b, b, {r, q, p, d});
+    if (tpr) {
+        with_tpr(tpr, [&](auto c) {
+            constexpr int TPR = decltype(c)::value;
+            with_nt<T>(sg.rows * b, [&](auto nt) {
+                hipLaunchKernelGGL((bcg_rp_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s,
+                                   r, q, p, d, sg, sc, partials);
+            });
         });
-    });
-    return true;
+        return;
+    }
+    hipLaunchKernelGGL(bcg_rp_kernel<T>, dim3(sg.G), dim3(kVT), 0, s, r, q, p, d, b, pow2_at_least(b), sg, sc,
+                       partials);
 }
 
-template <class T>
-static bool blaunch_p_groups(T *P, T *D, const T *R, int b, const BatchSeg &sg, const BatchCg &sc, hipStream_t s) {
-    const int tpr = group_tpr<T>(b, b, {P, D, R});
-    if (!tpr) return false;
-    with_tpr(tpr, [&](auto c) {
-        constexpr int TPR = decltype(c)::value;
-        with_nt<T>(sg.rows * b, [&](auto nt) {
-            hipLaunchKernelGGL((bcg_p_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s, P, D,
-                               R, sg, sc);
-        });
-    });
-    return true;
-}
-
-int bcg_launch_r(int dt, void *R, const void *Q, int b, const BatchSeg &sg, const BatchCg &sc, double *partials,
-                 hipStream_t s) {
-    const int bpad = pow2_at_least(b);
-    if (dt == SELL_F64 ? blaunch_r_groups(tp<double>(R), ctp<double>(Q), b, sg, sc, partials, s)
-                       : blaunch_r_groups(tp<float>(R), ctp<float>(Q), b, sg, sc, partials, s)) {
-        // launched on 16-byte groups
-    } else if (dt == SELL_F64)
-        hipLaunchKernelGGL(bcg_r_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), ctp<double>(Q), b, bpad,
-                           sg, sc, partials);
-    else
-        hipLaunchKernelGGL(bcg_r_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(R), ctp<float>(Q), b, bpad,
-                           sg, sc, partials);
-    if (ok() != SELL_OK) return SELL_ERR_HIP;
-    hipLaunchKernelGGL(bcg_beta_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, sc);
-    return ok();
-}
-
-int bcg_launch_p(int dt, void *P, void *D, const void *R, int b, const BatchSeg &sg, const BatchCg &sc,
-                 hipStream_t s) {
-    if (dt == SELL_F64 ? blaunch_p_groups(tp<double>(P), tp<double>(D), ctp<double>(R), b, sg, sc, s)
-                       : blaunch_p_groups(tp<float>(P), tp<float>(D), ctp<float>(R), b, sg, sc, s))
-        return ok();
-    const int bpad = pow2_at_least(b);
+int bcg_launch_rp(int dt, void *R, const void *Q, void *P, void *D, int b, const BatchSeg &sg, const BatchCg &sc,
+                  double *partials, hipStream_t s) {
     if (dt == SELL_F64)
-        hipLaunchKernelGGL(bcg_p_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), tp<double>(D),
-                           ctp<double>(R), b, bpad, sg, sc);
+        blaunch_rp<double>(R, Q, P, D, b, sg, sc, partials, s);
     else
-        hipLaunchKernelGGL(bcg_p_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(P), tp<float>(D), ctp<float>(R),
-                           b, bpad, sg, sc);
+        blaunch_rp<float>(R, Q, P, D, b, sg, sc, partials, s);
+    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    hipLaunchKernelGGL(bcg_rho_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, sc);
     return ok();
 }
 

@@ -228,13 +228,12 @@ struct CgDev {
     int32_t *active;  // per column: 1 while not converged
 };
 unsigned cg_reduce_grid(int64_t n, int b);
-int cg_launch_alpha(const double *prod_partials, int ntiles, int b, const CgDev &sc, hipStream_t s);
-// r -= alpha q with the partials of <r, r>, then beta, rho and the column flags
-int cg_launch_r(int dt, void *R, const void *Q, int64_t n, int b, int64_t ld, const CgDev &sc, double *partials,
-                hipStream_t s);
-// x += alpha p (the step along the old direction), then p = r + beta p
-int cg_launch_p(int dt, void *P, void *X, const void *R, int64_t n, int b, int64_t ld, const CgDev &sc,
-                hipStream_t s);
+// alpha and beta per column from the product's partials of <q, q> and <p, q> (q = A p)
+int cg_launch_step(const double *prod_partials, int ntiles, int b, const CgDev &sc, hipStream_t s);
+// r -= alpha q, x += alpha p, p = r + beta p in one pass with the partials of <r, r>, then rho
+// and the column flags
+int cg_launch_rp(int dt, void *R, const void *Q, void *P, void *X, int64_t n, int b, int64_t ld, const CgDev &sc,
+                 double *partials, hipStream_t s);
 int cg_launch_coldot(int dt, const void *U, const void *V, int64_t n, int b, int64_t ld, double *result,
                      double *partials, double *thresh2, int32_t *active, const double *ref, double f2,
                      hipStream_t s);
@@ -257,16 +256,14 @@ struct BatchCg {
     double *rho, *alpha, *beta, *thresh2;  // K * b each, index m * b + j
     int32_t *active;                       // K * b column flags
     int32_t *sys_active;                   // K system flags (some column active)
-    int32_t *sys_step;                     // K flags: the system took the current iteration's step
     int64_t *iters;                        // K iteration counters
 };
-int bcg_launch_alpha(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s);
-// r -= alpha q on the active systems' rows with the partials of <r, r>, then beta and flags
-int bcg_launch_r(int dt, void *R, const void *Q, int b, const BatchSeg &sg, const BatchCg &sc, double *partials,
-                 hipStream_t s);
-// d += alpha p on the rows of the systems that took the step, then p = r + beta p on the active ones
-int bcg_launch_p(int dt, void *P, void *D, const void *R, int b, const BatchSeg &sg, const BatchCg &sc,
-                 hipStream_t s);
+// alpha and beta of the iterating systems from the batched product's partials
+int bcg_launch_step(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s);
+// r -= alpha q, d += alpha p, p = r + beta p on the iterating systems' rows in one pass with
+// the partials of <r, r>, then rho, the flags and the iteration counters
+int bcg_launch_rp(int dt, void *R, const void *Q, void *P, void *D, int b, const BatchSeg &sg, const BatchCg &sc,
+                  double *partials, hipStream_t s);
 int bcg_launch_coldot(int dt, const void *U, const void *V, int b, const BatchSeg &sg, const int32_t *mask,
                       double *partials, double *result, double *thresh2, const double *ref, double f2,
                       hipStream_t s);

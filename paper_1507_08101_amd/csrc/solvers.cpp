@@ -2,10 +2,11 @@
 //
 // Both drivers run one CG per column of a block of right-hand sides (the paper's block
 // vectors, Sec. 5.2, with per-column scalars as in its vaxpy/vaxpby operations). An
-// iteration is three launches with no host synchronisation:
-//   q = A p            augmented product with the fused dot <p, q>
-//   r -= a q           update with <r, r> and the per-column scalars (device FP64)
-//   x += a p, p = r + b p   the step along the old direction and the new direction in one pass
+// iteration is one product and one vector pass, with no host synchronisation:
+//   q = A p            augmented product with the fused dots <p, q> and <q, q>
+//   alpha, beta        per-column scalars (device FP64); beta from <r', r'> = alpha^2 <q, q> - rho,
+//                      which holds because q is A-orthogonal to the previous direction
+//   r -= a q, x += a p, p = r + b p   the whole vector update in one pass, with <r, r>
 // The host reads the per-column "active" flags every few iterations.
 //
 // sell_cg:        FP64 throughout; convergence is confirmed on the true residual b - A x.
@@ -115,16 +116,15 @@ int cg_iterate(const sell_mat *A, int dt, sell_bv &X, sell_bv &R, sell_bv &P, se
     int rc = launch_copy(&P, &R, s);
     if (rc) return rc;
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
-    o.flags = SELL_SPMV_DOT_XY;
+    o.flags = SELL_SPMV_DOT_XY | SELL_SPMV_DOT_YY;
     *its = 0;
     bool any = true;
     if ((rc = any_active(S, b, s, &any))) return rc;
     while (any && *its < maxit) {
         int32_t nblk = 0;
         if ((rc = aug_impl(A, &P, &Q, nullptr, o, true, s, S.prod_parts, &nblk))) return rc;
-        if ((rc = cg_launch_alpha(S.prod_parts, nblk, b, S.dev(), s))) return rc;
-        if ((rc = cg_launch_r(dt, R.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
-        if ((rc = cg_launch_p(dt, P.ptr, X.ptr, R.ptr, n, b, b, S.dev(), s))) return rc;
+        if ((rc = cg_launch_step(S.prod_parts, nblk, b, S.dev(), s))) return rc;
+        if ((rc = cg_launch_rp(dt, R.ptr, Q.ptr, P.ptr, X.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
         ++*its;
         if (*its % kCheckEvery == 0 && (rc = any_active(S, b, s, &any))) return rc;
     }
@@ -311,14 +311,13 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
     if ((rc = launch_fill(P.ptr, SELL_F32, n, b, b, 1, 0.0, s))) return rc;
     if ((rc = reliable_update(false, &done))) return rc;
     sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
-    o.flags = SELL_SPMV_DOT_XY;
+    o.flags = SELL_SPMV_DOT_XY | SELL_SPMV_DOT_YY;
     int64_t since = 0;
     while (!done && st.iterations < maxit) {
         int32_t nblk = 0;
         if ((rc = aug_impl(Alo, &P, &Q, nullptr, o, true, s, S.prod_parts, &nblk))) return rc;
-        if ((rc = cg_launch_alpha(S.prod_parts, nblk, b, S.dev(), s))) return rc;
-        if ((rc = cg_launch_r(SELL_F32, R.ptr, Q.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
-        if ((rc = cg_launch_p(SELL_F32, P.ptr, D.ptr, R.ptr, n, b, b, S.dev(), s))) return rc;
+        if ((rc = cg_launch_step(S.prod_parts, nblk, b, S.dev(), s))) return rc;
+        if ((rc = cg_launch_rp(SELL_F32, R.ptr, Q.ptr, P.ptr, D.ptr, n, b, b, S.dev(), S.vec_parts, s))) return rc;
         ++st.iterations;
         ++since;
         if (st.iterations % kCheckEvery == 0 || st.iterations == maxit) {

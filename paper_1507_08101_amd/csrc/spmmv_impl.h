@@ -598,11 +598,12 @@ __global__ void __launch_bounds__(kBlock) prod_kernel(ProdArgs a, int vl_log2) {
 // call with its dot finish).
 constexpr uint32_t kKpmFlags = SELL_SPMV_SHIFT | SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
 
-// The flags of a CG iteration's product (q = A p with <p, q>): the FP32-vector kernels (FP32 or
-// BF16 values, the mixed-precision solvers' inner iterations) get their own compile-time copy,
-// single-matrix and batched (100^3 Laplacian, BF16 values, b = 8: 36.0 -> 33.7 us). The FP64
-// kernel gains nothing from it (64.1 against 65.0 us) and keeps the run-time flags.
-constexpr uint32_t kCgFlags = SELL_SPMV_DOT_XY;
+// The flags of a CG iteration's product (q = A p with <q, q> and <p, q>): the FP32-vector kernels
+// (FP32 or BF16 values, the mixed-precision solvers' inner iterations) get their own compile-time
+// copy, single-matrix and batched (100^3 Laplacian, BF16 values, b = 8, with <p, q> alone:
+// 36.0 -> 33.7 us). The FP64 kernel gained nothing from it (64.1 against 65.0 us) and keeps the
+// run-time flags.
+constexpr uint32_t kCgFlags = SELL_SPMV_DOT_YY | SELL_SPMV_DOT_XY;
 
 // One launch over a batch of matrices: workgroups [blk_start[m], blk_start[m+1]) of the
 // (XCD-remapped) grid work on matrix m, whose launch arguments are table[m]. A matrix m with

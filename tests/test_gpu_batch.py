@@ -47,7 +47,7 @@ def _value_ref(A, dt):
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("b", [1, 3, 8, 32])
-@pytest.mark.parametrize("flags_name", ["plain", "shift_scale_axpby_dots", "vshift_chain_dots", "cg_dot_xy"])
+@pytest.mark.parametrize("flags_name", ["plain", "shift_scale_axpby_dots", "vshift_chain_dots", "cg_dots"])
 def test_batch_product_vs_oracle_and_single(sc, dt, b, flags_name):
     import torch
 
@@ -55,7 +55,7 @@ def test_batch_product_vs_oracle_and_single(sc, dt, b, flags_name):
     flags = {"plain": 0,
              "shift_scale_axpby_dots": sc.SHIFT | sc.SCALE | sc.AXPBY | sc.DOTS,
              "vshift_chain_dots": sc.VSHIFT | sc.SCALE | sc.AXPBY | sc.DOTS | sc.CHAIN,
-             "cg_dot_xy": sc.DOT_XY}[flags_name]
+             "cg_dots": sc.DOT_YY | sc.DOT_XY}[flags_name]
     kw = dict(alpha=0.5, beta=-1.25, gamma=0.1, delta=0.3, eta=-2.0,
               gamma_v=np.linspace(-1, 1, b) if flags & sc.VSHIFT else None)
     Ms = [sc.SellMatrix.from_csr(A, C=32 if k % 2 == 0 else 8, sigma=[1, 64, 7][k % 3], dtype=dt)

@@ -156,9 +156,9 @@ def test_aug_every_flag_combination_bit_exact_on_integers(sc, flags):
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 @pytest.mark.parametrize("b", [1, 2, 4, 8, 16, 32])
 def test_cg_product_flags_low_precision(sc, dt, b):
-    """A CG iteration's product (only <x, y>) runs a compile-time copy of the FP32-vector kernels:
-    its y is the plain product's bit for bit (no scale, shift or y input), and <x, y> matches an
-    exact sum of the GPU's own y within the dot bound."""
+    """A CG iteration's product (only <y, y> and <x, y>) runs a compile-time copy of the FP32-vector
+    kernels: its y is the plain product's bit for bit (no scale, shift or y input), and both dots
+    match exact sums over the GPU's own y within the dot bound."""
     import torch
 
     A = MATS["random_ragged"]
@@ -168,14 +168,16 @@ def test_cg_product_flags_low_precision(sc, dt, b):
     Ya = torch.full((A.nrows, b), 5.0, dtype=torch.float32, device="cuda:0")
     dot = torch.zeros(3 * b, dtype=torch.float64, device="cuda:0")
     sc.sell_spmmv(M, X, Yp)
-    sc.sell_spmmv_aug(M, X, Ya, flags=sc.DOT_XY, dot=dot)
+    sc.sell_spmmv_aug(M, X, Ya, flags=sc.DOT_YY | sc.DOT_XY, dot=dot)
     yp, ya, x = host(Yp), host(Ya), host(X).astype(np.float64)
     M.close()
     assert np.array_equal(ya, yp), (dt, b)
-    d = host(dot)[b:2 * b]
-    for j in range(b):
-        terms = (x[:, j] * ya[:, j].astype(np.float64)).tolist()
-        assert abs(d[j] - math.fsum(terms)) <= 1e-12 * math.fsum(abs(t) for t in terms), (dt, b, j)
+    dg = host(dot)
+    y64 = ya.astype(np.float64)
+    for g, u in ((0, y64), (1, x)):
+        for j in range(b):
+            terms = (u[:, j] * y64[:, j]).tolist()
+            assert abs(dg[g * b + j] - math.fsum(terms)) <= 1e-12 * math.fsum(abs(t) for t in terms), (dt, b, g, j)
 
 
 @pytest.mark.parametrize("name,sigma", [("random_ragged", 64), ("irregular_5000", 1024), ("anderson_12", 1)])
