@@ -316,25 +316,24 @@ __device__ __forceinline__ void seg_rows(const BatchSeg &sg, int m, int bpad, F 
 
 // alpha[m, j] and beta[m, j] of every system that iterates, as cg_step_kernel computes them, from
 // the batched product's partials of matrix m (quantity t at pparts + 3 b pblk[m] + t npm,
-// npm = pblk[m+1] - pblk[m]; <q, q> is quantity j, <p, q> quantity b + j). One workgroup per system.
+// npm = pblk[m+1] - pblk[m]; <q, q> is quantity j, <p, q> quantity b + j). One workgroup per
+// system and column (grid K x b).
 __global__ void __launch_bounds__(kVT) bcg_step_kernel(const double *pparts, const int32_t *pblk, int b,
                                                        BatchCg sc) {
-    const int m = blockIdx.x;
+    const int m = blockIdx.x, j = blockIdx.y;
     if (!sc.sys_active[m]) return;
     const int npm = pblk[m + 1] - pblk[m];
     const double *base = pparts + size_t(3) * b * pblk[m];
-    for (int j = 0; j < b; ++j) {
-        const double qq = sum_partials(base + size_t(j) * npm, npm);
-        const double pq = sum_partials(base + size_t(b + j) * npm, npm);
-        if (threadIdx.x == 0) {
-            const int q = m * b + j;
-            const double rho = sc.rho[q];
-            const bool act = sc.active[q] != 0;
-            const double al = (act && pq != 0.0) ? rho / pq : 0.0;
-            const double num = al * al * qq - rho;
-            sc.alpha[q] = al;
-            sc.beta[q] = (act && rho != 0.0 && num > 0.0) ? num / rho : 0.0;
-        }
+    const double qq = sum_partials(base + size_t(j) * npm, npm);
+    const double pq = sum_partials(base + size_t(b + j) * npm, npm);
+    if (threadIdx.x == 0) {
+        const int q = m * b + j;
+        const double rho = sc.rho[q];
+        const bool act = sc.active[q] != 0;
+        const double al = (act && pq != 0.0) ? rho / pq : 0.0;
+        const double num = al * al * qq - rho;
+        sc.alpha[q] = al;
+        sc.beta[q] = (act && rho != 0.0 && num > 0.0) ? num / rho : 0.0;
     }
 }
 
@@ -703,7 +702,7 @@ const T *ctp(const void *p) { return static_cast<const T *>(p); }
 }  // namespace
 
 int bcg_launch_step(const double *pparts, const int32_t *pblk, int K, int b, const BatchCg &sc, hipStream_t s) {
-    hipLaunchKernelGGL(bcg_step_kernel, dim3(K), dim3(kVT), 0, s, pparts, pblk, b, sc);
+    hipLaunchKernelGGL(bcg_step_kernel, dim3(K, b), dim3(kVT), 0, s, pparts, pblk, b, sc);
     return ok();
 }
 
