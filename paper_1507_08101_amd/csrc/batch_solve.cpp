@@ -180,7 +180,9 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         (rc = DB.alloc(&pd, nv * isz)) || (rc = DB.alloc(&pp, nv * isz)) || (rc = DB.alloc(&pq, nv * isz)))
         return rc;
     // device scalars: rho alpha beta thresh2 bb rr(3Kb) | vec partials (b G) | int32 flags
-    const int32_t Gv = 2 * kCgMaxGrid;  // vector-kernel workgroups of an iteration
+    // vector-kernel workgroups of an iteration (4,096 and 8,192 ran 1-2 % faster than 2,048 and
+    // 1,024 with 8 rows in flight per thread)
+    const int32_t Gv = 4 * kCgMaxGrid;
     const size_t gmax = size_t(std::max(std::max(sg.G, Gv), K));
     const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * gmax;
     // active, sys_active, mask | iters (int64) | column mask | iteration workgroup offsets

@@ -35,10 +35,10 @@ __device__ void colsum_store(double v, int bpad, int b, double *partials) {
 // ---------------------------------------------------------------- 16-byte column groups
 // The iteration's vector pass in the common case: b a multiple of the 16-byte group
 // (4 floats or 2 doubles) with a power-of-two number of groups per row (TPR <= 16), rows 16-byte
-// aligned. Each thread owns one group of every row it visits and keeps kVU rows in flight, so a
-// wave moves 1 KiB per load instruction. Every element is computed as in the per-element
-// kernels (cg_rp_kernel and its batched form), which serve the other shapes; only the order in
-// which the column sums are accumulated differs.
+// aligned. Each thread owns one group of every row it visits and keeps kVU (batched: kVUB) rows in
+// flight, so a wave moves 1 KiB per load instruction. Every element is computed as in the
+// per-element kernels (cg_rp_kernel and its batched form), which serve the other shapes; only the
+// order in which the column sums are accumulated differs.
 template <class T>
 struct Vec16;
 template <>
@@ -52,9 +52,13 @@ struct Vec16<double> {
     static constexpr int V = 2;
 };
 
-// rows in flight per thread (8, or 1024 / 4096 workgroups instead of 2048 for the batched
-// kernels, changed the batched CG times by less than 2 %)
+// rows in flight per thread of the single-system passes
 constexpr int kVU = 4;
+// the same for the batched pass, whose vectors span the whole batch: a sweep of 1 / 2 / 4 / 8 rows
+// in flight over 1,024 to 8,192 workgroups, nontemporal or not, put 8 rows (nontemporal) first at
+// every grid size (64 Laplacians at b = 8, 4,096 workgroups: BF16-value CG 0.681 s against 0.696
+// with 4 rows, FP64 1.182 against 1.196 s)
+constexpr int kVUB = 8;
 
 template <bool NT, class VT>
 __device__ __forceinline__ VT ld16(const VT *p) {
@@ -385,7 +389,7 @@ __global__ void __launch_bounds__(kVT) bcg_rho_kernel(const double *partials, in
 }
 
 // bcg_rp_kernel on 16-byte column groups (b = TPR * V, rows contiguous)
-template <class T, int TPR, int U = kVU, bool NT = false>
+template <class T, int TPR, int U = kVUB, bool NT = false>
 __global__ void __launch_bounds__(kVT) bcg_rp_vec_kernel(T *R, const T *Q, T *P, T *D, BatchSeg sg, BatchCg sc,
                                                          double *partials) {
     using VT = typename Vec16<T>::type;
@@ -716,7 +720,7 @@ static void blaunch_rp(void *R, const void *Q, void *P, void *D, int b, const Ba
         with_tpr(tpr, [&](auto c) {
             constexpr int TPR = decltype(c)::value;
             with_nt<T>(sg.rows * b, [&](auto nt) {
-                hipLaunchKernelGGL((bcg_rp_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s,
+                hipLaunchKernelGGL((bcg_rp_vec_kernel<T, TPR, kVUB, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s,
                                    r, q, p, d, sg, sc, partials);
             });
         });
