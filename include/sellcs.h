@@ -330,7 +330,12 @@ typedef struct {
 /* Conjugate gradients for each column of B (A symmetric positive definite, F64 matrix,
  * F64 row-major vectors). X holds the initial guess and receives the solution. Stops
  * when every column has ||b - A x|| <= tol ||b|| (true FP64 residual, checked every few
- * iterations) or after maxit iterations. Synchronous (returns when done). */
+ * iterations) or after maxit iterations. Synchronous (returns when done). An iteration is
+ * one product q = A p with the fused <q, q> and <p, q>, and one vector pass r -= alpha q,
+ * x += alpha p, p = r + beta p with beta = (alpha^2 <q, q> - rho) / rho, which equals
+ * <r', r'> / rho in exact arithmetic (the single-reduction form of Rupp et al., ACM TOMS
+ * 43(2), 2016); rho = <r, r> is summed directly and decides convergence. sell_cg_mixed and
+ * sell_batch_cg iterate the same way. */
 int sell_cg(const sell_mat *A, const sell_bv *B, sell_bv *X, double tol, int64_t maxit,
             sell_cg_stats *stats, void *stream);
 
