@@ -247,22 +247,6 @@ __global__ void __launch_bounds__(kVT) coldot_finish_kernel(const double *partia
     }
 }
 
-// dst32 = src64 * s_j with s_j = 1 / sqrt(rr_j) for active columns, else 0; scale[j] = sqrt(rr_j)
-// (or 0). A column is active when rr_j > thresh2_j.
-__global__ void __launch_bounds__(kVT) scale_to_f32_kernel(float *dst, const double *src, int64_t n, int b,
-                                                           int64_t ld, const double *rr, const double *thresh2,
-                                                           double *scale) {
-    const int64_t N = n * b;
-    for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
-        const int64_t i = e / b;
-        const int j = int(e - i * b);
-        const bool act = rr[j] > thresh2[j];
-        const double s = act ? 1.0 / sqrt(rr[j]) : 0.0;
-        dst[i * ld + j] = float(src[i * ld + j] * s);
-        if (e < b) scale[j] = act ? sqrt(rr[j]) : 0.0;
-    }
-}
-
 // p = r in the columns with colmask[j] != 0 (one system)
 template <class T>
 __global__ void __launch_bounds__(kVT) copy_cols_kernel(T *P, const T *R, int64_t n, int b, int64_t ld,
@@ -275,14 +259,13 @@ __global__ void __launch_bounds__(kVT) copy_cols_kernel(T *P, const T *R, int64_
     }
 }
 
-// x += scale_j * d  (scale_j = 1 when scale is null)
-__global__ void __launch_bounds__(kVT) axpy_mixed_kernel(double *X, const float *D, int64_t n, int b, int64_t ld,
-                                                         const double *scale) {
+// x += d (the FP32 correction folded into the FP64 solution)
+__global__ void __launch_bounds__(kVT) axpy_mixed_kernel(double *X, const float *D, int64_t n, int b, int64_t ld) {
     const int64_t N = n * b;
     for (int64_t e = int64_t(blockIdx.x) * kVT + threadIdx.x; e < N; e += int64_t(gridDim.x) * kVT) {
         const int64_t i = e / b;
         const int j = int(e - i * b);
-        X[i * ld + j] += (scale ? scale[j] : 1.0) * double(D[i * ld + j]);
+        X[i * ld + j] += double(D[i * ld + j]);
     }
 }
 
@@ -672,13 +655,6 @@ int cg_launch_coldot(int dt, const void *U, const void *V, int64_t n, int b, int
     return ok();
 }
 
-int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int64_t ld, const double *rr,
-                           const double *thresh2, double *scale, hipStream_t s) {
-    hipLaunchKernelGGL(scale_to_f32_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, dst, src, n, b, ld, rr,
-                       thresh2, scale);
-    return ok();
-}
-
 int cg_launch_copy_cols(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const int32_t *colmask,
                         hipStream_t s) {
     if (n * b == 0) return SELL_OK;
@@ -691,9 +667,8 @@ int cg_launch_copy_cols(int dt, void *P, const void *R, int64_t n, int b, int64_
     return ok();
 }
 
-int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(axpy_mixed_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, X, D, n, b, ld, scale);
+int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_mixed_kernel, dim3(vgrid(n * b, 4096)), dim3(kVT), 0, s, X, D, n, b, ld);
     return ok();
 }
 

@@ -237,13 +237,10 @@ int cg_launch_rp(int dt, void *R, const void *Q, void *P, void *X, int64_t n, in
 int cg_launch_coldot(int dt, const void *U, const void *V, int64_t n, int b, int64_t ld, double *result,
                      double *partials, double *thresh2, int32_t *active, const double *ref, double f2,
                      hipStream_t s);
-int cg_launch_scale_to_f32(float *dst, const double *src, int64_t n, int b, int64_t ld, const double *rr,
-                           const double *thresh2, double *scale, hipStream_t s);
 // P = R in the columns with colmask[j] != 0 (device flags)
 int cg_launch_copy_cols(int dt, void *P, const void *R, int64_t n, int b, int64_t ld, const int32_t *colmask,
                         hipStream_t s);
-int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, const double *scale,
-                         hipStream_t s);
+int cg_launch_axpy_mixed(double *X, const float *D, int64_t n, int b, int64_t ld, hipStream_t s);
 
 // Batched CG (cg.hip): K systems stored one after another in the block vectors.
 struct BatchSeg {

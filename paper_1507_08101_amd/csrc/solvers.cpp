@@ -65,7 +65,7 @@ sell_bv view(void *p, int64_t n, int b, int dt) {
 }
 
 struct Scalars {
-    double *rho, *pq, *alpha, *beta, *thresh2, *bb, *rr, *scale, *thresh_out;
+    double *rho, *pq, *alpha, *beta, *thresh2, *bb, *rr, *thresh_out;
     int32_t *active;
     int32_t *colmask;     // per-column flags handed to the device (b)
     double *prod_parts;   // tile partials of the product's dots (3 b ntiles)
@@ -87,8 +87,7 @@ int alloc_scalars(Buffers &B, Scalars &S, int b, int32_t max_tiles) {
     S.thresh2 = d + 4 * b;
     S.bb = d + 5 * b;
     S.rr = d + 6 * b;         // 3b
-    S.scale = d + 9 * b;
-    S.thresh_out = d + 10 * b;
+    S.thresh_out = d + 9 * b;
     S.active = reinterpret_cast<int32_t *>(d + 11 * b);
     S.colmask = reinterpret_cast<int32_t *>(d + 13 * b);
     S.prod_parts = d + 16 * b;
@@ -267,7 +266,7 @@ int sell_cg_mixed(const sell_mat *A64, const sell_mat *Alo, const sell_bv *Bv, s
     auto reliable_update = [&](bool fold, bool *done) -> int {
         int r;
         if (fold && (r = cg_launch_axpy_mixed(static_cast<double *>(X->ptr), static_cast<const float *>(D.ptr), n,
-                                              b, b, nullptr, s)))
+                                              b, b, s)))
             return r;
         if ((r = true_residual(A64, Bv, X, R64, S, s))) return r;
         HIPCHK(hipMemcpyAsync(rr, S.rr, sizeof(double) * b, hipMemcpyDeviceToHost, s));
