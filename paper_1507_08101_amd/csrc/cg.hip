@@ -111,7 +111,9 @@ __device__ double sum_partials(const double *p, int n) {
 // numerator of beta is <r', r'> before r' exists, and the residual, the step and the new
 // direction are updated in one pass (the single-reduction form of Rupp et al., ACM TOMS 43(2),
 // 2016). rho itself stays the directly summed <r, r>, which also decides convergence. A
-// numerator that cancels to zero or below restarts the column from p = r' (beta = 0).
+// numerator that cancels to zero or below restarts the column from p = r' (beta = 0). After a
+// reliable update keeps p but replaces r by the true residual, <r, q> = <p, q> holds only up to
+// the drift that the update removed, and that iteration's beta carries the same small error.
 __global__ void __launch_bounds__(kVT) cg_step_kernel(const double *prod_partials, int ntiles, int b, CgDev sc) {
     const int j = blockIdx.x;
     const double qq = sum_partials(prod_partials + size_t(j) * ntiles, ntiles);
