@@ -228,7 +228,7 @@ def test_batch_cg_converges(sc, mode, graph):
 @pytest.mark.parametrize("mode", ["f64", "f32"])
 @pytest.mark.parametrize("b", [2, 8, 12, 16, 32])
 def test_batch_cg_every_vector_pass_width(sc, mode, b):
-    """The batched vector passes on 16-byte column groups (FP64 vectors: 1, 4, 8 and 16 groups
+    """The batched vector pass on 16-byte column groups (FP64 vectors: 1, 4, 8 and 16 groups
     per row; FP32 vectors: 2, 4 and 8) and per element (6 FP64 groups or 3 FP32 groups at
     b = 12; FP32 at b = 2, narrower than a group)."""
     import torch

@@ -50,7 +50,7 @@ def test_cg_fp64_reaches_tolerance(sc, b):
     M.close()
 
 
-# The iteration's two vector passes run on 16-byte column groups when b is a multiple of the
+# The iteration's vector pass runs on 16-byte column groups when b is a multiple of the
 # group (2 doubles, 4 floats) with a power-of-two number of groups per row up to 16, and per
 # element otherwise: every group count and both fallbacks (3 groups; 32 groups).
 @pytest.mark.parametrize("b", [2, 4, 6, 8, 16, 32, 64])
@@ -80,9 +80,9 @@ def test_cg_mixed_every_vector_pass_width(sc, b):
 
 
 def test_cg_fp64_unaligned_solution_takes_the_element_pass(sc):
-    """x 8 bytes past a 16-byte boundary sends the direction pass (which updates x) to the
-    per-element kernel, while the residual pass keeps the column groups: the two solves agree
-    to the tolerance and in their iteration counts (only the rounding of the dots differs)."""
+    """x 8 bytes past a 16-byte boundary sends the vector pass (which updates x) to the
+    per-element kernel: the solve agrees with the aligned one (column groups) to the tolerance
+    and in its iteration count (only the rounding of the dots differs)."""
     import torch
 
     A = synth.laplacian3d(12)
