@@ -185,8 +185,8 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     const int32_t Gv = 4 * kCgMaxGrid;
     const size_t gmax = size_t(std::max(std::max(sg.G, Gv), K));
     const size_t nd = 5 * Kb + 3 * Kb + size_t(b) * gmax;
-    // active, sys_active, mask | iters (int64) | column mask | iteration workgroup offsets
-    const size_t ni = Kb + 2 * size_t(K) + 2 * size_t(K) + 2 + Kb + size_t(K) + 1;
+    // active, sys_active, mask | iters (int64) | column mask | iteration and update workgroup offsets
+    const size_t ni = Kb + 2 * size_t(K) + 2 * size_t(K) + 2 + Kb + 2 * (size_t(K) + 1);
     if ((rc = DB.alloc(&pscal, nd * sizeof(double) + ni * sizeof(int32_t) + 16)))
         return rc;
     double *d = static_cast<double *>(pscal);
@@ -208,6 +208,7 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     sc.iters = iters_d;
     int32_t *colmask_d = reinterpret_cast<int32_t *>(iters_d + K);
     int32_t *vblk_d = colmask_d + Kb;
+    int32_t *vblkr_d = vblk_d + K + 1;
 
     sell_bv Bview = *Bv;
     sell_bv R64 = view(pr64, n, b, SELL_F64), R = view(pr, n, b, idt), D = view(pd, n, b, idt),
@@ -224,13 +225,33 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     HIPCHK(hipMemcpyAsync(bb.data(), bb_d, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 
+    std::vector<double> wrows(static_cast<size_t>(K));
+    for (int m = 0; m < K; ++m) wrows[size_t(m)] = double(batch_matrix(A64, m)->h.nrows);
+    // The workgroups of the update's vector kernels, split over the systems it updates (with the
+    // batch's own split, an update of a few systems ran on their small share of the grid).
+    std::vector<int32_t> vblkr;
+    BatchSeg sgr = sg;
+    sgr.vblk = vblkr_d;
+
     // Reliable update of the systems with mask[m] != 0: fold D into x, true residual in FP64,
     // restart the systems that have not converged from it.
     auto refresh = [&]() -> int {
         int r;
         HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        {
+            std::vector<int64_t> cap(static_cast<size_t>(K));
+            for (int m = 0; m < K; ++m) {
+                const int64_t nr = batch_matrix(A64, m)->h.nrows;
+                cap[size_t(m)] = (mask[size_t(m)] && nr > 0) ? std::max<int64_t>(1, (nr + 3) / 4) : 0;
+            }
+            apportion(wrows, cap, Gv, vblkr);
+            sgr.G = vblkr[size_t(K)];
+            // vblkr is not touched again before the synchronisation below
+            HIPCHK(hipMemcpyAsync(vblkr_d, vblkr.data(), (size_t(K) + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                                  s));
+        }
         if ((r = bcg_launch_refresh_prep(idt, static_cast<double *>(X->ptr), pd, static_cast<double *>(pr64),
-                                         static_cast<const double *>(Bv->ptr), b, sg, mask_d, s)))
+                                         static_cast<const double *>(Bv->ptr), b, sgr, mask_d, s)))
             return r;
         sell_spmv_opts o = SELL_SPMV_OPTS_INIT;
         o.flags = SELL_SPMV_SCALE | SELL_SPMV_AXPBY | SELL_SPMV_DOT_YY;
@@ -278,12 +299,12 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
         HIPCHK(hipMemcpyAsync(mask_d, mask.data(), K * sizeof(int32_t), hipMemcpyHostToDevice, s));
         // r = r64 in the iteration's precision, rho = <r, r>; the recursion retires a column
         // itself only in FP64 (thresh2 = tol^2 ||b||^2), in FP32 only the true residual does
-        if ((r = bcg_launch_convert(idt, pr, static_cast<const double *>(pr64), b, sg, mask_d, vparts, sc.rho,
+        if ((r = bcg_launch_convert(idt, pr, static_cast<const double *>(pr64), b, sgr, mask_d, vparts, sc.rho,
                                     sc.thresh2, bb_d, mixed ? 0.0 : tol * tol, s)))
             return r;
         if (any_reset) {
             HIPCHK(hipMemcpyAsync(colmask_d, reset.data(), Kb * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            if ((r = bcg_launch_copy(idt, pp, pr, b, sg, colmask_d, s))) return r;
+            if ((r = bcg_launch_copy(idt, pp, pr, b, sgr, colmask_d, s))) return r;
         }
         HIPCHK(hipMemcpyAsync(rho.data(), sc.rho, Kb * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -302,8 +323,6 @@ int sell_batch_cg(sell_batch *A64, sell_batch *Alo, const sell_bv *Bv, sell_bv *
     std::vector<int32_t> appo_active(static_cast<size_t>(K), -1), vblk;
     BatchSeg sgi = sg;
     sgi.vblk = vblk_d;
-    std::vector<double> wrows(static_cast<size_t>(K));
-    for (int m = 0; m < K; ++m) wrows[size_t(m)] = double(batch_matrix(A64, m)->h.nrows);
     auto resplit = [&](bool *changed) -> int {
         *changed = appo_active != sysact;
         if (!*changed) return SELL_OK;

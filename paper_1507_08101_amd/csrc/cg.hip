@@ -736,6 +736,7 @@ int bcg_launch_coldot(int dt, const void *U, const void *V, int b, const BatchSe
 
 int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const double *Bv, int b, const BatchSeg &sg,
                             const int32_t *mask, hipStream_t s) {
+    if (sg.G == 0) return SELL_OK;  // no workgroups: no system with rows to update
     const int bpad = pow2_at_least(b);
     if (dt == SELL_F64)
         hipLaunchKernelGGL(brefresh_prep_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, X, tp<double>(D), R64, Bv, b,
@@ -749,19 +750,22 @@ int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const doubl
 int bcg_launch_convert(int dt, void *R, const double *R64, int b, const BatchSeg &sg, const int32_t *mask,
                        double *partials, double *rho, double *thresh2, const double *ref, double f2, hipStream_t s) {
     const int bpad = pow2_at_least(b);
-    if (dt == SELL_F64)
-        hipLaunchKernelGGL(bconvert_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), R64, b, bpad, sg,
-                           mask, partials);
-    else
-        hipLaunchKernelGGL(bconvert_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(R), R64, b, bpad, sg,
-                           mask, partials);
-    if (ok() != SELL_OK) return SELL_ERR_HIP;
+    if (sg.G > 0) {  // (with no workgroups the finish below sums no partials: rho = 0)
+        if (dt == SELL_F64)
+            hipLaunchKernelGGL(bconvert_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), R64, b, bpad, sg,
+                               mask, partials);
+        else
+            hipLaunchKernelGGL(bconvert_kernel<float>, dim3(sg.G), dim3(kVT), 0, s, tp<float>(R), R64, b, bpad, sg,
+                               mask, partials);
+        if (ok() != SELL_OK) return SELL_ERR_HIP;
+    }
     hipLaunchKernelGGL(bcoldot_finish_kernel, dim3(sg.K), dim3(kVT), 0, s, partials, sg.G, sg, b, mask, rho,
                        thresh2, ref, f2);
     return ok();
 }
 
 int bcg_launch_copy(int dt, void *P, const void *R, int b, const BatchSeg &sg, const int32_t *mask, hipStream_t s) {
+    if (sg.G == 0) return SELL_OK;
     const int bpad = pow2_at_least(b);
     if (dt == SELL_F64)
         hipLaunchKernelGGL(bcopy_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(P), ctp<double>(R), b, bpad,
