@@ -493,6 +493,94 @@ __global__ void __launch_bounds__(kVT) bconvert_kernel(T *R, const double *R64, 
     colsum_store(acc, bpad, b, partials);
 }
 
+// brefresh_prep_kernel and bconvert_kernel on groups of two columns (b even, b / 2 a power of
+// two up to 16, rows 16-byte aligned): the FP64 rows move as 16-byte pieces, the rows of T as
+// pairs, kVU rows in flight per thread. Every element is computed as in the per-element kernels.
+template <class T>
+struct Pair;
+template <>
+struct Pair<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+template <class T, int TPR, int U, bool NT>
+__global__ void __launch_bounds__(kVT) brefresh_prep_vec_kernel(double *X, T *D, double *R64, const double *Bv,
+                                                                BatchSeg sg, const int32_t *mask) {
+    using V2 = typename Pair<double>::type;
+    using T2 = typename Pair<T>::type;
+    constexpr int rows_per = kVT / TPR;
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    if (!mask[m]) return;
+    const int g = threadIdx.x % TPR;
+    V2 *Xv = reinterpret_cast<V2 *>(X);
+    V2 *Rv = reinterpret_cast<V2 *>(R64);
+    const V2 *Bvv = reinterpret_cast<const V2 *>(Bv);
+    T2 *Dv = reinterpret_cast<T2 *>(D);
+    const int lb = int(blockIdx.x) - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
+    const int64_t r1 = sg.row_off[m + 1], st = int64_t(nbl) * rows_per;
+    for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / TPR; i < r1; i += U * st) {
+        V2 xv[U] = {}, bv[U] = {};
+        T2 dv[U] = {};
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < r1) {
+                const int64_t k = (i + u * st) * TPR + g;
+                xv[u] = ld16<NT>(Xv + k);
+                bv[u] = ld16<NT>(Bvv + k);
+                dv[u] = ld16<NT>(Dv + k);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i + u * st < r1) {
+                const int64_t k = (i + u * st) * TPR + g;
+                V2 xo;
+                xo[0] = xv[u][0] + double(dv[u][0]);
+                xo[1] = xv[u][1] + double(dv[u][1]);
+                st16<NT>(xo, Xv + k);
+                st16<NT>(T2{T(0), T(0)}, Dv + k);
+                st16<NT>(bv[u], Rv + k);
+            }
+    }
+}
+
+template <class T, int TPR, int U, bool NT>
+__global__ void __launch_bounds__(kVT) bconvert_vec_kernel(T *R, const double *R64, BatchSeg sg, const int32_t *mask,
+                                                           double *partials) {
+    using V2 = typename Pair<double>::type;
+    using T2 = typename Pair<T>::type;
+    constexpr int rows_per = kVT / TPR;
+    const int m = seg_of(blockIdx.x, sg.vblk, sg.K);
+    const int g = threadIdx.x % TPR;
+    double acc[2] = {0.0, 0.0};
+    if (mask[m]) {
+        const V2 *Rs = reinterpret_cast<const V2 *>(R64);
+        T2 *Rv = reinterpret_cast<T2 *>(R);
+        const int lb = int(blockIdx.x) - sg.vblk[m], nbl = sg.vblk[m + 1] - sg.vblk[m];
+        const int64_t r1 = sg.row_off[m + 1], st = int64_t(nbl) * rows_per;
+        for (int64_t i = sg.row_off[m] + int64_t(lb) * rows_per + threadIdx.x / TPR; i < r1; i += U * st) {
+            V2 sv[U] = {};
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i + u * st < r1) sv[u] = ld16<NT>(Rs + (i + u * st) * TPR + g);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i + u * st < r1) {
+                    T2 o;
+                    o[0] = T(sv[u][0]);
+                    o[1] = T(sv[u][1]);
+                    acc[0] += double(o[0]) * double(o[0]);
+                    acc[1] += double(o[1]) * double(o[1]);
+                    st16<NT>(o, Rv + (i + u * st) * TPR + g);
+                }
+        }
+    }
+    colsum_store_vec<2, TPR>(acc, partials);
+}
+
 // p = r in the columns with colmask[m * b + j] != 0
 template <class T>
 __global__ void __launch_bounds__(kVT) bcopy_kernel(T *P, const T *R, int b, int bpad, BatchSeg sg,
@@ -734,9 +822,53 @@ int bcg_launch_coldot(int dt, const void *U, const void *V, int b, const BatchSe
     return ok();
 }
 
+// Groups of two columns per thread for b even with b / 2 a power of two up to 16 and the
+// given pointers 16-byte aligned (0 otherwise).
+static int pair_tpr(int b, std::initializer_list<const void *> ptrs) {
+    if (b < 2 || b % 2) return 0;
+    const int tpr = b / 2;
+    if (tpr > 16 || (tpr & (tpr - 1))) return 0;
+    for (const void *p : ptrs)
+        if (reinterpret_cast<uintptr_t>(p) & 15u) return 0;
+    return tpr;
+}
+
+template <class T>
+static bool blaunch_prep_pairs(double *X, T *D, double *R64, const double *Bv, int b, const BatchSeg &sg,
+                               const int32_t *mask, hipStream_t s) {
+    const int tpr = pair_tpr(b, {X, D, R64, Bv});
+    if (!tpr) return false;
+    with_tpr(tpr, [&](auto c) {
+        constexpr int TPR = decltype(c)::value;
+        with_nt<double>(sg.rows * b, [&](auto nt) {
+            hipLaunchKernelGGL((brefresh_prep_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT),
+                               0, s, X, D, R64, Bv, sg, mask);
+        });
+    });
+    return true;
+}
+
+template <class T>
+static bool blaunch_convert_pairs(T *R, const double *R64, int b, const BatchSeg &sg, const int32_t *mask,
+                                  double *partials, hipStream_t s) {
+    const int tpr = pair_tpr(b, {R, R64});
+    if (!tpr) return false;
+    with_tpr(tpr, [&](auto c) {
+        constexpr int TPR = decltype(c)::value;
+        with_nt<double>(sg.rows * b, [&](auto nt) {
+            hipLaunchKernelGGL((bconvert_vec_kernel<T, TPR, kVU, decltype(nt)::value>), dim3(sg.G), dim3(kVT), 0, s, R,
+                               R64, sg, mask, partials);
+        });
+    });
+    return true;
+}
+
 int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const double *Bv, int b, const BatchSeg &sg,
                             const int32_t *mask, hipStream_t s) {
     if (sg.G == 0) return SELL_OK;  // no workgroups: no system with rows to update
+    if (dt == SELL_F64 ? blaunch_prep_pairs(X, tp<double>(D), R64, Bv, b, sg, mask, s)
+                       : blaunch_prep_pairs(X, tp<float>(D), R64, Bv, b, sg, mask, s))
+        return ok();
     const int bpad = pow2_at_least(b);
     if (dt == SELL_F64)
         hipLaunchKernelGGL(brefresh_prep_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, X, tp<double>(D), R64, Bv, b,
@@ -750,7 +882,9 @@ int bcg_launch_refresh_prep(int dt, double *X, void *D, double *R64, const doubl
 int bcg_launch_convert(int dt, void *R, const double *R64, int b, const BatchSeg &sg, const int32_t *mask,
                        double *partials, double *rho, double *thresh2, const double *ref, double f2, hipStream_t s) {
     const int bpad = pow2_at_least(b);
-    if (sg.G > 0) {  // (with no workgroups the finish below sums no partials: rho = 0)
+    if (sg.G > 0 && !(dt == SELL_F64 ? blaunch_convert_pairs(tp<double>(R), R64, b, sg, mask, partials, s)
+                                     : blaunch_convert_pairs(tp<float>(R), R64, b, sg, mask, partials, s))) {
+        // (with no workgroups the finish below sums no partials: rho = 0)
         if (dt == SELL_F64)
             hipLaunchKernelGGL(bconvert_kernel<double>, dim3(sg.G), dim3(kVT), 0, s, tp<double>(R), R64, b, bpad, sg,
                                mask, partials);
